@@ -1,0 +1,76 @@
+"""The plain definition of the result and of the convergence measure.
+
+* The wanted result is the m lowest eigenpairs (lambda_i, x_i) of the
+  symmetric-definite pencil H x = lambda S x (Section 2, eq. (ghep)), lambda
+  ascending, X S-orthonormal.  At the Gamma point the matrices are real.
+* Res (eq. (res1)) is ||r_i|| / ||H psi_i|| with r_i = H psi_i - eps_i S psi_i.
+  The experiments shift H by sigma0 so that H - sigma0 S is positive definite
+  (Section 5); the denominator here uses that shifted H, ||(H - sigma0 S) psi_i||,
+  while r_i is shift-invariant.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def dense_eigs(H, S, m: int):
+    """Lowest m eigenpairs of the dense pencil (H, S) by LAPACK's symmetric-definite
+    driver: the textbook definition of the GHEP solution (eq. (ghep))."""
+    H = np.asarray(H.toarray() if hasattr(H, "toarray") else H, dtype=np.float64)
+    S = np.asarray(S.toarray() if hasattr(S, "toarray") else S, dtype=np.float64)
+    lam, X = sla.eigh(H, S, subset_by_index=[0, m - 1])
+    return lam, X
+
+
+def mp_eigs(H, S, dps: int = 40):
+    """All eigenvalues of (H, S) in mpmath at ``dps`` digits: Cholesky S = L L^T,
+    then the symmetric eigenvalues of L^{-1} H L^{-T}.  Independent of LAPACK."""
+    import mpmath as mp
+    H = np.asarray(H.toarray() if hasattr(H, "toarray") else H, dtype=np.float64)
+    S = np.asarray(S.toarray() if hasattr(S, "toarray") else S, dtype=np.float64)
+    with mp.workdps(dps):
+        Hm = mp.matrix(H.tolist())
+        Sm = mp.matrix(S.tolist())
+        Lm = mp.cholesky(Sm)
+        Li = mp.inverse(Lm)
+        C = Li * Hm * Li.T
+        C = (C + C.T) / 2
+        ev = mp.eigsy(C, eigvals_only=True)
+        vals = sorted(float(v) for v in ev)
+    return np.array(vals)
+
+
+def relative_residuals(H, S, lam, X, sigma0: float):
+    """Res_i = ||H x_i - lam_i S x_i|| / ||(H - sigma0 S) x_i||  (eq. (res1), shifted H)."""
+    HX = H @ X
+    SX = S @ X
+    R = HX - SX * lam[None, :]
+    den = np.linalg.norm(HX - sigma0 * SX, axis=0)
+    return np.linalg.norm(R, axis=0) / den
+
+
+def clusters(lam, sigma0: float, rel_gap: float = 1e-6):
+    """Maximal runs of eigenvalues whose neighbour gaps are below
+    rel_gap * |lambda - sigma0|; returned as a list of index lists."""
+    out = [[0]]
+    for i in range(1, len(lam)):
+        if abs(lam[i] - lam[i - 1]) < rel_gap * abs(lam[i] - sigma0):
+            out[-1].append(i)
+        else:
+            out.append([i])
+    return out
+
+
+def s_principal_angles(S, X, Y):
+    """Principal angles between span(X) and span(Y) in the S inner product."""
+    def sorth(A):
+        G = A.T @ (S @ A)
+        G = 0.5 * (G + G.T)
+        w, V = np.linalg.eigh(G)
+        return A @ (V / np.sqrt(w)[None, :])
+    Qx, Qy = sorth(X), sorth(Y)
+    M = Qx.T @ (S @ Qy)
+    sv = np.linalg.svd(M, compute_uv=False)
+    sv = np.clip(sv, -1.0, 1.0)
+    return np.arccos(sv)

@@ -1,0 +1,396 @@
+"""Seeded synthetic PUFE-shaped generalized eigenproblems (inputs only).
+
+This module builds the sparse pencil (H, S) that the solver and the oracle both
+consume.  It holds none of the eigensolver's arithmetic: it is the
+discretisation that produces the input matrices, and the random draws
+(atom positions, cold-start blocks) that the solver treats as given data.
+
+Construction (the stand-in for the paper's PUFE Hamiltonian and overlap
+matrices, Section 2, eq. (ghep), and the cubic-cell setting of Section 5):
+
+* periodic cube of side ``L`` meshed with ``ne**3`` trilinear hexahedra,
+  h = L / ne, one finite-element node per mesh vertex (ne**3 nodes);
+* effective potential  V(r) = -4 * sum_atoms sum_images exp(-|r - R|^2 / (2 * 0.5^2));
+* partition-of-unity enrichment: every FE node lying within 2 bohr of an atom
+  (nearest periodic image) carries one extra basis function, its hat function
+  times g(r) = exp(-alpha |r - R*|^2) with R* the atom image nearest that node;
+* H_ij = 1/2 int grad(phi_i).grad(phi_j) + int V phi_i phi_j,
+  S_ij = int phi_i phi_j, with 3^3 Gauss points per element, or 4^3 Gauss
+  points for every integral of an element that has an enriched node.
+
+Degrees of freedom are numbered node-major: each node's standard function
+first, then its enriched functions in atom order.  H and S share one sparsity
+pattern (as the paper notes for PUFE, Section 4 footnote on eq. (k1)).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+ENRICH_RADIUS = 2.0          # bohr: node-within-radius enrichment rule
+ENRICH_ALPHA = 1.0           # g(r) = exp(-alpha |r - R|^2)
+V_DEPTH = 4.0                # V = -V_DEPTH * exp(-|r - R|^2 / (2 * V_WIDTH^2))
+V_WIDTH = 0.5
+MIN_SEP = 1.5                # minimum atom separation (minimum image), bohr
+V_CUTOFF = 5.5               # potential terms beyond this distance are < 1e-26
+
+
+@dataclasses.dataclass
+class Problem:
+    """A sparse symmetric-definite pencil (H, S) with one shared CSR pattern."""
+    n: int
+    rowptr: np.ndarray       # int64[n+1]
+    col: np.ndarray          # int32[nnz], sorted within each row
+    h_val: np.ndarray        # float64[nnz]
+    s_val: np.ndarray        # float64[nnz]
+    v_min: float             # minimum of V over all quadrature points
+    sigma0: float            # shift making H - sigma0 S positive definite
+    eps_bar: float           # default global preconditioner shift (below lambda_1)
+    L: float
+    ne: int
+    atoms: np.ndarray        # (natoms, 3)
+    amplitudes: np.ndarray   # (natoms,) potential depth multipliers (SCF-like drift)
+    dof_node: np.ndarray     # int64[n] host node of every dof
+    dof_atom: np.ndarray     # int64[n] enrichment atom (-1 for standard dofs)
+    seed: int
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    def H(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.h_val, self.col, self.rowptr), shape=(self.n, self.n))
+
+    def S(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.s_val, self.col, self.rowptr), shape=(self.n, self.n))
+
+
+def _gauss01(npts: int):
+    x, w = np.polynomial.legendre.leggauss(npts)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def _quad3d(npts: int):
+    x, w = _gauss01(npts)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    W = (w[:, None, None] * w[None, :, None] * w[None, None, :]).ravel()
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1), W
+
+
+# local node a = ax + 2 ay + 4 az at offsets (ax, ay, az) in {0,1}^3
+_LOCAL_OFF = np.array([[a & 1, (a >> 1) & 1, (a >> 2) & 1] for a in range(8)], dtype=np.int64)
+
+
+def _shape(xi: np.ndarray):
+    """Trilinear shape functions and reference gradients at points xi (nq,3)."""
+    nq = xi.shape[0]
+    N = np.empty((nq, 8))
+    dN = np.empty((nq, 8, 3))
+    for a in range(8):
+        o = _LOCAL_OFF[a]
+        f = [np.where(o[d] == 1, xi[:, d], 1.0 - xi[:, d]) for d in range(3)]
+        g = [np.where(o[d] == 1, 1.0, -1.0) * np.ones(nq) for d in range(3)]
+        N[:, a] = f[0] * f[1] * f[2]
+        dN[:, a, 0] = g[0] * f[1] * f[2]
+        dN[:, a, 1] = f[0] * g[1] * f[2]
+        dN[:, a, 2] = f[0] * f[1] * g[2]
+    return N, dN
+
+
+def place_atoms(natoms: int, L: float, seed: int, min_sep: float = MIN_SEP) -> np.ndarray:
+    """Uniform positions in [0,L)^3, rejecting any closer than min_sep (minimum image)."""
+    rng = np.random.default_rng(seed)
+    atoms = []
+    tries = 0
+    while len(atoms) < natoms:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place atoms with the requested separation")
+        p = rng.uniform(0.0, L, size=3)
+        ok = True
+        for q in atoms:
+            d = p - q
+            d -= L * np.round(d / L)
+            if np.linalg.norm(d) < min_sep:
+                ok = False
+                break
+        if ok:
+            atoms.append(p)
+    return np.array(atoms, dtype=np.float64).reshape(natoms, 3)
+
+
+def _potential_at(elem_ijk: np.ndarray, xi: np.ndarray, h: float,
+                  ne: int, atoms: np.ndarray, amps: np.ndarray) -> np.ndarray:
+    """V at quadrature points xi of the listed elements, all periodic images within cutoff.
+
+    Returns an array (len(elem_ijk), nq).
+    """
+    nel = elem_ijk.shape[0]
+    nq = xi.shape[0]
+    V = np.zeros((nel, nq))
+    # element id -> row in elem_ijk
+    lookup = -np.ones(ne ** 3, dtype=np.int64)
+    eid = elem_ijk[:, 0] + ne * (elem_ijk[:, 1] + ne * elem_ijk[:, 2])
+    lookup[eid] = np.arange(nel)
+    reach = int(math.ceil(V_CUTOFF / h)) + 1
+    inv2w2 = 1.0 / (2.0 * V_WIDTH * V_WIDTH)
+    for a in range(atoms.shape[0]):
+        R = atoms[a]
+        base = np.floor(R / h).astype(np.int64)
+        rngs = [np.arange(base[d] - reach, base[d] + reach + 1) for d in range(3)]
+        I, J, K = np.meshgrid(*rngs, indexing="ij")
+        I, J, K = I.ravel(), J.ravel(), K.ravel()
+        # unwrapped element origin minus atom -> displacement of quadrature points
+        org = np.stack([I, J, K], axis=1) * h - R            # (nb,3)
+        cen = org + 0.5 * h
+        keep = np.linalg.norm(cen, axis=1) <= V_CUTOFF + h
+        I, J, K, org = I[keep], J[keep], K[keep], org[keep]
+        phys = (I % ne) + ne * ((J % ne) + ne * (K % ne))
+        rows = lookup[phys]
+        sel = rows >= 0
+        if not np.any(sel):
+            continue
+        rows, org = rows[sel], org[sel]
+        d = org[:, None, :] + h * xi[None, :, :]              # (nb,nq,3)
+        contrib = -V_DEPTH * amps[a] * np.exp(-inv2w2 * np.einsum("bqd,bqd->bq", d, d))
+        np.add.at(V, rows, contrib)
+    return V
+
+
+def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
+             atoms: np.ndarray | None = None) -> Problem:
+    """Assemble the PUFE-shaped pencil for a periodic cube (see module docstring)."""
+    h = L / ne
+    nnode = ne ** 3
+    if atoms is None:
+        atoms = place_atoms(natoms, L, seed) if natoms > 0 else np.zeros((0, 3))
+    atoms = np.asarray(atoms, dtype=np.float64).reshape(-1, 3)
+    natoms = atoms.shape[0]
+    amps = np.ones(natoms) if amplitudes is None else np.asarray(amplitudes, dtype=np.float64)
+
+    # ---- enrichment: (node, atom) pairs with node within ENRICH_RADIUS of the atom
+    pairs_node, pairs_atom = [], []
+    reachn = int(math.ceil(ENRICH_RADIUS / h)) + 1
+    for a in range(natoms):
+        R = atoms[a]
+        base = np.round(R / h).astype(np.int64)
+        rngs = [np.arange(base[d] - reachn, base[d] + reachn + 1) for d in range(3)]
+        I, J, K = np.meshgrid(*rngs, indexing="ij")
+        I, J, K = I.ravel(), J.ravel(), K.ravel()
+        nid = (I % ne) + ne * ((J % ne) + ne * (K % ne))
+        nid = np.unique(nid)
+        ii, jj, kk = nid % ne, (nid // ne) % ne, nid // (ne * ne)
+        d = np.stack([ii, jj, kk], axis=1) * h - R
+        d -= L * np.round(d / L)
+        dist = np.linalg.norm(d, axis=1)
+        nid = nid[dist <= ENRICH_RADIUS]
+        pairs_node.append(nid)
+        pairs_atom.append(np.full(nid.shape[0], a, dtype=np.int64))
+    if natoms:
+        pn = np.concatenate(pairs_node)
+        pa = np.concatenate(pairs_atom)
+    else:
+        pn = np.zeros(0, dtype=np.int64)
+        pa = np.zeros(0, dtype=np.int64)
+    order = np.lexsort((pa, pn))
+    pn, pa = pn[order], pa[order]
+    nenr_node = np.bincount(pn, minlength=nnode)
+    # node-major dof numbering
+    first_dof = np.zeros(nnode + 1, dtype=np.int64)
+    first_dof[1:] = np.cumsum(1 + nenr_node)
+    n = int(first_dof[-1])
+    # dof of enriched pair = first_dof[node] + 1 + rank within node
+    rank = np.arange(pn.shape[0]) - np.searchsorted(pn, pn, side="left")
+    pair_dof = first_dof[pn] + 1 + rank
+    dof_node = np.repeat(np.arange(nnode), 1 + nenr_node)
+    dof_atom = -np.ones(n, dtype=np.int64)
+    dof_atom[pair_dof] = pa
+    max_enr = int(nenr_node.max()) if nnode else 0
+
+    # ---- elements
+    ee = np.arange(ne ** 3)
+    E = np.stack([ee % ne, (ee // ne) % ne, ee // (ne * ne)], axis=1)     # element ijk
+    enodes = np.empty((ne ** 3, 8), dtype=np.int64)
+    for a in range(8):
+        o = _LOCAL_OFF[a]
+        enodes[:, a] = ((E[:, 0] + o[0]) % ne) + ne * (((E[:, 1] + o[1]) % ne) + ne * ((E[:, 2] + o[2]) % ne))
+    enr_elem = nenr_node[enodes].sum(axis=1) > 0
+
+    rows_all, cols_all, hv_all, sv_all = [], [], [], []
+    vmin = np.inf
+
+    # ---- standard elements: 3^3 Gauss, 8 trilinear functions
+    xi3, w3 = _quad3d(3)
+    N3, dN3 = _shape(xi3)
+    Kref = 0.5 * np.einsum("q,qad,qbd->ab", w3, dN3, dN3) * h        # 1/2 int grad.grad (h^3 / h^2)
+    Mref = np.einsum("q,qa,qb->ab", w3, N3, N3) * h ** 3
+    std = np.nonzero(~enr_elem)[0]
+    chunk = 65536
+    for c0 in range(0, std.shape[0], chunk):
+        els = std[c0:c0 + chunk]
+        Vq = _potential_at(E[els], xi3, h, ne, atoms, amps)
+        if Vq.size:
+            vmin = min(vmin, float(Vq.min()))
+        Vloc = np.einsum("eq,q,qa,qb->eab", Vq, w3 * h ** 3, N3, N3)
+        Hloc = Kref[None] + Vloc
+        Sloc = np.broadcast_to(Mref, Hloc.shape)
+        dofs = first_dof[enodes[els]]                                   # (e,8)
+        rows_all.append(np.repeat(dofs, 8, axis=1).ravel())
+        cols_all.append(np.tile(dofs, (1, 8)).ravel())
+        hv_all.append(Hloc.reshape(-1))
+        sv_all.append(np.ascontiguousarray(Sloc).reshape(-1))
+
+    # ---- enriched elements: 4^3 Gauss, 8 hats plus the enriched functions of their nodes
+    xi4, w4 = _quad3d(4)
+    N4, dN4 = _shape(xi4)
+    enr = np.nonzero(enr_elem)[0]
+    F = 8 + 8 * max_enr
+    echunk = 4096
+    for c0 in range(0, enr.shape[0], echunk):
+        els = enr[c0:c0 + echunk]
+        ne_c = els.shape[0]
+        Vq = _potential_at(E[els], xi4, h, ne, atoms, amps)
+        if Vq.size:
+            vmin = min(vmin, float(Vq.min()))
+        nq = xi4.shape[0]
+        phi = np.zeros((ne_c, nq, F))
+        grad = np.zeros((ne_c, nq, F, 3))
+        dof = np.zeros((ne_c, F), dtype=np.int64)
+        valid = np.zeros((ne_c, F), dtype=bool)
+        phi[:, :, :8] = N4[None]
+        grad[:, :, :8, :] = dN4[None] / h
+        nodes = enodes[els]
+        dof[:, :8] = first_dof[nodes]
+        valid[:, :8] = True
+        org = E[els] * h                                                # unwrapped element origin
+        rq = org[:, None, :] + h * xi4[None, :, :]                      # (e,nq,3)
+        slot = 8
+        for a in range(8):
+            nd = nodes[:, a]
+            xnode = org + _LOCAL_OFF[a] * h                             # (e,3) local node position
+            for r in range(max_enr):
+                has = nenr_node[nd] > r
+                if not np.any(has):
+                    continue
+                pdof = first_dof[nd] + 1 + r
+                at = np.where(has, dof_atom[np.where(has, pdof, 0)], 0)
+                dd = xnode - atoms[at]
+                dd -= L * np.round(dd / L)
+                Rstar = xnode - dd                                      # nearest image to the node
+                u = rq - Rstar[:, None, :]                              # (e,nq,3)
+                g = np.exp(-ENRICH_ALPHA * np.einsum("eqd,eqd->eq", u, u))
+                dg = -2.0 * ENRICH_ALPHA * u * g[..., None]
+                m = has[:, None]
+                phi[:, :, slot] = np.where(m, N4[None, :, a] * g, 0.0)
+                gr = g[..., None] * (dN4[None, :, a, :] / h) + N4[None, :, a, None] * dg
+                grad[:, :, slot, :] = np.where(m[..., None], gr, 0.0)
+                dof[:, slot] = np.where(has, pdof, 0)
+                valid[:, slot] = has
+                slot += 1
+        wq = w4 * h ** 3
+        Hloc = 0.5 * np.einsum("q,eqfd,eqgd->efg", wq, grad, grad, optimize=True) \
+            + np.einsum("q,eq,eqf,eqg->efg", wq, Vq, phi, phi, optimize=True)
+        Sloc = np.einsum("q,eqf,eqg->efg", wq, phi, phi, optimize=True)
+        vv = valid[:, :, None] & valid[:, None, :]
+        R_ = np.repeat(dof[:, :, None], F, axis=2)
+        C_ = np.repeat(dof[:, None, :], F, axis=1)
+        rows_all.append(R_[vv])
+        cols_all.append(C_[vv])
+        hv_all.append(Hloc[vv])
+        sv_all.append(Sloc[vv])
+
+    rows = np.concatenate(rows_all)
+    cols = np.concatenate(cols_all)
+    Hc = sp.coo_matrix((np.concatenate(hv_all), (rows, cols)), shape=(n, n)).tocsr()
+    Sc = sp.coo_matrix((np.concatenate(sv_all), (rows, cols)), shape=(n, n)).tocsr()
+    # exact symmetry (duplicate summation order may differ between (i,j) and (j,i))
+    Hc = ((Hc + Hc.T) * 0.5).tocsr()
+    Sc = ((Sc + Sc.T) * 0.5).tocsr()
+    # one shared pattern: union of both patterns, explicit zeros kept
+    pat = (abs(Hc) + abs(Sc)).tocsr()
+    pat.sort_indices()
+    Hc = _on_pattern(Hc, pat)
+    Sc = _on_pattern(Sc, pat)
+    if not np.isfinite(vmin):
+        vmin = 0.0
+    return Problem(n=n, rowptr=pat.indptr.astype(np.int64), col=pat.indices.astype(np.int32),
+                   h_val=Hc, s_val=Sc, v_min=vmin, sigma0=vmin - 1.0, eps_bar=vmin - 0.1,
+                   L=float(L), ne=int(ne), atoms=atoms, amplitudes=amps, dof_node=dof_node,
+                   dof_atom=dof_atom, seed=int(seed))
+
+
+def _on_pattern(A: sp.csr_matrix, pat: sp.csr_matrix) -> np.ndarray:
+    """Values of A laid out on the CSR pattern ``pat`` (zeros where A has none)."""
+    A = A.tocsr()
+    A.sort_indices()
+    out = np.zeros(pat.indices.shape[0])
+    # both sorted per row: merge by row-wise search
+    n = pat.shape[0]
+    prow = np.repeat(np.arange(n), np.diff(pat.indptr))
+    arow = np.repeat(np.arange(n), np.diff(A.indptr))
+    pkey = prow.astype(np.int64) * n + pat.indices
+    akey = arow.astype(np.int64) * n + A.indices
+    pos = np.searchsorted(pkey, akey)
+    out[pos] = A.data
+    return out
+
+
+def count_dofs(L: float, ne: int, natoms: int, seed: int) -> int:
+    """Number of dofs the construction gives, without assembling (nodes + enriched pairs)."""
+    h = L / ne
+    atoms = place_atoms(natoms, L, seed) if natoms > 0 else np.zeros((0, 3))
+    g = np.arange(ne) * h
+    total = ne ** 3
+    for a in range(atoms.shape[0]):
+        d = [g - atoms[a, k] for k in range(3)]
+        d = [x - L * np.round(x / L) for x in d]
+        r2 = d[0][:, None, None] ** 2 + d[1][None, :, None] ** 2 + d[2][None, None, :] ** 2
+        total += int(np.count_nonzero(r2 <= ENRICH_RADIUS ** 2))
+    return total
+
+
+# ------------------------------------------------------------------ named workloads
+
+#: The five workload shapes: (L, ne, natoms, nev).  Serving draws its own.
+WORKLOADS = {
+    "c1": dict(L=6.0, ne=6, natoms=1, nev=4),
+    "c2": dict(L=12.0, ne=24, natoms=8, nev=32),
+    "c3": dict(L=24.0, ne=48, natoms=64, nev=256),
+    "c5": dict(L=32.0, ne=64, natoms=128, nev=512),
+}
+
+
+def guard_vectors(nev: int) -> int:
+    """Number of extra guard vectors m0 carried beside the nev wanted ones."""
+    return max(int(math.ceil(nev / 10.0)), 4)
+
+
+def workload(name: str, seed: int = 0, **kw) -> Problem:
+    w = WORKLOADS[name]
+    return generate(w["L"], w["ne"], w["natoms"], seed, **kw)
+
+
+def start_block(n: int, b: int, seed: int) -> np.ndarray:
+    """Cold-start block: i.i.d. standard normal n x b, column-major (Fortran) order."""
+    rng = np.random.default_rng(seed + 1000)
+    return np.asfortranarray(rng.standard_normal((n, b)))
+
+
+def free_particle_eigs(ne: int, L: float, count: int) -> np.ndarray:
+    """Exact spectrum of the assembled trilinear pencil with V = 0 and no enrichment.
+
+    Separable: per dimension the 1-D linear-element pencil on a periodic ring has
+    K_1 = (2 - 2cos t)/h and M_1 = h (4 + 2cos t)/6 at wavenumber t = 2 pi j / ne;
+    the 3-D stiffness is sum_d K_d prod_{e!=d} M_e and the mass prod_d M_d,
+    so lambda = 1/2 sum_d K_d / M_d.
+    """
+    h = L / ne
+    t = 2.0 * np.pi * np.arange(ne) / ne
+    k1 = (2.0 - 2.0 * np.cos(t)) / h
+    m1 = h * (4.0 + 2.0 * np.cos(t)) / 6.0
+    r = k1 / m1
+    lam = 0.5 * (r[:, None, None] + r[None, :, None] + r[None, None, :])
+    return np.sort(lam.ravel())[:count]
