@@ -1,0 +1,234 @@
+/*
+ * labpsd.h -- C ABI of the MI355X (gfx950) LABPSD eigensolver library, liblabpsd.so.
+ *
+ * LABPSD is the locally accelerated block preconditioned steepest descent method
+ * with hybrid (global + locally accelerated) preconditioning of Cai, Bai, Pask and
+ * Sukumar, arXiv:1308.2445.  It computes the lowest eigenpairs of a sparse
+ * symmetric-definite pencil H x = lambda S x (Section 2, eq. (ghep)) in which H
+ * and S share one sparsity pattern (Section 4, footnote to eq. (k1)).
+ *
+ * Conventions shared by every call
+ *   - Status: 0 OK; > 0 warning with valid outputs; < 0 error.  On error the
+ *     message is available from labpsd_last_error() (thread-local) and no
+ *     output buffer has been written unless the call says otherwise.
+ *   - Block vectors are column-major FP64 with an explicit leading dimension
+ *     (ld >= number of rows).  "device" pointers are HIP device memory on the
+ *     context's device; "host" pointers are ordinary host memory.
+ *   - Every call that takes device pointers enqueues its work on the context's
+ *     stream and returns without waiting, unless it returns host data (it then
+ *     synchronises that stream).  The caller keeps ownership of all buffers it
+ *     passes; the library owns the device copies it makes (matrix, factor,
+ *     workspaces) and frees them in the matching destroy call.
+ *   - A context is used by one host thread at a time.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef LABPSD_H
+#define LABPSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LABPSD_OK = 0,
+    LABPSD_NOT_CONVERGED = 1, /* iteration cap reached; outputs hold the last iterate   */
+    LABPSD_EINVAL = -1,       /* invalid argument or input (message says which)         */
+    LABPSD_ENOMEM = -2,       /* device or host allocation failed                       */
+    LABPSD_EHIP = -3,         /* a HIP runtime call failed                              */
+    LABPSD_ENOTSPD = -4,      /* H - eps_bar S is not positive definite                 */
+    LABPSD_ERANK = -5,        /* search space [Psi P] lost rank below the block width   */
+    LABPSD_ESTATE = -6        /* call out of order (e.g. solve before set_global_precond)*/
+} labpsd_status;
+
+/* Precision of the preconditioner step (global apply and MINRES refinement).
+ * Residuals, products of the search directions, Gram matrices, the
+ * S-orthonormalisation and Rayleigh-Ritz are FP64 in both modes.           */
+typedef enum { LABPSD_FP64 = 0, LABPSD_MIXED = 1 } labpsd_precision;
+
+/* Which preconditioner acts on the residuals (Section 3 hybrid scheme;
+ * Section 5.4 compares the three).                                         */
+typedef enum {
+    LABPSD_HYBRID = 0,      /* global everywhere, MINRES refinement of localised pairs */
+    LABPSD_GLOBAL_ONLY = 1, /* step 6(a) only                                          */
+    LABPSD_LOCAL_ONLY = 2   /* localised pairs: MINRES from zero; others global        */
+} labpsd_precond_mode;
+
+typedef enum { LABPSD_MEM_HOST = 0, LABPSD_MEM_DEVICE = 1 } labpsd_mem;
+
+typedef struct labpsd_ctx labpsd_ctx;
+typedef struct labpsd_problem labpsd_problem;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device` that enqueues all work on `stream`
+ * (a hipStream_t; NULL means the null stream).  The stream is borrowed.     */
+labpsd_status labpsd_ctx_create(int device, void* stream, labpsd_ctx** out);
+void labpsd_ctx_destroy(labpsd_ctx* ctx);
+/* Rebind the context to another stream of the same device. */
+labpsd_status labpsd_ctx_set_stream(labpsd_ctx* ctx, void* stream);
+/* Message of the last error on this thread ("" if none). */
+const char* labpsd_last_error(void);
+/* Library version string. */
+const char* labpsd_version(void);
+
+/* ------------------------------------------------------------------ problem */
+
+/* Upload the pencil (H, S) (Section 2, eq. (ghep)).  Host arrays: rowptr
+ * int64[n+1], col int32[nnz] (per row strictly increasing; the pattern must be
+ * structurally symmetric), h_val and s_val float64[nnz] on that one pattern.
+ * The library copies everything (a sliced-ELL device layout plus FP32 value
+ * copies for the mixed-precision preconditioner); the caller may free on
+ * return.  EINVAL on n < 1, nnz < n, unsorted/duplicate/out-of-range columns
+ * or a pattern that is not structurally symmetric.                          */
+labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz,
+                                    const int64_t* rowptr, const int32_t* col,
+                                    const double* h_val, const double* s_val,
+                                    labpsd_problem** out);
+/* Replace the values of H (host float64[nnz], same pattern) for the next GHEP of
+ * an SCF-like sequence (Section 2).  S and the global factorisation are kept:
+ * the paper builds the global preconditioner once, from the first H (Section 4). */
+labpsd_status labpsd_problem_update_h(labpsd_problem* p, const double* h_val);
+void labpsd_problem_destroy(labpsd_problem* p);
+int64_t labpsd_problem_n(const labpsd_problem* p);
+
+/* Global preconditioner K = (H - eps_bar S)^{-1} (eq. (globalprecond), eq. (k1p)).
+ * Factorises H - eps_bar S once on the host (FP64 supernodal Cholesky after a
+ * nested-dissection ordering; eq. (ldl) with 1x1 pivots only, since eps_bar
+ * below lambda_1 makes the matrix positive definite) and uploads the factor
+ * panels in FP64 and FP32.  `coords` (host float64[n*3], row-major x,y,z per
+ * dof, or NULL) guides the ordering by coordinate bisection; with NULL a
+ * breadth-first level-structure bisection of the graph is used.
+ * ENOTSPD if a pivot is not positive (eps_bar too high).                    */
+labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const double* coords);
+
+/* Locally accelerated preconditioner parameters (Section 3 remark 4, Section 5):
+ * a pair is localised when Res_i <= tau1 and |eps_i - eps_i^prev| <= tau2
+ * |eps_i^prev|; its direction is refined by MINRES on (H - eps_i S) p = -r_i
+ * (eq. (indls)) until ||(H - eps_i S) p + r_i|| <= eta ||r_i|| (eq. (approxp))
+ * or max_inner iterations.  Defaults: 0.1, 0.1, 0.25, 20, HYBRID.           */
+labpsd_status labpsd_set_local_precond(labpsd_problem* p, double tau1, double tau2, double eta,
+                                       int max_inner, labpsd_precond_mode mode);
+
+/* Factor statistics: supernodes, levels, nnz(L), host factorisation seconds. */
+typedef struct {
+    int64_t n_supernodes;
+    int32_t n_levels;
+    int64_t nnz_factor;      /* stored entries of L (lower triangles of diagonal blocks + off-diagonal) */
+    double flops_factor;     /* host factorisation flops                                                */
+    double t_order_s, t_factor_s, t_upload_s;
+} labpsd_factor_info;
+labpsd_status labpsd_get_factor_info(const labpsd_problem* p, labpsd_factor_info* info);
+
+/* ------------------------------------------------------------------ solve */
+
+typedef struct {
+    int nev;              /* m: wanted eigenpairs                                         */
+    int m0;               /* guard vectors; block width b = nev + m0 (Section 3 remark 1)  */
+    double tol;           /* converged when max_i Res_i <= tol over the first nev (eq. (resL)) */
+    int max_outer;        /* outer iteration cap                                          */
+    double sigma0;        /* shift in the Res denominator ||(H - sigma0 S) psi|| (Section 5) */
+    int precision;        /* labpsd_precision                                             */
+    int refresh_every;    /* recompute H Psi, S Psi from H and S every this many iterations */
+    int timing;           /* nonzero: time every step with HIP events (stats.t_step_s)      */
+} labpsd_solve_params;
+
+typedef struct {
+    int outer_iters;          /* outer LABPSD iterations performed                         */
+    int64_t minres_iters;     /* total MINRES iterations (M_s of Section 5.2)               */
+    int64_t localized_cols;   /* total localised columns refined                           */
+    int rank_dropped;         /* search directions dropped by the rank-revealing RR         */
+    int refreshes;            /* explicit recomputations of H Psi, S Psi                    */
+    double hp;                /* outer iterations per solve (Hp for one GHEP)               */
+    double la;                /* M_s / (outer_iters * nev) (La, Section 5.2)                */
+    double t_solve_s;         /* wall time inside labpsd_solve                              */
+    /* per-step device time (timing != 0), seconds, and kernel launches:
+     * 0 products of Psi, 1 residual+Res, 2 global apply, 3 local refinement,
+     * 4 products of P, 5 Gram, 6 Rayleigh-Ritz, 7 block update, 8 gather/cast  */
+    double t_step_s[12];
+    int64_t n_launch[12];
+    int64_t n_cols[12];       /* columns processed by each step, summed over its launches */
+} labpsd_stats;
+
+/* Run LABPSD (Section 3 outline) from the start block X0 (n x (nev+m0),
+ * column-major, ld n; host or device per in_where).  E0 (nev+m0 values or
+ * NULL) are the previous Ritz values of a warm start; they serve as the
+ * previous-iteration values of the first localisation test.
+ * Outputs (host or device per out_where, caller-allocated):
+ *   lambda[nev] ascending; X n x nev (ld n), S-orthonormal;
+ *   res_hist[max_outer * nev] (may be NULL): Res_i at the start of every
+ *   iteration, iteration-major; *n_hist = iterations recorded (may be NULL).
+ *   stats may be NULL.
+ * Returns OK, NOT_CONVERGED (outputs hold the last iterate) or an error.
+ * Requires labpsd_set_global_precond first (ESTATE otherwise).              */
+labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* params, const double* X0,
+                           const double* E0, labpsd_mem in_where, double* lambda, double* X,
+                           double* res_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats);
+
+/* ------------------------------------------------------------------ hot-path steps
+ * The steps of one LABPSD iteration, each callable on its own for testing and
+ * measurement.  All pointers are device pointers; work is enqueued on the
+ * context's stream.                                                          */
+
+/* Steps 3 and 7: YH = H X and YS = S X in one pass over the shared pattern.
+ * X is n x w (ld ldx), YH and YS n x w (ld ldy).                             */
+labpsd_status labpsd_spmm(labpsd_problem* p, const double* X, int64_t ldx, int w, double* YH,
+                          double* YS, int64_t ldy);
+
+/* Per-column shifted product Y[:, j] = (H - shift[j] S) X[:, j] (Section 5 shifted
+ * matvec, used by the refinement).  precision LABPSD_FP64: X, Y float64 and
+ * FP64 values; LABPSD_MIXED: X, Y float32 with FP32 values and accumulation.
+ * shift: device float64[w].                                                   */
+labpsd_status labpsd_spmm_shifted(labpsd_problem* p, int precision, const void* X, int64_t ldx,
+                                  int w, const double* shift, void* Y, int64_t ldy);
+
+/* Step 4 and eq. (res1): R = PsiH[:, :m] - PsiS[:, :m] diag(E[:m]) (n x m, ld ldr),
+ * res[i] = ||r_i|| / ||PsiH[:, i] - sigma0 PsiS[:, i]||, rnorm[i] = ||r_i||.
+ * E, res, rnorm: device float64[m].                                           */
+labpsd_status labpsd_residual(labpsd_ctx* ctx, int64_t n, int m, const double* PsiH,
+                              const double* PsiS, int64_t ld, const double* E, double sigma0,
+                              double* R, int64_t ldr, double* res, double* rnorm);
+
+/* Step 6(a), eq. (k1p): P = -(H - eps_bar S)^{-1} R for p columns (R, P n x p).
+ * precision LABPSD_MIXED runs the substitutions in FP32 on FP32 factor panels. */
+labpsd_status labpsd_precond_apply(labpsd_problem* p, int precision, const double* R, int64_t ldr,
+                                   int ncols, double* P, int64_t ldp);
+
+/* Step 6(b): refine the columns cols[0..q) of P (n x *, ld ldp) in place so that
+ * ||(H - shift_j S) p + r|| <= eta ||r||, r the matching column of R (ld ldr),
+ * by MINRES on (H - shift_j S) dp = -((H - shift_j S) p + r) (eq. (indls)),
+ * at most max_inner iterations.  cols: device int32[q] column indices into
+ * both P and R; shift: device float64[q]; its: device int32[q] iterations used.
+ * precision LABPSD_MIXED runs MINRES in FP32.                                 */
+labpsd_status labpsd_local_refine(labpsd_problem* p, int precision, const double* R, int64_t ldr,
+                                  double* P, int64_t ldp, int q, const int32_t* cols,
+                                  const double* shift, double eta, int max_inner, int32_t* its);
+
+/* Step 8: HR = Z^T ZH and SR = Z^T ZS for k columns (n rows), symmetric parts.
+ * Z, ZH, ZS share ld ldz; HR, SR are k x k with ld ldr.                        */
+labpsd_status labpsd_gram(labpsd_ctx* ctx, int64_t n, int k, const double* Z, const double* ZH,
+                          const double* ZS, int64_t ldz, double* HR, double* SR, int64_t ldr);
+
+/* Step 9 with S-orthonormalisation: lowest nwant eigenpairs of (HR, SR) (k x k):
+ * gamma ascending, W (k x nwant, ld ldw) with W^T SR W = I.  SR is scaled to
+ * unit diagonal and Cholesky-factorised; if that fails the scaled SR is
+ * eigen-decomposed and directions below 1e-14 of its largest eigenvalue are
+ * dropped (the rank-revealing step the conclusions call for).  info: device
+ * int32[2] = {directions dropped, status (0 ok, -5 rank below nwant)}.
+ * k <= 4096.                                                                   */
+labpsd_status labpsd_rayleigh_ritz(labpsd_ctx* ctx, int k, int nwant, const double* HR,
+                                   const double* SR, int64_t ldr, double* gamma, double* W,
+                                   int64_t ldw, int32_t* info);
+
+/* Steps 10-11: Psi = Z W, PsiH = ZH W, PsiS = ZS W (Z* n x k, W k x b).
+ * Outputs must not alias the inputs.                                           */
+labpsd_status labpsd_block_update(labpsd_ctx* ctx, int64_t n, int k, int b, const double* Z,
+                                  const double* ZH, const double* ZS, int64_t ldz, const double* W,
+                                  int64_t ldw, double* Psi, double* PsiH, double* PsiS, int64_t ldo);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LABPSD_H */

@@ -1,0 +1,325 @@
+"""Python binding of liblabpsd, the MI355X (gfx950) LABPSD eigensolver.
+
+Argument marshalling only: every step of the solver runs in the HIP kernels and
+host C++ of liblabpsd.so; this module passes pointers and sizes.  PyTorch supplies
+device memory and the current HIP stream.  Block vectors on the device are torch
+tensors of shape (columns, ld) -- row j of the tensor is column j of the
+column-major block the library sees.
+
+The library must be built first (``python -m paper_1308_2445_amd.build``); if it
+is missing, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+# torch first: the process must hold exactly one HIP runtime, and liblabpsd.so then
+# binds to the one torch already loaded (same soname) instead of a second copy
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblabpsd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("liblabpsd.so is not built: run `python -m paper_1308_2445_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ENOMEM, EHIP, ENOTSPD, ERANK, ESTATE = -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+HYBRID, GLOBAL_ONLY, LOCAL_ONLY = 0, 1, 2
+MEM_HOST, MEM_DEVICE = 0, 1
+
+_STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
+                 -5: "ERANK", -6: "ESTATE"}
+
+#: names of the entries of labpsd_stats.t_step_s / n_launch
+STEP_NAMES = ["products_psi", "residual", "global_precond", "local_refine", "products_p", "gram",
+              "rayleigh_ritz", "block_update", "cast"]
+
+
+class LabpsdError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.labpsd_last_error().decode()
+        super().__init__("%s: %s (%s)" % (where, _STATUS_NAMES.get(code, code), msg))
+        self.code = code
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int), ("m0", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("sigma0", ctypes.c_double),
+                ("precision", ctypes.c_int), ("refresh_every", ctypes.c_int),
+                ("timing", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("minres_iters", ctypes.c_int64),
+                ("localized_cols", ctypes.c_int64), ("rank_dropped", ctypes.c_int),
+                ("refreshes", ctypes.c_int), ("hp", ctypes.c_double), ("la", ctypes.c_double),
+                ("t_solve_s", ctypes.c_double), ("t_step_s", ctypes.c_double * 12),
+                ("n_launch", ctypes.c_int64 * 12), ("n_cols", ctypes.c_int64 * 12)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("t_step_s", "n_launch", "n_cols")}
+        d["t_step_s"] = {STEP_NAMES[i]: self.t_step_s[i] for i in range(len(STEP_NAMES))}
+        d["n_launch"] = {STEP_NAMES[i]: int(self.n_launch[i]) for i in range(len(STEP_NAMES))}
+        d["cols"] = {STEP_NAMES[i]: int(self.n_cols[i]) for i in range(len(STEP_NAMES))}
+        return d
+
+
+class FactorInfo(ctypes.Structure):
+    _fields_ = [("n_supernodes", ctypes.c_int64), ("n_levels", ctypes.c_int32),
+                ("nnz_factor", ctypes.c_int64), ("flops_factor", ctypes.c_double),
+                ("t_order_s", ctypes.c_double), ("t_factor_s", ctypes.c_double),
+                ("t_upload_s", ctypes.c_double)]
+
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int
+_d = ctypes.c_double
+
+_SIGS = {
+    "labpsd_ctx_create": ([_i32, _p, ctypes.POINTER(_p)], _i32),
+    "labpsd_ctx_destroy": ([_p], None),
+    "labpsd_ctx_set_stream": ([_p, _p], _i32),
+    "labpsd_last_error": ([], ctypes.c_char_p),
+    "labpsd_version": ([], ctypes.c_char_p),
+    "labpsd_problem_create": ([_p, _i64, _i64, _p, _p, _p, _p, ctypes.POINTER(_p)], _i32),
+    "labpsd_problem_update_h": ([_p, _p], _i32),
+    "labpsd_problem_destroy": ([_p], None),
+    "labpsd_problem_n": ([_p], _i64),
+    "labpsd_set_global_precond": ([_p, _d, _p], _i32),
+    "labpsd_set_local_precond": ([_p, _d, _d, _d, _i32, _i32], _i32),
+    "labpsd_get_factor_info": ([_p, ctypes.POINTER(FactorInfo)], _i32),
+    "labpsd_solve": ([_p, ctypes.POINTER(SolveParams), _p, _p, _i32, _p, _p, _p,
+                      ctypes.POINTER(ctypes.c_int), _i32, ctypes.POINTER(Stats)], _i32),
+    "labpsd_spmm": ([_p, _p, _i64, _i32, _p, _p, _i64], _i32),
+    "labpsd_spmm_shifted": ([_p, _i32, _p, _i64, _i32, _p, _p, _i64], _i32),
+    "labpsd_residual": ([_p, _i64, _i32, _p, _p, _i64, _p, _d, _p, _i64, _p, _p], _i32),
+    "labpsd_precond_apply": ([_p, _i32, _p, _i64, _i32, _p, _i64], _i32),
+    "labpsd_local_refine": ([_p, _i32, _p, _i64, _p, _i64, _i32, _p, _p, _d, _i32, _p], _i32),
+    "labpsd_gram": ([_p, _i64, _i32, _p, _p, _p, _i64, _p, _p, _i64], _i32),
+    "labpsd_rayleigh_ritz": ([_p, _i32, _i32, _p, _p, _i64, _p, _p, _i64, _p], _i32),
+    "labpsd_block_update": ([_p, _i64, _i32, _i32, _p, _p, _p, _i64, _p, _i64, _p, _p, _p, _i64],
+                            _i32),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+#: every C symbol the header declares (checked by the CPU tests)
+EXPORTED = sorted(_SIGS)
+
+
+def _check(rc: int, where: str, allow=(OK,)) -> int:
+    if rc not in allow:
+        raise LabpsdError(rc, where)
+    return rc
+
+
+def version() -> str:
+    return _lib.labpsd_version().decode()
+
+
+def _ptr(a) -> int | None:
+    """Address of a numpy array or torch tensor (None passes NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ld(t) -> int:
+    """Leading dimension of a (columns, ld) torch tensor whose rows are contiguous."""
+    if t.dim() == 1:
+        return t.shape[0]
+    assert t.stride(1) == 1, "block tensors must have contiguous rows (shape (cols, ld))"
+    return t.stride(0)
+
+
+class Context:
+    """A library context bound to a HIP device and the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        torch.cuda.set_device(device)
+        h = _p()
+        _check(_lib.labpsd_ctx_create(device, _stream(), ctypes.byref(h)), "labpsd_ctx_create")
+        self.h = h
+        self.device = device
+
+    def sync_stream(self):
+        _check(_lib.labpsd_ctx_set_stream(self.h, _stream()), "labpsd_ctx_set_stream")
+
+    def close(self):
+        if self.h:
+            _lib.labpsd_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class SolveResult:
+    status: int
+    lam: object
+    X: object
+    res_hist: np.ndarray
+    stats: dict
+
+    @property
+    def converged(self) -> bool:
+        return self.status == OK
+
+
+class Problem:
+    """The pencil (H, S) on one shared CSR pattern, resident on the device."""
+
+    def __init__(self, ctx: Context, n, rowptr, col, h_val, s_val):
+        self.ctx = ctx
+        self.n = int(n)
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        h_val = np.ascontiguousarray(h_val, dtype=np.float64)
+        s_val = np.ascontiguousarray(s_val, dtype=np.float64)
+        self.nnz = int(col.shape[0])
+        h = _p()
+        ctx.sync_stream()
+        _check(_lib.labpsd_problem_create(ctx.h, self.n, self.nnz, _ptr(rowptr), _ptr(col), _ptr(h_val),
+                                          _ptr(s_val), ctypes.byref(h)), "labpsd_problem_create")
+        self.h = h
+
+    @classmethod
+    def from_pencil(cls, ctx: Context, P) -> "Problem":
+        return cls(ctx, P.n, P.rowptr, P.col, P.h_val, P.s_val)
+
+    def update_h(self, h_val):
+        h_val = np.ascontiguousarray(h_val, dtype=np.float64)
+        _check(_lib.labpsd_problem_update_h(self.h, _ptr(h_val)), "labpsd_problem_update_h")
+
+    def set_global_precond(self, eps_bar: float, coords=None):
+        c = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64).reshape(-1, 3)
+        self.ctx.sync_stream()
+        _check(_lib.labpsd_set_global_precond(self.h, float(eps_bar), _ptr(c)), "labpsd_set_global_precond")
+
+    def set_local_precond(self, tau1=0.1, tau2=0.1, eta=0.25, max_inner=20, mode=HYBRID):
+        _check(_lib.labpsd_set_local_precond(self.h, tau1, tau2, eta, max_inner, mode),
+               "labpsd_set_local_precond")
+
+    def factor_info(self) -> dict:
+        fi = FactorInfo()
+        _check(_lib.labpsd_get_factor_info(self.h, ctypes.byref(fi)), "labpsd_get_factor_info")
+        return {f: getattr(fi, f) for f, _ in fi._fields_}
+
+    def solve(self, nev: int, m0: int, X0, *, tol=1e-8, max_outer=200, sigma0=0.0,
+              precision=FP64, refresh_every=10, timing=False, E0=None, device_out=False):
+        """Run LABPSD from X0 (numpy n x b Fortran array, or torch (b, n) device tensor)."""
+        import torch
+        b = nev + m0
+        n = self.n
+        self.ctx.sync_stream()
+        if isinstance(X0, np.ndarray):
+            X0 = np.asfortranarray(X0, dtype=np.float64)
+            assert X0.shape == (n, b)
+            in_where = MEM_HOST
+        else:
+            assert tuple(X0.shape) == (b, n) and X0.is_contiguous() and X0.dtype == torch.float64
+            in_where = MEM_DEVICE
+        E0a = None if E0 is None else np.ascontiguousarray(E0, dtype=np.float64)
+        prm = SolveParams(nev, m0, tol, max_outer, sigma0, precision, refresh_every, 1 if timing else 0)
+        hist = np.zeros(max_outer * nev + nev)
+        nh = ctypes.c_int(0)
+        st = Stats()
+        if device_out:
+            lam = torch.empty(nev, dtype=torch.float64, device="cuda")
+            X = torch.empty((nev, n), dtype=torch.float64, device="cuda")
+            out_where = MEM_DEVICE
+            hist_arg = None
+        else:
+            lam = np.zeros(nev)
+            X = np.zeros((n, nev), order="F")
+            out_where = MEM_HOST
+            hist_arg = hist
+        rc = _lib.labpsd_solve(self.h, ctypes.byref(prm), _ptr(X0), _ptr(E0a), in_where, _ptr(lam), _ptr(X),
+                               _ptr(hist_arg), ctypes.byref(nh), out_where, ctypes.byref(st))
+        _check(rc, "labpsd_solve", allow=(OK, NOT_CONVERGED))
+        return SolveResult(status=rc, lam=lam, X=X,
+                           res_hist=hist[: nh.value * nev].reshape(nh.value, nev) if hist_arg is not None
+                           else np.zeros((0, nev)),
+                           stats=st.as_dict())
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.labpsd_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ hot-path steps
+# Device tensors only; blocks are (columns, ld) tensors.
+
+def labpsd_spmm(prob: Problem, X, YH, YS):
+    prob.ctx.sync_stream()
+    _check(_lib.labpsd_spmm(prob.h, _ptr(X), _ld(X), X.shape[0], _ptr(YH), _ptr(YS), _ld(YH)), "labpsd_spmm")
+
+
+def labpsd_spmm_shifted(prob: Problem, precision: int, X, shift, Y):
+    prob.ctx.sync_stream()
+    _check(_lib.labpsd_spmm_shifted(prob.h, precision, _ptr(X), _ld(X), X.shape[0], _ptr(shift), _ptr(Y),
+                                    _ld(Y)), "labpsd_spmm_shifted")
+
+
+def labpsd_residual(ctx: Context, n: int, m: int, PsiH, PsiS, E, sigma0: float, R, res, rnorm):
+    ctx.sync_stream()
+    _check(_lib.labpsd_residual(ctx.h, n, m, _ptr(PsiH), _ptr(PsiS), _ld(PsiH), _ptr(E), sigma0, _ptr(R),
+                                _ld(R), _ptr(res), _ptr(rnorm)), "labpsd_residual")
+
+
+def labpsd_precond_apply(prob: Problem, precision: int, R, P):
+    prob.ctx.sync_stream()
+    _check(_lib.labpsd_precond_apply(prob.h, precision, _ptr(R), _ld(R), R.shape[0], _ptr(P), _ld(P)),
+           "labpsd_precond_apply")
+
+
+def labpsd_local_refine(prob: Problem, precision: int, R, P, cols, shift, eta: float, max_inner: int, its):
+    prob.ctx.sync_stream()
+    _check(_lib.labpsd_local_refine(prob.h, precision, _ptr(R), _ld(R), _ptr(P), _ld(P), cols.shape[0],
+                                    _ptr(cols), _ptr(shift), eta, max_inner, _ptr(its)), "labpsd_local_refine")
+
+
+def labpsd_gram(ctx: Context, n: int, k: int, Z, ZH, ZS, HR, SR):
+    ctx.sync_stream()
+    _check(_lib.labpsd_gram(ctx.h, n, k, _ptr(Z), _ptr(ZH), _ptr(ZS), _ld(Z), _ptr(HR), _ptr(SR), _ld(HR)),
+           "labpsd_gram")
+
+
+def labpsd_rayleigh_ritz(ctx: Context, k: int, nwant: int, HR, SR, gamma, W, info):
+    ctx.sync_stream()
+    _check(_lib.labpsd_rayleigh_ritz(ctx.h, k, nwant, _ptr(HR), _ptr(SR), _ld(HR), _ptr(gamma), _ptr(W),
+                                     _ld(W), _ptr(info)), "labpsd_rayleigh_ritz")
+
+
+def labpsd_block_update(ctx: Context, n: int, k: int, b: int, Z, ZH, ZS, W, Psi, PsiH, PsiS):
+    ctx.sync_stream()
+    _check(_lib.labpsd_block_update(ctx.h, n, k, b, _ptr(Z), _ptr(ZH), _ptr(ZS), _ld(Z), _ptr(W), _ld(W),
+                                    _ptr(Psi), _ptr(PsiH), _ptr(PsiS), _ld(Psi)), "labpsd_block_update")

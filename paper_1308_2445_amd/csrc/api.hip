@@ -1,0 +1,815 @@
+// C ABI of liblabpsd and the LABPSD solve driver (Section 3 outline, hybrid scheme).
+//
+// The driver runs on the host and enqueues every step of an iteration as device
+// kernels on the context's stream.  Per outer iteration it reads back one small
+// vector (Res of the nev wanted pairs and the Ritz values) to take the host-side
+// decisions: convergence, the unconverged set U (remark 3: step 6 only for the
+// unconverged pairs) and the localisation test (remark 4).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "common.h"
+
+namespace labpsd {
+
+namespace {
+thread_local std::string g_err;
+
+double wall() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename F>
+labpsd_status guarded(F&& f) {
+    try {
+        g_err.clear();
+        // a launch error left behind by other code on this thread is not ours
+        (void)hipGetLastError();
+        return f();
+    } catch (const Error& e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return LABPSD_ENOMEM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return LABPSD_EINVAL;
+    }
+}
+
+// pinned host staging buffer
+template <typename T>
+struct Pinned {
+    T* p = nullptr;
+    size_t n = 0;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+    void alloc(size_t count) {
+        if (count <= n && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        LABPSD_HIP(hipHostMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
+        n = count;
+    }
+};
+
+// Event timing of the steps (stats.t_step_s)
+struct StepTimer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    int cur = -1;
+    hipEvent_t cur_start = nullptr;
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            LABPSD_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void begin(int step) {
+        if (!on) return;
+        cur = step;
+        cur_start = get();
+        LABPSD_HIP(hipEventRecord(cur_start, s));
+    }
+    void end() {
+        if (!on || cur < 0) return;
+        hipEvent_t e = get();
+        LABPSD_HIP(hipEventRecord(e, s));
+        marks.push_back({cur, {cur_start, e}});
+        cur = -1;
+    }
+    // fold recorded intervals into the stats (stream must be synchronised)
+    void collect(labpsd_stats* st) {
+        if (!on) return;
+        for (auto& m : marks) {
+            float ms = 0.f;
+            LABPSD_HIP(hipEventElapsedTime(&ms, m.second.first, m.second.second));
+            if (st) st->t_step_s[m.first] += ms * 1e-3;
+        }
+        marks.clear();
+        used = 0;
+    }
+    ~StepTimer() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+enum Step { S_PROD_PSI = 0, S_RESID, S_GLOBAL, S_LOCAL, S_PROD_P, S_GRAM, S_RR, S_UPDATE, S_CAST };
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+Problem::~Problem() { delete factor; }
+
+// ------------------------------------------------------------------ factor upload
+
+static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
+    hipStream_t s = P.ctx->stream;
+    auto F = std::make_unique<DevFactor>();
+    F->n = H.n;
+    F->nsn = (int)H.sn.size();
+    F->nlevels = H.nlevels;
+    F->eps_bar = eps_bar;
+    F->rows.upload(H.rows.data(), H.rows.size(), s);
+    F->panels64.upload(H.panels.data(), H.panels.size(), s);
+    {
+        std::vector<float> p32(H.panels.size());
+        for (size_t i = 0; i < p32.size(); ++i) p32[i] = (float)H.panels[i];
+        F->panels32.upload(p32.data(), p32.size(), s);
+        LABPSD_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int32_t> nc(F->nsn), nr(F->nsn);
+    std::vector<int64_t> ix(F->nsn), vl(F->nsn);
+    for (int i = 0; i < F->nsn; ++i) {
+        nc[i] = H.sn[i].ncol;
+        nr[i] = H.sn[i].nrow;
+        ix[i] = H.sn[i].idx_off;
+        vl[i] = H.sn[i].val_off;
+    }
+    F->sn_ncol.upload(nc.data(), nc.size(), s);
+    F->sn_nrow.upload(nr.data(), nr.size(), s);
+    F->sn_idx.upload(ix.data(), ix.size(), s);
+    F->sn_val.upload(vl.data(), vl.size(), s);
+    std::vector<int32_t> td, to;
+    F->lev_diag_off.assign(1, 0);
+    F->lev_off_off.assign(1, 0);
+    for (int l = 0; l < F->nlevels; ++l) {
+        for (int i = 0; i < F->nsn; ++i) {
+            if (H.sn[i].level != l) continue;
+            const int ncol = H.sn[i].ncol, nb = H.sn[i].nrow - H.sn[i].ncol;
+            for (int t = 0; t * 64 < ncol; ++t) { td.push_back(i); td.push_back(t); }
+            for (int t = 0; t * 64 < nb; ++t) { to.push_back(i); to.push_back(t); }
+        }
+        F->lev_diag_off.push_back((int64_t)td.size() / 2);
+        F->lev_off_off.push_back((int64_t)to.size() / 2);
+    }
+    F->task_diag.upload(td.data(), td.size(), s);
+    F->task_offd.upload(to.data(), to.size(), s);
+    LABPSD_HIP(hipStreamSynchronize(s));
+    F->info.n_supernodes = F->nsn;
+    F->info.n_levels = F->nlevels;
+    F->info.nnz_factor = H.nnz_factor;
+    F->info.flops_factor = H.flops;
+    F->info.t_order_s = H.t_order;
+    F->info.t_factor_s = H.t_factor;
+    delete P.factor;
+    P.factor = F.release();
+}
+
+// ------------------------------------------------------------------ workspace
+
+namespace {
+
+template <typename T>
+struct PrecWS {
+    T* Y;
+    T* W1;
+    T* W2;
+    T* RT;
+    T* mres;
+};
+
+struct SolveBuffers {
+    // FP64 blocks
+    double* Zb[2][3];
+    double* R;
+    double* HR;
+    double* SR;
+    double* W;
+    double* gamma;
+    double* res;
+    double* rnorm;
+    double* red;
+    double* gram_ws;
+    double* shifts;
+    double* stopn;
+    double* scal;
+    void* rr_ws;
+    int32_t* cols;
+    int32_t* loc;
+    int32_t* info;
+    int32_t* its;
+    int32_t* counter;
+};
+
+}  // namespace
+
+// Reserve the solve workspace inside the problem and carve it up.
+template <typename T>
+static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T>& W) {
+    const int kmax = b + m;
+    const int nblk = residual_blocks(n);
+    // the Gram partial layout depends on k; reserve the largest over every k <= kmax
+    size_t gws = 0;
+    for (int k = 1; k <= kmax; ++k) gws = std::max(gws, gram_ws_doubles(n, k, P.ctx->cu_count));
+    const size_t rrb = (rr_ws_bytes(kmax) + 7) / 8;
+    size_t need = 6 * (size_t)n * kmax + (size_t)n * m + 2 * (size_t)kmax * kmax +
+                  (size_t)kmax * b + (size_t)b + 2 * (size_t)m +
+                  std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m) + gws + 2 * (size_t)m +
+                  16 * (size_t)m + 4 + rrb + 64;
+    P.ws64.alloc(need);
+    double* p = P.ws64.p;
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c) { B.Zb[a][c] = p; p += (size_t)n * kmax; }
+    B.R = p; p += (size_t)n * m;
+    B.HR = p; p += (size_t)kmax * kmax;
+    B.SR = p; p += (size_t)kmax * kmax;
+    B.W = p; p += (size_t)kmax * b;
+    B.gamma = p; p += b;
+    B.res = p; p += m;
+    B.rnorm = p; p += m;
+    B.red = p; p += std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m);
+    B.gram_ws = p; p += gws;
+    B.shifts = p; p += m;
+    B.stopn = p; p += m;
+    B.scal = p; p += 16 * (size_t)m + 4;
+    B.rr_ws = (void*)p; p += rrb;
+    // T-precision blocks
+    const size_t mw = minres_ws_elems(n, m);
+    const size_t needT = 4 * (size_t)n * m + mw;
+    T* t;
+    if constexpr (sizeof(T) == 8) {
+        // FP64 mode: the preconditioner blocks live in a second FP64 arena
+        P.red.alloc(needT);
+        t = P.red.p;
+    } else {
+        P.ws32.alloc(needT);
+        t = P.ws32.p;
+    }
+    W.Y = t; t += (size_t)n * m;
+    W.W1 = t; t += (size_t)n * m;
+    W.W2 = t; t += (size_t)n * m;
+    W.RT = t; t += (size_t)n * m;
+    W.mres = t;
+    P.iws.alloc(4 * (size_t)m + 8);
+    B.cols = P.iws.p;
+    B.loc = B.cols + m;
+    B.its = B.loc + m;
+    B.info = B.its + m;
+    B.counter = B.info + 4;
+}
+
+// ------------------------------------------------------------------ solve
+
+template <typename T>
+static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, const double* X0,
+                                const double* E0, labpsd_mem in_where, double* lambda, double* X,
+                                double* res_hist, int* n_hist, labpsd_mem out_where,
+                                labpsd_stats* stats) {
+    const double t_start = wall();
+    hipStream_t s = P.ctx->stream;
+    const int64_t n = P.n;
+    const int m = prm.nev, b = prm.nev + prm.m0;
+    const int kmax = b + m;
+    const int64_t ldz = n;
+    SolveBuffers B;
+    PrecWS<T> Wt;
+    carve<T>(P, n, b, m, B, Wt);
+    const int nblk = residual_blocks(n);
+    labpsd_stats st{};
+    StepTimer tm;
+    tm.on = prm.timing != 0;
+    tm.s = s;
+
+    Pinned<double> h_res, h_gamma;
+    Pinned<int32_t> h_int, h_its;
+    h_its.alloc(m);
+    h_res.alloc(2 * (size_t)m);
+    h_gamma.alloc(b);
+    h_int.alloc(8);
+    int cur = 0;
+    auto Z = [&](int which) { return B.Zb[cur][which]; };
+
+    // steps 1-3: start block, its products and one Rayleigh-Ritz step on span(X0)
+    LABPSD_HIP(hipMemcpy2DAsync(Z(0), ldz * sizeof(double), X0, n * sizeof(double),
+                                n * sizeof(double), b,
+                                in_where == LABPSD_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                              : hipMemcpyHostToDevice,
+                                s));
+    tm.begin(S_PROD_PSI);
+    launch_spmm_hs(P.sell, Z(0), ldz, b, Z(1), Z(2), ldz, s);
+    tm.end();
+    st.n_launch[S_PROD_PSI] += 1;
+    st.n_cols[S_PROD_PSI] += b;
+    auto rayleigh_ritz_update = [&](int k) -> int {
+        tm.begin(S_GRAM);
+        launch_gram(n, k, Z(0), Z(1), Z(2), ldz, B.HR, B.SR, kmax, B.gram_ws, P.ctx->cu_count, s);
+        tm.end();
+        st.n_launch[S_GRAM] += 1;
+        st.n_cols[S_GRAM] += k;
+        tm.begin(S_RR);
+        launch_rayleigh_ritz(k, b, B.HR, B.SR, kmax, B.gamma, B.W, kmax, B.info, B.rr_ws, s);
+        tm.end();
+        st.n_launch[S_RR] += 1;
+        st.n_cols[S_RR] += k;
+        tm.begin(S_UPDATE);
+        const int nxt = 1 - cur;
+        launch_block_update(n, k, b, Z(0), Z(1), Z(2), ldz, B.W, kmax, B.Zb[nxt][0], B.Zb[nxt][1],
+                            B.Zb[nxt][2], ldz, s);
+        tm.end();
+        st.n_launch[S_UPDATE] += 1;
+        st.n_cols[S_UPDATE] += k;
+        cur = nxt;
+        LABPSD_HIP(hipMemcpyAsync(h_gamma.p, B.gamma, b * sizeof(double), hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipMemcpyAsync(h_int.p, B.info, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipStreamSynchronize(s));
+        st.rank_dropped += h_int.p[0];
+        return h_int.p[1];
+    };
+    if (rayleigh_ritz_update(b) != 0) throw Error{LABPSD_ERANK, "start block is rank deficient"};
+
+    std::vector<double> E(h_gamma.p, h_gamma.p + b);
+    std::vector<double> Eprev;
+    if (E0) Eprev.assign(E0, E0 + m);
+    bool fresh = false;
+    int since_refresh = 0;
+    bool converged = false;
+    int outer = 0, nh = 0;
+    std::vector<double> res(m), rn(m);
+    std::vector<int32_t> U, locpos;
+    std::vector<double> shifts, stopn;
+    const LocalParams& lp = P.local;
+
+    auto refresh = [&]() {
+        tm.begin(S_PROD_PSI);
+        launch_spmm_hs(P.sell, Z(0), ldz, b, Z(1), Z(2), ldz, s);
+        tm.end();
+        st.n_launch[S_PROD_PSI] += 1;
+        st.n_cols[S_PROD_PSI] += b;
+        fresh = true;
+        since_refresh = 0;
+        st.refreshes += 1;
+    };
+    auto residuals = [&]() {
+        tm.begin(S_RESID);
+        launch_residual(n, m, Z(1), Z(2), ldz, B.gamma, prm.sigma0, B.R, n, B.red, nblk, s);
+        launch_residual_finish(m, B.red, nblk, B.res, B.rnorm, s);
+        tm.end();
+        st.n_launch[S_RESID] += 1;
+        st.n_cols[S_RESID] += m;
+        LABPSD_HIP(hipMemcpyAsync(h_res.p, B.res, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipMemcpyAsync(h_res.p + m, B.rnorm, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < m; ++i) { res[i] = h_res.p[i]; rn[i] = h_res.p[m + i]; }
+    };
+    auto maxres = [&]() {
+        double mx = 0.0;
+        for (double r : res) mx = std::max(mx, std::isnan(r) ? INFINITY : r);
+        return mx;
+    };
+    std::vector<double> hist;
+    for (int it = 1; it <= prm.max_outer; ++it) {
+        if (since_refresh >= prm.refresh_every) refresh();
+        residuals();   // step 4 and eq. (res1)
+        if (maxres() <= prm.tol) {   // step 5, on the true residual
+            if (!fresh) {
+                refresh();
+                residuals();
+            }
+            if (maxres() <= prm.tol) {
+                converged = true;
+                hist.insert(hist.end(), res.begin(), res.end());
+                ++nh;
+                break;
+            }
+        }
+        hist.insert(hist.end(), res.begin(), res.end());
+        ++nh;
+        outer = it;
+        // step 6: directions for the unconverged pairs
+        U.clear();
+        for (int i = 0; i < m; ++i)
+            if (!(res[i] <= prm.tol)) U.push_back(i);
+        const int p = (int)U.size();
+        locpos.clear();
+        shifts.clear();
+        stopn.clear();
+        if ((lp.mode == LABPSD_HYBRID || lp.mode == LABPSD_LOCAL_ONLY) && !Eprev.empty()) {
+            for (int c = 0; c < p; ++c) {
+                const int i = U[c];
+                if (res[i] <= lp.tau1 && std::fabs(E[i] - Eprev[i]) <= lp.tau2 * std::fabs(Eprev[i])) {
+                    locpos.push_back(c);
+                    shifts.push_back(E[i]);
+                    stopn.push_back(rn[i]);
+                }
+            }
+        }
+        const int q = (int)locpos.size();
+        LABPSD_HIP(hipMemcpyAsync(B.cols, U.data(), p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (q) {
+            LABPSD_HIP(hipMemcpyAsync(B.loc, locpos.data(), q * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            LABPSD_HIP(hipMemcpyAsync(B.shifts, shifts.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+            LABPSD_HIP(hipMemcpyAsync(B.stopn, stopn.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        // 6(a): P = -K^{-1} R_U in the preconditioner precision
+        tm.begin(S_CAST);
+        launch_gather_cast<double, T>(n, p, B.R, n, B.cols, -1.0, Wt.Y, n, s);
+        if (q) launch_gather_cast<double, T>(n, p, B.R, n, B.cols, 1.0, Wt.RT, n, s);
+        tm.end();
+        st.n_launch[S_CAST] += q ? 2 : 1;
+        st.n_cols[S_CAST] += q ? 2 * p : p;
+        tm.begin(S_GLOBAL);
+        launch_precond_solve<T>(*P.factor, Wt.Y, Wt.W1, Wt.W2, n, p, s);
+        tm.end();
+        st.n_launch[S_GLOBAL] += 1;
+        st.n_cols[S_GLOBAL] += p;
+        // 6(b): MINRES refinement of the localised columns
+        if (q) {
+            if (lp.mode == LABPSD_LOCAL_ONLY)
+                launch_scatter_cast<T, T>(n, q, Wt.W2, n, B.loc, 0.0, Wt.W2, n, s);
+            tm.begin(S_LOCAL);
+            int64_t nl = 0;
+            run_minres<T>(P.sell, Wt.W2, n, Wt.RT, n, q, B.loc, B.shifts, B.stopn, lp.eta,
+                          lp.max_inner, B.its, Wt.mres, B.scal, h_int.p + 4, s, &nl);
+            tm.end();
+            st.n_launch[S_LOCAL] += nl;
+            st.n_cols[S_LOCAL] += q;
+            LABPSD_HIP(hipMemcpyAsync(h_its.p, B.its, q * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            LABPSD_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j < q; ++j) st.minres_iters += h_its.p[j];
+            st.localized_cols += q;
+        }
+        // P into the search-space block, FP64
+        tm.begin(S_CAST);
+        launch_gather_cast<T, double>(n, p, Wt.W2, n, nullptr, 1.0, Z(0) + (size_t)b * ldz, ldz, s);
+        tm.end();
+        st.n_launch[S_CAST] += 1;
+        st.n_cols[S_CAST] += p;
+        // step 7: P_H, P_S
+        tm.begin(S_PROD_P);
+        launch_spmm_hs(P.sell, Z(0) + (size_t)b * ldz, ldz, p, Z(1) + (size_t)b * ldz,
+                       Z(2) + (size_t)b * ldz, ldz, s);
+        tm.end();
+        st.n_launch[S_PROD_P] += 1;
+        st.n_cols[S_PROD_P] += p;
+        // steps 8-11
+        Eprev.assign(E.begin(), E.begin() + m);
+        const int rc = rayleigh_ritz_update(b + p);
+        if (rc != 0) throw Error{LABPSD_ERANK, "search space [Psi P] lost rank below the block width"};
+        E.assign(h_gamma.p, h_gamma.p + b);
+        fresh = false;
+        ++since_refresh;
+    }
+    LABPSD_HIP(hipStreamSynchronize(s));
+    tm.collect(&st);
+    // outputs
+    const hipMemcpyKind kd = out_where == LABPSD_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                            : hipMemcpyDeviceToHost;
+    LABPSD_HIP(hipMemcpyAsync(lambda, B.gamma, m * sizeof(double), kd, s));
+    LABPSD_HIP(hipMemcpy2DAsync(X, n * sizeof(double), Z(0), ldz * sizeof(double), n * sizeof(double),
+                                m, kd, s));
+    if (res_hist && nh > 0) {
+        if (out_where == LABPSD_MEM_DEVICE)
+            LABPSD_HIP(hipMemcpyAsync(res_hist, hist.data(), hist.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, s));
+        else
+            std::memcpy(res_hist, hist.data(), hist.size() * sizeof(double));
+    }
+    LABPSD_HIP(hipStreamSynchronize(s));
+    if (n_hist) *n_hist = nh;
+    st.outer_iters = outer;
+    st.hp = outer;
+    st.la = outer > 0 ? (double)st.minres_iters / ((double)outer * m) : 0.0;
+    st.t_solve_s = wall() - t_start;
+    if (stats) *stats = st;
+    return converged ? LABPSD_OK : LABPSD_NOT_CONVERGED;
+}
+
+}  // namespace labpsd
+
+using namespace labpsd;
+
+// ------------------------------------------------------------------ C ABI
+
+struct labpsd_problem : labpsd::Problem {};
+
+namespace labpsd {
+template <typename T>
+static void local_refine_impl(Problem* p, DBuf<T>& arena, const double* R, int64_t ldr,
+                              double* Pm, int64_t ldp, int q, const int32_t* cols,
+                              const double* shift, double eta, int max_inner, int32_t* its) {
+    hipStream_t s = p->ctx->stream;
+    const int64_t n = p->n;
+    const size_t mw = minres_ws_elems(n, q);
+    arena.alloc(2 * (size_t)n * q + mw);
+    T* PT = arena.p;
+    T* RT = PT + (size_t)n * q;
+    T* mws = RT + (size_t)n * q;
+    const int nblk = residual_blocks(n);
+    p->ctx->scratch.alloc((size_t)nblk * q + 16 * (size_t)q + 8 + q);
+    double* part = p->ctx->scratch.p;
+    double* scal = part + (size_t)nblk * q;
+    double* rn = scal + 16 * (size_t)q + 4;
+    p->iws.alloc((size_t)q + 8);
+    int32_t* iota = p->iws.p;
+    std::vector<int32_t> h(q);
+    for (int j = 0; j < q; ++j) h[j] = j;
+    LABPSD_HIP(hipMemcpyAsync(iota, h.data(), q * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    launch_gather_cast<double, T>(n, q, Pm, ldp, cols, 1.0, PT, n, s);
+    launch_gather_cast<double, T>(n, q, R, ldr, cols, 1.0, RT, n, s);
+    launch_colnorms<double>(n, q, R, ldr, cols, part, rn, s);
+    Pinned<int32_t> flag;
+    flag.alloc(1);
+    run_minres<T>(p->sell, PT, n, RT, n, q, iota, shift, rn, eta, max_inner, its, mws, scal, flag.p, s,
+                  nullptr);
+    launch_scatter_cast<T, double>(n, q, PT, n, cols, 1.0, Pm, ldp, s);
+    LABPSD_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace labpsd
+
+extern "C" {
+
+const char* labpsd_last_error(void) { return labpsd::get_error(); }
+const char* labpsd_version(void) { return "liblabpsd 0.1 (gfx950)"; }
+
+labpsd_status labpsd_ctx_create(int device, void* stream, labpsd_ctx** out) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        int count = 0;
+        LABPSD_HIP(hipGetDeviceCount(&count));
+        LABPSD_REQUIRE(device >= 0 && device < count, "device index out of range");
+        LABPSD_HIP(hipSetDevice(device));
+        auto c = std::make_unique<labpsd_ctx>();
+        c->device = device;
+        c->stream = (hipStream_t)stream;
+        hipDeviceProp_t prop;
+        LABPSD_HIP(hipGetDeviceProperties(&prop, device));
+        c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        *out = c.release();
+        return LABPSD_OK;
+    });
+}
+
+void labpsd_ctx_destroy(labpsd_ctx* ctx) { delete ctx; }
+
+labpsd_status labpsd_ctx_set_stream(labpsd_ctx* ctx, void* stream) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(ctx != nullptr, "ctx is NULL");
+        ctx->stream = (hipStream_t)stream;
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
+                                    const int32_t* col, const double* h_val, const double* s_val,
+                                    labpsd_problem** out) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(ctx && out && rowptr && col && h_val && s_val, "NULL argument");
+        *out = nullptr;
+        LABPSD_REQUIRE(n >= 1 && n < (int64_t)INT32_MAX, "n out of range");
+        LABPSD_REQUIRE(nnz >= n, "nnz smaller than n");
+        LABPSD_REQUIRE(rowptr[0] == 0 && rowptr[n] == nnz, "rowptr does not span [0, nnz]");
+        for (int64_t i = 0; i < n; ++i) {
+            LABPSD_REQUIRE(rowptr[i + 1] > rowptr[i], "empty row " + std::to_string(i));
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                LABPSD_REQUIRE(col[e] >= 0 && col[e] < n, "column index out of range in row " + std::to_string(i));
+                if (e > rowptr[i])
+                    LABPSD_REQUIRE(col[e] > col[e - 1], "columns not strictly increasing in row " + std::to_string(i));
+            }
+        }
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                const int32_t j = col[e];
+                const int32_t* b0 = col + rowptr[j];
+                const int32_t* b1 = col + rowptr[j + 1];
+                LABPSD_REQUIRE(std::binary_search(b0, b1, (int32_t)i),
+                               "pattern not structurally symmetric at (" + std::to_string(i) + "," +
+                                   std::to_string(j) + ")");
+            }
+        LABPSD_HIP(hipSetDevice(ctx->device));
+        auto p = std::make_unique<labpsd_problem>();
+        p->ctx = ctx;
+        p->n = n;
+        p->nnz = nnz;
+        p->csr.n = n;
+        p->csr.nnz = nnz;
+        p->csr.rowptr.assign(rowptr, rowptr + n + 1);
+        p->csr.col.assign(col, col + nnz);
+        p->h_val.assign(h_val, h_val + nnz);
+        p->s_val.assign(s_val, s_val + nnz);
+        build_sell(p->sell, p->csr, h_val, s_val, ctx->stream);
+        *out = p.release();
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_problem_update_h(labpsd_problem* p, const double* h_val) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && h_val, "NULL argument");
+        p->h_val.assign(h_val, h_val + p->nnz);
+        refresh_sell_h(p->sell, h_val, p->ctx->stream);
+        return LABPSD_OK;
+    });
+}
+
+void labpsd_problem_destroy(labpsd_problem* p) { delete p; }
+
+int64_t labpsd_problem_n(const labpsd_problem* p) { return p ? p->n : -1; }
+
+labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const double* coords) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p != nullptr, "problem is NULL");
+        LABPSD_REQUIRE(std::isfinite(eps_bar), "eps_bar must be finite");
+        std::vector<double> kval(p->nnz);
+        for (int64_t e = 0; e < p->nnz; ++e) kval[e] = p->h_val[e] - eps_bar * p->s_val[e];
+        HostFactor F;
+        std::string msg;
+        const int rc = factorize(p->csr, kval.data(), coords, F, msg);
+        if (rc == -4) throw Error{LABPSD_ENOTSPD, msg};
+        if (rc != 0) throw Error{LABPSD_EINVAL, msg};
+        const double t0 = wall();
+        upload_factor(*p, F, eps_bar);
+        p->factor->info.t_upload_s = wall() - t0;
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_set_local_precond(labpsd_problem* p, double tau1, double tau2, double eta,
+                                       int max_inner, labpsd_precond_mode mode) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p != nullptr, "problem is NULL");
+        LABPSD_REQUIRE(tau1 >= 0 && tau2 >= 0 && eta > 0 && max_inner >= 0, "invalid local parameters");
+        LABPSD_REQUIRE(mode == LABPSD_HYBRID || mode == LABPSD_GLOBAL_ONLY || mode == LABPSD_LOCAL_ONLY,
+                       "invalid mode");
+        p->local.tau1 = tau1;
+        p->local.tau2 = tau2;
+        p->local.eta = eta;
+        p->local.max_inner = max_inner;
+        p->local.mode = mode;
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_get_factor_info(const labpsd_problem* p, labpsd_factor_info* info) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && info, "NULL argument");
+        if (!p->factor) throw Error{LABPSD_ESTATE, "no global preconditioner set"};
+        *info = p->factor->info;
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* prm, const double* X0,
+                           const double* E0, labpsd_mem in_where, double* lambda, double* X,
+                           double* res_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && prm && X0 && lambda && X, "NULL argument");
+        if (!p->factor) throw Error{LABPSD_ESTATE, "labpsd_set_global_precond must come first"};
+        LABPSD_REQUIRE(prm->nev >= 1 && prm->m0 >= 0, "nev must be >= 1 and m0 >= 0");
+        LABPSD_REQUIRE((int64_t)(2 * prm->nev + prm->m0) <= p->n, "n < 2 nev + m0");
+        LABPSD_REQUIRE(prm->nev + prm->m0 + prm->nev <= kRRMax, "block too wide");
+        LABPSD_REQUIRE(prm->tol > 0 && prm->max_outer >= 1 && prm->refresh_every >= 1,
+                       "tol, max_outer and refresh_every must be positive");
+        LABPSD_REQUIRE(prm->precision == LABPSD_FP64 || prm->precision == LABPSD_MIXED,
+                       "invalid precision");
+        LABPSD_HIP(hipSetDevice(p->ctx->device));
+        if (prm->precision == LABPSD_MIXED)
+            return solve_impl<float>(*p, *prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where,
+                                     stats);
+        return solve_impl<double>(*p, *prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where,
+                                  stats);
+    });
+}
+
+// ------------------------------------------------------------------ steps
+
+labpsd_status labpsd_spmm(labpsd_problem* p, const double* X, int64_t ldx, int w, double* YH,
+                          double* YS, int64_t ldy) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && X && YH && YS, "NULL argument");
+        LABPSD_REQUIRE(w >= 0 && ldx >= p->n && ldy >= p->n, "bad width or leading dimension");
+        launch_spmm_hs(p->sell, X, ldx, w, YH, YS, ldy, p->ctx->stream);
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_spmm_shifted(labpsd_problem* p, int precision, const void* X, int64_t ldx,
+                                  int w, const double* shift, void* Y, int64_t ldy) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && X && Y && shift, "NULL argument");
+        LABPSD_REQUIRE(w >= 0 && ldx >= p->n && ldy >= p->n, "bad width or leading dimension");
+        if (precision == LABPSD_MIXED)
+            launch_spmm_shift<float>(p->sell, (const float*)X, ldx, w, shift, (float*)Y, ldy, p->ctx->stream);
+        else if (precision == LABPSD_FP64)
+            launch_spmm_shift<double>(p->sell, (const double*)X, ldx, w, shift, (double*)Y, ldy,
+                                      p->ctx->stream);
+        else
+            throw Error{LABPSD_EINVAL, "invalid precision"};
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_residual(labpsd_ctx* ctx, int64_t n, int m, const double* PsiH,
+                              const double* PsiS, int64_t ld, const double* E, double sigma0,
+                              double* R, int64_t ldr, double* res, double* rnorm) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(ctx && PsiH && PsiS && E && R && res && rnorm, "NULL argument");
+        LABPSD_REQUIRE(n >= 1 && m >= 0 && ld >= n && ldr >= n, "bad sizes");
+        const int nblk = residual_blocks(n);
+        ctx->scratch.alloc((size_t)nblk * m * 2 + 1);
+        launch_residual(n, m, PsiH, PsiS, ld, E, sigma0, R, ldr, ctx->scratch.p, nblk, ctx->stream);
+        launch_residual_finish(m, ctx->scratch.p, nblk, res, rnorm, ctx->stream);
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_precond_apply(labpsd_problem* p, int precision, const double* R, int64_t ldr,
+                                   int ncols, double* Pout, int64_t ldp) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && R && Pout, "NULL argument");
+        if (!p->factor) throw Error{LABPSD_ESTATE, "no global preconditioner set"};
+        LABPSD_REQUIRE(ncols >= 0 && ldr >= p->n && ldp >= p->n, "bad sizes");
+        if (ncols == 0) return LABPSD_OK;
+        hipStream_t s = p->ctx->stream;
+        const int64_t n = p->n;
+        if (precision == LABPSD_MIXED) {
+            p->ws32.alloc(3 * (size_t)n * ncols);
+            float* Y = p->ws32.p;
+            launch_gather_cast<double, float>(n, ncols, R, ldr, nullptr, -1.0, Y, n, s);
+            launch_precond_solve<float>(*p->factor, Y, Y + n * ncols, Y + 2 * n * ncols, n, ncols, s);
+            launch_gather_cast<float, double>(n, ncols, Y + 2 * n * ncols, n, nullptr, 1.0, Pout, ldp, s);
+        } else if (precision == LABPSD_FP64) {
+            p->red.alloc(3 * (size_t)n * ncols);
+            double* Y = p->red.p;
+            launch_gather_cast<double, double>(n, ncols, R, ldr, nullptr, -1.0, Y, n, s);
+            launch_precond_solve<double>(*p->factor, Y, Y + n * ncols, Y + 2 * n * ncols, n, ncols, s);
+            launch_gather_cast<double, double>(n, ncols, Y + 2 * n * ncols, n, nullptr, 1.0, Pout, ldp, s);
+        } else {
+            throw Error{LABPSD_EINVAL, "invalid precision"};
+        }
+        // the workspace is reused by the next call: finish before returning it
+        LABPSD_HIP(hipStreamSynchronize(s));
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_local_refine(labpsd_problem* p, int precision, const double* R, int64_t ldr,
+                                  double* Pm, int64_t ldp, int q, const int32_t* cols,
+                                  const double* shift, double eta, int max_inner, int32_t* its) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && R && Pm && cols && shift && its, "NULL argument");
+        LABPSD_REQUIRE(q >= 0 && ldr >= p->n && ldp >= p->n && eta > 0 && max_inner >= 0, "bad arguments");
+        if (q == 0) return LABPSD_OK;
+        if (precision == LABPSD_MIXED)
+            local_refine_impl<float>(p, p->ws32, R, ldr, Pm, ldp, q, cols, shift, eta, max_inner, its);
+        else if (precision == LABPSD_FP64)
+            local_refine_impl<double>(p, p->red, R, ldr, Pm, ldp, q, cols, shift, eta, max_inner, its);
+        else
+            throw Error{LABPSD_EINVAL, "invalid precision"};
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_gram(labpsd_ctx* ctx, int64_t n, int k, const double* Z, const double* ZH,
+                          const double* ZS, int64_t ldz, double* HR, double* SR, int64_t ldr) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(ctx && Z && ZH && ZS && HR && SR, "NULL argument");
+        LABPSD_REQUIRE(n >= 1 && k >= 0 && ldz >= n && ldr >= k, "bad sizes");
+        ctx->scratch.alloc(gram_ws_doubles(n, k, ctx->cu_count) + 1);
+        launch_gram(n, k, Z, ZH, ZS, ldz, HR, SR, ldr, ctx->scratch.p, ctx->cu_count, ctx->stream);
+        LABPSD_HIP(hipStreamSynchronize(ctx->stream));
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_rayleigh_ritz(labpsd_ctx* ctx, int k, int nwant, const double* HR,
+                                   const double* SR, int64_t ldr, double* gamma, double* W,
+                                   int64_t ldw, int32_t* info) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(ctx && HR && SR && gamma && W && info, "NULL argument");
+        LABPSD_REQUIRE(k >= 1 && nwant >= 1 && nwant <= k && ldr >= k && ldw >= k, "bad sizes");
+        ctx->rr_ws.alloc(rr_ws_bytes(k));
+        launch_rayleigh_ritz(k, nwant, HR, SR, ldr, gamma, W, ldw, info, ctx->rr_ws.p, ctx->stream);
+        LABPSD_HIP(hipStreamSynchronize(ctx->stream));
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_block_update(labpsd_ctx* ctx, int64_t n, int k, int b, const double* Z,
+                                  const double* ZH, const double* ZS, int64_t ldz, const double* W,
+                                  int64_t ldw, double* Psi, double* PsiH, double* PsiS, int64_t ldo) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(ctx && Z && ZH && ZS && W && Psi && PsiH && PsiS, "NULL argument");
+        LABPSD_REQUIRE(n >= 1 && k >= 1 && b >= 1 && ldz >= n && ldw >= k && ldo >= n, "bad sizes");
+        launch_block_update(n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi, PsiH, PsiS, ldo, ctx->stream);
+        return LABPSD_OK;
+    });
+}
+
+}  // extern "C"

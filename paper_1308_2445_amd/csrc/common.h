@@ -1,0 +1,221 @@
+// Internal declarations shared by the HIP translation units of liblabpsd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/labpsd.h"
+#include "factor.h"
+
+namespace labpsd {
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const std::string& msg);
+const char* get_error();
+
+struct Error {
+    labpsd_status code;
+    std::string msg;
+};
+
+#define LABPSD_HIP(call)                                                                      \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            throw ::labpsd::Error{LABPSD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define LABPSD_REQUIRE(cond, msg)                                                             \
+    do {                                                                                      \
+        if (!(cond)) throw ::labpsd::Error{LABPSD_EINVAL, (msg)};                             \
+    } while (0)
+
+// ------------------------------------------------------------------ device memory
+
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count) {
+        if (count <= n && p) return;
+        release();
+        if (count == 0) return;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error{LABPSD_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
+                                           " bytes failed: " + hipGetErrorString(e)};
+        }
+        n = count;
+    }
+    void upload(const T* h, size_t count, hipStream_t s) {
+        alloc(count);
+        if (count) LABPSD_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+};
+
+// ------------------------------------------------------------------ sliced ELL
+
+// Rows in slices of 64 (one wavefront, one row per lane); each slice is padded to
+// its longest row and stored slot-major (64 consecutive entries per slot), so the
+// loads of col/values across a wavefront are contiguous.
+constexpr int kSlice = 64;
+
+struct Sell {
+    int64_t n = 0;
+    int64_t nslices = 0;
+    int64_t stored = 0;          // padded entries
+    DBuf<int64_t> slice_off;     // nslices + 1 offsets (entries)
+    DBuf<int32_t> col;
+    DBuf<double> hv, sv;         // FP64 values
+    DBuf<float> hv32, sv32;      // FP32 copies for the mixed-precision preconditioner
+    std::vector<int64_t> h_slice_off;   // host copies of the layout (for update_h)
+    std::vector<int64_t> h_map;         // stored entry -> CSR entry (-1 for padding)
+};
+
+// ------------------------------------------------------------------ device factor
+
+struct DevFactor {
+    int64_t n = 0;
+    int nsn = 0;
+    int nlevels = 0;
+    double eps_bar = 0.0;
+    DBuf<int32_t> rows;          // row lists (dof ids)
+    DBuf<double> panels64;
+    DBuf<float> panels32;
+    // per-supernode metadata: ncol, nrow, idx_off, val_off
+    DBuf<int32_t> sn_ncol, sn_nrow;
+    DBuf<int64_t> sn_idx, sn_val;
+    // per level task lists of (supernode, 64-row tile) pairs: tiles of D serve the
+    // diagonal-block products and the backward gather, tiles of B the forward update
+    std::vector<int64_t> lev_diag_off, lev_off_off;   // offsets into the task arrays
+    DBuf<int32_t> task_diag;     // pairs (sn, tile) over D rows
+    DBuf<int32_t> task_offd;     // pairs (sn, tile) over B rows
+    labpsd_factor_info info{};
+};
+
+// ------------------------------------------------------------------ context / problem
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 256;
+    DBuf<double> scratch;        // small reductions
+    DBuf<char> rr_ws;            // Rayleigh-Ritz workspace
+};
+
+struct LocalParams {
+    double tau1 = 0.1, tau2 = 0.1, eta = 0.25;
+    int max_inner = 20;
+    int mode = LABPSD_HYBRID;
+};
+
+struct Problem;
+
+}  // namespace labpsd
+
+struct labpsd_ctx : labpsd::Ctx {};
+
+namespace labpsd {
+
+struct Problem {
+    labpsd_ctx* ctx = nullptr;
+    int64_t n = 0, nnz = 0;
+    HostCSR csr;
+    std::vector<double> h_val, s_val;
+    Sell sell;
+    DevFactor* factor = nullptr;
+    LocalParams local;
+    // solver workspace (kept between solves)
+    DBuf<double> ws64;
+    DBuf<float> ws32;
+    DBuf<double> red;            // reduction partials
+    DBuf<int32_t> iws;
+    ~Problem();
+};
+
+// ------------------------------------------------------------------ kernel launchers
+// All launchers enqueue on `s` and check the launch.
+
+void build_sell(Sell& S, const HostCSR& A, const double* hv, const double* sv, hipStream_t s);
+void refresh_sell_h(Sell& S, const double* hv, hipStream_t s);
+
+// YH = H X, YS = S X (FP64)
+void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
+                    int64_t ldy, hipStream_t s);
+// Y = (H - shift_j S) X (T = double or float; shift in double)
+template <typename T>
+void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
+                       int64_t ldy, hipStream_t s);
+
+// residual and per-column norms (partials reduced by launch_residual_finish)
+void launch_residual(int64_t n, int m, const double* PsiH, const double* PsiS, int64_t ld,
+                     const double* E, double sigma0, double* R, int64_t ldr, double* partial,
+                     int nblk, hipStream_t s);
+void launch_residual_finish(int m, const double* partial, int nblk, double* res, double* rnorm,
+                            hipStream_t s);
+int residual_blocks(int64_t n);
+
+// Gram: HR = Z^T ZH, SR = Z^T ZS (symmetric parts); partial workspace sized by gram_ws
+size_t gram_ws_doubles(int64_t n, int k, int cu_count);
+void launch_gram(int64_t n, int k, const double* Z, const double* ZH, const double* ZS, int64_t ldz,
+                 double* HR, double* SR, int64_t ldr, double* ws, int cu_count, hipStream_t s);
+
+// Block update: out_i = in_i W for i = 0..2
+void launch_block_update(int64_t n, int k, int b, const double* Z, const double* ZH,
+                         const double* ZS, int64_t ldz, const double* W, int64_t ldw, double* Psi,
+                         double* PsiH, double* PsiS, int64_t ldo, hipStream_t s);
+
+// Rayleigh-Ritz (single work-group, k <= kRRMax)
+constexpr int kRRMax = 4096;
+size_t rr_ws_bytes(int k);
+void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, int64_t ldr,
+                          double* gamma, double* W, int64_t ldw, int32_t* info, void* ws,
+                          hipStream_t s);
+
+// Gathers / casts
+// dst[:, j] = (T) src[:, cols[j]] * scale  (cols may be null: identity)
+template <typename TS, typename TD>
+void launch_gather_cast(int64_t n, int ncols, const TS* src, int64_t lds, const int32_t* cols,
+                        double scale, TD* dst, int64_t ldd, hipStream_t s);
+
+// dst[:, cols[j]] = (TD) src[:, j] * scale
+template <typename TS, typename TD>
+void launch_scatter_cast(int64_t n, int ncols, const TS* src, int64_t lds, const int32_t* cols,
+                         double scale, TD* dst, int64_t ldd, hipStream_t s);
+// out[j] = ||src[:, cols[j]]|| (cols may be null); partial holds residual_blocks(n) * q doubles
+template <typename T>
+void launch_colnorms(int64_t n, int q, const T* src, int64_t ld, const int32_t* cols,
+                     double* partial, double* out, hipStream_t s);
+
+// Global preconditioner: W2 := K^{-1} Y for n x ncols blocks (ld ld) of precision T;
+// Y is consumed, W1 is scratch
+template <typename T>
+void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t ld, int ncols,
+                          hipStream_t s);
+
+// MINRES batched refinement (T = double or float). P (n x *, ld ldp) in precision T is
+// refined in place on the columns cols[0..q), with the residual columns R[:, cols[j]] in
+// precision T, shifts shift[j] and stopping norms eta * rnorm[j].  ws holds
+// minres_ws_elems(n, q) elements of T, scal_ws 16 * q + 2 doubles.
+size_t minres_ws_elems(int64_t n, int q);
+template <typename T>
+void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q,
+                const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
+                double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
+                int32_t* flag_host_pinned, hipStream_t s, int64_t* launches);
+
+}  // namespace labpsd

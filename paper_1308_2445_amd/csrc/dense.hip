@@ -1,0 +1,384 @@
+// Tall-skinny dense steps of one LABPSD iteration:
+//   residual block and Res (outline step 4, eq. (res1)),
+//   Gram matrices H_R = Z^T (HZ), S_R = Z^T (SZ) (step 8) on FP64 matrix cores,
+//   block update [Psi P] W for Psi, Psi_H, Psi_S (steps 10-11) on FP64 matrix cores,
+//   and the gathers / precision casts between the FP64 blocks and the preconditioner.
+#include "common.h"
+
+namespace labpsd {
+
+namespace {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ residual
+
+constexpr int kResRows = 4096;   // rows per residual work-group
+
+// grid (nblk, m): column j of R = PsiH_j - E_j PsiS_j; partial sums of ||r||^2 and
+// ||PsiH_j - sigma0 PsiS_j||^2 per work-group
+__global__ __launch_bounds__(256) void k_residual(int64_t n, const double* __restrict__ PsiH,
+                                                  const double* __restrict__ PsiS, int64_t ld,
+                                                  const double* __restrict__ E, double sigma0,
+                                                  double* __restrict__ R, int64_t ldr,
+                                                  double* __restrict__ partial) {
+    const int j = blockIdx.y;
+    const double e = E[j];
+    const double* h = PsiH + (int64_t)j * ld;
+    const double* s = PsiS + (int64_t)j * ld;
+    double* r = R + (int64_t)j * ldr;
+    const int64_t r0 = (int64_t)blockIdx.x * kResRows;
+    const int64_t r1 = min(n, r0 + kResRows);
+    double num = 0.0, den = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
+        const double hi = h[i], si = s[i];
+        const double ri = hi - e * si;
+        r[i] = ri;
+        num = fma(ri, ri, num);
+        const double di = hi - sigma0 * si;
+        den = fma(di, di, den);
+    }
+    __shared__ double sh[2][4];
+    num = wave_sum(num);
+    den = wave_sum(den);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sh[0][wv] = num; sh[1][wv] = den; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < 4; ++k) { a += sh[0][k]; b += sh[1][k]; }
+        partial[((int64_t)j * gridDim.x + blockIdx.x) * 2 + 0] = a;
+        partial[((int64_t)j * gridDim.x + blockIdx.x) * 2 + 1] = b;
+    }
+}
+
+__global__ void k_residual_finish(int m, const double* __restrict__ partial, int nblk,
+                                  double* __restrict__ res, double* __restrict__ rnorm) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+        a += partial[((int64_t)j * nblk + k) * 2 + 0];
+        b += partial[((int64_t)j * nblk + k) * 2 + 1];
+    }
+    rnorm[j] = sqrt(a);
+    res[j] = b > 0.0 ? sqrt(a / b) : (a > 0.0 ? INFINITY : 0.0);
+}
+
+// ------------------------------------------------------------------ gather / cast
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_gather_cast(int64_t n, const TS* __restrict__ src,
+                                                     int64_t lds, const int32_t* __restrict__ cols,
+                                                     double scale, TD* __restrict__ dst,
+                                                     int64_t ldd) {
+    const int j = blockIdx.y;
+    const int64_t sc = cols ? cols[j] : j;
+    const TS* a = src + sc * lds;
+    TD* b = dst + (int64_t)j * ldd;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        b[i] = (TD)((double)a[i] * scale);
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_scatter_cast(int64_t n, const TS* __restrict__ src,
+                                                      int64_t lds, const int32_t* __restrict__ cols,
+                                                      double scale, TD* __restrict__ dst,
+                                                      int64_t ldd) {
+    const int j = blockIdx.y;
+    const TS* a = src + (int64_t)j * lds;
+    TD* b = dst + (int64_t)cols[j] * ldd;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        b[i] = (TD)((double)a[i] * scale);
+}
+
+// partial sums of squares of the columns cols[j] (or j) per block of rows
+template <typename T>
+__global__ __launch_bounds__(256) void k_colnorm_partial(int64_t n, const T* __restrict__ src,
+                                                         int64_t ld, const int32_t* __restrict__ cols,
+                                                         double* __restrict__ partial) {
+    const int j = blockIdx.y;
+    const T* a = src + (int64_t)(cols ? cols[j] : j) * ld;
+    const int64_t r0 = (int64_t)blockIdx.x * kResRows, r1 = min(n, r0 + kResRows);
+    double acc = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
+        const double v = (double)a[i];
+        acc = fma(v, v, acc);
+    }
+    __shared__ double sh[4];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void k_colnorm_finish(int q, const double* __restrict__ partial, int nblk,
+                                 double* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    double a = 0.0;
+    for (int k = 0; k < nblk; ++k) a += partial[(int64_t)j * nblk + k];
+    out[j] = sqrt(a);
+}
+
+// ------------------------------------------------------------------ Gram on MFMA
+
+// Output tile 32 x 32 per work-group: four wavefronts, each one 16 x 16 tile of both
+// H_R and S_R.  Rows of Z are staged in LDS 64 at a time, transposed so that each
+// lane's MFMA operand (row k, column i) is a conflict-free LDS read.
+constexpr int GT = 32;
+constexpr int GR = 64;
+
+__global__ __launch_bounds__(256) void k_gram(int64_t n, int k, const double* __restrict__ Z,
+                                              const double* __restrict__ ZH,
+                                              const double* __restrict__ ZS, int64_t ld, int nb,
+                                              int64_t rows_per_chunk, double* __restrict__ part,
+                                              int kp) {
+    int p = blockIdx.x, bi = 0;
+    while (p >= nb - bi) { p -= nb - bi; ++bi; }
+    const int bj = bi + p;
+    const int i0 = bi * GT, j0 = bj * GT;
+    __shared__ double sZ[GT][GR + 1];
+    __shared__ double sH[GT][GR + 1];
+    __shared__ double sS[GT][GR + 1];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const int ti = wave >> 1, tj = wave & 1;
+    double4_t accH = {0.0, 0.0, 0.0, 0.0};
+    double4_t accS = {0.0, 0.0, 0.0, 0.0};
+    const int64_t rb = (int64_t)blockIdx.y * rows_per_chunk;
+    const int64_t re = min(n, rb + rows_per_chunk);
+    for (int64_t r0 = rb; r0 < re; r0 += GR) {
+#pragma unroll
+        for (int q = 0; q < (GT * GR) / 256; ++q) {
+            const int e = t + 256 * q;
+            const int rr = e & (GR - 1), cc = e / GR;
+            const int64_t row = r0 + rr;
+            const bool okr = row < re;
+            sZ[cc][rr] = (okr && i0 + cc < k) ? Z[row + (int64_t)(i0 + cc) * ld] : 0.0;
+            const bool okc = okr && j0 + cc < k;
+            sH[cc][rr] = okc ? ZH[row + (int64_t)(j0 + cc) * ld] : 0.0;
+            sS[cc][rr] = okc ? ZS[row + (int64_t)(j0 + cc) * ld] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < GR; kk += 4) {
+            const double a = sZ[ti * 16 + (lane & 15)][kk + (lane >> 4)];
+            const double bh = sH[tj * 16 + (lane & 15)][kk + (lane >> 4)];
+            const double bs = sS[tj * 16 + (lane & 15)][kk + (lane >> 4)];
+            accH = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bh, accH, 0, 0, 0);
+            accS = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs, accS, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double* ph = part + (int64_t)blockIdx.y * 2 * kp * kp;
+    double* ps = ph + (int64_t)kp * kp;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int ii = i0 + ti * 16 + 4 * (lane >> 4) + q;
+        const int jj = j0 + tj * 16 + (lane & 15);
+        ph[ii + (int64_t)jj * kp] = accH[q];
+        ps[ii + (int64_t)jj * kp] = accS[q];
+    }
+}
+
+// sum the chunk partials of the upper triangle (i <= j) and mirror it
+__global__ __launch_bounds__(256) void k_gram_reduce(int k, int kp, int nchunk,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ HR,
+                                                     double* __restrict__ SR, int64_t ldr) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)k * k) return;
+    const int i = (int)(idx % k), j = (int)(idx / k);
+    if (i > j) return;
+    double h = 0.0, s = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+        h += part[((int64_t)c * 2 + 0) * kp * kp + i + (int64_t)j * kp];
+        s += part[((int64_t)c * 2 + 1) * kp * kp + i + (int64_t)j * kp];
+    }
+    HR[i + (int64_t)j * ldr] = h;
+    HR[j + (int64_t)i * ldr] = h;
+    SR[i + (int64_t)j * ldr] = s;
+    SR[j + (int64_t)i * ldr] = s;
+}
+
+// ------------------------------------------------------------------ block update on MFMA
+
+// out = Zm W for the three (Zm, out) pairs (grid.z).  Work-group tile: 64 rows x 32
+// columns; wavefront w owns rows [16w, 16w+16) and both 16-column halves.
+__global__ __launch_bounds__(256) void k_block_update(int64_t n, int k, int b,
+                                                      const double* __restrict__ Z0,
+                                                      const double* __restrict__ Z1,
+                                                      const double* __restrict__ Z2, int64_t ldz,
+                                                      const double* __restrict__ W, int64_t ldw,
+                                                      double* __restrict__ O0,
+                                                      double* __restrict__ O1,
+                                                      double* __restrict__ O2, int64_t ldo) {
+    const double* Zm = blockIdx.z == 0 ? Z0 : (blockIdx.z == 1 ? Z1 : Z2);
+    double* O = blockIdx.z == 0 ? O0 : (blockIdx.z == 1 ? O1 : O2);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int c0 = blockIdx.y * 32;
+    const int64_t arow = r0 + (lane & 15);
+    const int kq = lane >> 4;
+    const int bc0 = c0 + (lane & 15), bc1 = bc0 + 16;
+    double4_t acc0 = {0.0, 0.0, 0.0, 0.0};
+    double4_t acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < k; kk += 4) {
+        const int kr = kk + kq;
+        const bool kin = kr < k;
+        const double a = (kin && arow < n) ? Zm[arow + (int64_t)kr * ldz] : 0.0;
+        const double w0 = (kin && bc0 < b) ? W[kr + (int64_t)bc0 * ldw] : 0.0;
+        const double w1 = (kin && bc1 < b) ? W[kr + (int64_t)bc1 * ldw] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, w0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, w1, acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t row = r0 + 4 * (lane >> 4) + q;
+        if (row < n) {
+            if (bc0 < b) O[row + (int64_t)bc0 * ldo] = acc0[q];
+            if (bc1 < b) O[row + (int64_t)bc1 * ldo] = acc1[q];
+        }
+    }
+}
+
+}  // namespace
+
+int residual_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kResRows - 1) / kResRows); }
+
+void launch_residual(int64_t n, int m, const double* PsiH, const double* PsiS, int64_t ld,
+                     const double* E, double sigma0, double* R, int64_t ldr, double* partial,
+                     int nblk, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_residual, dim3(nblk, m), dim3(256), 0, s, n, PsiH, PsiS, ld, E, sigma0, R,
+                       ldr, partial);
+    LABPSD_HIP(hipGetLastError());
+}
+
+void launch_residual_finish(int m, const double* partial, int nblk, double* res, double* rnorm,
+                            hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_residual_finish, dim3((m + 255) / 256), dim3(256), 0, s, m, partial, nblk,
+                       res, rnorm);
+    LABPSD_HIP(hipGetLastError());
+}
+
+template <typename TS, typename TD>
+void launch_gather_cast(int64_t n, int ncols, const TS* src, int64_t lds, const int32_t* cols,
+                        double scale, TD* dst, int64_t ldd, hipStream_t s) {
+    if (ncols <= 0 || n <= 0) return;
+    const int64_t bx = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL((k_gather_cast<TS, TD>), dim3((unsigned)bx, ncols), dim3(256), 0, s, n, src,
+                       lds, cols, scale, dst, ldd);
+    LABPSD_HIP(hipGetLastError());
+}
+
+template void launch_gather_cast<double, double>(int64_t, int, const double*, int64_t,
+                                                 const int32_t*, double, double*, int64_t,
+                                                 hipStream_t);
+template void launch_gather_cast<double, float>(int64_t, int, const double*, int64_t,
+                                                const int32_t*, double, float*, int64_t,
+                                                hipStream_t);
+template void launch_gather_cast<float, double>(int64_t, int, const float*, int64_t,
+                                                const int32_t*, double, double*, int64_t,
+                                                hipStream_t);
+template void launch_gather_cast<float, float>(int64_t, int, const float*, int64_t,
+                                               const int32_t*, double, float*, int64_t,
+                                               hipStream_t);
+
+template <typename TS, typename TD>
+void launch_scatter_cast(int64_t n, int ncols, const TS* src, int64_t lds, const int32_t* cols,
+                         double scale, TD* dst, int64_t ldd, hipStream_t s) {
+    if (ncols <= 0 || n <= 0) return;
+    const int64_t bx = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL((k_scatter_cast<TS, TD>), dim3((unsigned)bx, ncols), dim3(256), 0, s, n, src,
+                       lds, cols, scale, dst, ldd);
+    LABPSD_HIP(hipGetLastError());
+}
+
+template void launch_scatter_cast<double, double>(int64_t, int, const double*, int64_t,
+                                                  const int32_t*, double, double*, int64_t,
+                                                  hipStream_t);
+template void launch_scatter_cast<float, double>(int64_t, int, const float*, int64_t,
+                                                 const int32_t*, double, double*, int64_t,
+                                                 hipStream_t);
+template void launch_scatter_cast<double, float>(int64_t, int, const double*, int64_t,
+                                                 const int32_t*, double, float*, int64_t,
+                                                 hipStream_t);
+template void launch_scatter_cast<float, float>(int64_t, int, const float*, int64_t,
+                                                const int32_t*, double, float*, int64_t,
+                                                hipStream_t);
+
+template <typename T>
+void launch_colnorms(int64_t n, int q, const T* src, int64_t ld, const int32_t* cols,
+                     double* partial, double* out, hipStream_t s) {
+    if (q <= 0) return;
+    const int nblk = residual_blocks(n);
+    hipLaunchKernelGGL((k_colnorm_partial<T>), dim3(nblk, q), dim3(256), 0, s, n, src, ld, cols,
+                       partial);
+    LABPSD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_colnorm_finish, dim3((q + 255) / 256), dim3(256), 0, s, q, partial, nblk,
+                       out);
+    LABPSD_HIP(hipGetLastError());
+}
+
+template void launch_colnorms<double>(int64_t, int, const double*, int64_t, const int32_t*, double*,
+                                      double*, hipStream_t);
+template void launch_colnorms<float>(int64_t, int, const float*, int64_t, const int32_t*, double*,
+                                     double*, hipStream_t);
+
+static void gram_shape(int64_t n, int k, int cu_count, int& nb, int& kp, int& nchunk,
+                       int64_t& rows) {
+    nb = (k + GT - 1) / GT;
+    kp = nb * GT;
+    const int pairs = nb * (nb + 1) / 2;
+    // enough work-groups to fill the chip twice, chunks of at least 256 rows
+    int64_t want = std::max<int64_t>(1, (2LL * cu_count + pairs - 1) / pairs);
+    int64_t maxc = std::max<int64_t>(1, (n + 255) / 256);
+    nchunk = (int)std::min<int64_t>(want, maxc);
+    rows = (n + nchunk - 1) / nchunk;
+    rows = ((rows + GR - 1) / GR) * GR;
+    nchunk = (int)std::max<int64_t>(1, (n + rows - 1) / rows);
+}
+
+size_t gram_ws_doubles(int64_t n, int k, int cu_count) {
+    int nb, kp, nchunk;
+    int64_t rows;
+    gram_shape(n, k, cu_count, nb, kp, nchunk, rows);
+    return (size_t)nchunk * 2 * kp * kp;
+}
+
+void launch_gram(int64_t n, int k, const double* Z, const double* ZH, const double* ZS, int64_t ldz,
+                 double* HR, double* SR, int64_t ldr, double* ws, int cu_count, hipStream_t s) {
+    if (k <= 0) return;
+    int nb, kp, nchunk;
+    int64_t rows;
+    gram_shape(n, k, cu_count, nb, kp, nchunk, rows);
+    const int pairs = nb * (nb + 1) / 2;
+    hipLaunchKernelGGL(k_gram, dim3(pairs, nchunk), dim3(256), 0, s, n, k, Z, ZH, ZS, ldz, nb, rows,
+                       ws, kp);
+    LABPSD_HIP(hipGetLastError());
+    const int64_t tot = (int64_t)k * k;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, k, kp,
+                       nchunk, ws, HR, SR, ldr);
+    LABPSD_HIP(hipGetLastError());
+}
+
+void launch_block_update(int64_t n, int k, int b, const double* Z, const double* ZH,
+                         const double* ZS, int64_t ldz, const double* W, int64_t ldw, double* Psi,
+                         double* PsiH, double* PsiS, int64_t ldo, hipStream_t s) {
+    if (n <= 0 || b <= 0) return;
+    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((b + 31) / 32), 3);
+    hipLaunchKernelGGL(k_block_update, grid, dim3(256), 0, s, n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi,
+                       PsiH, PsiS, ldo);
+    LABPSD_HIP(hipGetLastError());
+}
+
+}  // namespace labpsd

@@ -1,0 +1,182 @@
+// Application of the global preconditioner K = (H - eps_bar S)^{-1} (eq. (k1p)) with the
+// supernodal Cholesky factor P^T K P = L L^T computed once on the host (eq. (ldl)).
+//
+// Each supernode t owns columns D_t (its separator or leaf) and row set D_t + B_t
+// (B_t in ancestors).  Its panel holds inv(L11) (lower) on top and L21 below, so the
+// substitutions become small dense products.  Supernodes of one tree level are
+// independent; levels run leaves to root (forward) and root to leaves (backward):
+//   forward  level l:  y[D] <- inv(L11) y[D]          (diag kernel, assign)
+//                      r[B] -= L21 y[D]               (off-diag kernel, atomic: siblings
+//                                                      share ancestor rows)
+//   backward level l:  z[D] <- y[D] - L21^T x[B]      (gather kernel)
+//                      x[D] <- inv(L11)^T z[D]        (diag kernel)
+// The permutation is folded into the row lists (dof ids), so every block is read and
+// written in the caller's ordering.  Work-group tile: 64 output rows x 16 right-hand
+// sides; the reduction dimension is staged through LDS 32 at a time.  T is double
+// (FP64 mode) or float (mixed mode: FP32 panels, FP32 accumulation).
+#include "common.h"
+
+namespace labpsd {
+
+namespace {
+
+constexpr int TR = 64;   // output rows per work-group
+constexpr int TC = 16;   // right-hand sides per work-group
+constexpr int TK = 32;   // reduction chunk
+
+enum { OP_DIAG = 0, OP_DIAG_T = 1, OP_OFFD = 2, OP_OFFD_T = 3 };
+
+// Generic tiled product for one task (supernode sn, output tile) of a level.
+//  OP_DIAG   out[D[r]] = sum_{k<=r} inv(L11)[r,k] in[D[k]]             (assign)
+//  OP_DIAG_T out[D[r]] = sum_{k>=r} inv(L11)[k,r] in[D[k]]             (assign)
+//  OP_OFFD   out[B[r]] -= sum_k L21[r,k] in[D[k]]                        (atomic)
+//  OP_OFFD_T out[D[r]] = base[D[r]] - sum_k L21[k,r] in[B[k]]            (assign)
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_sn_product(const int32_t* __restrict__ tasks,
+                                                    const int32_t* __restrict__ sn_ncol,
+                                                    const int32_t* __restrict__ sn_nrow,
+                                                    const int64_t* __restrict__ sn_idx,
+                                                    const int64_t* __restrict__ sn_val,
+                                                    const int32_t* __restrict__ rows,
+                                                    const T* __restrict__ panels,
+                                                    const T* __restrict__ in, T* __restrict__ out,
+                                                    const T* __restrict__ base, int64_t ld,
+                                                    int nrhs) {
+    const int sn = tasks[2 * blockIdx.x];
+    const int tile = tasks[2 * blockIdx.x + 1];
+    const int ncol = sn_ncol[sn], nrow = sn_nrow[sn];
+    const int nb = nrow - ncol;
+    const int32_t* rl = rows + sn_idx[sn];
+    const T* P = panels + sn_val[sn];   // nrow x ncol, ld nrow
+    const int c0 = blockIdx.y * TC;
+    const int nc = min(TC, nrhs - c0);
+
+    // output and reduction extents
+    int nout, nred;
+    if (OP == OP_OFFD) { nout = nb; nred = ncol; }
+    else if (OP == OP_OFFD_T) { nout = ncol; nred = nb; }
+    else { nout = ncol; nred = ncol; }
+    const int r0 = tile * TR;
+    // reduction range (triangular blocks skip the zero half)
+    int k_begin = 0, k_end = nred;
+    if (OP == OP_DIAG) k_end = min(nred, r0 + TR);
+    if (OP == OP_DIAG_T) k_begin = (r0 / TK) * TK;
+
+    __shared__ T sM[TK][TR + 1];      // sM[k][r] = M(r, k)
+    __shared__ T sX[TK][TC];          // sX[k][c] = in[row(k), c0 + c]
+    const int t = threadIdx.x;
+    const int orow = t & (TR - 1);     // this thread's output row within the tile
+    const int cq = (t >> 6) * 4;       // its four right-hand sides
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+
+    for (int kb = k_begin; kb < k_end; kb += TK) {
+        // stage M(r, k) for r in [r0, r0+TR), k in [kb, kb+TK)
+        for (int e = t; e < TR * TK; e += 256) {
+            int rr, kk;
+            T v = T(0);
+            if (OP == OP_DIAG || OP == OP_OFFD) {
+                // column-major panel: consecutive threads walk rows (contiguous)
+                rr = e % TR; kk = e / TR;
+                const int r = r0 + rr, k = kb + kk;
+                if (r < nout && k < k_end) {
+                    const int prow = (OP == OP_OFFD) ? ncol + r : r;
+                    if (OP == OP_OFFD || k <= r) v = P[prow + (int64_t)k * nrow];
+                }
+            } else {
+                // transposed: M(r, k) = panel(krow, r); consecutive threads walk k
+                kk = e % TK; rr = e / TK;
+                const int r = r0 + rr, k = kb + kk;
+                if (r < nout && k < k_end) {
+                    const int krow = (OP == OP_OFFD_T) ? ncol + k : k;
+                    if (OP == OP_OFFD_T || k >= r) v = P[krow + (int64_t)r * nrow];
+                }
+            }
+            sM[kk][rr] = v;
+        }
+        // stage the gathered right-hand sides
+        for (int e = t; e < TK * TC; e += 256) {
+            const int kk = e / TC, c = e % TC;
+            const int k = kb + kk;
+            T v = T(0);
+            if (k < k_end && c < nc) {
+                const int grow = (OP == OP_OFFD_T) ? rl[ncol + k] : rl[k];
+                v = in[grow + (int64_t)(c0 + c) * ld];
+            }
+            sX[kk][c] = v;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < TK; ++kk) {
+            const T m = sM[kk][orow];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = fma(m, sX[kk][cq + q], acc[q]);
+        }
+        __syncthreads();
+    }
+    const int r = r0 + orow;
+    if (r >= nout) return;
+    if (OP == OP_OFFD) {
+        const int64_t g = rl[ncol + r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (cq + q < nc) atomicAdd(&out[g + (int64_t)(c0 + cq + q) * ld], -acc[q]);
+    } else {
+        const int64_t g = rl[r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (cq + q < nc) {
+                const int64_t o = g + (int64_t)(c0 + cq + q) * ld;
+                out[o] = (OP == OP_OFFD_T) ? base[o] - acc[q] : acc[q];
+            }
+        }
+    }
+}
+
+template <typename T, int OP>
+void launch_level(const DevFactor& F, const int32_t* tasks, int64_t ntasks, const T* panels,
+                  const T* in, T* out, const T* base, int64_t ld, int nrhs, hipStream_t s) {
+    if (ntasks <= 0 || nrhs <= 0) return;
+    LABPSD_REQUIRE(tasks != nullptr && panels != nullptr && in != nullptr && out != nullptr &&
+                       (OP != OP_OFFD_T || base != nullptr),
+                   "supernodal product launched without its task list or buffers");
+    dim3 grid((unsigned)ntasks, (unsigned)((nrhs + TC - 1) / TC));
+    hipLaunchKernelGGL((k_sn_product<T, OP>), grid, dim3(256), 0, s, tasks, F.sn_ncol.p, F.sn_nrow.p,
+                       F.sn_idx.p, F.sn_val.p, F.rows.p, panels, in, out, base, ld, nrhs);
+    LABPSD_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// Y: right-hand sides on entry (consumed); W1: forward solution; W2: result K^{-1} Y.
+template <typename T>
+void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t ld, int ncols,
+                          hipStream_t s) {
+    const T* panels;
+    if constexpr (sizeof(T) == 8) panels = F.panels64.p;
+    else panels = F.panels32.p;
+    const int L = F.nlevels;
+    for (int l = 0; l < L; ++l) {
+        const int64_t d0 = F.lev_diag_off[l], d1 = F.lev_diag_off[l + 1];
+        const int64_t o0 = F.lev_off_off[l], o1 = F.lev_off_off[l + 1];
+        launch_level<T, OP_DIAG>(F, F.task_diag.p + 2 * d0, d1 - d0, panels, Y, W1, nullptr, ld,
+                                 ncols, s);
+        launch_level<T, OP_OFFD>(F, F.task_offd.p + 2 * o0, o1 - o0, panels, W1, Y, nullptr, ld,
+                                 ncols, s);
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        const int64_t d0 = F.lev_diag_off[l], d1 = F.lev_diag_off[l + 1];
+        // z[D] = W1[D] - L21^T W2[B] over the D tiles, written into Y (free after the
+        // forward sweep)
+        launch_level<T, OP_OFFD_T>(F, F.task_diag.p + 2 * d0, d1 - d0, panels, W2, Y, W1, ld,
+                                   ncols, s);
+        launch_level<T, OP_DIAG_T>(F, F.task_diag.p + 2 * d0, d1 - d0, panels, Y, W2, nullptr, ld,
+                                   ncols, s);
+    }
+}
+
+template void launch_precond_solve<double>(const DevFactor&, double*, double*, double*, int64_t, int,
+                                           hipStream_t);
+template void launch_precond_solve<float>(const DevFactor&, float*, float*, float*, int64_t, int,
+                                          hipStream_t);
+
+}  // namespace labpsd

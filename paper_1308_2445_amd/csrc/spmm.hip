@@ -1,0 +1,220 @@
+// Sparse products with the shared pattern of H and S (outline steps 3 and 7, and the
+// shifted products (H - sigma S) v of the refinement; Section 5 notes the PUFE code
+// forms (H - sigma S) v for any shift).
+//
+// Layout: sliced ELL with 64-row slices (one wavefront per slice, one row per lane),
+// each slice padded to its longest row and stored slot-major, so a wavefront's
+// loads of column indices and values are contiguous.  H and S values sit on the same
+// pattern, so one pass over the pattern and one gather of X serve both products.
+// Work-groups map slices XCD-locally: consecutive slices land on the same XCD so the
+// neighbouring rows' gathers of X hit the same L2.
+#include "common.h"
+
+namespace labpsd {
+
+namespace {
+
+constexpr int kWaves = 4;  // slices per work-group
+
+// Map a linear work-group index to a slice-block index so that each XCD (work-groups
+// are dealt round-robin to the 8 XCDs) receives a contiguous range of slice blocks.
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
+    constexpr int kXcd = 8;
+    if (nblocks < 2 * kXcd) return bid;
+    const int64_t per = nblocks / kXcd, rem = nblocks % kXcd;
+    const int64_t xcd = bid % kXcd, idx = bid / kXcd;
+    // XCDs 0..rem-1 own per+1 blocks, the rest own per
+    const int64_t start = xcd * per + (xcd < rem ? xcd : rem);
+    const int64_t own = per + (xcd < rem ? 1 : 0);
+    if (idx < own) return start + idx;
+    return bid;  // unreachable for bid < nblocks; kept total
+}
+
+template <int CW>
+__global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off,
+                                                 const int32_t* __restrict__ col,
+                                                 const double* __restrict__ hv,
+                                                 const double* __restrict__ sv, int64_t n,
+                                                 int64_t nslices, const double* __restrict__ X,
+                                                 int64_t ldx, int w, double* __restrict__ YH,
+                                                 double* __restrict__ YS, int64_t ldy) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nblk = (nslices + kWaves - 1) / kWaves;
+    const int64_t sb = xcd_block(blockIdx.x, nblk);
+    const int64_t slice = sb * kWaves + (threadIdx.x >> 6);
+    if (slice >= nslices) return;
+    const int j0 = blockIdx.y * CW;
+    const int nc = min(CW, w - j0);
+    const int64_t row = slice * kSlice + lane;
+    const int64_t e0 = off[slice], e1 = off[slice + 1];
+    double ah[CW], as[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) { ah[j] = 0.0; as[j] = 0.0; }
+    const double* Xj = X + (int64_t)j0 * ldx;
+    for (int64_t e = e0 + lane; e < e1; e += kSlice) {
+        const int64_t c = col[e];
+        const double h = hv[e], s = sv[e];
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            if (j < nc) {
+                const double x = Xj[c + j * ldx];
+                ah[j] = fma(h, x, ah[j]);
+                as[j] = fma(s, x, as[j]);
+            }
+        }
+    }
+    if (row < n) {
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            if (j < nc) {
+                YH[row + (int64_t)(j0 + j) * ldy] = ah[j];
+                YS[row + (int64_t)(j0 + j) * ldy] = as[j];
+            }
+        }
+    }
+}
+
+// Y[:, j] = H X[:, j] - shift[j] S X[:, j]
+template <typename T, int CW>
+__global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ off,
+                                                    const int32_t* __restrict__ col,
+                                                    const T* __restrict__ hv,
+                                                    const T* __restrict__ sv, int64_t n,
+                                                    int64_t nslices, const T* __restrict__ X,
+                                                    int64_t ldx, int w,
+                                                    const double* __restrict__ shift,
+                                                    T* __restrict__ Y, int64_t ldy) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nblk = (nslices + kWaves - 1) / kWaves;
+    const int64_t sb = xcd_block(blockIdx.x, nblk);
+    const int64_t slice = sb * kWaves + (threadIdx.x >> 6);
+    if (slice >= nslices) return;
+    const int j0 = blockIdx.y * CW;
+    const int nc = min(CW, w - j0);
+    const int64_t row = slice * kSlice + lane;
+    const int64_t e0 = off[slice], e1 = off[slice + 1];
+    T ah[CW], as[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) { ah[j] = T(0); as[j] = T(0); }
+    const T* Xj = X + (int64_t)j0 * ldx;
+    for (int64_t e = e0 + lane; e < e1; e += kSlice) {
+        const int64_t c = col[e];
+        const T h = hv[e], s = sv[e];
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            if (j < nc) {
+                const T x = Xj[c + j * ldx];
+                ah[j] = fma(h, x, ah[j]);
+                as[j] = fma(s, x, as[j]);
+            }
+        }
+    }
+    if (row < n) {
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            if (j < nc) {
+                const T sh = (T)shift[j0 + j];
+                Y[row + (int64_t)(j0 + j) * ldy] = ah[j] - sh * as[j];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void build_sell(Sell& S, const HostCSR& A, const double* hv, const double* sv, hipStream_t s) {
+    const int64_t n = A.n;
+    S.n = n;
+    S.nslices = (n + kSlice - 1) / kSlice;
+    S.h_slice_off.assign(S.nslices + 1, 0);
+    for (int64_t sl = 0; sl < S.nslices; ++sl) {
+        int64_t mx = 0;
+        for (int64_t r = sl * kSlice; r < std::min(n, (sl + 1) * kSlice); ++r)
+            mx = std::max<int64_t>(mx, A.rowptr[r + 1] - A.rowptr[r]);
+        S.h_slice_off[sl + 1] = S.h_slice_off[sl] + mx * kSlice;
+    }
+    S.stored = S.h_slice_off[S.nslices];
+    std::vector<int32_t> col(S.stored);
+    std::vector<double> h(S.stored, 0.0), sv_(S.stored, 0.0);
+    std::vector<float> h32(S.stored, 0.0f), s32(S.stored, 0.0f);
+    S.h_map.assign(S.stored, -1);
+    for (int64_t sl = 0; sl < S.nslices; ++sl) {
+        const int64_t base = S.h_slice_off[sl];
+        const int64_t len = (S.h_slice_off[sl + 1] - base) / kSlice;
+        for (int lane = 0; lane < kSlice; ++lane) {
+            const int64_t r = sl * kSlice + lane;
+            const int64_t b = r < n ? A.rowptr[r] : 0;
+            const int64_t cnt = r < n ? A.rowptr[r + 1] - b : 0;
+            for (int64_t k = 0; k < len; ++k) {
+                const int64_t e = base + k * kSlice + lane;
+                if (k < cnt) {
+                    col[e] = A.col[b + k];
+                    h[e] = hv[b + k];
+                    sv_[e] = sv[b + k];
+                    h32[e] = (float)hv[b + k];
+                    s32[e] = (float)sv[b + k];
+                    S.h_map[e] = b + k;
+                } else {
+                    col[e] = (int32_t)(r < n ? r : 0);   // padding: own row, value 0
+                }
+            }
+        }
+    }
+    S.slice_off.upload(S.h_slice_off.data(), S.h_slice_off.size(), s);
+    S.col.upload(col.data(), col.size(), s);
+    S.hv.upload(h.data(), h.size(), s);
+    S.sv.upload(sv_.data(), sv_.size(), s);
+    S.hv32.upload(h32.data(), h32.size(), s);
+    S.sv32.upload(s32.data(), s32.size(), s);
+    LABPSD_HIP(hipStreamSynchronize(s));
+}
+
+void refresh_sell_h(Sell& S, const double* hv, hipStream_t s) {
+    std::vector<double> h(S.stored, 0.0);
+    std::vector<float> h32(S.stored, 0.0f);
+    for (int64_t e = 0; e < S.stored; ++e)
+        if (S.h_map[e] >= 0) {
+            h[e] = hv[S.h_map[e]];
+            h32[e] = (float)h[e];
+        }
+    S.hv.upload(h.data(), h.size(), s);
+    S.hv32.upload(h32.data(), h32.size(), s);
+    LABPSD_HIP(hipStreamSynchronize(s));
+}
+
+void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
+                    int64_t ldy, hipStream_t s) {
+    if (w <= 0 || A.n == 0) return;
+    constexpr int CW = 8;
+    dim3 grid((unsigned)((A.nslices + kWaves - 1) / kWaves), (unsigned)((w + CW - 1) / CW));
+    hipLaunchKernelGGL(k_spmm_hs<CW>, grid, dim3(256), 0, s, A.slice_off.p, A.col.p, A.hv.p,
+                       A.sv.p, A.n, A.nslices, X, ldx, w, YH, YS, ldy);
+    LABPSD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
+                       int64_t ldy, hipStream_t s) {
+    if (w <= 0 || A.n == 0) return;
+    constexpr int CW = 8;
+    dim3 grid((unsigned)((A.nslices + kWaves - 1) / kWaves), (unsigned)((w + CW - 1) / CW));
+    const T* hv;
+    const T* sv;
+    if constexpr (sizeof(T) == 8) {
+        hv = A.hv.p;
+        sv = A.sv.p;
+    } else {
+        hv = A.hv32.p;
+        sv = A.sv32.p;
+    }
+    hipLaunchKernelGGL((k_spmm_shift<T, CW>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, hv, sv,
+                       A.n, A.nslices, X, ldx, w, shift, Y, ldy);
+    LABPSD_HIP(hipGetLastError());
+}
+
+template void launch_spmm_shift<double>(const Sell&, const double*, int64_t, int, const double*,
+                                        double*, int64_t, hipStream_t);
+template void launch_spmm_shift<float>(const Sell&, const float*, int64_t, int, const double*,
+                                       float*, int64_t, hipStream_t);
+
+}  // namespace labpsd

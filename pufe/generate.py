@@ -338,6 +338,15 @@ def _on_pattern(A: sp.csr_matrix, pat: sp.csr_matrix) -> np.ndarray:
     return out
 
 
+def dof_coordinates(P: Problem) -> np.ndarray:
+    """Position (x, y, z) of every dof's host node, row-major n x 3 (for orderings)."""
+    ne = P.ne
+    h = P.L / ne
+    nd = P.dof_node
+    return np.ascontiguousarray(np.stack([nd % ne, (nd // ne) % ne, nd // (ne * ne)], axis=1) * h,
+                                dtype=np.float64)
+
+
 def count_dofs(L: float, ne: int, natoms: int, seed: int) -> int:
     """Number of dofs the construction gives, without assembling (nodes + enriched pairs)."""
     h = L / ne

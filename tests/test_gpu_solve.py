@@ -1,0 +1,191 @@
+"""GPU parity of whole LABPSD solves against the oracle, plus edge cases and error paths."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import pufe
+from oracle import eigs as oeig
+from oracle import labpsd as olab
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _lp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1308_2445_amd as lp
+    return lp
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return _lp().Context(0)
+
+
+def _problem(ctx, P):
+    lp = _lp()
+    pr = lp.Problem.from_pencil(ctx, P)
+    pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P))
+    return pr
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, "%s_eigs.json" % name)) as f:
+        return json.load(f)
+
+
+def _rel_err(lam, ref, sigma0):
+    return np.abs(np.asarray(lam) - np.asarray(ref)) / np.abs(np.asarray(ref) - sigma0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c1_matches_dense(ctx, precision):
+    lp = _lp()
+    P = pufe.workload("c1", 0)
+    pr = _problem(ctx, P)
+    m, m0 = 4, pufe.guard_vectors(4)
+    print("\n[case] c1 precision=%d" % precision, flush=True)
+    out = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-10, sigma0=P.sigma0, precision=precision)
+    assert out.converged
+    lam, X = oeig.dense_eigs(P.H(), P.S(), m)
+    assert _rel_err(out.lam, lam, P.sigma0).max() < 1e-10
+    res = oeig.relative_residuals(P.H(), P.S(), out.lam, out.X, P.sigma0)
+    assert res.max() <= 1e-10 * 1.01
+    S = P.S()
+    assert np.abs(out.X.T @ (S @ out.X) - np.eye(m)).max() < 1e-10
+    for cl in oeig.clusters(lam, P.sigma0):
+        assert oeig.s_principal_angles(S, out.X[:, cl], X[:, cl]).max() < 1e-7
+
+
+@pytest.fixture(scope="module")
+def c2(ctx):
+    P = pufe.workload("c2", 0)
+    g = _golden("c2")
+    assert g["n"] == P.n and g["nnz"] == P.nnz
+    return P, _problem(ctx, P), g
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_eigenvalues_match_oracle(c2, precision):
+    P, pr, g = c2
+    m, m0 = g["nev"], g["m0"]
+    print("\n[case] c2 precision=%d" % precision, flush=True)
+    out = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-8, sigma0=P.sigma0, precision=precision)
+    assert out.converged, out.stats
+    err = _rel_err(out.lam, g["lam"], P.sigma0)
+    print("[c2] precision=%d iters=%d La=%.2f max rel eig err %.2e" % (precision, out.stats["outer_iters"],
+                                                                       out.stats["la"], err.max()))
+    assert err.max() < 1e-10
+    res = oeig.relative_residuals(P.H(), P.S(), out.lam, out.X, P.sigma0)
+    assert res.max() <= 1e-8 * 1.01
+    assert out.res_hist.shape[1] == m and out.res_hist[-1].max() <= 1e-8
+
+
+@pytest.fixture(scope="module")
+def c2_oracle(c2):
+    P, pr, g = c2
+    m, m0 = g["nev"], g["m0"]
+    prm = olab.Params(nev=m, m0=m0, tol=1e-11, sigma0=P.sigma0, eps_bar=P.eps_bar)
+    return olab.solve(P.H(), P.S(), prm, pufe.start_block(P.n, m + m0, 0))
+
+
+def test_c2_subspaces_match_oracle(c2, c2_oracle):
+    P, pr, g = c2
+    m, m0 = g["nev"], g["m0"]
+    out = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-11, sigma0=P.sigma0, precision=0)
+    assert out.converged
+    ref = c2_oracle
+    assert _rel_err(out.lam, ref.lam, P.sigma0).max() < 1e-10
+    S = P.S()
+    for cl in oeig.clusters(ref.lam, P.sigma0):
+        assert oeig.s_principal_angles(S, out.X[:, cl], ref.X[:, cl]).max() < 1e-7
+
+
+def test_c2_trajectory_tracks_oracle(c2, c2_oracle):
+    """Per-iteration Res_max of the FP64 GPU run follows the oracle's for the first
+    iterations (before near-threshold localisation decisions can diverge)."""
+    P, pr, g = c2
+    m, m0 = g["nev"], g["m0"]
+    out = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-11, sigma0=P.sigma0, precision=0)
+    ref = np.array([h.res for h in c2_oracle.history])
+    k = min(6, len(ref), len(out.res_hist))
+    assert np.allclose(out.res_hist[:k], ref[:k], rtol=1e-6, atol=0)
+
+
+def test_free_particle_closed_form(ctx):
+    P = pufe.generate(6.0, 12, 0, 0)
+    P.eps_bar, P.sigma0 = -0.1, -1.0
+    pr = _problem(ctx, P)
+    out = pr.solve(7, 4, pufe.start_block(P.n, 11, 0), tol=1e-10, sigma0=P.sigma0)
+    assert out.converged
+    ref = pufe.free_particle_eigs(12, 6.0, 7)
+    assert _rel_err(out.lam, ref, P.sigma0).max() < 1e-10
+
+
+def test_warm_start_converges_fast(ctx):
+    P = pufe.workload("c1", 0)
+    pr = _problem(ctx, P)
+    m, m0 = 4, 4
+    a = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-10, sigma0=P.sigma0)
+    # SCF-like next step: amplitudes drift by 1%
+    P2 = pufe.generate(P.L, P.ne, 0, 0, atoms=P.atoms, amplitudes=P.amplitudes * 1.01)
+    pr.update_h(P2.h_val)
+    X0 = np.hstack([a.X, pufe.start_block(P.n, m + m0, 1)[:, :m0]])
+    b = pr.solve(m, m0, X0, tol=1e-8, sigma0=P.sigma0, E0=np.concatenate([a.lam, np.zeros(m0)]))
+    assert b.converged
+    lam, _ = oeig.dense_eigs(P2.H(), P2.S(), m)
+    assert _rel_err(b.lam, lam, P.sigma0).max() < 1e-10
+    assert b.stats["outer_iters"] < a.stats["outer_iters"]
+
+
+def test_modes_and_minimal_block(ctx):
+    lp = _lp()
+    P = pufe.workload("c1", 0)
+    pr = _problem(ctx, P)
+    lam, _ = oeig.dense_eigs(P.H(), P.S(), 4)
+    for mode in (lp.GLOBAL_ONLY, lp.LOCAL_ONLY, lp.HYBRID):
+        pr.set_local_precond(mode=mode)
+        out = pr.solve(4, 4, pufe.start_block(P.n, 8, 0), tol=1e-9, sigma0=P.sigma0)
+        assert out.converged
+        assert _rel_err(out.lam, lam, P.sigma0).max() < 1e-10
+        if mode == lp.GLOBAL_ONLY:
+            assert out.stats["minres_iters"] == 0
+    # one wanted pair, one guard vector
+    out = pr.solve(1, 1, pufe.start_block(P.n, 2, 0), tol=1e-9, sigma0=P.sigma0)
+    assert out.converged and _rel_err(out.lam, lam[:1], P.sigma0).max() < 1e-10
+
+
+def test_not_converged_keeps_valid_outputs(ctx):
+    lp = _lp()
+    P = pufe.workload("c1", 0)
+    pr = _problem(ctx, P)
+    out = pr.solve(4, 4, pufe.start_block(P.n, 8, 0), tol=1e-12, max_outer=1, sigma0=P.sigma0)
+    assert out.status == lp.NOT_CONVERGED
+    assert np.all(np.isfinite(out.lam)) and np.all(np.isfinite(out.X))
+    assert out.res_hist.shape == (1, 4)
+
+
+def test_error_paths(ctx):
+    lp = _lp()
+    P = pufe.workload("c1", 0)
+    pr = lp.Problem.from_pencil(ctx, P)
+    with pytest.raises(lp.LabpsdError) as e:
+        pr.solve(4, 4, pufe.start_block(P.n, 8, 0))
+    assert e.value.code == lp.ESTATE
+    lam, _ = oeig.dense_eigs(P.H(), P.S(), 3)
+    with pytest.raises(lp.LabpsdError) as e:
+        pr.set_global_precond(0.5 * (lam[1] + lam[2]))
+    assert e.value.code == lp.ENOTSPD
+    bad = P.col.copy()
+    bad[[0, 1]] = bad[[1, 0]]
+    with pytest.raises(lp.LabpsdError) as e:
+        lp.Problem(ctx, P.n, P.rowptr, bad, P.h_val, P.s_val)
+    assert e.value.code == lp.EINVAL
+    pr.set_global_precond(P.eps_bar)   # graph ordering (no coordinates) also works
+    with pytest.raises(lp.LabpsdError) as e:
+        pr.solve(P.n, 4, np.zeros((P.n, P.n + 4)))
+    assert e.value.code == lp.EINVAL
