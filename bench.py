@@ -35,6 +35,13 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="serve the SCF-like request stream instead of single solves")
+    ap.add_argument("--systems", type=int, default=25)
+    ap.add_argument("--chain", type=int, default=8)
+    ap.add_argument("--rate", type=float, default=4.0, help="system arrivals per second (Poisson)")
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
     return ap.parse_args()
 
 
@@ -64,12 +71,90 @@ def algorithmic(step, P, fi, st, nev, b, prec_bytes):
     return None, 0.0
 
 
+def serving(args):
+    """SCF-like stream: systems arrive as a Poisson process; each is a chain of GHEPs
+    whose potential drifts by up to 1% per step, every step warm-started from the last."""
+    import torch
+
+    import paper_1308_2445_amd as lp
+    import pufe
+    rng = np.random.default_rng(2024)
+    t0 = time.perf_counter()
+    pencils = []
+    for i in range(args.systems):
+        ne = int(rng.choice([12, 16, 24, 32]))
+        na = int(rng.integers(1, 17))
+        nev = int(rng.choice([8, 16, 32, 64]))
+        P = pufe.generate(ne / 2.0, ne, na, 100 + i)
+        scales = np.cumprod(1.0 + rng.uniform(-0.01, 0.01, args.chain))
+        pencils.append((P, nev, scales))
+    t_gen = time.perf_counter() - t0
+    ctx = lp.Context(0)
+    systems = []
+    t0 = time.perf_counter()
+    for P, nev, _ in pencils:
+        pr = lp.Problem.from_pencil(ctx, P)
+        pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P))
+        systems.append(pr)
+    t_setup = time.perf_counter() - t0
+    print("[serve] %d systems generated in %.1fs, factorised in %.1fs" % (len(systems), t_gen, t_setup),
+          flush=True)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, args.systems))
+    srv = lp.Server(ctx, int(args.budget_gb * 2 ** 30), args.slots)
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    outstanding = {}            # request id -> (system index, step)
+    nxt = 0
+    done = []
+    while len(done) < args.systems * args.chain:
+        now = time.perf_counter() - start
+        while nxt < args.systems and arrivals[nxt] <= now:
+            P, nev, sc = pencils[nxt]
+            m0 = pufe.guard_vectors(nev)
+            rid = srv.submit(systems[nxt], nev, m0, X0=pufe.start_block(P.n, nev + m0, nxt),
+                             h_val=P.h_scaled(sc[0]), tol=args.tol, sigma0=P.sigma0, precision=lp.MIXED)
+            outstanding[rid] = (nxt, 0)
+            nxt += 1
+        for rid in list(outstanding):
+            r = srv.poll(rid)
+            if r is None:
+                continue
+            i, j = outstanding.pop(rid)
+            assert r.converged, "a served solve did not converge"
+            done.append((i, j, r))
+            if j + 1 < args.chain:
+                P, nev, sc = pencils[i]
+                m0 = pufe.guard_vectors(nev)
+                rid2 = srv.submit(systems[i], nev, m0, h_val=P.h_scaled(sc[j + 1]), tol=args.tol,
+                                  sigma0=P.sigma0, precision=lp.MIXED)
+                outstanding[rid2] = (i, j + 1)
+        time.sleep(0.0005)
+    makespan = time.perf_counter() - start
+    srv.close()
+    lat = [r.latency for _, _, r in done]
+    pairs = sum(pencils[i][1] for i, _, _ in done)
+    line = {"metric": METRIC, "value": pairs / makespan, "unit": "eigenpairs/s", "n_gpus": 1,
+            "steps": len(done), "warmup": 0, "ms_per_step": 1e3 * makespan / len(done), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+            "config": {"workload": "serving: %d systems x %d SCF-like steps, meshes 12-32^3 at h=0.5, 1-16 "
+                                   "atoms, nev 8-64, Poisson arrivals %.1f/s, mixed precision, %d slots"
+                                   % (args.systems, args.chain, args.rate, args.slots)},
+            "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99)},
+            "iterations_cold_warm": [float(np.mean([r.stats["outer_iters"] for _, j, r in done if j == 0])),
+                                     float(np.mean([r.stats["outer_iters"] for _, j, r in done if j > 0]))],
+            "makespan_s": makespan}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); %d GPUs were requested" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        serving(args)
+        return
     import torch
 
     import paper_1308_2445_amd as lp

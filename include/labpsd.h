@@ -40,6 +40,7 @@ typedef enum {
     LABPSD_EHIP = -3,         /* a HIP runtime call failed                              */
     LABPSD_ENOTSPD = -4,      /* H - eps_bar S is not positive definite                 */
     LABPSD_ERANK = -5,        /* search space [Psi P] lost rank below the block width   */
+    LABPSD_PENDING = 2,       /* serving: the request has not finished yet              */
     LABPSD_ESTATE = -6        /* call out of order (e.g. solve before set_global_precond)*/
 } labpsd_status;
 
@@ -227,6 +228,44 @@ labpsd_status labpsd_rayleigh_ritz(labpsd_ctx* ctx, int k, int nwant, const doub
 labpsd_status labpsd_block_update(labpsd_ctx* ctx, int64_t n, int k, int b, const double* Z,
                                   const double* ZH, const double* ZS, int64_t ldz, const double* W,
                                   int64_t ldw, double* Psi, double* PsiH, double* PsiS, int64_t ldo);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop for SCF-like streams of GHEPs (Section 2: one GHEP per SCF step,
+ * each warm-started from the previous step's Psi, Section 3 remark 1).  Systems
+ * (labpsd_problem handles with their global preconditioner set) stay resident: H, S,
+ * the factor and the last block Psi.  Requests are admitted as slots and device
+ * memory free up (continuous batching: a request that arrives while others run
+ * starts as soon as a slot and its footprint fit); every slot runs on its own HIP
+ * stream, so the kernels of concurrent requests overlap on the device.  Requests of
+ * one system run in submission order, one at a time.  All server calls are
+ * thread-safe.                                                                     */
+typedef struct labpsd_server labpsd_server;
+
+/* hbm_budget_bytes bounds the sum of the footprints (labpsd_solve_footprint) of the
+ * requests in flight; max_slots (1..64) bounds how many run at once.              */
+labpsd_status labpsd_server_create(labpsd_ctx* ctx, size_t hbm_budget_bytes, int max_slots,
+                                   labpsd_server** out);
+/* Queue one GHEP.  system: a problem with its global preconditioner set (it must
+ * outlive the request).  h_val: host float64[nnz] new H values on the system's
+ * pattern (NULL keeps the current H).  X0: host n x (nev+m0) start block, or NULL to
+ * warm-start from the system's last result (EINVAL if it has none).  Returns at
+ * once with *req_id.  ENOMEM if the request's footprint alone exceeds the budget.  */
+labpsd_status labpsd_server_submit(labpsd_server* s, labpsd_problem* system, const double* h_val,
+                                   const labpsd_solve_params* params, const double* X0,
+                                   uint64_t* req_id);
+/* Collect a finished request: lambda[nev], X (n x nev, host) and stats may be NULL;
+ * times (may be NULL) receives {submitted, started, finished} in seconds since the
+ * server was created.  Returns PENDING while it runs (outputs untouched), else the
+ * request's solve status; a collected request is forgotten.                        */
+labpsd_status labpsd_server_poll(labpsd_server* s, uint64_t req_id, double* lambda, double* X,
+                                 labpsd_stats* stats, double* times);
+/* As labpsd_server_poll, but blocks until the request has finished.               */
+labpsd_status labpsd_server_wait(labpsd_server* s, uint64_t req_id, double* lambda, double* X,
+                                 labpsd_stats* stats, double* times);
+/* Device bytes one request of this shape reserves while it runs.                  */
+size_t labpsd_solve_footprint(int64_t n, int nev, int m0, int precision);
+/* Stops admitting, waits for running requests, frees the slots.                   */
+void labpsd_server_destroy(labpsd_server* s);
 
 #ifdef __cplusplus
 }

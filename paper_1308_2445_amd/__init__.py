@@ -6,7 +6,7 @@ device memory and the current HIP stream.  Block vectors on the device are torch
 tensors of shape (columns, ld) -- row j of the tensor is column j of the
 column-major block the library sees.
 
-The library must be built first (``python -m paper_1308_2445_amd.build``); if it
+The library must be built first (``python paper_1308_2445_amd/build.py``); if it
 is missing, importing this package raises.
 """
 from __future__ import annotations
@@ -24,16 +24,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblabpsd.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("liblabpsd.so is not built: run `python -m paper_1308_2445_amd.build`")
+    raise ImportError("liblabpsd.so is not built: run `python paper_1308_2445_amd/build.py`")
 _lib = ctypes.CDLL(LIB_PATH)
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, PENDING = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ENOTSPD, ERANK, ESTATE = -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 HYBRID, GLOBAL_ONLY, LOCAL_ONLY = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 
-_STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
+_STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
                  -5: "ERANK", -6: "ESTATE"}
 
 #: names of the entries of labpsd_stats.t_step_s / n_launch
@@ -106,6 +106,13 @@ _SIGS = {
     "labpsd_rayleigh_ritz": ([_p, _i32, _i32, _p, _p, _i64, _p, _p, _i64, _p], _i32),
     "labpsd_block_update": ([_p, _i64, _i32, _i32, _p, _p, _p, _i64, _p, _i64, _p, _p, _p, _i64],
                             _i32),
+    "labpsd_server_create": ([_p, ctypes.c_size_t, _i32, ctypes.POINTER(_p)], _i32),
+    "labpsd_server_submit": ([_p, _p, _p, ctypes.POINTER(SolveParams), _p, ctypes.POINTER(ctypes.c_uint64)],
+                             _i32),
+    "labpsd_server_poll": ([_p, ctypes.c_uint64, _p, _p, ctypes.POINTER(Stats), _p], _i32),
+    "labpsd_server_wait": ([_p, ctypes.c_uint64, _p, _p, ctypes.POINTER(Stats), _p], _i32),
+    "labpsd_solve_footprint": ([_i64, _i32, _i32, _i32], ctypes.c_size_t),
+    "labpsd_server_destroy": ([_p], None),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -144,6 +151,8 @@ def _ld(t) -> int:
     """Leading dimension of a (columns, ld) torch tensor whose rows are contiguous."""
     if t.dim() == 1:
         return t.shape[0]
+    if t.shape[0] <= 1:
+        return t.shape[1]          # one column: its stride is not meaningful
     assert t.stride(1) == 1, "block tensors must have contiguous rows (shape (cols, ld))"
     return t.stride(0)
 
@@ -323,3 +332,81 @@ def labpsd_block_update(ctx: Context, n: int, k: int, b: int, Z, ZH, ZS, W, Psi,
     ctx.sync_stream()
     _check(_lib.labpsd_block_update(ctx.h, n, k, b, _ptr(Z), _ptr(ZH), _ptr(ZS), _ld(Z), _ptr(W), _ld(W),
                                     _ptr(Psi), _ptr(PsiH), _ptr(PsiS), _ld(Psi)), "labpsd_block_update")
+
+
+# ------------------------------------------------------------------ serving
+
+@dataclasses.dataclass
+class Served:
+    status: int
+    lam: np.ndarray
+    X: np.ndarray
+    stats: dict
+    submitted: float
+    started: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.submitted
+
+
+def solve_footprint(n: int, nev: int, m0: int, precision: int = FP64) -> int:
+    return int(_lib.labpsd_solve_footprint(n, nev, m0, precision))
+
+
+class Server:
+    """Continuous-batching request loop over resident systems (labpsd_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int):
+        h = _p()
+        _check(_lib.labpsd_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)),
+               "labpsd_server_create")
+        self.h = h
+        self.ctx = ctx
+        self._shape = {}
+
+    def submit(self, system: Problem, nev: int, m0: int, *, X0=None, h_val=None, tol=1e-8, max_outer=200,
+               sigma0=0.0, precision=FP64, refresh_every=10) -> int:
+        prm = SolveParams(nev, m0, tol, max_outer, sigma0, precision, refresh_every, 0)
+        x = None if X0 is None else np.asfortranarray(X0, dtype=np.float64)
+        if x is not None:
+            assert x.shape == (system.n, nev + m0)
+        hv = None if h_val is None else np.ascontiguousarray(h_val, dtype=np.float64)
+        rid = ctypes.c_uint64(0)
+        _check(_lib.labpsd_server_submit(self.h, system.h, _ptr(hv), ctypes.byref(prm), _ptr(x),
+                                         ctypes.byref(rid)), "labpsd_server_submit")
+        self._shape[rid.value] = (system.n, nev)
+        return rid.value
+
+    def _collect(self, rid: int, block: bool):
+        n, nev = self._shape[rid]
+        lam = np.zeros(nev)
+        X = np.zeros((n, nev), order="F")
+        st = Stats()
+        times = np.zeros(3)
+        fn = _lib.labpsd_server_wait if block else _lib.labpsd_server_poll
+        rc = fn(self.h, rid, _ptr(lam), _ptr(X), ctypes.byref(st), _ptr(times))
+        if rc == PENDING:
+            return None
+        del self._shape[rid]
+        _check(rc, "labpsd_server_wait", allow=(OK, NOT_CONVERGED))
+        return Served(status=rc, lam=lam, X=X, stats=st.as_dict(), submitted=times[0], started=times[1],
+                      finished=times[2])
+
+    def poll(self, rid: int):
+        return self._collect(rid, False)
+
+    def wait(self, rid: int) -> Served:
+        return self._collect(rid, True)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.labpsd_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,6 +1,6 @@
 """Build liblabpsd.so (HIP kernels for gfx950 + host C++) in-tree.
 
-    python -m paper_1308_2445_amd.build
+    python paper_1308_2445_amd/build.py
 """
 from __future__ import annotations
 
@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "liblabpsd.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["spmm.hip", "dense.hip", "rr.hip", "precond.hip", "minres.hip", "api.hip"]
+HIP_SOURCES = ["spmm.hip", "dense.hip", "rr.hip", "precond.hip", "minres.hip", "api.hip", "serve.hip"]
 CPP_SOURCES = ["factor.cpp"]
 
 HIPCC_FLAGS = [

@@ -269,9 +269,8 @@ template <typename T>
 static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, const double* X0,
                                 const double* E0, labpsd_mem in_where, double* lambda, double* X,
                                 double* res_hist, int* n_hist, labpsd_mem out_where,
-                                labpsd_stats* stats) {
+                                labpsd_stats* stats, hipStream_t s) {
     const double t_start = wall();
-    hipStream_t s = P.ctx->stream;
     const int64_t n = P.n;
     const int m = prm.nev, b = prm.nev + prm.m0;
     const int kmax = b + m;
@@ -466,6 +465,12 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     }
     LABPSD_HIP(hipStreamSynchronize(s));
     tm.collect(&st);
+    // keep the whole block (guards included) resident for a warm start
+    P.resident_X.alloc((size_t)n * b);
+    LABPSD_HIP(hipMemcpy2DAsync(P.resident_X.p, n * sizeof(double), Z(0), ldz * sizeof(double),
+                                n * sizeof(double), b, hipMemcpyDeviceToDevice, s));
+    P.resident_E = E;
+    P.resident_b = b;
     // outputs
     const hipMemcpyKind kd = out_where == LABPSD_MEM_DEVICE ? hipMemcpyDeviceToDevice
                                                             : hipMemcpyDeviceToHost;
@@ -489,13 +494,40 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     return converged ? LABPSD_OK : LABPSD_NOT_CONVERGED;
 }
 
+labpsd_status run_solve(Problem& P, const labpsd_solve_params& prm, const double* X0,
+                        const double* E0, labpsd_mem in_where, double* lambda, double* X,
+                        double* res_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats,
+                        hipStream_t stream) {
+    if (prm.precision == LABPSD_MIXED)
+        return solve_impl<float>(P, prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where,
+                                 stats, stream);
+    return solve_impl<double>(P, prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where,
+                              stats, stream);
+}
+
+size_t solve_footprint_bytes(int64_t n, int nev, int m0, int precision, int cu_count) {
+    const int b = nev + m0, m = nev, kmax = b + m;
+    const int nblk = residual_blocks(n);
+    size_t gws = 0;
+    for (int k = 1; k <= kmax; ++k) gws = std::max(gws, gram_ws_doubles(n, k, cu_count));
+    const size_t rrb = (rr_ws_bytes(kmax) + 7) / 8;
+    const size_t f64 = 6 * (size_t)n * kmax + (size_t)n * m + 2 * (size_t)kmax * kmax +
+                       (size_t)kmax * b + (size_t)b + 2 * (size_t)m +
+                       std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m) + gws +
+                       2 * (size_t)m + 16 * (size_t)m + 4 + rrb + 64;
+    const size_t tel = 4 * (size_t)n * m + minres_ws_elems(n, m);
+    const size_t tb = precision == LABPSD_MIXED ? 4 : 8;
+    return f64 * 8 + tel * tb + (size_t)n * b * 8 /* resident block */ + (4 * (size_t)m + 8) * 4;
+}
+
+labpsd_status abi_guard(const std::function<labpsd_status()>& f) { return guarded(f); }
+
 }  // namespace labpsd
 
 using namespace labpsd;
 
 // ------------------------------------------------------------------ C ABI
 
-struct labpsd_problem : labpsd::Problem {};
 
 namespace labpsd {
 template <typename T>
@@ -679,11 +711,8 @@ labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* prm, co
         LABPSD_REQUIRE(prm->precision == LABPSD_FP64 || prm->precision == LABPSD_MIXED,
                        "invalid precision");
         LABPSD_HIP(hipSetDevice(p->ctx->device));
-        if (prm->precision == LABPSD_MIXED)
-            return solve_impl<float>(*p, *prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where,
-                                     stats);
-        return solve_impl<double>(*p, *prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where,
-                                  stats);
+        return run_solve(*p, *prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where, stats,
+                         p->ctx->stream);
     });
 }
 

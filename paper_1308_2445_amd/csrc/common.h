@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -142,16 +143,37 @@ struct Problem {
     // solver workspace (kept between solves)
     DBuf<double> ws64;
     DBuf<float> ws32;
-    DBuf<double> red;            // reduction partials
+    DBuf<double> red;            // FP64 preconditioner arena
     DBuf<int32_t> iws;
+    // the last solve's full block (n x b, all Ritz vectors incl. guards) and Ritz
+    // values, kept resident for warm starts of the next GHEP of the sequence
+    DBuf<double> resident_X;
+    std::vector<double> resident_E;
+    int resident_b = 0;
     ~Problem();
 };
+
+}  // namespace labpsd
+
+struct labpsd_problem : labpsd::Problem {};
+
+namespace labpsd {
+
+// Run one LABPSD solve of P on `stream` (the driver of labpsd_solve).
+labpsd_status run_solve(Problem& P, const labpsd_solve_params& prm, const double* X0,
+                        const double* E0, labpsd_mem in_where, double* lambda, double* X,
+                        double* res_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats,
+                        hipStream_t stream);
+// Device bytes one solve reserves beyond the resident problem.
+size_t solve_footprint_bytes(int64_t n, int nev, int m0, int precision, int cu_count);
 
 // ------------------------------------------------------------------ kernel launchers
 // All launchers enqueue on `s` and check the launch.
 
 void build_sell(Sell& S, const HostCSR& A, const double* hv, const double* sv, hipStream_t s);
 void refresh_sell_h(Sell& S, const double* hv, hipStream_t s);
+// the guarded-call wrapper of the C ABI (maps exceptions to status codes)
+labpsd_status abi_guard(const std::function<labpsd_status()>& f);
 
 // YH = H X, YS = S X (FP64)
 void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,

@@ -179,9 +179,11 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int k, const double* __
     }
     double* ph = part + (int64_t)blockIdx.y * 2 * kp * kp;
     double* ps = ph + (int64_t)kp * kp;
+    // accumulator layout of the f64 16x16x4 MFMA on gfx950 (measured): register q of
+    // lane l holds row 4q + l / 16 and column l % 16 of the 16 x 16 tile
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int ii = i0 + ti * 16 + 4 * (lane >> 4) + q;
+        const int ii = i0 + ti * 16 + 4 * q + (lane >> 4);
         const int jj = j0 + tj * 16 + (lane & 15);
         ph[ii + (int64_t)jj * kp] = accH[q];
         ps[ii + (int64_t)jj * kp] = accS[q];
@@ -239,9 +241,10 @@ __global__ __launch_bounds__(256) void k_block_update(int64_t n, int k, int b,
         acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, w0, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, w1, acc1, 0, 0, 0);
     }
+    // accumulator layout (see k_gram): register q of lane l is row 4q + l / 16, column l % 16
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int64_t row = r0 + 4 * (lane >> 4) + q;
+        const int64_t row = r0 + 4 * q + (lane >> 4);
         if (row < n) {
             if (bc0 < b) O[row + (int64_t)bc0 * ldo] = acc0[q];
             if (bc1 < b) O[row + (int64_t)bc1 * ldo] = acc1[q];

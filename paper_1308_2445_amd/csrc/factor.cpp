@@ -513,11 +513,13 @@ int factorize(const HostCSR& A, const double* kval, const double* coords, HostFa
         for (int c : kids[i]) f = std::min(f, first_of[c]);
         first_of[i] = f;
     }
+    const double t_sub0 = wall();
     parallel_for((int64_t)sub_roots.size(), nthreads, [&](int64_t k) {
         std::vector<int32_t> loc(n, -1);
         const int r = sub_roots[k];
         for (int i = first_of[r]; i <= r && fail.load() < 0; ++i) do_node(i, loc, 1);
     });
+    F.t_subtrees = wall() - t_sub0;
     {
         std::vector<int32_t> loc(n, -1);
         for (int i : top_nodes) {

@@ -57,6 +57,7 @@ struct HostFactor {
     double flops = 0.0;
     double t_order = 0.0;
     double t_factor = 0.0;
+    double t_subtrees = 0.0;   // part of t_factor spent in the parallel subtrees
 };
 
 // Factor K (values `kval` on the pattern of A).  Returns 0, or -4 when a pivot is

@@ -56,6 +56,11 @@ class Problem:
     dof_node: np.ndarray     # int64[n] host node of every dof
     dof_atom: np.ndarray     # int64[n] enrichment atom (-1 for standard dofs)
     seed: int
+    k_val: np.ndarray | None = None   # kinetic part 1/2 int grad.grad on the pattern (h_val - k_val is V)
+
+    def h_scaled(self, scale: float) -> np.ndarray:
+        """H values with every potential amplitude multiplied by ``scale``."""
+        return self.k_val + scale * (self.h_val - self.k_val)
 
     @property
     def nnz(self) -> int:
@@ -219,7 +224,7 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
         enodes[:, a] = ((E[:, 0] + o[0]) % ne) + ne * (((E[:, 1] + o[1]) % ne) + ne * ((E[:, 2] + o[2]) % ne))
     enr_elem = nenr_node[enodes].sum(axis=1) > 0
 
-    rows_all, cols_all, hv_all, sv_all = [], [], [], []
+    rows_all, cols_all, hv_all, sv_all, kv_all = [], [], [], [], []
     vmin = np.inf
 
     # ---- standard elements: 3^3 Gauss, 8 trilinear functions
@@ -241,6 +246,7 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
         rows_all.append(np.repeat(dofs, 8, axis=1).ravel())
         cols_all.append(np.tile(dofs, (1, 8)).ravel())
         hv_all.append(Hloc.reshape(-1))
+        kv_all.append(np.broadcast_to(Kref, Hloc.shape).reshape(-1))
         sv_all.append(np.ascontiguousarray(Sloc).reshape(-1))
 
     # ---- enriched elements: 4^3 Gauss, 8 hats plus the enriched functions of their nodes
@@ -291,8 +297,8 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
                 valid[:, slot] = has
                 slot += 1
         wq = w4 * h ** 3
-        Hloc = 0.5 * np.einsum("q,eqfd,eqgd->efg", wq, grad, grad, optimize=True) \
-            + np.einsum("q,eq,eqf,eqg->efg", wq, Vq, phi, phi, optimize=True)
+        Kloc = 0.5 * np.einsum("q,eqfd,eqgd->efg", wq, grad, grad, optimize=True)
+        Hloc = Kloc + np.einsum("q,eq,eqf,eqg->efg", wq, Vq, phi, phi, optimize=True)
         Sloc = np.einsum("q,eqf,eqg->efg", wq, phi, phi, optimize=True)
         vv = valid[:, :, None] & valid[:, None, :]
         R_ = np.repeat(dof[:, :, None], F, axis=2)
@@ -300,12 +306,15 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
         rows_all.append(R_[vv])
         cols_all.append(C_[vv])
         hv_all.append(Hloc[vv])
+        kv_all.append(Kloc[vv])
         sv_all.append(Sloc[vv])
 
     rows = np.concatenate(rows_all)
     cols = np.concatenate(cols_all)
     Hc = sp.coo_matrix((np.concatenate(hv_all), (rows, cols)), shape=(n, n)).tocsr()
     Sc = sp.coo_matrix((np.concatenate(sv_all), (rows, cols)), shape=(n, n)).tocsr()
+    Kc = sp.coo_matrix((np.concatenate(kv_all), (rows, cols)), shape=(n, n)).tocsr()
+    Kc = ((Kc + Kc.T) * 0.5).tocsr()
     # exact symmetry (duplicate summation order may differ between (i,j) and (j,i))
     Hc = ((Hc + Hc.T) * 0.5).tocsr()
     Sc = ((Sc + Sc.T) * 0.5).tocsr()
@@ -314,12 +323,13 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
     pat.sort_indices()
     Hc = _on_pattern(Hc, pat)
     Sc = _on_pattern(Sc, pat)
+    Kc = _on_pattern(Kc, pat)
     if not np.isfinite(vmin):
         vmin = 0.0
     return Problem(n=n, rowptr=pat.indptr.astype(np.int64), col=pat.indices.astype(np.int32),
                    h_val=Hc, s_val=Sc, v_min=vmin, sigma0=vmin - 1.0, eps_bar=vmin - 0.1,
                    L=float(L), ne=int(ne), atoms=atoms, amplitudes=amps, dof_node=dof_node,
-                   dof_atom=dof_atom, seed=int(seed))
+                   dof_atom=dof_atom, seed=int(seed), k_val=Kc)
 
 
 def _on_pattern(A: sp.csr_matrix, pat: sp.csr_matrix) -> np.ndarray:
