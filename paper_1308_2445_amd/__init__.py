@@ -350,6 +350,10 @@ class Served:
     def latency(self) -> float:
         return self.finished - self.submitted
 
+    @property
+    def converged(self) -> bool:
+        return self.status == OK
+
 
 def solve_footprint(n: int, nev: int, m0: int, precision: int = FP64) -> int:
     return int(_lib.labpsd_solve_footprint(n, nev, m0, precision))

@@ -93,7 +93,7 @@ def test_alone_equals_mix(pencils, precision):
 def test_admission_respects_budget(pencils):
     lp = _lp()
     ctx = lp.Context(0)
-    fps = [lp.solve_footprint(P.n, nev, pufe.guard_vectors(nev)) for P, nev in pencils]
+    fps = [lp.solve_footprint(P.n, nev, pufe.guard_vectors(nev), lp.MIXED) for P, nev in pencils]
     budget = int(max(fps) * 1.5)        # at most one big request at a time, sometimes two
     r1, r2 = _run(ctx, pencils, 4, budget, 1)
     rs = r1 + r2
