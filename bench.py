@@ -243,6 +243,9 @@ def main():
                    "n": P.n, "nnz": P.nnz, "nev": nev, "m0": m0, "tol": args.tol, "precision": "fp64"},
         "latency_ms": {"p50": 1e3 * percentile(f["lat"], 50), "p99": 1e3 * percentile(f["lat"], 99)},
         "iterations": f["outs"][0].stats["outer_iters"], "la": f["outs"][0].stats["la"],
+        "rank_dropped": f["outs"][0].stats["rank_dropped"],
+        "device": {"name": torch.cuda.get_device_name(0),
+                   "lds_per_block": getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", None)},
         "steps_ms_per_solve": steps_ms,
         "setup_s": {"generate": t_gen, "factor_total": t_setup, "order": fi["t_order_s"],
                     "factor": fi["t_factor_s"], "upload": fi["t_upload_s"], "nnz_factor": fi["nnz_factor"]},

@@ -144,21 +144,35 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
     F->sn_nrow.upload(nr.data(), nr.size(), s);
     F->sn_idx.upload(ix.data(), ix.size(), s);
     F->sn_val.upload(vl.data(), vl.size(), s);
-    std::vector<int32_t> td, to;
-    F->lev_diag_off.assign(1, 0);
-    F->lev_off_off.assign(1, 0);
+    // task triples per level and product (reduction chunks of 128 columns or rows)
+    constexpr int kTile = 64, kChunk = 128;
+    std::vector<int32_t> tk;
+    F->lev_off.assign(4 * (size_t)F->nlevels, 0);
+    F->lev_count.assign(4 * (size_t)F->nlevels, 0);
     for (int l = 0; l < F->nlevels; ++l) {
-        for (int i = 0; i < F->nsn; ++i) {
-            if (H.sn[i].level != l) continue;
-            const int ncol = H.sn[i].ncol, nb = H.sn[i].nrow - H.sn[i].ncol;
-            for (int t = 0; t * 64 < ncol; ++t) { td.push_back(i); td.push_back(t); }
-            for (int t = 0; t * 64 < nb; ++t) { to.push_back(i); to.push_back(t); }
+        for (int op = 0; op < 4; ++op) {
+            F->lev_off[4 * l + op] = (int64_t)tk.size() / 3;
+            for (int i = 0; i < F->nsn; ++i) {
+                if (H.sn[i].level != l) continue;
+                const int ncol = H.sn[i].ncol, nb = H.sn[i].nrow - H.sn[i].ncol;
+                const int nout = (op == 1) ? nb : ncol;
+                for (int t = 0; t * kTile < nout; ++t) {
+                    int k0 = 0, k1 = 0;
+                    if (op == 0) { k0 = 0; k1 = std::min(ncol, (t + 1) * kTile); }
+                    else if (op == 1) { k0 = 0; k1 = ncol; }
+                    else if (op == 2) { k0 = 0; k1 = nb; }
+                    else { k0 = t * kTile; k1 = ncol; }
+                    for (int kc = k0; kc < k1; kc += kChunk) {
+                        tk.push_back(i);
+                        tk.push_back(t);
+                        tk.push_back(kc);
+                    }
+                }
+            }
+            F->lev_count[4 * l + op] = (int64_t)tk.size() / 3 - F->lev_off[4 * l + op];
         }
-        F->lev_diag_off.push_back((int64_t)td.size() / 2);
-        F->lev_off_off.push_back((int64_t)to.size() / 2);
     }
-    F->task_diag.upload(td.data(), td.size(), s);
-    F->task_offd.upload(to.data(), to.size(), s);
+    F->tasks.upload(tk.data(), tk.size(), s);
     LABPSD_HIP(hipStreamSynchronize(s));
     F->info.n_supernodes = F->nsn;
     F->info.n_levels = F->nlevels;

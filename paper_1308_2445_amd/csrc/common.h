@@ -100,11 +100,11 @@ struct DevFactor {
     // per-supernode metadata: ncol, nrow, idx_off, val_off
     DBuf<int32_t> sn_ncol, sn_nrow;
     DBuf<int64_t> sn_idx, sn_val;
-    // per level task lists of (supernode, 64-row tile) pairs: tiles of D serve the
-    // diagonal-block products and the backward gather, tiles of B the forward update
-    std::vector<int64_t> lev_diag_off, lev_off_off;   // offsets into the task arrays
-    DBuf<int32_t> task_diag;     // pairs (sn, tile) over D rows
-    DBuf<int32_t> task_offd;     // pairs (sn, tile) over B rows
+    // task triples (supernode, 64-row output tile, reduction chunk start) grouped per
+    // level and per product: [level][op] with op 0 diag, 1 off-diag (forward),
+    // 2 off-diag transposed, 3 diag transposed (backward)
+    std::vector<int64_t> lev_off, lev_count;   // 4 * nlevels each
+    DBuf<int32_t> tasks;
     labpsd_factor_info info{};
 };
 

@@ -199,11 +199,24 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int k, int kp, int nchunk,
     if (idx >= (int64_t)k * k) return;
     const int i = (int)(idx % k), j = (int)(idx / k);
     if (i > j) return;
-    double h = 0.0, s = 0.0;
-    for (int c = 0; c < nchunk; ++c) {
-        h += part[((int64_t)c * 2 + 0) * kp * kp + i + (int64_t)j * kp];
-        s += part[((int64_t)c * 2 + 1) * kp * kp + i + (int64_t)j * kp];
+    // eight independent partial sums keep several loads in flight
+    double h8[8] = {0, 0, 0, 0, 0, 0, 0, 0}, s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t stride = (int64_t)kp * kp, off = i + (int64_t)j * kp;
+    int c = 0;
+    for (; c + 8 <= nchunk; c += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            h8[u] += part[((int64_t)(c + u) * 2 + 0) * stride + off];
+            s8[u] += part[((int64_t)(c + u) * 2 + 1) * stride + off];
+        }
     }
+    for (; c < nchunk; ++c) {
+        h8[0] += part[((int64_t)c * 2 + 0) * stride + off];
+        s8[0] += part[((int64_t)c * 2 + 1) * stride + off];
+    }
+    double h = 0.0, s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) { h += h8[u]; s += s8[u]; }
     HR[i + (int64_t)j * ldr] = h;
     HR[j + (int64_t)i * ldr] = h;
     SR[i + (int64_t)j * ldr] = s;

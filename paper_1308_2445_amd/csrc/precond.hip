@@ -12,8 +12,12 @@
 //                      x[D] <- inv(L11)^T z[D]        (diag kernel)
 // The permutation is folded into the row lists (dof ids), so every block is read and
 // written in the caller's ordering.  Work-group tile: 64 output rows x 16 right-hand
-// sides; the reduction dimension is staged through LDS 32 at a time.  T is double
-// (FP64 mode) or float (mixed mode: FP32 panels, FP32 accumulation).
+// sides x one 128-wide chunk of the reduction dimension (staged through LDS 32 at a
+// time); chunks of one output tile accumulate with atomics, so the large separators at
+// the top of the tree spread over many work-groups.  Outputs are zeroed (or seeded)
+// first.  T is double (FP64 mode) or float (mixed mode: FP32 panels, FP32 accumulation).
+#include <algorithm>
+
 #include "common.h"
 
 namespace labpsd {
@@ -22,15 +26,17 @@ namespace {
 
 constexpr int TR = 64;   // output rows per work-group
 constexpr int TC = 16;   // right-hand sides per work-group
-constexpr int TK = 32;   // reduction chunk
+constexpr int TK = 32;   // reduction staging depth
+constexpr int KS = 128;  // reduction chunk per work-group
 
 enum { OP_DIAG = 0, OP_DIAG_T = 1, OP_OFFD = 2, OP_OFFD_T = 3 };
 
-// Generic tiled product for one task (supernode sn, output tile) of a level.
-//  OP_DIAG   out[D[r]] = sum_{k<=r} inv(L11)[r,k] in[D[k]]             (assign)
-//  OP_DIAG_T out[D[r]] = sum_{k>=r} inv(L11)[k,r] in[D[k]]             (assign)
-//  OP_OFFD   out[B[r]] -= sum_k L21[r,k] in[D[k]]                        (atomic)
-//  OP_OFFD_T out[D[r]] = base[D[r]] - sum_k L21[k,r] in[B[k]]            (assign)
+// Tiled product for one task (supernode sn, output tile, reduction chunk) of a level;
+// every op accumulates atomically into its output:
+//  OP_DIAG   out[D[r]] += sum_{k<=r} inv(L11)[r,k] in[D[k]]
+//  OP_DIAG_T out[D[r]] += sum_{k>=r} inv(L11)[k,r] in[D[k]]
+//  OP_OFFD   out[B[r]] -= sum_k L21[r,k] in[D[k]]
+//  OP_OFFD_T out[D[r]] -= sum_k L21[k,r] in[B[k]]
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void k_sn_product(const int32_t* __restrict__ tasks,
                                                     const int32_t* __restrict__ sn_ncol,
@@ -40,10 +46,10 @@ __global__ __launch_bounds__(256) void k_sn_product(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ rows,
                                                     const T* __restrict__ panels,
                                                     const T* __restrict__ in, T* __restrict__ out,
-                                                    const T* __restrict__ base, int64_t ld,
-                                                    int nrhs) {
-    const int sn = tasks[2 * blockIdx.x];
-    const int tile = tasks[2 * blockIdx.x + 1];
+                                                    int64_t ld, int nrhs) {
+    const int sn = tasks[3 * blockIdx.x];
+    const int tile = tasks[3 * blockIdx.x + 1];
+    const int kc = tasks[3 * blockIdx.x + 2];
     const int ncol = sn_ncol[sn], nrow = sn_nrow[sn];
     const int nb = nrow - ncol;
     const int32_t* rl = rows + sn_idx[sn];
@@ -60,7 +66,9 @@ __global__ __launch_bounds__(256) void k_sn_product(const int32_t* __restrict__ 
     // reduction range (triangular blocks skip the zero half)
     int k_begin = 0, k_end = nred;
     if (OP == OP_DIAG) k_end = min(nred, r0 + TR);
-    if (OP == OP_DIAG_T) k_begin = (r0 / TK) * TK;
+    if (OP == OP_DIAG_T) k_begin = r0;
+    k_begin = max(k_begin, kc);
+    k_end = min(k_end, kc + KS);
 
     __shared__ T sM[TK][TR + 1];      // sM[k][r] = M(r, k)
     __shared__ T sX[TK][TC];          // sX[k][c] = in[row(k), c0 + c]
@@ -115,33 +123,37 @@ __global__ __launch_bounds__(256) void k_sn_product(const int32_t* __restrict__ 
     }
     const int r = r0 + orow;
     if (r >= nout) return;
-    if (OP == OP_OFFD) {
-        const int64_t g = rl[ncol + r];
+    const int64_t g = (OP == OP_OFFD) ? rl[ncol + r] : rl[r];
+    const bool sub = (OP == OP_OFFD || OP == OP_OFFD_T);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (cq + q < nc) atomicAdd(&out[g + (int64_t)(c0 + cq + q) * ld], -acc[q]);
-    } else {
-        const int64_t g = rl[r];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (cq + q < nc) {
-                const int64_t o = g + (int64_t)(c0 + cq + q) * ld;
-                out[o] = (OP == OP_OFFD_T) ? base[o] - acc[q] : acc[q];
-            }
-        }
-    }
+    for (int q = 0; q < 4; ++q)
+        if (cq + q < nc) atomicAdd(&out[g + (int64_t)(c0 + cq + q) * ld], sub ? -acc[q] : acc[q]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_copy(int64_t count, T* __restrict__ dst,
+                                                   const T* __restrict__ src) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+        dst[i] = src ? src[i] : T(0);
+}
+
+template <typename T>
+void fill_copy(T* dst, const T* src, int64_t count, hipStream_t s) {
+    if (count <= 0) return;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 2048);
+    hipLaunchKernelGGL((k_fill_copy<T>), dim3((unsigned)blocks), dim3(256), 0, s, count, dst, src);
+    LABPSD_HIP(hipGetLastError());
 }
 
 template <typename T, int OP>
 void launch_level(const DevFactor& F, const int32_t* tasks, int64_t ntasks, const T* panels,
-                  const T* in, T* out, const T* base, int64_t ld, int nrhs, hipStream_t s) {
+                  const T* in, T* out, int64_t ld, int nrhs, hipStream_t s) {
     if (ntasks <= 0 || nrhs <= 0) return;
-    LABPSD_REQUIRE(tasks != nullptr && panels != nullptr && in != nullptr && out != nullptr &&
-                       (OP != OP_OFFD_T || base != nullptr),
+    LABPSD_REQUIRE(tasks != nullptr && panels != nullptr && in != nullptr && out != nullptr,
                    "supernodal product launched without its task list or buffers");
     dim3 grid((unsigned)ntasks, (unsigned)((nrhs + TC - 1) / TC));
     hipLaunchKernelGGL((k_sn_product<T, OP>), grid, dim3(256), 0, s, tasks, F.sn_ncol.p, F.sn_nrow.p,
-                       F.sn_idx.p, F.sn_val.p, F.rows.p, panels, in, out, base, ld, nrhs);
+                       F.sn_idx.p, F.sn_val.p, F.rows.p, panels, in, out, ld, nrhs);
     LABPSD_HIP(hipGetLastError());
 }
 
@@ -155,21 +167,23 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t ld, in
     if constexpr (sizeof(T) == 8) panels = F.panels64.p;
     else panels = F.panels32.p;
     const int L = F.nlevels;
+    const int64_t nb = ld * ncols;
+    fill_copy<T>(W1, nullptr, nb, s);
+    fill_copy<T>(W2, nullptr, nb, s);
     for (int l = 0; l < L; ++l) {
-        const int64_t d0 = F.lev_diag_off[l], d1 = F.lev_diag_off[l + 1];
-        const int64_t o0 = F.lev_off_off[l], o1 = F.lev_off_off[l + 1];
-        launch_level<T, OP_DIAG>(F, F.task_diag.p + 2 * d0, d1 - d0, panels, Y, W1, nullptr, ld,
+        const int64_t* o = &F.lev_off[4 * l];
+        launch_level<T, OP_DIAG>(F, F.tasks.p + 3 * o[0], F.lev_count[4 * l + 0], panels, Y, W1, ld,
                                  ncols, s);
-        launch_level<T, OP_OFFD>(F, F.task_offd.p + 2 * o0, o1 - o0, panels, W1, Y, nullptr, ld,
+        launch_level<T, OP_OFFD>(F, F.tasks.p + 3 * o[1], F.lev_count[4 * l + 1], panels, W1, Y, ld,
                                  ncols, s);
     }
+    // z = y - L21^T x accumulates into a copy of the forward solution, held in Y
+    fill_copy<T>(Y, W1, nb, s);
     for (int l = L - 1; l >= 0; --l) {
-        const int64_t d0 = F.lev_diag_off[l], d1 = F.lev_diag_off[l + 1];
-        // z[D] = W1[D] - L21^T W2[B] over the D tiles, written into Y (free after the
-        // forward sweep)
-        launch_level<T, OP_OFFD_T>(F, F.task_diag.p + 2 * d0, d1 - d0, panels, W2, Y, W1, ld,
+        const int64_t* o = &F.lev_off[4 * l];
+        launch_level<T, OP_OFFD_T>(F, F.tasks.p + 3 * o[2], F.lev_count[4 * l + 2], panels, W2, Y, ld,
                                    ncols, s);
-        launch_level<T, OP_DIAG_T>(F, F.task_diag.p + 2 * d0, d1 - d0, panels, Y, W2, nullptr, ld,
+        launch_level<T, OP_DIAG_T>(F, F.tasks.p + 3 * o[3], F.lev_count[4 * l + 3], panels, Y, W2, ld,
                                    ncols, s);
     }
 }

@@ -51,6 +51,7 @@ __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off
 #pragma unroll
     for (int j = 0; j < CW; ++j) { ah[j] = 0.0; as[j] = 0.0; }
     const double* Xj = X + (int64_t)j0 * ldx;
+#pragma unroll 2
     for (int64_t e = e0 + lane; e < e1; e += kSlice) {
         const int64_t c = col[e];
         const double h = hv[e], s = sv[e];
@@ -97,6 +98,7 @@ __global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ 
 #pragma unroll
     for (int j = 0; j < CW; ++j) { ah[j] = T(0); as[j] = T(0); }
     const T* Xj = X + (int64_t)j0 * ldx;
+#pragma unroll 2
     for (int64_t e = e0 + lane; e < e1; e += kSlice) {
         const int64_t c = col[e];
         const T h = hv[e], s = sv[e];
@@ -182,21 +184,39 @@ void refresh_sell_h(Sell& S, const double* hv, hipStream_t s) {
     LABPSD_HIP(hipStreamSynchronize(s));
 }
 
-void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
-                    int64_t ldy, hipStream_t s) {
-    if (w <= 0 || A.n == 0) return;
-    constexpr int CW = 8;
+// Column-chunk width: the widest of 8, 4, 2 that still gives the launch enough
+// wavefronts (slices x chunks) to hide the gathers' latency; wider chunks re-read the
+// pattern fewer times.
+static int chunk_width(int64_t nslices, int w) {
+    constexpr int64_t kWantWaves = 4096;
+    for (int cw : {8, 4}) {
+        if (nslices * ((w + cw - 1) / cw) >= kWantWaves) return cw;
+    }
+    return 2;
+}
+
+template <int CW>
+static void spmm_hs_cw(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
+                       int64_t ldy, hipStream_t s) {
     dim3 grid((unsigned)((A.nslices + kWaves - 1) / kWaves), (unsigned)((w + CW - 1) / CW));
     hipLaunchKernelGGL(k_spmm_hs<CW>, grid, dim3(256), 0, s, A.slice_off.p, A.col.p, A.hv.p,
                        A.sv.p, A.n, A.nslices, X, ldx, w, YH, YS, ldy);
     LABPSD_HIP(hipGetLastError());
 }
 
-template <typename T>
-void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
-                       int64_t ldy, hipStream_t s) {
+void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
+                    int64_t ldy, hipStream_t s) {
     if (w <= 0 || A.n == 0) return;
-    constexpr int CW = 8;
+    switch (chunk_width(A.nslices, w)) {
+        case 8: spmm_hs_cw<8>(A, X, ldx, w, YH, YS, ldy, s); break;
+        case 4: spmm_hs_cw<4>(A, X, ldx, w, YH, YS, ldy, s); break;
+        default: spmm_hs_cw<2>(A, X, ldx, w, YH, YS, ldy, s); break;
+    }
+}
+
+template <typename T, int CW>
+static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
+                          int64_t ldy, hipStream_t s) {
     dim3 grid((unsigned)((A.nslices + kWaves - 1) / kWaves), (unsigned)((w + CW - 1) / CW));
     const T* hv;
     const T* sv;
@@ -210,6 +230,17 @@ void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const doub
     hipLaunchKernelGGL((k_spmm_shift<T, CW>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, hv, sv,
                        A.n, A.nslices, X, ldx, w, shift, Y, ldy);
     LABPSD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
+                       int64_t ldy, hipStream_t s) {
+    if (w <= 0 || A.n == 0) return;
+    switch (chunk_width(A.nslices, w)) {
+        case 8: spmm_shift_cw<T, 8>(A, X, ldx, w, shift, Y, ldy, s); break;
+        case 4: spmm_shift_cw<T, 4>(A, X, ldx, w, shift, Y, ldy, s); break;
+        default: spmm_shift_cw<T, 2>(A, X, ldx, w, shift, Y, ldy, s); break;
+    }
 }
 
 template void launch_spmm_shift<double>(const Sell&, const double*, int64_t, int, const double*,
