@@ -132,29 +132,19 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
         F->panels32.upload(p32.data(), p32.size(), s);
         LABPSD_HIP(hipStreamSynchronize(s));
     }
-    std::vector<int32_t> nc(F->nsn), nr(F->nsn);
-    std::vector<int64_t> ix(F->nsn), vl(F->nsn);
-    for (int i = 0; i < F->nsn; ++i) {
-        nc[i] = H.sn[i].ncol;
-        nr[i] = H.sn[i].nrow;
-        ix[i] = H.sn[i].idx_off;
-        vl[i] = H.sn[i].val_off;
-    }
-    F->sn_ncol.upload(nc.data(), nc.size(), s);
-    F->sn_nrow.upload(nr.data(), nr.size(), s);
-    F->sn_idx.upload(ix.data(), ix.size(), s);
-    F->sn_val.upload(vl.data(), vl.size(), s);
-    // task triples per level and product (reduction chunks of 128 columns or rows)
-    constexpr int kTile = 64, kChunk = 128;
-    std::vector<int32_t> tk;
+    // tasks per level and product: 64-row output tiles x 64-wide reduction chunks
+    // (triangular products skip the chunks above or below the diagonal tile)
+    constexpr int kTile = 64, kChunk = 64;
+    std::vector<SnTask> tk;
     F->lev_off.assign(4 * (size_t)F->nlevels, 0);
     F->lev_count.assign(4 * (size_t)F->nlevels, 0);
     for (int l = 0; l < F->nlevels; ++l) {
         for (int op = 0; op < 4; ++op) {
-            F->lev_off[4 * l + op] = (int64_t)tk.size() / 3;
+            F->lev_off[4 * l + op] = (int64_t)tk.size();
             for (int i = 0; i < F->nsn; ++i) {
-                if (H.sn[i].level != l) continue;
-                const int ncol = H.sn[i].ncol, nb = H.sn[i].nrow - H.sn[i].ncol;
+                const Supernode& sn = H.sn[i];
+                if (sn.level != l) continue;
+                const int ncol = sn.ncol, nb = sn.nrow - sn.ncol;
                 const int nout = (op == 1) ? nb : ncol;
                 for (int t = 0; t * kTile < nout; ++t) {
                     int k0 = 0, k1 = 0;
@@ -162,14 +152,11 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
                     else if (op == 1) { k0 = 0; k1 = ncol; }
                     else if (op == 2) { k0 = 0; k1 = nb; }
                     else { k0 = t * kTile; k1 = ncol; }
-                    for (int kc = k0; kc < k1; kc += kChunk) {
-                        tk.push_back(i);
-                        tk.push_back(t);
-                        tk.push_back(kc);
-                    }
+                    for (int kc = k0; kc < k1; kc += kChunk)
+                        tk.push_back(SnTask{sn.idx_off, sn.val_off, ncol, sn.nrow, t * kTile, kc});
                 }
             }
-            F->lev_count[4 * l + op] = (int64_t)tk.size() / 3 - F->lev_off[4 * l + op];
+            F->lev_count[4 * l + op] = (int64_t)tk.size() - F->lev_off[4 * l + op];
         }
     }
     F->tasks.upload(tk.data(), tk.size(), s);
@@ -234,7 +221,7 @@ static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T
     size_t need = 6 * (size_t)n * kmax + (size_t)n * m + 2 * (size_t)kmax * kmax +
                   (size_t)kmax * b + (size_t)b + 2 * (size_t)m +
                   std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m) + gws + 2 * (size_t)m +
-                  16 * (size_t)m + 4 + rrb + 64;
+                  minres_scal_doubles(m) + 4 + rrb + 64;
     P.ws64.alloc(need);
     double* p = P.ws64.p;
     for (int a = 0; a < 2; ++a)
@@ -250,7 +237,7 @@ static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T
     B.gram_ws = p; p += gws;
     B.shifts = p; p += m;
     B.stopn = p; p += m;
-    B.scal = p; p += 16 * (size_t)m + 4;
+    B.scal = p; p += minres_scal_doubles(m) + 4;
     B.rr_ws = (void*)p; p += rrb;
     // T-precision blocks
     const size_t mw = minres_ws_elems(n, m);
@@ -429,8 +416,9 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             LABPSD_HIP(hipMemcpyAsync(B.stopn, stopn.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
         }
         // 6(a): P = -K^{-1} R_U in the preconditioner precision
+        // (the preconditioner works on row-major blocks: -R_U is cast into Y row-major)
         tm.begin(S_CAST);
-        launch_gather_cast<double, T>(n, p, B.R, n, B.cols, -1.0, Wt.Y, n, s);
+        launch_cast_to_rm<double, T>(n, p, B.R, n, B.cols, -1.0, Wt.Y, s);
         if (q) launch_gather_cast<double, T>(n, p, B.R, n, B.cols, 1.0, Wt.RT, n, s);
         tm.end();
         st.n_launch[S_CAST] += q ? 2 : 1;
@@ -440,13 +428,19 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         tm.end();
         st.n_launch[S_GLOBAL] += 1;
         st.n_cols[S_GLOBAL] += p;
-        // 6(b): MINRES refinement of the localised columns
+        // 6(b): MINRES refinement of the localised columns (column-major copy in W1, which
+        // the preconditioner no longer needs)
         if (q) {
+            tm.begin(S_CAST);
+            launch_cast_from_rm<T, T>(n, p, Wt.W2, 1.0, Wt.W1, n, s);
+            tm.end();
+            st.n_launch[S_CAST] += 1;
+            st.n_cols[S_CAST] += p;
             if (lp.mode == LABPSD_LOCAL_ONLY)
-                launch_scatter_cast<T, T>(n, q, Wt.W2, n, B.loc, 0.0, Wt.W2, n, s);
+                launch_scatter_cast<T, T>(n, q, Wt.W1, n, B.loc, 0.0, Wt.W1, n, s);
             tm.begin(S_LOCAL);
             int64_t nl = 0;
-            run_minres<T>(P.sell, Wt.W2, n, Wt.RT, n, q, B.loc, B.shifts, B.stopn, lp.eta,
+            run_minres<T>(P.sell, Wt.W1, n, Wt.RT, n, q, B.loc, B.shifts, B.stopn, lp.eta,
                           lp.max_inner, B.its, Wt.mres, B.scal, h_int.p + 4, s, &nl);
             tm.end();
             st.n_launch[S_LOCAL] += nl;
@@ -458,7 +452,8 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         }
         // P into the search-space block, FP64
         tm.begin(S_CAST);
-        launch_gather_cast<T, double>(n, p, Wt.W2, n, nullptr, 1.0, Z(0) + (size_t)b * ldz, ldz, s);
+        if (q) launch_gather_cast<T, double>(n, p, Wt.W1, n, nullptr, 1.0, Z(0) + (size_t)b * ldz, ldz, s);
+        else launch_cast_from_rm<T, double>(n, p, Wt.W2, 1.0, Z(0) + (size_t)b * ldz, ldz, s);
         tm.end();
         st.n_launch[S_CAST] += 1;
         st.n_cols[S_CAST] += p;
@@ -528,7 +523,7 @@ size_t solve_footprint_bytes(int64_t n, int nev, int m0, int precision, int cu_c
     const size_t f64 = 6 * (size_t)n * kmax + (size_t)n * m + 2 * (size_t)kmax * kmax +
                        (size_t)kmax * b + (size_t)b + 2 * (size_t)m +
                        std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m) + gws +
-                       2 * (size_t)m + 16 * (size_t)m + 4 + rrb + 64;
+                       2 * (size_t)m + minres_scal_doubles(m) + 4 + rrb + 64;
     const size_t tel = 4 * (size_t)n * m + minres_ws_elems(n, m);
     const size_t tb = precision == LABPSD_MIXED ? 4 : 8;
     return f64 * 8 + tel * tb + (size_t)n * b * 8 /* resident block */ + (4 * (size_t)m + 8) * 4;
@@ -556,10 +551,10 @@ static void local_refine_impl(Problem* p, DBuf<T>& arena, const double* R, int64
     T* RT = PT + (size_t)n * q;
     T* mws = RT + (size_t)n * q;
     const int nblk = residual_blocks(n);
-    p->ctx->scratch.alloc((size_t)nblk * q + 16 * (size_t)q + 8 + q);
+    p->ctx->scratch.alloc((size_t)nblk * q + minres_scal_doubles(q) + 8 + q);
     double* part = p->ctx->scratch.p;
     double* scal = part + (size_t)nblk * q;
-    double* rn = scal + 16 * (size_t)q + 4;
+    double* rn = scal + minres_scal_doubles(q) + 4;
     p->iws.alloc((size_t)q + 8);
     int32_t* iota = p->iws.p;
     std::vector<int32_t> h(q);
@@ -784,15 +779,15 @@ labpsd_status labpsd_precond_apply(labpsd_problem* p, int precision, const doubl
         if (precision == LABPSD_MIXED) {
             p->ws32.alloc(3 * (size_t)n * ncols);
             float* Y = p->ws32.p;
-            launch_gather_cast<double, float>(n, ncols, R, ldr, nullptr, -1.0, Y, n, s);
+            launch_cast_to_rm<double, float>(n, ncols, R, ldr, nullptr, -1.0, Y, s);
             launch_precond_solve<float>(*p->factor, Y, Y + n * ncols, Y + 2 * n * ncols, n, ncols, s);
-            launch_gather_cast<float, double>(n, ncols, Y + 2 * n * ncols, n, nullptr, 1.0, Pout, ldp, s);
+            launch_cast_from_rm<float, double>(n, ncols, Y + 2 * n * ncols, 1.0, Pout, ldp, s);
         } else if (precision == LABPSD_FP64) {
             p->red.alloc(3 * (size_t)n * ncols);
             double* Y = p->red.p;
-            launch_gather_cast<double, double>(n, ncols, R, ldr, nullptr, -1.0, Y, n, s);
+            launch_cast_to_rm<double, double>(n, ncols, R, ldr, nullptr, -1.0, Y, s);
             launch_precond_solve<double>(*p->factor, Y, Y + n * ncols, Y + 2 * n * ncols, n, ncols, s);
-            launch_gather_cast<double, double>(n, ncols, Y + 2 * n * ncols, n, nullptr, 1.0, Pout, ldp, s);
+            launch_cast_from_rm<double, double>(n, ncols, Y + 2 * n * ncols, 1.0, Pout, ldp, s);
         } else {
             throw Error{LABPSD_EINVAL, "invalid precision"};
         }

@@ -75,6 +75,58 @@ struct DBuf {
 // loads of col/values across a wavefront are contiguous.
 constexpr int kSlice = 64;
 
+// Map a linear work-group index to a slice-block index so that each XCD (work-groups
+// are dealt round-robin to the 8 XCDs) receives a contiguous range of slice blocks, and
+// neighbouring rows' gathers hit the same L2.  A bijection on [0, nblocks).
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
+    constexpr int kXcd = 8;
+    if (nblocks < 2 * kXcd) return bid;
+    const int64_t per = nblocks / kXcd, rem = nblocks % kXcd;
+    const int64_t xcd = bid % kXcd, idx = bid / kXcd;
+    // XCDs 0..rem-1 own per+1 blocks, the rest own per
+    const int64_t start = xcd * per + (xcd < rem ? xcd : rem);
+    const int64_t own = per + (xcd < rem ? 1 : 0);
+    if (idx < own) return start + idx;
+    return bid;  // unreachable for bid < nblocks; kept total
+}
+
+// Launch shape of the sliced-ELL kernels: CW right-hand-side columns per wavefront and
+// WPS wavefronts per slice (the slice's slots are dealt round-robin to them, which
+// shortens each wavefront's chain of dependent gathers when there are few slices or
+// few columns).  A 256-thread work-group covers 4 / WPS slices.
+struct SellShape {
+    int cw;
+    int wps;
+};
+SellShape sell_shape(int64_t nslices, int w, int max_cw);
+
+// Sum the per-lane accumulators of the WPS wavefronts that share a slice; the sums are
+// valid in the slice's first wavefront.  red: LDS of 256 * 2 * CW elements.  Every
+// thread of the work-group must call it.
+template <typename T, int CW, int WPS>
+__device__ __forceinline__ void slice_reduce(T (&ah)[CW], T (&as)[CW], T* red) {
+    if constexpr (WPS > 1) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, sw = wave % WPS;
+        if (sw != 0) {
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                red[(wave * 2 * CW + j) * 64 + lane] = ah[j];
+                red[(wave * 2 * CW + CW + j) * 64 + lane] = as[j];
+            }
+        }
+        __syncthreads();
+        if (sw == 0) {
+#pragma unroll
+            for (int w = 1; w < WPS; ++w)
+#pragma unroll
+                for (int j = 0; j < CW; ++j) {
+                    ah[j] += red[((wave + w) * 2 * CW + j) * 64 + lane];
+                    as[j] += red[((wave + w) * 2 * CW + CW + j) * 64 + lane];
+                }
+        }
+    }
+}
+
 struct Sell {
     int64_t n = 0;
     int64_t nslices = 0;
@@ -89,6 +141,19 @@ struct Sell {
 
 // ------------------------------------------------------------------ device factor
 
+// One work-group task of the supernodal apply: a 64-row output tile of one supernode's
+// product and one 64-wide chunk of its reduction dimension, with the supernode's
+// metadata folded in so a work-group needs a single (scalar) load to start.
+struct SnTask {
+    int64_t idx_off;   // offset of the supernode's row list in DevFactor::rows
+    int64_t val_off;   // offset of its panel [inv(L11) ; L21] (ld nrow)
+    int32_t ncol;      // |D|
+    int32_t nrow;      // |D| + |B|
+    int32_t r0;        // first output row of the tile
+    int32_t k0;        // first reduction index of the chunk
+};
+static_assert(sizeof(SnTask) == 32, "SnTask is two 16-byte words");
+
 struct DevFactor {
     int64_t n = 0;
     int nsn = 0;
@@ -97,14 +162,10 @@ struct DevFactor {
     DBuf<int32_t> rows;          // row lists (dof ids)
     DBuf<double> panels64;
     DBuf<float> panels32;
-    // per-supernode metadata: ncol, nrow, idx_off, val_off
-    DBuf<int32_t> sn_ncol, sn_nrow;
-    DBuf<int64_t> sn_idx, sn_val;
-    // task triples (supernode, 64-row output tile, reduction chunk start) grouped per
-    // level and per product: [level][op] with op 0 diag, 1 off-diag (forward),
-    // 2 off-diag transposed, 3 diag transposed (backward)
+    // work-group tasks grouped per level and per product: [level][op] with op 0 diag,
+    // 1 off-diag (forward), 2 off-diag transposed, 3 diag transposed (backward)
     std::vector<int64_t> lev_off, lev_count;   // 4 * nlevels each
-    DBuf<int32_t> tasks;
+    DBuf<SnTask> tasks;
     labpsd_factor_info info{};
 };
 
@@ -209,6 +270,15 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
                           hipStream_t s);
 
 // Gathers / casts
+// row-major blocks (the ncols values of a row contiguous) for the global preconditioner:
+// dst[i * ncols + j] = (TD) src[i + cols[j] * lds] * scale  (cols may be null: identity)
+template <typename TS, typename TD>
+void launch_cast_to_rm(int64_t n, int ncols, const TS* src, int64_t lds, const int32_t* cols,
+                       double scale, TD* dst, hipStream_t s);
+// dst[i + j * ldd] = (TD) src[i * ncols + j] * scale
+template <typename TS, typename TD>
+void launch_cast_from_rm(int64_t n, int ncols, const TS* src, double scale, TD* dst, int64_t ldd,
+                         hipStream_t s);
 // dst[:, j] = (T) src[:, cols[j]] * scale  (cols may be null: identity)
 template <typename TS, typename TD>
 void launch_gather_cast(int64_t n, int ncols, const TS* src, int64_t lds, const int32_t* cols,
@@ -223,17 +293,18 @@ template <typename T>
 void launch_colnorms(int64_t n, int q, const T* src, int64_t ld, const int32_t* cols,
                      double* partial, double* out, hipStream_t s);
 
-// Global preconditioner: W2 := K^{-1} Y for n x ncols blocks (ld ld) of precision T;
-// Y is consumed, W1 is scratch
+// Global preconditioner: W2 := K^{-1} Y for n x ncols row-major blocks (element (i, j)
+// at i * ncols + j) of precision T; Y is consumed, W1 is scratch
 template <typename T>
-void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t ld, int ncols,
+void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int ncols,
                           hipStream_t s);
 
 // MINRES batched refinement (T = double or float). P (n x *, ld ldp) in precision T is
 // refined in place on the columns cols[0..q), with the residual columns R[:, cols[j]] in
 // precision T, shifts shift[j] and stopping norms eta * rnorm[j].  ws holds
-// minres_ws_elems(n, q) elements of T, scal_ws 16 * q + 2 doubles.
+// minres_ws_elems(n, q) elements of T, scal_ws minres_scal_doubles(q) doubles.
 size_t minres_ws_elems(int64_t n, int q);
+size_t minres_scal_doubles(int q);
 template <typename T>
 void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q,
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,

@@ -98,6 +98,49 @@ __global__ __launch_bounds__(256) void k_scatter_cast(int64_t n, const TS* __res
         b[i] = (TD)((double)a[i] * scale);
 }
 
+// Column-major <-> row-major casts through a 64-row x 32-column LDS tile, so both the
+// column-major side (rows contiguous) and the row-major side (the ncols values of a
+// row contiguous) are read and written in whole cache lines.
+// to_rm:   dst[i * ncols + j] = (TD) src[i + cols[j] * lds] * scale  (cols may be null)
+// to_cm:   dst[i + j * ldd]   = (TD) src[i * ncols + j] * scale
+template <typename TS, typename TD, bool TO_RM>
+__global__ __launch_bounds__(256) void k_transpose_cast(int64_t n, int ncols, const TS* __restrict__ src,
+                                                        int64_t lds, const int32_t* __restrict__ cols,
+                                                        double scale, TD* __restrict__ dst, int64_t ldd) {
+    __shared__ double tile[32][65];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 32;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int ii, jj;
+        if (TO_RM) { ii = t % 64; jj = t / 64 + 4 * k; }    // column-major read
+        else { jj = t % 32; ii = t / 32 + 8 * k; }          // row-major read
+        const int64_t i = i0 + ii;
+        const int j = j0 + jj;
+        double v = 0.0;
+        if (i < n && j < ncols) {
+            if (TO_RM) v = (double)src[i + (int64_t)(cols ? cols[j] : j) * lds];
+            else v = (double)src[i * ncols + j];
+        }
+        tile[jj][ii] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int ii, jj;
+        if (TO_RM) { jj = t % 32; ii = t / 32 + 8 * k; }    // row-major write
+        else { ii = t % 64; jj = t / 64 + 4 * k; }          // column-major write
+        const int64_t i = i0 + ii;
+        const int j = j0 + jj;
+        if (i < n && j < ncols) {
+            const TD v = (TD)(tile[jj][ii] * scale);
+            if (TO_RM) dst[i * ncols + j] = v;
+            else dst[i + (int64_t)j * ldd] = v;
+        }
+    }
+}
+
 // partial sums of squares of the columns cols[j] (or j) per block of rows
 template <typename T>
 __global__ __launch_bounds__(256) void k_colnorm_partial(int64_t n, const T* __restrict__ src,
@@ -308,6 +351,37 @@ template void launch_gather_cast<float, double>(int64_t, int, const float*, int6
 template void launch_gather_cast<float, float>(int64_t, int, const float*, int64_t,
                                                const int32_t*, double, float*, int64_t,
                                                hipStream_t);
+
+template <typename TS, typename TD>
+void launch_cast_to_rm(int64_t n, int ncols, const TS* src, int64_t lds, const int32_t* cols,
+                       double scale, TD* dst, hipStream_t s) {
+    if (ncols <= 0 || n <= 0) return;
+    const dim3 g((unsigned)((n + 63) / 64), (unsigned)((ncols + 31) / 32));
+    hipLaunchKernelGGL((k_transpose_cast<TS, TD, true>), g, dim3(256), 0, s, n, ncols, src, lds, cols,
+                       scale, dst, (int64_t)0);
+    LABPSD_HIP(hipGetLastError());
+}
+
+template <typename TS, typename TD>
+void launch_cast_from_rm(int64_t n, int ncols, const TS* src, double scale, TD* dst, int64_t ldd,
+                         hipStream_t s) {
+    if (ncols <= 0 || n <= 0) return;
+    const dim3 g((unsigned)((n + 63) / 64), (unsigned)((ncols + 31) / 32));
+    hipLaunchKernelGGL((k_transpose_cast<TS, TD, false>), g, dim3(256), 0, s, n, ncols, src, (int64_t)0,
+                       (const int32_t*)nullptr, scale, dst, ldd);
+    LABPSD_HIP(hipGetLastError());
+}
+
+template void launch_cast_to_rm<double, double>(int64_t, int, const double*, int64_t, const int32_t*,
+                                                double, double*, hipStream_t);
+template void launch_cast_to_rm<double, float>(int64_t, int, const double*, int64_t, const int32_t*,
+                                               double, float*, hipStream_t);
+template void launch_cast_from_rm<double, double>(int64_t, int, const double*, double, double*, int64_t,
+                                                  hipStream_t);
+template void launch_cast_from_rm<float, float>(int64_t, int, const float*, double, float*, int64_t,
+                                                hipStream_t);
+template void launch_cast_from_rm<float, double>(int64_t, int, const float*, double, double*, int64_t,
+                                                 hipStream_t);
 
 template <typename TS, typename TD>
 void launch_scatter_cast(int64_t n, int ncols, const TS* src, int64_t lds, const int32_t* cols,

@@ -3,15 +3,19 @@
 // dp = 0, until the recurred residual norm ||dr_j + (H - eps_j S) dp|| is at most
 // eta ||r_j|| (eq. (approxp)) or the iteration cap; then p_j += dp.
 //
-// All localised columns advance together, one MINRES iteration per sweep of kernels:
-//   spmv    w = (H - eps_j S) v - beta_j v_prev, partial v.w   (one pass over the pattern)
-//   alpha   alpha_j = v.w
-//   axpy    w -= alpha_j v, partial ||w||^2
-//   scalar  beta_{k+1}, the Givens rotation of the tridiagonal QR, step tau, |phibar|
-//   update  d = (v - delta d1 - eps d2) / gamma, x += tau d, v_next = w / beta_{k+1}
-// A converged column stops changing; the host rotates the vector buffers between
-// sweeps and stops once every column is done.  T = double (FP64) or float (mixed:
-// FP32 vectors, FP32 products and FP32 per-slice sums).
+// MINRES (Paige and Saunders): Lanczos on A = H - eps_j S builds an orthonormal Krylov
+// basis with A V_k = V_{k+1} T_k; the least-squares problem with T_k is solved by one
+// Givens rotation per step, whose running product gives the residual norm for free.
+// All localised columns advance together, three kernels per iteration:
+//   spmv    w = A v - beta_k v_prev, per-slice partial sums of v.w    (one pattern pass)
+//   axpy    alpha_k = v.w; w -= alpha_k v, partial sums of ||w||^2
+//   update  beta_{k+1} = ||w||, the new rotation, tau_k and |phibar_k|;
+//           d = (v - delta_k d1 - eps_k d2) / gamma_k, x += tau_k d, v_next = w / beta_{k+1}
+// Every block recomputes the column's scalars from the partial sums (identical values);
+// block 0 of the column stores the new scalar state into the other half of a double
+// buffer, so no block reads a state that another block of the same kernel writes.
+// The host checks the count of active columns every few iterations.  T = double (FP64)
+// or float (mixed: FP32 vectors, FP32 products and FP32 per-slice sums).
 #include "common.h"
 
 namespace labpsd {
@@ -19,9 +23,11 @@ namespace labpsd {
 namespace {
 
 struct MinresScal {
-    double beta, cprev, sprev, cpp, spp, phibar, stop;
-    double alpha, gamma, delta, eps, tau, betanext;
-    int apply, done, its, pad;
+    double beta;        // beta_k: coupling of v_k to v_{k-1}
+    double cprev, sprev, cpp, spp;   // rotations k-1 and k-2
+    double phibar;      // rotated right-hand side, |phibar| = residual norm
+    double stop;        // eta * ||r_j||
+    int its, done, pad0, pad1;
 };
 
 template <typename T>
@@ -32,37 +38,43 @@ __device__ __forceinline__ T wave_sum_t(T v) {
 }
 
 constexpr int kWaves = 4;
-constexpr int kCW = 4;
 
-template <typename T, int MODE>
+template <typename T, int MODE, int CW, int WPS>
 __global__ __launch_bounds__(256) void k_minres_spmv(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, const T* __restrict__ hv,
     const T* __restrict__ sv, int64_t n, int64_t nslices, const T* __restrict__ X, int64_t ldx,
     const int32_t* __restrict__ xcols, const T* __restrict__ aux, int64_t ldaux,
     const int32_t* __restrict__ auxcols, const double* __restrict__ shift,
     const MinresScal* __restrict__ sc, T* __restrict__ out, T* __restrict__ partial, int q) {
-    const int lane = threadIdx.x & 63;
-    const int64_t slice = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (slice >= nslices) return;
-    const int j0 = blockIdx.y * kCW;
+    constexpr int SPB = 4 / WPS;   // slices per work-group
+    __shared__ T sred[WPS > 1 ? 256 * 2 * CW : 1];
+    __shared__ T red[kWaves][CW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nblk = (nslices + SPB - 1) / SPB;
+    const int64_t sb = xcd_block(blockIdx.x, nblk);
+    const int64_t slice = sb * SPB + wave / WPS;
+    const int sw = wave % WPS;
+    const bool valid = slice < nslices;
+    const int j0 = blockIdx.y * CW;
     const int64_t row = slice * kSlice + lane;
-    const int64_t e0 = off[slice], e1 = off[slice + 1];
-    bool act[kCW];
-    const T* xc[kCW];
-    T ah[kCW], as[kCW];
+    const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
+    bool act[CW];
+    const T* xc[CW];
+    T ah[CW], as[CW];
 #pragma unroll
-    for (int j = 0; j < kCW; ++j) {
+    for (int j = 0; j < CW; ++j) {
         const int jj = j0 + j;
         act[j] = jj < q && (MODE == 0 || !sc[jj].done);
         xc[j] = act[j] ? X + (int64_t)(MODE == 0 ? xcols[jj] : jj) * ldx : X;
         ah[j] = T(0);
         as[j] = T(0);
     }
-    for (int64_t e = e0 + lane; e < e1; e += kSlice) {
+#pragma unroll 2
+    for (int64_t e = e0 + sw * kSlice + lane; e < e1; e += kSlice * WPS) {
         const int64_t c = col[e];
         const T h = hv[e], s = sv[e];
 #pragma unroll
-        for (int j = 0; j < kCW; ++j) {
+        for (int j = 0; j < CW; ++j) {
             if (act[j]) {
                 const T x = xc[j][c];
                 ah[j] = fma(h, x, ah[j]);
@@ -70,11 +82,13 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
             }
         }
     }
+    slice_reduce<T, CW, WPS>(ah, as, sred);
+    const bool lead = valid && sw == 0;
 #pragma unroll
-    for (int j = 0; j < kCW; ++j) {
+    for (int j = 0; j < CW; ++j) {
         const int jj = j0 + j;
         T contrib = T(0);
-        if (act[j] && row < n) {
+        if (act[j] && lead && row < n) {
             const T y = ah[j] - (T)shift[jj] * as[j];
             T v;
             if (MODE == 0) {
@@ -86,20 +100,53 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
             }
             out[row + (int64_t)jj * n] = v;
         }
+        contrib = wave_sum_t(contrib);
+        if (lane == 0) red[wave][j] = contrib;
+    }
+    __syncthreads();
+    // one partial per work-group and column (the slice block sb owns slot sb); the
+    // wavefronts that only helped a slice contributed zeros
+    if (threadIdx.x < CW) {
+        const int jj = j0 + threadIdx.x;
         if (jj < q) {
-            contrib = wave_sum_t(contrib);
-            if (lane == 0) partial[slice * q + jj] = act[j] ? contrib : T(0);
+            T t = T(0);
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) t += red[w][threadIdx.x];
+            partial[sb * q + jj] = (MODE == 0 || !sc[jj].done) ? t : T(0);
         }
     }
 }
 
-// sum of the per-slice partials of column j (one wavefront per column)
+// sum of the np partials of column j, computed by one wavefront (fixed order, so every
+// wavefront that computes it gets the same value)
 template <typename T>
-__device__ double column_sum(const T* partial, int64_t nslices, int q, int j) {
+__device__ double column_sum(const T* partial, int64_t np, int q, int j) {
     double s = 0.0;
-    for (int64_t i = threadIdx.x & 63; i < nslices; i += 64) s += (double)partial[i * q + j];
+    for (int64_t i = threadIdx.x & 63; i < np; i += 64) s += (double)partial[i * q + j];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     return __shfl(s, 0, 64);
+}
+
+// the same sum for a whole work-group: wavefront 0 computes it, LDS broadcasts it
+template <typename T>
+__device__ double block_column_sum(const T* partial, int64_t np, int q, int j) {
+    __shared__ double bc;
+    if (threadIdx.x < 64) {
+        const double v = column_sum(partial, np, q, j);
+        if (threadIdx.x == 0) bc = v;
+    }
+    __syncthreads();
+    return bc;
+}
+
+// sum over the work-group, valid in thread 0
+template <typename T>
+__device__ T block_sum(T v) {
+    __shared__ T w[4];
+    v = wave_sum_t(v);
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return w[0] + w[1] + w[2] + w[3];
 }
 
 template <typename T>
@@ -119,7 +166,6 @@ __global__ __launch_bounds__(256) void k_minres_init_finish(const T* __restrict_
     s.phibar = beta1;
     s.stop = eta * rnorm[j];
     s.done = (beta1 == 0.0 || beta1 <= s.stop || max_inner <= 0) ? 1 : 0;
-    s.apply = 0;
     s.its = 0;
     sc[j] = s;
 }
@@ -144,106 +190,96 @@ __global__ __launch_bounds__(256) void k_minres_init_vectors(int64_t n, int q,
     }
 }
 
+// alpha = v.w (from the spmv partials); w -= alpha v; one partial of ||w||^2 per
+// work-group.  Grid (G, q): work-group x of column j strides over rows x*256 + G*256*i.
 template <typename T>
-__global__ __launch_bounds__(256) void k_minres_alpha(const T* __restrict__ partial, int64_t nslices,
-                                                      int q, MinresScal* __restrict__ sc,
-                                                      int32_t* __restrict__ active_count) {
-    // the scalar kernel of this sweep counts the columns still active
-    if (blockIdx.x == 0 && threadIdx.x == 0) *active_count = 0;
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= q) return;
-    const double a = column_sum(partial, nslices, q, j);
-    if ((threadIdx.x & 63) == 0 && !sc[j].done) sc[j].alpha = a;
-}
-
-// w -= alpha v; partial ||w||^2 per slice-sized chunk of rows
-template <typename T>
-__global__ __launch_bounds__(256) void k_minres_axpy(int64_t n, int q, int64_t nslices,
+__global__ __launch_bounds__(256) void k_minres_axpy(int64_t n, int q, int64_t npa,
                                                      const MinresScal* __restrict__ sc,
+                                                     const T* __restrict__ pa, double* __restrict__ alpha,
                                                      const T* __restrict__ V, T* __restrict__ Wb,
-                                                     T* __restrict__ partial) {
+                                                     T* __restrict__ pw, int32_t* __restrict__ active) {
     const int j = blockIdx.y;
-    const int64_t slice = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (slice >= nslices) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t row = slice * kSlice + lane;
-    T c = T(0);
-    const bool live = !sc[j].done;
-    if (live && row < n) {
-        const int64_t o = row + (int64_t)j * n;
-        const T w = Wb[o] - (T)sc[j].alpha * V[o];
-        Wb[o] = w;
-        c = w * w;
-    }
-    c = wave_sum_t(c);
-    if (lane == 0) partial[slice * q + j] = c;
-}
-
-// scalar recurrences of the tridiagonal QR (one wavefront per column)
-template <typename T>
-__global__ __launch_bounds__(256) void k_minres_scalar(const T* __restrict__ partial,
-                                                       int64_t nslices, int q, int max_inner,
-                                                       MinresScal* __restrict__ sc,
-                                                       int32_t* __restrict__ active_count) {
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= q) return;
-    const double w2 = column_sum(partial, nslices, q, j);
-    if ((threadIdx.x & 63) != 0) return;
-    MinresScal s = sc[j];
-    if (s.done) {
-        s.apply = 0;
-        sc[j] = s;
+    if (blockIdx.x == 0 && j == 0 && threadIdx.x == 0) *active = 0;
+    if (sc[j].done) {   // uniform over the work-group
+        if (threadIdx.x == 0) pw[(int64_t)blockIdx.x * q + j] = T(0);
         return;
     }
-    const double bnext = sqrt(w2);
+    const double a = block_column_sum(pa, npa, q, j);
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha[j] = a;
+    const T ta = (T)a;
+    T c = T(0);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t o = i + (int64_t)j * n;
+        const T w = Wb[o] - ta * V[o];
+        Wb[o] = w;
+        c += w * w;
+    }
+    c = block_sum(c);
+    if (threadIdx.x == 0) pw[(int64_t)blockIdx.x * q + j] = c;
+}
+
+// Scalar recurrences of the tridiagonal QR, computed identically by every work-group of
+// the column, then the vector updates of its rows.  Work-group 0 of the column stores
+// the new state in sc_out (the host swaps sc_in and sc_out between iterations).
+template <typename T>
+__global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max_inner,
+                                                       const MinresScal* __restrict__ sc_in,
+                                                       MinresScal* __restrict__ sc_out,
+                                                       const T* __restrict__ pw,
+                                                       const double* __restrict__ alpha,
+                                                       const T* __restrict__ V, T* __restrict__ Wb,
+                                                       const T* __restrict__ D1, T* __restrict__ D2,
+                                                       T* __restrict__ Xs, int32_t* __restrict__ active) {
+    const int j = blockIdx.y;
+    const MinresScal s = sc_in[j];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (s.done) {
+        if (lead) sc_out[j] = s;
+        return;
+    }
+    const double bnext = sqrt(block_column_sum(pw, (int64_t)gridDim.x, q, j));
+    const double al = alpha[j];
     const int k = s.its + 1;
     // rotation k-2 maps (0, beta_k) to (eps_k, t1); column 1 has no entry above the diagonal
     const double epsk = k > 1 ? s.spp * s.beta : 0.0;
     const double t1 = k > 1 ? s.cpp * s.beta : 0.0;
     // rotation k-1 maps (t1, alpha_k) to (delta_k, gammabar_k)
-    const double delta = s.cprev * t1 + s.sprev * s.alpha;
-    const double gbar = -s.sprev * t1 + s.cprev * s.alpha;
+    const double delta = s.cprev * t1 + s.sprev * al;
+    const double gbar = -s.sprev * t1 + s.cprev * al;
     const double gamma = sqrt(gbar * gbar + bnext * bnext);
     if (gamma == 0.0) {
-        s.apply = 0;
-        s.done = 1;
-        sc[j] = s;
+        if (lead) {
+            MinresScal t = s;
+            t.done = 1;
+            sc_out[j] = t;
+        }
         return;
     }
+    // rotation k maps (gammabar_k, beta_{k+1}) to (gamma_k, 0)
     const double c = gbar / gamma, sn = bnext / gamma;
-    s.tau = c * s.phibar;
-    s.phibar = -sn * s.phibar;
-    s.gamma = gamma;
-    s.delta = delta;
-    s.eps = epsk;
-    s.betanext = bnext;
-    s.apply = 1;
-    s.its = k;
-    s.cpp = s.cprev; s.spp = s.sprev;
-    s.cprev = c; s.sprev = sn;
-    s.beta = bnext;
-    if (fabs(s.phibar) <= s.stop || bnext == 0.0 || k >= max_inner) s.done = 1;
-    sc[j] = s;
-    if (!s.done) atomicAdd(active_count, 1);
-}
-
-// d2 <- (v - delta d1 - eps d2) / gamma ; x += tau d2 ; w <- w / beta_{k+1}
-template <typename T>
-__global__ __launch_bounds__(256) void k_minres_update(int64_t n, const MinresScal* __restrict__ sc,
-                                                       const T* __restrict__ V,
-                                                       T* __restrict__ Wb, const T* __restrict__ D1,
-                                                       T* __restrict__ D2, T* __restrict__ Xs) {
-    const int j = blockIdx.y;
-    const MinresScal& s = sc[j];
-    if (!s.apply) return;
-    const T ig = (T)(1.0 / s.gamma), de = (T)s.delta, ep = (T)s.eps, ta = (T)s.tau;
-    const T ib = s.betanext > 0.0 ? (T)(1.0 / s.betanext) : T(0);
+    const double tau = c * s.phibar;
+    const double phibar = -sn * s.phibar;
+    const T ig = (T)(1.0 / gamma), de = (T)delta, ep = (T)epsk, ta = (T)tau;
+    const T ib = bnext > 0.0 ? (T)(1.0 / bnext) : T(0);
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int64_t o = i + (int64_t)j * n;
         const T d = (V[o] - de * D1[o] - ep * D2[o]) * ig;
         D2[o] = d;
         Xs[o] += ta * d;
         Wb[o] *= ib;
+    }
+    if (lead) {
+        MinresScal t = s;
+        t.its = k;
+        t.phibar = phibar;
+        t.cpp = s.cprev;
+        t.spp = s.sprev;
+        t.cprev = c;
+        t.sprev = sn;
+        t.beta = bnext;
+        t.done = (fabs(phibar) <= s.stop || bnext == 0.0 || k >= max_inner) ? 1 : 0;
+        sc_out[j] = t;
+        if (!t.done) atomicAdd(active, 1);
     }
 }
 
@@ -261,16 +297,60 @@ __global__ __launch_bounds__(256) void k_minres_final(int64_t n, int q, const in
     if (blockIdx.x == 0 && threadIdx.x == 0 && its) its[j] = sc[j].its;
 }
 
+template <typename T, int MODE, int CW, int WPS>
+int64_t launch_spmv_s(const Sell& A, const T* hv, const T* sv, const T* X, int64_t ldx,
+                      const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
+                      const double* shift, const MinresScal* sc, T* out, T* partial, int q,
+                      hipStream_t s) {
+    constexpr int SPB = 4 / WPS;
+    const int64_t nblk = (A.nslices + SPB - 1) / SPB;
+    const dim3 g((unsigned)nblk, (unsigned)((q + CW - 1) / CW));
+    hipLaunchKernelGGL((k_minres_spmv<T, MODE, CW, WPS>), g, dim3(256), 0, s, A.slice_off.p, A.col.p, hv,
+                       sv, A.n, A.nslices, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q);
+    return nblk;
+}
+
+// (H - eps_j S) products of the MINRES columns in the launch shape sell_shape picks (at
+// most 4 columns per wavefront); returns the number of partials per column
+template <typename T, int MODE>
+int64_t launch_spmv(const Sell& A, SellShape sh, const T* hv, const T* sv, const T* X, int64_t ldx,
+                    const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
+                    const double* shift, const MinresScal* sc, T* out, T* partial, int q, hipStream_t s) {
+#define LABPSD_SPMV(CW, WPS) \
+    launch_spmv_s<T, MODE, CW, WPS>(A, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q, s)
+    if (sh.wps == 4) {
+        if (sh.cw >= 4) return LABPSD_SPMV(4, 4);
+        if (sh.cw == 2) return LABPSD_SPMV(2, 4);
+        return LABPSD_SPMV(1, 4);
+    }
+    if (sh.cw >= 4) return LABPSD_SPMV(4, 1);
+    if (sh.cw == 2) return LABPSD_SPMV(2, 1);
+    return LABPSD_SPMV(1, 1);
+#undef LABPSD_SPMV
+}
+
 }  // namespace
 
-size_t minres_ws_elems(int64_t n, int q) { return (size_t)6 * n * q + (size_t)((n + 63) / 64 + 1) * q; }
+size_t minres_ws_elems(int64_t n, int q) {
+    return (size_t)6 * n * q + 2 * (size_t)((n + 63) / 64 + 1) * q;
+}
+
+size_t minres_scal_doubles(int q) {
+    static_assert(sizeof(MinresScal) % 8 == 0, "scalar state must be a whole number of doubles");
+    return 2 * (sizeof(MinresScal) / 8) * (size_t)q + (size_t)q + 2;
+}
+
+// Work-groups per column of the row-wise kernels: enough to cover the rows at one
+// element per thread up to 128, beyond that each thread takes several rows (this also
+// bounds the partials every work-group of the next kernel re-sums).
+static unsigned rowwise_groups(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 128); }
 
 template <typename T>
 void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q,
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
                 int32_t* flag_host_pinned, hipStream_t s, int64_t* launches) {
-    if (q <= 0) return;
+    if (q <= 0 || A.n == 0) return;
     const int64_t n = A.n;
     T* V = ws;
     T* VP = V + n * q;
@@ -278,51 +358,60 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     T* D1 = Wb + n * q;
     T* D2 = D1 + n * q;
     T* Xs = D2 + n * q;
-    T* partial = Xs + n * q;
-    MinresScal* sc = (MinresScal*)scal_ws;
-    int32_t* counter = (int32_t*)(sc + q);
+    const SellShape sh = sell_shape(A.nslices, q, 4);
+    const unsigned G = rowwise_groups(n);
+    T* pa = Xs + n * q;                          // spmv partials (v.w, or b.b)
+    T* pw = pa + (A.nslices + 1) * q;            // axpy partials of ||w||^2, G per column
+    // scalar state double buffer, alpha, and the active-column counter
+    constexpr size_t kScalDoubles = sizeof(MinresScal) / 8;
+    MinresScal* sa = (MinresScal*)scal_ws;
+    MinresScal* sb = (MinresScal*)(scal_ws + kScalDoubles * q);
+    double* alpha = scal_ws + 2 * kScalDoubles * q;
+    int32_t* counter = (int32_t*)(alpha + q);
     const T* hv;
     const T* sv;
     if constexpr (sizeof(T) == 8) { hv = A.hv.p; sv = A.sv.p; }
     else { hv = A.hv32.p; sv = A.sv32.p; }
-    const dim3 gsp((unsigned)((A.nslices + kWaves - 1) / kWaves), (unsigned)((q + kCW - 1) / kCW));
     const dim3 gcol((unsigned)((q + 3) / 4));
     const unsigned bx = (unsigned)std::min<int64_t>((n + 255) / 256, 512);
     const dim3 gel(bx, q);
-    const dim3 gsl((unsigned)((A.nslices + kWaves - 1) / kWaves), q);
+    const dim3 grow(G, q);
     int64_t nl = 0;
     // b = -((H - eps S) p + r); beta1 = ||b||
-    hipLaunchKernelGGL((k_minres_spmv<T, 0>), gsp, dim3(256), 0, s, A.slice_off.p, A.col.p, hv, sv, n,
-                       A.nslices, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev,
-                       (const MinresScal*)sc, V, partial, q);
-    hipLaunchKernelGGL((k_minres_init_finish<T>), gcol, dim3(256), 0, s, partial, A.nslices, q,
-                       rnorm_dev, eta, max_inner, sc);
-    hipLaunchKernelGGL((k_minres_init_vectors<T>), gel, dim3(256), 0, s, n, q, (const MinresScal*)sc, V,
+    // spmv partials: one per work-group and column (at most nslices)
+    const int64_t npa =
+        launch_spmv<T, 0>(A, sh, hv, sv, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev, sa, V, pa, q, s);
+    hipLaunchKernelGGL((k_minres_init_finish<T>), gcol, dim3(256), 0, s, (const T*)pa, npa, q, rnorm_dev,
+                       eta, max_inner, sa);
+    hipLaunchKernelGGL((k_minres_init_vectors<T>), gel, dim3(256), 0, s, n, q, (const MinresScal*)sa, V,
                        VP, D1, D2, Xs);
     LABPSD_HIP(hipGetLastError());
     nl += 3;
+    MinresScal* cur = sa;
+    MinresScal* nxt = sb;
+    // the host reads the active count every few iterations; iterations issued after the
+    // last column finished find every column done and exit at once
+    constexpr int kCheckEvery = 3;
     for (int it = 0; it < max_inner; ++it) {
-        hipLaunchKernelGGL((k_minres_spmv<T, 1>), gsp, dim3(256), 0, s, A.slice_off.p, A.col.p, hv, sv,
-                           n, A.nslices, V, n, nullptr, VP, n, nullptr, shift_dev,
-                           (const MinresScal*)sc, Wb, partial, q);
-        hipLaunchKernelGGL((k_minres_alpha<T>), gcol, dim3(256), 0, s, partial, A.nslices, q, sc,
-                           counter);
-        hipLaunchKernelGGL((k_minres_axpy<T>), gsl, dim3(256), 0, s, n, q, A.nslices,
-                           (const MinresScal*)sc, V, Wb, partial);
-        hipLaunchKernelGGL((k_minres_scalar<T>), gcol, dim3(256), 0, s, partial, A.nslices, q,
-                           max_inner, sc, counter);
-        hipLaunchKernelGGL((k_minres_update<T>), gel, dim3(256), 0, s, n, (const MinresScal*)sc, V, Wb,
-                           D1, D2, Xs);
+        launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s);
+        hipLaunchKernelGGL((k_minres_axpy<T>), grow, dim3(256), 0, s, n, q, npa, (const MinresScal*)cur,
+                           (const T*)pa, alpha, (const T*)V, Wb, pw, counter);
+        hipLaunchKernelGGL((k_minres_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
+                           (const MinresScal*)cur, nxt, (const T*)pw, (const double*)alpha, (const T*)V, Wb,
+                           (const T*)D1, D2, Xs, counter);
         LABPSD_HIP(hipGetLastError());
-        nl += 5;
-        // rotate: v_prev <- v, v <- w (now scaled), w <- old v_prev; d1 <- d2 (new d), d2 <- old d1
+        nl += 3;
+        // rotate: v_prev <- v, v <- w (now scaled), w <- old v_prev; d1 <- new d, d2 <- old d1
         T* t0 = VP; VP = V; V = Wb; Wb = t0;
         T* t1 = D1; D1 = D2; D2 = t1;
-        LABPSD_HIP(hipMemcpyAsync(flag_host_pinned, counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        LABPSD_HIP(hipStreamSynchronize(s));
-        if (*flag_host_pinned == 0) break;
+        MinresScal* t2 = cur; cur = nxt; nxt = t2;
+        if ((it + 1) % kCheckEvery == 0 || it + 1 == max_inner) {
+            LABPSD_HIP(hipMemcpyAsync(flag_host_pinned, counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            LABPSD_HIP(hipStreamSynchronize(s));
+            if (*flag_host_pinned == 0) break;
+        }
     }
-    hipLaunchKernelGGL((k_minres_final<T>), gel, dim3(256), 0, s, n, q, cols_dev, (const MinresScal*)sc,
+    hipLaunchKernelGGL((k_minres_final<T>), gel, dim3(256), 0, s, n, q, cols_dev, (const MinresScal*)cur,
                        Xs, P, ldp, its_dev);
     LABPSD_HIP(hipGetLastError());
     nl += 1;

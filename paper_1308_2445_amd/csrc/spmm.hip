@@ -2,9 +2,10 @@
 // shifted products (H - sigma S) v of the refinement; Section 5 notes the PUFE code
 // forms (H - sigma S) v for any shift).
 //
-// Layout: sliced ELL with 64-row slices (one wavefront per slice, one row per lane),
-// each slice padded to its longest row and stored slot-major, so a wavefront's
-// loads of column indices and values are contiguous.  H and S values sit on the same
+// Layout: sliced ELL with 64-row slices (one row per lane), each slice padded to its
+// longest row and stored slot-major, so a wavefront's loads of column indices and
+// values are contiguous.  A slice's slots go to one wavefront, or round-robin to four
+// whose sums meet in LDS when the launch would otherwise have too few wavefronts.  H and S values sit on the same
 // pattern, so one pass over the pattern and one gather of X serve both products.
 // Work-groups map slices XCD-locally: consecutive slices land on the same XCD so the
 // neighbouring rows' gathers of X hit the same L2.
@@ -14,23 +15,9 @@ namespace labpsd {
 
 namespace {
 
-constexpr int kWaves = 4;  // slices per work-group
-
-// Map a linear work-group index to a slice-block index so that each XCD (work-groups
-// are dealt round-robin to the 8 XCDs) receives a contiguous range of slice blocks.
-__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
-    constexpr int kXcd = 8;
-    if (nblocks < 2 * kXcd) return bid;
-    const int64_t per = nblocks / kXcd, rem = nblocks % kXcd;
-    const int64_t xcd = bid % kXcd, idx = bid / kXcd;
-    // XCDs 0..rem-1 own per+1 blocks, the rest own per
-    const int64_t start = xcd * per + (xcd < rem ? xcd : rem);
-    const int64_t own = per + (xcd < rem ? 1 : 0);
-    if (idx < own) return start + idx;
-    return bid;  // unreachable for bid < nblocks; kept total
-}
-
-template <int CW>
+// One work-group of 256 threads covers 4 / WPS slices; wavefront `wave` serves slice
+// sb * (4 / WPS) + wave / WPS and takes every WPS-th slot of it.
+template <int CW, int WPS>
 __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off,
                                                  const int32_t* __restrict__ col,
                                                  const double* __restrict__ hv,
@@ -38,21 +25,24 @@ __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off
                                                  int64_t nslices, const double* __restrict__ X,
                                                  int64_t ldx, int w, double* __restrict__ YH,
                                                  double* __restrict__ YS, int64_t ldy) {
-    const int lane = threadIdx.x & 63;
-    const int64_t nblk = (nslices + kWaves - 1) / kWaves;
+    constexpr int SPB = 4 / WPS;
+    __shared__ double red[WPS > 1 ? 256 * 2 * CW : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nblk = (nslices + SPB - 1) / SPB;
     const int64_t sb = xcd_block(blockIdx.x, nblk);
-    const int64_t slice = sb * kWaves + (threadIdx.x >> 6);
-    if (slice >= nslices) return;
+    const int64_t slice = sb * SPB + wave / WPS;
+    const int sw = wave % WPS;
+    const bool valid = slice < nslices;
     const int j0 = blockIdx.y * CW;
     const int nc = min(CW, w - j0);
     const int64_t row = slice * kSlice + lane;
-    const int64_t e0 = off[slice], e1 = off[slice + 1];
+    const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
     double ah[CW], as[CW];
 #pragma unroll
     for (int j = 0; j < CW; ++j) { ah[j] = 0.0; as[j] = 0.0; }
     const double* Xj = X + (int64_t)j0 * ldx;
 #pragma unroll 2
-    for (int64_t e = e0 + lane; e < e1; e += kSlice) {
+    for (int64_t e = e0 + sw * kSlice + lane; e < e1; e += kSlice * WPS) {
         const int64_t c = col[e];
         const double h = hv[e], s = sv[e];
 #pragma unroll
@@ -64,7 +54,8 @@ __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off
             }
         }
     }
-    if (row < n) {
+    slice_reduce<double, CW, WPS>(ah, as, red);
+    if (valid && sw == 0 && row < n) {
 #pragma unroll
         for (int j = 0; j < CW; ++j) {
             if (j < nc) {
@@ -76,7 +67,7 @@ __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off
 }
 
 // Y[:, j] = H X[:, j] - shift[j] S X[:, j]
-template <typename T, int CW>
+template <typename T, int CW, int WPS>
 __global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ col,
                                                     const T* __restrict__ hv,
@@ -85,21 +76,24 @@ __global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ 
                                                     int64_t ldx, int w,
                                                     const double* __restrict__ shift,
                                                     T* __restrict__ Y, int64_t ldy) {
-    const int lane = threadIdx.x & 63;
-    const int64_t nblk = (nslices + kWaves - 1) / kWaves;
+    constexpr int SPB = 4 / WPS;
+    __shared__ T red[WPS > 1 ? 256 * 2 * CW : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nblk = (nslices + SPB - 1) / SPB;
     const int64_t sb = xcd_block(blockIdx.x, nblk);
-    const int64_t slice = sb * kWaves + (threadIdx.x >> 6);
-    if (slice >= nslices) return;
+    const int64_t slice = sb * SPB + wave / WPS;
+    const int sw = wave % WPS;
+    const bool valid = slice < nslices;
     const int j0 = blockIdx.y * CW;
     const int nc = min(CW, w - j0);
     const int64_t row = slice * kSlice + lane;
-    const int64_t e0 = off[slice], e1 = off[slice + 1];
+    const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
     T ah[CW], as[CW];
 #pragma unroll
     for (int j = 0; j < CW; ++j) { ah[j] = T(0); as[j] = T(0); }
     const T* Xj = X + (int64_t)j0 * ldx;
 #pragma unroll 2
-    for (int64_t e = e0 + lane; e < e1; e += kSlice) {
+    for (int64_t e = e0 + sw * kSlice + lane; e < e1; e += kSlice * WPS) {
         const int64_t c = col[e];
         const T h = hv[e], s = sv[e];
 #pragma unroll
@@ -111,7 +105,8 @@ __global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ 
             }
         }
     }
-    if (row < n) {
+    slice_reduce<T, CW, WPS>(ah, as, red);
+    if (valid && sw == 0 && row < n) {
 #pragma unroll
         for (int j = 0; j < CW; ++j) {
             if (j < nc) {
@@ -184,40 +179,61 @@ void refresh_sell_h(Sell& S, const double* hv, hipStream_t s) {
     LABPSD_HIP(hipStreamSynchronize(s));
 }
 
-// Column-chunk width: the widest of 8, 4, 2 that still gives the launch enough
-// wavefronts (slices x chunks) to hide the gathers' latency; wider chunks re-read the
-// pattern fewer times.
-static int chunk_width(int64_t nslices, int w) {
+// Launch shape: the widest column chunk (fewest passes over the pattern) that, with 1
+// or 4 wavefronts per slice, gives at least kWantWaves wavefronts to hide the gathers'
+// latency; failing that the shape with the most wavefronts.
+SellShape sell_shape(int64_t nslices, int w, int max_cw) {
     constexpr int64_t kWantWaves = 4096;
-    for (int cw : {8, 4}) {
-        if (nslices * ((w + cw - 1) / cw) >= kWantWaves) return cw;
+    SellShape best{1, 4};
+    int64_t best_waves = -1;
+    for (int cw : {8, 4, 2, 1}) {
+        if (cw > max_cw) continue;
+        for (int wps : {1, 4}) {
+            const int64_t waves = nslices * ((w + cw - 1) / cw) * wps;
+            if (waves >= kWantWaves) return SellShape{cw, wps};
+            if (waves > best_waves) {
+                best_waves = waves;
+                best = SellShape{cw, wps};
+            }
+        }
     }
-    return 2;
+    return best;
+}
+
+template <int CW, int WPS>
+static void spmm_hs_cw(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
+                       int64_t ldy, hipStream_t s) {
+    constexpr int SPB = 4 / WPS;
+    dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)((w + CW - 1) / CW));
+    hipLaunchKernelGGL((k_spmm_hs<CW, WPS>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, A.hv.p,
+                       A.sv.p, A.n, A.nslices, X, ldx, w, YH, YS, ldy);
+    LABPSD_HIP(hipGetLastError());
 }
 
 template <int CW>
-static void spmm_hs_cw(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
-                       int64_t ldy, hipStream_t s) {
-    dim3 grid((unsigned)((A.nslices + kWaves - 1) / kWaves), (unsigned)((w + CW - 1) / CW));
-    hipLaunchKernelGGL(k_spmm_hs<CW>, grid, dim3(256), 0, s, A.slice_off.p, A.col.p, A.hv.p,
-                       A.sv.p, A.n, A.nslices, X, ldx, w, YH, YS, ldy);
-    LABPSD_HIP(hipGetLastError());
+static void spmm_hs_w(const Sell& A, int wps, const double* X, int64_t ldx, int w, double* YH,
+                      double* YS, int64_t ldy, hipStream_t s) {
+    if (wps == 4) spmm_hs_cw<CW, 4>(A, X, ldx, w, YH, YS, ldy, s);
+    else spmm_hs_cw<CW, 1>(A, X, ldx, w, YH, YS, ldy, s);
 }
 
 void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
                     int64_t ldy, hipStream_t s) {
     if (w <= 0 || A.n == 0) return;
-    switch (chunk_width(A.nslices, w)) {
-        case 8: spmm_hs_cw<8>(A, X, ldx, w, YH, YS, ldy, s); break;
-        case 4: spmm_hs_cw<4>(A, X, ldx, w, YH, YS, ldy, s); break;
-        default: spmm_hs_cw<2>(A, X, ldx, w, YH, YS, ldy, s); break;
+    const SellShape sh = sell_shape(A.nslices, w, 8);
+    switch (sh.cw) {
+        case 8: spmm_hs_w<8>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
+        case 4: spmm_hs_w<4>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
+        case 2: spmm_hs_w<2>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
+        default: spmm_hs_w<1>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
     }
 }
 
-template <typename T, int CW>
+template <typename T, int CW, int WPS>
 static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
                           int64_t ldy, hipStream_t s) {
-    dim3 grid((unsigned)((A.nslices + kWaves - 1) / kWaves), (unsigned)((w + CW - 1) / CW));
+    constexpr int SPB = 4 / WPS;
+    dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)((w + CW - 1) / CW));
     const T* hv;
     const T* sv;
     if constexpr (sizeof(T) == 8) {
@@ -227,19 +243,28 @@ static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const d
         hv = A.hv32.p;
         sv = A.sv32.p;
     }
-    hipLaunchKernelGGL((k_spmm_shift<T, CW>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, hv, sv,
+    hipLaunchKernelGGL((k_spmm_shift<T, CW, WPS>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, hv, sv,
                        A.n, A.nslices, X, ldx, w, shift, Y, ldy);
     LABPSD_HIP(hipGetLastError());
+}
+
+template <typename T, int CW>
+static void spmm_shift_w(const Sell& A, int wps, const T* X, int64_t ldx, int w, const double* shift,
+                         T* Y, int64_t ldy, hipStream_t s) {
+    if (wps == 4) spmm_shift_cw<T, CW, 4>(A, X, ldx, w, shift, Y, ldy, s);
+    else spmm_shift_cw<T, CW, 1>(A, X, ldx, w, shift, Y, ldy, s);
 }
 
 template <typename T>
 void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
                        int64_t ldy, hipStream_t s) {
     if (w <= 0 || A.n == 0) return;
-    switch (chunk_width(A.nslices, w)) {
-        case 8: spmm_shift_cw<T, 8>(A, X, ldx, w, shift, Y, ldy, s); break;
-        case 4: spmm_shift_cw<T, 4>(A, X, ldx, w, shift, Y, ldy, s); break;
-        default: spmm_shift_cw<T, 2>(A, X, ldx, w, shift, Y, ldy, s); break;
+    const SellShape sh = sell_shape(A.nslices, w, 8);
+    switch (sh.cw) {
+        case 8: spmm_shift_w<T, 8>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
+        case 4: spmm_shift_w<T, 4>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
+        case 2: spmm_shift_w<T, 2>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
+        default: spmm_shift_w<T, 1>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
     }
 }
 
