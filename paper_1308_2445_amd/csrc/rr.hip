@@ -1,17 +1,22 @@
 // Rayleigh-Ritz step with S-orthonormalisation (outline step 9; the conclusions ask for a
 // rank-revealing treatment when [Psi P] loses rank).
 //
-// One work-group solves the reduced pencil (H_R, S_R) of order k:
+// One work-group solves the reduced pencil (H_R, S_R) of order k for its lowest nwant
+// pairs:
 //   1. diagonal scaling D = diag(S_R)^{-1/2}, so the scaled S_R has unit diagonal;
-//   2. Cholesky of the scaled S_R (the S-orthonormalisation of the search space) and the
-//      explicit inverse of its factor; if a pivot falls below 1e-14 the scaled S_R is
-//      instead diagonalised and only eigen-directions above 1e-14 of its largest
-//      eigenvalue are kept;
-//   3. C = T^T (D H_R D) T with T = L^{-T} (or the kept scaled eigenvectors) is
-//      diagonalised by the cyclic Jacobi method in round-robin order: each round applies
-//      r/2 disjoint rotations at once, as independent 2 x 2 block transforms of C;
-//   4. the lowest nwant eigenvalues (ascending) and W = D T V are written out.
-// Matrices live in LDS when they fit, otherwise in a global workspace.
+//   2. Cholesky L L^T of the scaled S_R (the S-orthonormalisation of the search space),
+//      right-looking with one barrier per column;
+//   3. C = L^{-1} (D H_R D) L^{-T} by two right-looking triangular solves;
+//   4. the lowest nwant eigenpairs of C: Householder reduction to tridiagonal form,
+//      eigenvalues by multisection on Sturm counts, eigenvectors by inverse iteration
+//      with the tridiagonal LU (partial pivoting) and Gram-Schmidt inside clusters of
+//      close eigenvalues, then the reflectors applied back;
+//   5. W = D L^{-T} Z by back substitution.
+// If a Cholesky pivot falls below 1e-14 the scaled S_R is instead diagonalised (cyclic
+// Jacobi) and only its eigen-directions above 1e-14 of the largest eigenvalue are kept;
+// C on that basis is diagonalised by cyclic Jacobi as well.
+// Everything lives in LDS when it fits the per-block limit, otherwise in a global
+// workspace.
 #include "common.h"
 
 namespace labpsd {
@@ -146,8 +151,554 @@ __device__ void small_gemm(const double* X, bool xt, const double* Z, bool zt, d
     }
 }
 
-// ALL_LDS: every matrix and the rotation table in LDS (pointers derived from the LDS base
-// only, so the compiler emits LDS instructions); otherwise lds_mask picks what fits.
+// Cross-lane sums with DPP moves (VALU latency, no LDS round trip).  A DPP source lane
+// that is inactive contributes 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+// sum over the 16 lanes of a DPP row, in every lane of the row
+__device__ __forceinline__ double row16_allsum(double v) {
+    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x124>(v);   // row_ror 4
+    v += dpp_d<0x128>(v);   // row_ror 8
+    return v;
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
+}
+// sum over the wavefront, in every lane; all 64 lanes must be active
+__device__ __forceinline__ double wave_allsum(double v) {
+    v = row16_allsum(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// 1 / x and 1 / sqrt(x) from the hardware approximations with two Newton steps
+// (within an ulp or two, without the long IEEE division sequence)
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * fma(-0.5 * x * r, r, 1.5);
+    return r * fma(-0.5 * x * r, r, 1.5);
+}
+
+typedef double rr_double4 __attribute__((ext_vector_type(4)));
+
+// C = op(A) op(B) (m x n, inner kd) with the FP64 16x16x4 MFMA, one 16 x 16 tile per
+// wavefront at a time; op(A)[i, p] = ta ? A[p + i lda] : A[i + p lda], op(B)[p, j] =
+// tb ? B[j + p ldb] : B[p + j ldb]; store(i, j, v) receives every element.
+template <typename Store>
+__device__ void gemm_mfma(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, int m,
+                          int n, int kd, Store store) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int tm = (m + 15) / 16, tn = (n + 15) / 16;
+    for (int t = wave; t < tm * tn; t += nwave) {
+        const int i0 = (t % tm) * 16, j0 = (t / tm) * 16;
+        rr_double4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int ar = i0 + (lane & 15), bc = j0 + (lane & 15), kq = lane >> 4;
+        for (int p0 = 0; p0 < kd; p0 += 4) {
+            const int pk = p0 + kq;
+            double a = 0.0, b = 0.0;
+            if (ar < m && pk < kd) a = ta ? A[pk + (int64_t)ar * lda] : A[ar + (int64_t)pk * lda];
+            if (bc < n && pk < kd) b = tb ? B[bc + (int64_t)pk * ldb] : B[pk + (int64_t)bc * ldb];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        // accumulator layout: register q of lane l holds row 4q + l / 16, column l % 16
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + 4 * q + (lane >> 4), j = j0 + (lane & 15);
+            if (i < m && j < n) store(i, j, acc[q]);
+        }
+    }
+}
+
+// Right-looking Cholesky of the r x r matrix A (lower triangle, column-major, ld r) in
+// place, one barrier per column: step j updates the trailing matrix with the unscaled
+// column j and scales column j - 1, which no thread of step j reads.  invd receives
+// 1 / L[j, j].  Returns false (uniformly) at the first pivot not above kPivotTol.
+__device__ bool cholesky_rl(double* A, int r, double* invd) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    double il_prev = 0.0, l_prev = 0.0;
+    for (int j = 0; j < r; ++j) {
+        const double piv = A[j + (int64_t)j * r];
+        if (!(piv > kPivotTol)) return false;
+        const double il = rsq_nr(piv);
+        const double ip = il * il;
+        if (j > 0) {
+            for (int i = j + tid; i < r; i += nt) A[i + (int64_t)(j - 1) * r] *= il_prev;
+            if (tid == 0) {
+                A[(j - 1) + (int64_t)(j - 1) * r] = l_prev;
+                invd[j - 1] = il_prev;
+            }
+        }
+        for (int c = j + 1 + wave; c < r; c += nwave) {
+            const double acj = A[c + (int64_t)j * r] * ip;
+            for (int i = c + lane; i < r; i += 64) A[i + (int64_t)c * r] -= A[i + (int64_t)j * r] * acj;
+        }
+        il_prev = il;
+        l_prev = piv * il;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        A[(r - 1) + (int64_t)(r - 1) * r] = l_prev;
+        invd[r - 1] = il_prev;
+    }
+    return true;
+}
+
+// X = L^{-1} (lower triangular, column-major, ld r) by right-looking substitution on the
+// identity, one barrier per row: step j eliminates row j (scaled by invd[j]) from the
+// rows below and scales row j - 1.
+__device__ void invert_lower_rl(const double* L, const double* invd, double* X, int r) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    for (int64_t e = tid; e < (int64_t)r * r; e += nt) {
+        const int i = (int)(e % r), c = (int)(e / r);
+        X[e] = (i == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        const double ij = invd[j];
+        if (j > 0) {
+            const double ip = invd[j - 1];
+            for (int c = tid; c < j; c += nt) X[(j - 1) + (int64_t)c * r] *= ip;
+        }
+        for (int c = wave; c <= j; c += nwave) {
+            const double xjc = X[j + (int64_t)c * r] * ij;
+            for (int i = j + 1 + lane; i < r; i += 64) X[i + (int64_t)c * r] -= L[i + (int64_t)j * r] * xjc;
+        }
+        __syncthreads();
+    }
+    const double ip = invd[r - 1];
+    for (int c = tid; c < r; c += nt) X[(r - 1) + (int64_t)c * r] *= ip;
+}
+
+// B <- (B + B^T) / 2 in place
+__device__ void symmetrize(double* B, int r) {
+    for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += blockDim.x) {
+        const int i = (int)(e % r), j = (int)(e / r);
+        if (i < j) {
+            const double m = 0.5 * (B[i + (int64_t)j * r] + B[j + (int64_t)i * r]);
+            B[i + (int64_t)j * r] = m;
+            B[j + (int64_t)i * r] = m;
+        }
+    }
+}
+
+// Reflector that maps column j's tail B[j+1.., j] to (beta, 0, ...): H = I - tau v v^T,
+// v = (1, v_{j+2}, ...), from alpha = B[j+1, j] and sigma = |B[j+2.., j]|^2.
+__device__ __forceinline__ void reflector(double alpha, double sigma, double& tau, double& beta,
+                                          double& scal) {
+    tau = 0.0;
+    beta = alpha;
+    scal = 0.0;
+    if (sigma != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+    }
+}
+
+// Householder reduction of the symmetric r x r matrix B (both triangles stored) to
+// tridiagonal form Q^T B Q = T (diagonal d, off-diagonal e), with Q = H_0 H_1 ... and
+// H_j = I - tau_j v v^T on rows j+1..r-1, v = (1, v_{j+2}, ...).  The reflectors are
+// accumulated on the right of M (r x r, row-major: M[i, c] at i r + c), M <- M H_j.
+// Two barriers per reflector: the products p = tau A22 v and M v (16 lanes per row,
+// with the terms of p . v stored per row), then the rank-2 update
+// A22 -= v w^T + w v^T, w = p - (tau/2)(p . v) v, and the rank-1 update of M.
+// Wavefront 0 owns column j + 1 in the update and builds the next reflector from it
+// right away (vb double buffer of 2 r doubles; sc[2 s], sc[2 s + 1]: tau, beta).
+// pA, pM, pv: r doubles each.
+__device__ void tridiagonalize_acc(double* B, double* M, int r, double* d, double* e, double* vb,
+                                   double* pA, double* pM, double* pv, double* sc) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    if (r == 1) {
+        if (tid == 0) d[0] = B[0];
+        return;
+    }
+    if (r >= 3 && wave == 0) {
+        double sg = 0.0, a1 = 0.0;
+        for (int i = 1 + lane; i < r; i += 64) {
+            const double x = B[i];
+            if (i >= 2) sg += x * x;
+            if (i == 1) a1 = x;
+        }
+        const double sigma = wave_allsum(sg), alpha = wave_allsum(a1);
+        double t, beta, scal;
+        reflector(alpha, sigma, t, beta, scal);
+        for (int i = 1 + lane; i < r; i += 64) vb[i] = (i == 1) ? 1.0 : B[i] * scal;
+        if (lane == 0) {
+            sc[0] = t;
+            sc[1] = beta;
+        }
+    }
+    __syncthreads();
+    const int g = tid >> 4, sub = tid & 15, ng = nt >> 4;
+    for (int j = 0; j + 2 < r; ++j) {
+        const int s0 = j & 1, s1 = s0 ^ 1;
+        const double t = sc[2 * s0], beta = sc[2 * s0 + 1];
+        const bool refl = t != 0.0;   // uniform: every thread read the same tau
+        const double* v = vb + s0 * r;
+        if (refl) {
+            // row tasks: A22 rows j+1..r-1 (p = tau A22 v; A22 symmetric, so column i),
+            // then M rows 0..r-1 (M v)
+            const int na = r - j - 1;
+            for (int task = g; task < na + r; task += ng) {
+                const bool isa = task < na;
+                const int i = isa ? j + 1 + task : task - na;
+                const double* src = isa ? B + (int64_t)i * r : M + (int64_t)i * r;
+                double part = 0.0;
+                for (int c = j + 1 + sub; c < r; c += 16) part = fma(src[c], v[c], part);
+                part = row16_allsum(part);
+                if (sub == 0) {
+                    if (isa) {
+                        const double pi = t * part;
+                        pA[i] = pi;
+                        pv[i] = pi * v[i];
+                    } else {
+                        pM[i] = part;
+                    }
+                }
+            }
+        }
+        if (tid == 0) {
+            d[j] = B[j + (int64_t)j * r];
+            e[j] = beta;
+        }
+        __syncthreads();
+        double K = 0.0;
+        if (refl) {
+            double part = 0.0;
+            for (int i = j + 1 + lane; i < r; i += 64) part += pv[i];
+            K = 0.5 * t * wave_allsum(part);
+        }
+        for (int c = j + 1 + wave; c < r; c += nwave) {
+            const double vc = v[c];
+            const double wc = refl ? pA[c] - K * vc : 0.0;
+            double* colc = B + (int64_t)c * r;
+            double sg = 0.0, a1 = 0.0;
+            for (int i = j + 1 + lane; i < r; i += 64) {
+                double x = colc[i];
+                if (refl) {
+                    const double vi = v[i];
+                    x -= vi * wc + (pA[i] - K * vi) * vc;
+                    colc[i] = x;
+                }
+                if (i >= j + 3) sg += x * x;
+                if (i == j + 2) a1 = x;
+            }
+            if (c == j + 1 && j + 3 < r) {   // uniform over the wavefront (wavefront 0)
+                const double sigma = wave_allsum(sg), alpha = wave_allsum(a1);
+                double t2, beta2, scal2;
+                reflector(alpha, sigma, t2, beta2, scal2);
+                double* vn = vb + s1 * r;
+                // each lane reads back only the rows it wrote above
+                for (int i = j + 1 + lane; i < r; i += 64)
+                    if (i >= j + 2) vn[i] = (i == j + 2) ? 1.0 : colc[i] * scal2;
+                if (lane == 0) {
+                    sc[2 * s1] = t2;
+                    sc[2 * s1 + 1] = beta2;
+                }
+            }
+        }
+        // M <- M - tau (M v) v^T on columns j+1..r-1
+        if (refl) {
+            for (int i = wave; i < r; i += nwave) {
+                const double mi = t * pM[i];
+                double* rowi = M + (int64_t)i * r;
+                for (int c = j + 1 + lane; c < r; c += 64) rowi[c] -= mi * v[c];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d[r - 2] = B[(r - 2) + (int64_t)(r - 2) * r];
+        d[r - 1] = B[(r - 1) + (int64_t)(r - 1) * r];
+        e[r - 2] = B[(r - 1) + (int64_t)(r - 2) * r];
+    }
+}
+
+constexpr double kEps = 1.1102230246251565e-16;      // 2^-53
+constexpr double kSafmin = 2.2250738585072014e-308;
+
+// number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots)
+__device__ int sturm_count(const double* d, const double* e2, int r, double x, double pivmin) {
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0 ? 1 : 0;
+#pragma unroll 4
+    for (int i = 1; i < r; ++i) {
+        q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0 ? 1 : 0;
+    }
+    return cnt;
+}
+
+// Lowest nw eigenvalues of T (ascending) by multisection: G lanes per eigenvalue (a
+// power of two, at most 32, so a group never straddles a wavefront) evaluate the Sturm
+// count at G interior points of the bracket, which shrinks G + 1 fold per step, down to
+// the absolute width eps ||T|| (or 2 eps |lambda| when larger).  The bracket starts from
+// the Gershgorin interval.  sc[4..7]: gl, gu, pivmin, ||T||.
+__device__ void bisect_lowest(const double* d, const double* e, double* e2, int r, int nw,
+                              double* theta, double* sc) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i + 1 < r; i += nt) e2[i] = e[i] * e[i];
+    if (wave == 0) {
+        double lo = 1.0 / 0.0, hi = -1.0 / 0.0, emax = 0.0;
+        for (int i = lane; i < r; i += 64) {
+            const double rad = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < r ? fabs(e[i]) : 0.0);
+            lo = fmin(lo, d[i] - rad);
+            hi = fmax(hi, d[i] + rad);
+            if (i + 1 < r) emax = fmax(emax, e[i] * e[i]);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, o, 64));
+            hi = fmax(hi, __shfl_xor(hi, o, 64));
+            emax = fmax(emax, __shfl_xor(emax, o, 64));
+        }
+        if (lane == 0) {
+            const double tnorm = fmax(fabs(lo), fabs(hi));
+            const double pivmin = kSafmin * fmax(1.0, emax);
+            const double pad = 2.0 * kEps * tnorm * r + 2.0 * pivmin;
+            sc[4] = lo - pad;
+            sc[5] = hi + pad;
+            sc[6] = pivmin;
+            sc[7] = tnorm;
+        }
+    }
+    __syncthreads();
+    const double gl = sc[4], gu = sc[5], pivmin = sc[6];
+    const double atol = kEps * sc[7];
+    int G = 1;
+    while (G < 32 && 2 * G * nw <= nt) G *= 2;
+    const int ng = nt / G;
+    const int g = tid % G;
+    const uint64_t gmask = (1ull << G) - 1;
+    const int gbase = (lane / G) * G;
+    const double inv_g1 = 1.0 / (double)(G + 1);
+    for (int j0 = 0; j0 < nw; j0 += ng) {
+        const int j = j0 + tid / G;
+        const bool act = j < nw;
+        double lo = gl, hi = gu;
+        for (int it = 0; it < 100; ++it) {
+            const bool done =
+                !act || hi - lo <= fmax(atol, 2.0 * kEps * fmax(fabs(lo), fabs(hi))) + 2.0 * pivmin;
+            if (__all(done)) break;
+            const double w = hi - lo;
+            const double x = lo + w * (double)(g + 1) * inv_g1;
+            const int cnt = act ? sturm_count(d, e2, r, x, pivmin) : 0;
+            const uint64_t bal = __ballot(cnt > j);
+            const uint64_t gm = (bal >> gbase) & gmask;
+            const int f = gm ? __builtin_ctzll(gm) : G;   // first point with lambda_j below it
+            const double nlo = f > 0 ? lo + w * (double)f * inv_g1 : lo;
+            const double nhi = f < G ? lo + w * (double)(f + 1) * inv_g1 : hi;
+            if (!done) {
+                lo = nlo;
+                hi = nhi;
+            }
+        }
+        if (act && g == 0) theta[j] = 0.5 * (lo + hi);
+    }
+}
+
+// One solve (T - lam I) x = z in place (z and the factor strided by nwp): LU with
+// partial pivoting between neighbouring rows, U with two superdiagonals (its diagonal
+// kept as reciprocals); the row operations are applied to z as they are made.  Zero
+// pivots become eps ||T||.
+__device__ void tri_solve(const double* d, const double* e, int r, double lam, double* z, double* u,
+                          int nwp, double tiny) {
+    double cd = d[0] - lam, cs1 = r > 1 ? e[0] : 0.0, cs2 = 0.0;
+    double yc = z[0];
+#pragma unroll 2
+    for (int i = 0; i + 1 < r; ++i) {
+        const double nd = e[i];
+        const double ns1 = d[i + 1] - lam;
+        const double ns2 = (i + 2 < r) ? e[i + 1] : 0.0;
+        const double yn = z[(int64_t)(i + 1) * nwp];
+        double* ui = u + (int64_t)3 * i * nwp;
+        if (fabs(cd) >= fabs(nd)) {
+            if (cd == 0.0) cd = tiny;
+            const double icd = rcp_nr(cd);
+            const double m = nd * icd;
+            ui[0] = icd;
+            ui[nwp] = cs1;
+            ui[2 * nwp] = cs2;
+            z[(int64_t)i * nwp] = yc;
+            cd = ns1 - m * cs1;
+            cs1 = ns2 - m * cs2;
+            yc = yn - m * yc;
+        } else {
+            const double ind = rcp_nr(nd);
+            const double m = cd * ind;
+            ui[0] = ind;
+            ui[nwp] = ns1;
+            ui[2 * nwp] = ns2;
+            z[(int64_t)i * nwp] = yn;
+            cd = cs1 - m * ns1;
+            cs1 = cs2 - m * ns2;
+            yc = yc - m * yn;
+        }
+        cs2 = 0.0;
+    }
+    if (cd == 0.0) cd = tiny;
+    double x1 = yc * rcp_nr(cd), x2 = 0.0;
+    z[(int64_t)(r - 1) * nwp] = x1;
+#pragma unroll 4
+    for (int i = r - 2; i >= 0; --i) {
+        const double* ui = u + (int64_t)3 * i * nwp;
+        double s = z[(int64_t)i * nwp] - ui[nwp] * x1;
+        if (i + 2 < r) s -= ui[2 * nwp] * x2;
+        const double xi = s * ui[0];
+        z[(int64_t)i * nwp] = xi;
+        x2 = x1;
+        x1 = xi;
+    }
+}
+
+// Eigenvectors of T for theta[0..nw) by two steps of inverse iteration, every vector in
+// its own thread; eigenvalues closer than 1e-3 ||T|| form a cluster whose vectors are
+// orthonormalised by modified Gram-Schmidt (one wavefront per cluster) after every
+// step, and whose equal shifts are separated by a few ulps.  Zt: r x nwp row-major
+// (vector q in column q); U3: 3 r x nwp.
+__device__ void inverse_iteration(const double* d, const double* e, int r, int nw, int nwp,
+                                  const double* theta, double* sh, double* Zt, double* U3,
+                                  int* cstart, int* csize, int* ncl, double tnorm) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+    if (tid == 0) {
+        const double ortol = 1e-3 * tnorm;
+        int c = -1;
+        for (int j = 0; j < nw; ++j) {
+            double s = theta[j];
+            if (j == 0 || theta[j] - theta[j - 1] > ortol) {
+                ++c;
+                cstart[c] = j;
+                csize[c] = 1;
+            } else {
+                ++csize[c];
+                const double prev = sh[j - 1];
+                if (s <= prev + 10.0 * kEps * fabs(prev)) s = prev + 10.0 * kEps * fmax(fabs(prev), 1e-3 * tnorm);
+            }
+            sh[j] = s;
+        }
+        *ncl = c + 1;
+    }
+    __syncthreads();
+    const double tiny = kEps * tnorm > 0.0 ? kEps * tnorm : kSafmin;
+    const int nc = *ncl;
+    for (int it = 0; it < 2; ++it) {
+        for (int q = tid; q < nw; q += nt) {
+            double* z = Zt + q;
+            if (it == 0) {
+                // start vector: a fixed, non-degenerate pattern per column
+                for (int i = 0; i < r; ++i) {
+                    const uint32_t h = (uint32_t)(i + 1) * 2654435761u ^ (uint32_t)(q + 1) * 2246822519u;
+                    z[(int64_t)i * nwp] = (double)((h >> 8) & 0xffff) * (1.0 / 65536.0) + 0.25;
+                }
+            }
+            tri_solve(d, e, r, sh[q], z, U3 + q, nwp, tiny);
+            double s2 = 0.0;
+#pragma unroll 4
+            for (int i = 0; i < r; ++i) s2 = fma(z[(int64_t)i * nwp], z[(int64_t)i * nwp], s2);
+            const double inv = rsq_nr(s2);
+#pragma unroll 4
+            for (int i = 0; i < r; ++i) z[(int64_t)i * nwp] *= inv;
+        }
+        __syncthreads();
+        for (int c = wave; c < nc; c += nwave) {
+            const int c0 = cstart[c], cn = csize[c];
+            for (int m = 1; m < cn; ++m) {
+                const int jj = c0 + m;
+                for (int i0 = c0; i0 < jj; ++i0) {
+                    double dot = 0.0;
+                    for (int row = lane; row < r; row += 64)
+                        dot = fma(Zt[(int64_t)row * nwp + i0], Zt[(int64_t)row * nwp + jj], dot);
+                    dot = wave_allsum(dot);
+                    for (int row = lane; row < r; row += 64)
+                        Zt[(int64_t)row * nwp + jj] -= dot * Zt[(int64_t)row * nwp + i0];
+                }
+                double s2 = 0.0;
+                for (int row = lane; row < r; row += 64)
+                    s2 = fma(Zt[(int64_t)row * nwp + jj], Zt[(int64_t)row * nwp + jj], s2);
+                const double inv = rsq_nr(wave_allsum(s2));
+                for (int row = lane; row < r; row += 64) Zt[(int64_t)row * nwp + jj] *= inv;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Workspace layout of the kernel, in doubles from a 16-byte-aligned base.  The main
+// route and the rank-revealing route share D, the flags, A and B, and otherwise overlay.
+// On the main route A holds L, then the product scratch, B holds D H_R D, then C, T
+// holds L^{-1} = M^T, then M = L^{-T} Q; the inverse-iteration factors reuse A and B
+// when they fit there.
+struct RRLayout {
+    int64_t D, flags, A, B;
+    int64_t T, Zt, U3, d, e, e2, invd, pA, pM, pv, vb, theta, sh, sc, icl, main_end;   // main route
+    int64_t V, fT, rot, ftheta, fsel, fb_end;                                      // rank-revealing
+    int64_t total;
+};
+
+__host__ __device__ inline RRLayout rr_layout(int k, int nwp) {
+    RRLayout L{};
+    const int64_t kk = (int64_t)k * k;
+    L.D = 0;
+    L.flags = k + (k & 1);             // 8 ints
+    L.A = L.flags + 4;
+    L.B = L.A + kk;
+    L.T = L.B + kk;
+    L.Zt = L.T + kk;
+    L.d = L.Zt + (int64_t)k * nwp;
+    L.e = L.d + k;
+    L.e2 = L.e + k;
+    L.invd = L.e2 + k;
+    L.pA = L.invd + k;
+    L.pM = L.pA + k;
+    L.pv = L.pM + k;
+    L.vb = L.pv + k;                   // 2 k
+    L.theta = L.vb + 2 * (int64_t)k;
+    L.sh = L.theta + k;
+    L.sc = L.sh + k;                   // 8 doubles
+    L.icl = L.sc + 8;                  // 2 k + 2 ints
+    L.main_end = L.icl + k + 1;
+    if ((int64_t)3 * k * nwp <= 2 * kk) {
+        L.U3 = L.A;
+    } else {
+        L.U3 = L.main_end;
+        L.main_end += (int64_t)3 * k * nwp;
+    }
+    L.V = L.B + kk;
+    L.fT = L.V + kk;
+    L.rot = L.fT + kk;                 // (k/2 + 1) double2 then (k/2 + 1) int2
+    if (L.rot & 1) L.rot += 1;
+    L.ftheta = L.rot + 3 * (int64_t)(k / 2 + 1);
+    L.fsel = L.ftheta + k;             // k ints
+    L.fb_end = L.fsel + k / 2 + 1;
+    L.total = L.main_end > L.fb_end ? L.main_end : L.fb_end;
+    return L;
+}
+
+// ALL_LDS: the whole layout in LDS (pointers derived from the LDS base only, so the
+// compiler emits LDS instructions); otherwise in the global workspace.  The global
+// workspace always holds the k x k product scratch of the rank-revealing route.
 template <bool ALL_LDS>
 __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
                                                               const double* __restrict__ HR,
@@ -155,51 +706,25 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
                                                               int64_t ldr, double* __restrict__ gamma,
                                                               double* __restrict__ W, int64_t ldw,
                                                               int32_t* __restrict__ info,
-                                                              double* gws, int lds_mask) {
+                                                              double* gws) {
     extern __shared__ double lds[];
+    __shared__ double red[kRRThreads / 64];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int64_t kk = (int64_t)k * k;
-    double* small = gws + 5 * kk;
-    double* D = small;                    // k
-    double* theta = D + k;                // k
-    double* after_theta = theta + k;
-    if ((uintptr_t)after_theta & 15) after_theta += 1;   // 16-byte alignment for double2
-    double2* rcs = (double2*)after_theta;          // k/2+1 rotations (cos, sin)
-    int2* rpq = (int2*)(rcs + (k / 2 + 1));        //       their index pairs
-    int* sel = (int*)(rpq + (k / 2 + 1));          // k
-    int* flag = sel + k;                           // 4
-    __shared__ double red[kRRThreads / 64];
-    // placement: bit 0 the rotation table, bit 1 B (H_R, then C: the Jacobi matrix),
-    // bit 2 V, bit 3 A, bit 4 T -- each in LDS when set, else in the global workspace
-    if (ALL_LDS) lds_mask = 31;
-    double* nextl = lds;
-    if (lds_mask & 1) {
-        rcs = (double2*)nextl;
-        rpq = (int2*)(rcs + (k / 2 + 1));
-        nextl += 3 * (k / 2 + 1);
-    }
-    double* B;
-    double* V;
-    double* A;
-    double* T;
-    if (ALL_LDS) {
-        B = nextl;
-        V = B + kk;
-        A = V + kk;
-        T = A + kk;
-    } else {
-        B = (lds_mask & 2) ? (nextl += kk) - kk : gws + kk;
-        V = (lds_mask & 4) ? (nextl += kk) - kk : gws + 2 * kk;
-        A = (lds_mask & 8) ? (nextl += kk) - kk : gws;
-        T = (lds_mask & 16) ? (nextl += kk) - kk : gws + 3 * kk;
-    }
-    double* U = gws + 4 * kk;    // scratch (global)
+    const int nwp = nwant | 1;
+    const RRLayout Lo = rr_layout(k, nwp);
+    double* galigned = gws + (((uintptr_t)gws & 15) ? 1 : 0);
+    double* base = ALL_LDS ? lds : galigned;
+    double* U = galigned + Lo.total;   // global scratch (rank-revealing route)
+    double* D = base + Lo.D;
+    int* flag = (int*)(base + Lo.flags);
+    double* A = base + Lo.A;
+    double* B = base + Lo.B;
 
     for (int i = tid; i < k; i += nt) {
-        const double d = SR[i + (int64_t)i * ldr];
-        D[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+        const double dd = SR[i + (int64_t)i * ldr];
+        D[i] = dd > 0.0 ? 1.0 / sqrt(dd) : 0.0;
     }
-    if (tid == 0) { flag[0] = 0; flag[1] = 0; }
     __syncthreads();
     for (int64_t e = tid; e < kk; e += nt) {
         const int i = (int)(e % k), j = (int)(e / k);
@@ -207,90 +732,84 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         B[e] = D[i] * HR[i + (int64_t)j * ldr] * D[j];
     }
     __syncthreads();
-    // Cholesky of the scaled S_R, right-looking, lower triangle in place
-    for (int j = 0; j < k; ++j) {
-        const double piv = A[j + (int64_t)j * k];
-        if (!(piv > kPivotTol)) {
-            if (tid == 0) flag[0] = 1;
-            break;   // uniform: every thread read the same pivot
-        }
-        const double l = sqrt(piv);
+    double* invd = base + Lo.invd;
+    if (cholesky_rl(A, k, invd)) {
         __syncthreads();
-        for (int i = j + 1 + tid; i < k; i += nt) A[i + (int64_t)j * k] /= l;
-        if (tid == 0) A[j + (int64_t)j * k] = l;
+        double* T = base + Lo.T;
+        double* Zt = base + Lo.Zt;
+        double* U3 = base + Lo.U3;
+        double* d = base + Lo.d;
+        double* e = base + Lo.e;
+        double* e2 = base + Lo.e2;
+        double* theta = base + Lo.theta;
+        double* sh = base + Lo.sh;
+        double* sc = base + Lo.sc;
+        int* cstart = (int*)(base + Lo.icl);
+        int* csize = cstart + k;
+        int* ncl = csize + k;
+        // X = L^{-1} into T; C = X B X^T via U = B X^T (into A, L is no longer needed)
+        invert_lower_rl(A, invd, T, k);
         __syncthreads();
-        // trailing update of the lower triangle, columns over thread rows, rows over lanes
-        {
-            const int tx = tid & 31, ty = tid >> 5, tys = nt >> 5;
-            for (int cc = j + 1 + ty; cc < k; cc += tys) {
-                const double lc = A[cc + (int64_t)j * k];
-                for (int i = cc + tx; i < k; i += 32) A[i + (int64_t)cc * k] -= A[i + (int64_t)j * k] * lc;
-            }
-        }
+        gemm_mfma(B, k, false, T, k, true, k, k, k,
+                  [&](int i, int j, double v) { A[i + (int64_t)j * k] = v; });
         __syncthreads();
+        gemm_mfma(T, k, false, A, k, false, k, k, k,
+                  [&](int i, int j, double v) { B[i + (int64_t)j * k] = v; });
+        __syncthreads();
+        symmetrize(B, k);
+        __syncthreads();
+        // T read row-major is X^T = L^{-T}: the reflectors accumulate onto it
+        tridiagonalize_acc(B, T, k, d, e, base + Lo.vb, base + Lo.pA, base + Lo.pM, base + Lo.pv, sc);
+        __syncthreads();
+        bisect_lowest(d, e, e2, k, nwant, theta, sc);
+        __syncthreads();
+        inverse_iteration(d, e, k, nwant, nwp, theta, sh, Zt, U3, cstart, csize, ncl, sc[7]);
+        // W = D M Z (M row-major in T, Z row-major in Zt with ld nwp)
+        gemm_mfma(T, k, true, Zt, nwp, true, k, nwant, k,
+                  [&](int i, int q, double v) { W[i + (int64_t)q * ldw] = D[i] * v; });
+        for (int q = tid; q < nwant; q += nt) gamma[q] = theta[q];
+        if (tid == 0) { info[0] = 0; info[1] = 0; }
+        return;
+    }
+    // ------------------------------------------------------------ rank-revealing route
+    __syncthreads();
+    double* V = base + Lo.V;
+    double* T = base + Lo.fT;
+    double2* rcs = (double2*)(base + Lo.rot);
+    int2* rpq = (int2*)(rcs + (k / 2 + 1));
+    double* theta = base + Lo.ftheta;
+    int* sel = (int*)(base + Lo.fsel);
+    // eigen-decompose the scaled S_R (V accumulates its vectors)
+    for (int64_t e = tid; e < kk; e += nt) {
+        const int i = (int)(e % k), j = (int)(e / k);
+        A[e] = D[i] * SR[i + (int64_t)j * ldr] * D[j];
+        V[e] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    const bool fallback = flag[0] != 0;
-    int r = k;
-    if (!fallback) {
-        // T = inv(L): one column per wavefront, forward substitution on e_c with the
-        // dot product of each row spread over the lanes
-        {
-            const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
-            for (int c = wave; c < k; c += nwave) {
-                double* t = T + (int64_t)c * k;
-                for (int i = lane; i < c; i += 64) t[i] = 0.0;
-                for (int i = c; i < k; ++i) {
-                    double part = 0.0;
-                    for (int p = c + lane; p < i; p += 64) part += A[i + (int64_t)p * k] * t[p];
-                    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
-                    part = __shfl(part, 0, 64);
-                    if (lane == 0) t[i] = (((i == c) ? 1.0 : 0.0) - part) / A[i + (int64_t)i * k];
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                }
-            }
-        }
-        __syncthreads();
-        // C = inv(L) B inv(L)^T  (U = B inv(L)^T, then C = inv(L) U into B)
-        small_gemm(B, false, T, true, U, k, k, k, k, k, k);
-        __syncthreads();
-        small_gemm(T, false, U, false, B, k, k, k, k, k, k);
-        __syncthreads();
-    } else {
-        // rank-revealing: eigen-decompose the scaled S_R (V accumulates its vectors)
-        for (int64_t e = tid; e < kk; e += nt) {
-            const int i = (int)(e % k), j = (int)(e / k);
-            A[e] = D[i] * SR[i + (int64_t)j * ldr] * D[j];
-            V[e] = (i == j) ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        jacobi(A, k, V, k, k, red, rcs, rpq);
-        __syncthreads();
-        double mx = 0.0;
-        for (int i = 0; i < k; ++i) mx = fmax(mx, A[i + (int64_t)i * k]);
-        if (tid == 0) {
-            int c = 0;
-            for (int i = 0; i < k; ++i)
-                if (A[i + (int64_t)i * k] > kRankTol * mx) sel[c++] = i;
-            flag[1] = c;
-        }
-        __syncthreads();
-        r = flag[1];
-        // T = Q_keep / sqrt(lambda_keep) (k x r, ld k)
-        for (int64_t e = tid; e < (int64_t)k * r; e += nt) {
-            const int i = (int)(e % k), c = (int)(e / k);
-            const int src = sel[c];
-            T[i + (int64_t)c * k] = V[i + (int64_t)src * k] / sqrt(A[src + (int64_t)src * k]);
-        }
-        __syncthreads();
-        // C = T^T B T (r x r, ld r) into B, via U = B T (k x r)
-        small_gemm(B, false, T, false, U, k, r, k, k, k, k);
-        __syncthreads();
-        small_gemm(T, true, U, false, B, r, r, k, k, k, r);
-        __syncthreads();
+    jacobi(A, k, V, k, k, red, rcs, rpq);
+    __syncthreads();
+    double mx = 0.0;
+    for (int i = 0; i < k; ++i) mx = fmax(mx, A[i + (int64_t)i * k]);
+    if (tid == 0) {
+        int c = 0;
+        for (int i = 0; i < k; ++i)
+            if (A[i + (int64_t)i * k] > kRankTol * mx) sel[c++] = i;
+        flag[1] = c;
     }
+    __syncthreads();
+    const int r = flag[1];
+    // T = Q_keep / sqrt(lambda_keep) (k x r, ld k)
+    for (int64_t e = tid; e < (int64_t)k * r; e += nt) {
+        const int i = (int)(e % k), c = (int)(e / k);
+        const int src = sel[c];
+        T[i + (int64_t)c * k] = V[i + (int64_t)src * k] / sqrt(A[src + (int64_t)src * k]);
+    }
+    __syncthreads();
+    // C = T^T B T (r x r, ld r) into B, via U = B T (k x r)
+    small_gemm(B, false, T, false, U, k, r, k, k, k, k);
+    __syncthreads();
+    small_gemm(T, true, U, false, B, r, r, k, k, k, r);
+    __syncthreads();
     if (r < nwant) {
         if (tid == 0) { info[0] = k - r; info[1] = (int)LABPSD_ERANK; }
         return;
@@ -321,16 +840,12 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     }
     __syncthreads();
     for (int q = tid; q < nwant; q += nt) gamma[q] = theta[sel[q]];
-    // W = D T_eff V(:, sel): T_eff = inv(L)^T (k x k) or the fallback basis (k x r)
+    // W = D T V(:, sel)
     for (int64_t e = tid; e < (int64_t)k * nwant; e += nt) {
         const int i = (int)(e % k), q = (int)(e / k);
         const int src = sel[q];
         double acc = 0.0;
-        if (!fallback) {
-            for (int p = i; p < k; ++p) acc = fma(T[p + (int64_t)i * k], V[p + (int64_t)src * r], acc);
-        } else {
-            for (int p = 0; p < r; ++p) acc = fma(T[i + (int64_t)p * k], V[p + (int64_t)src * r], acc);
-        }
+        for (int p = 0; p < r; ++p) acc = fma(T[i + (int64_t)p * k], V[p + (int64_t)src * r], acc);
         W[i + (int64_t)q * ldw] = D[i] * acc;
     }
     if (tid == 0) { info[0] = k - r; info[1] = 0; }
@@ -339,9 +854,9 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
 }  // namespace
 
 size_t rr_ws_bytes(int k) {
-    const size_t kk = (size_t)k * k;
-    return sizeof(double) * (5 * kk + 2 * (size_t)k + 2 * (size_t)(k / 2 + 1)) +
-           sizeof(int) * (2 * (size_t)(k / 2 + 1) + (size_t)k + 4) + 256;
+    // the layout at the widest nwant (= k) plus the k x k product scratch and alignment
+    const RRLayout L = rr_layout(k, k | 1);
+    return sizeof(double) * ((size_t)L.total + (size_t)k * k + 4);
 }
 
 void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, int64_t ldr,
@@ -350,7 +865,6 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
     if (k <= 0 || nwant <= 0) return;
     LABPSD_REQUIRE(k <= kRRMax, "Rayleigh-Ritz order exceeds the supported maximum");
     LABPSD_REQUIRE(nwant <= k, "more Ritz pairs requested than the search space holds");
-    // A, B, V, T and the rotation table in LDS when they fit the device's per-block limit
     static int lds_limit = -1;
     if (lds_limit < 0) {
         int dev = 0, v = 0;
@@ -360,33 +874,21 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
         (void)hipGetLastError();
         lds_limit = v;
     }
-    // fill LDS greedily: rotation table, the Jacobi matrix, its vectors, then L and inv(L)
-    const size_t mat = (size_t)k * k * sizeof(double);
-    size_t bytes = (size_t)(k / 2 + 1) * 24;
-    int mask = 1;
-    const size_t cap = lds_limit > 2048 ? (size_t)lds_limit - 1024 : 0;
-    for (int bit : {2, 4, 8, 16}) {
-        if (bytes + mat <= cap) {
-            bytes += mat;
-            mask |= bit;
-        }
-    }
-    if (bytes <= cap) {
-        const void* fn = mask == 31 ? (const void*)k_rayleigh_ritz<true> : (const void*)k_rayleigh_ritz<false>;
+    const RRLayout L = rr_layout(k, nwant | 1);
+    const size_t bytes = (size_t)L.total * sizeof(double);
+    // the static LDS of the kernel (the reduction array) stays below 1 KiB
+    if (lds_limit > 2048 && bytes <= (size_t)lds_limit - 1024) {
         if (bytes > 64 * 1024)
-            (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz<true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         (void)hipGetLastError();
-        if (mask == 31)
-            hipLaunchKernelGGL(k_rayleigh_ritz<true>, dim3(1), dim3(kRRThreads), bytes, s, k, nwant, HR,
-                               SR, ldr, gamma, W, ldw, info, (double*)ws, mask);
-        else
-            hipLaunchKernelGGL(k_rayleigh_ritz<false>, dim3(1), dim3(kRRThreads), bytes, s, k, nwant, HR,
-                               SR, ldr, gamma, W, ldw, info, (double*)ws, mask);
+        hipLaunchKernelGGL(k_rayleigh_ritz<true>, dim3(1), dim3(kRRThreads), bytes, s, k, nwant, HR, SR,
+                           ldr, gamma, W, ldw, info, (double*)ws);
         if (hipGetLastError() == hipSuccess) return;
         // the launch was refused (nothing ran): use the global-memory variant
     }
     hipLaunchKernelGGL(k_rayleigh_ritz<false>, dim3(1), dim3(kRRThreads), 0, s, k, nwant, HR, SR, ldr,
-                       gamma, W, ldw, info, (double*)ws, 0);
+                       gamma, W, ldw, info, (double*)ws);
     LABPSD_HIP(hipGetLastError());
 }
 
