@@ -7,10 +7,13 @@ in HBM.  The FP64 solve is the headline value; the mixed-precision solve (FP32
 preconditioner) is timed the same way beside it.
 
     python bench.py [--steps K] [--warmup W] [--workload c2] [--no-cpu-baseline]
+    python bench.py --serving            # SCF-like request stream
+    python bench.py --copy-calibration   # plain device copies of known size (counter scale)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -42,6 +45,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=4.0, help="system arrivals per second (Poisson)")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run 8 plain device copies of 512 MiB (the scale for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -49,26 +54,65 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else float("nan")
 
 
-def algorithmic(step, P, fi, st, nev, b, prec_bytes):
-    """Algorithmic bytes or flops of one step over the timed solves."""
-    n, nnz = P.n, P.nnz
-    nl = st["n_launch"][step]
-    cols = st["cols"][step]
-    if step in ("products_psi", "products_p"):
-        # matrix pattern + both value arrays once per launch, X read once, Y_H and Y_S written
-        return "hbm", nl * (4 * nnz + 16 * nnz + 8 * (n + 1)) + 24 * n * cols
-    if step == "residual":
-        return "hbm", 24 * n * cols
-    if step == "gram":
-        return "hbm", 24 * n * cols
-    if step == "block_update":
-        return "hbm", 24 * n * cols + 24 * n * b * (nl)
-    if step == "global_precond":
-        # factor panels read in the forward and the backward sweep, right-hand sides
-        # gathered, written and re-read once per sweep
-        applies = max(1, st["applies"])
-        return "hbm", applies * 2 * fi["nnz_factor"] * prec_bytes + 6 * n * cols * prec_bytes
-    return None, 0.0
+def rr_flops(k, nwant):
+    """Algorithmic flops of the reduced dense GHEP for its lowest nwant pairs (the LAPACK
+    route): Cholesky k^3/3, reduction to standard form k^3, tridiagonalisation 4k^3/3,
+    back-transformation of the vectors 2k^2 nwant, triangular solve k^2 nwant."""
+    return (8.0 / 3.0) * k ** 3 + 3.0 * k * k * nwant
+
+
+def spmm_bytes(P, w):
+    """Algorithmic bytes of one fused H/S product on w columns: the pattern (int32 columns,
+    int64 row offsets) and both FP64 value arrays once, X read once, Y_H and Y_S written."""
+    return 4 * P.nnz + 16 * P.nnz + 8 * (P.n + 1) + 8 * P.n * w + 16 * P.n * w
+
+
+def rr_orders(res_hist, b, tol):
+    """Orders k of the Rayleigh-Ritz problems of one solve: the start block (k = b), then
+    b + |U| for every iteration that found unconverged pairs."""
+    ks = [b]
+    for row in res_hist:
+        p = int(np.count_nonzero(row > tol))
+        if p:
+            ks.append(b + p)
+    return ks
+
+
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
+    there is none or the kernel's source has changed since the counters were taken."""
+    path = os.path.join(PROFILE_DIR, "hbm_traffic_c2.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("kernel="):
+            continue
+        f = dict(kv.split("=", 1) for kv in line.split())
+        if f.get("kernel") != kernel:
+            continue
+        src = os.path.join(ROOT, f["source"])
+        if not os.path.exists(src):
+            return None
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != f["sha256"]:
+            return None
+        return float(f["bytes_per_launch"])
+    return None
+
+
+def copy_calibration():
+    """Plain device-to-device copies of a known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 512 * 2 ** 20 // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(8):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_dispatch": 8 * n, "bytes_written_per_dispatch": 8 * n,
+                                           "dispatches": 8}}), flush=True)
 
 
 def serving(args):
@@ -155,6 +199,9 @@ def main():
     if args.serving:
         serving(args)
         return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     import paper_1308_2445_amd as lp
@@ -193,15 +240,23 @@ def main():
             lat.append(time.perf_counter() - t)
             outs.append(out)
             st = out.stats
+            ks = rr_orders(out.res_hist.cpu().numpy(), b, args.tol)
+            nrr, krr = st["n_launch"]["rayleigh_ritz"], st["cols"]["rayleigh_ritz"]
+            if len(ks) != nrr or sum(ks) != krr:
+                # the history does not resolve the orders: use their mean
+                print("[bench] Rayleigh-Ritz orders from the history disagree with the counters; "
+                      "using the mean order", file=sys.stderr, flush=True)
+                ks = [krr / max(1, nrr)] * nrr
             if agg is None:
                 agg = {"t": dict(st["t_step_s"]), "n_launch": dict(st["n_launch"]),
-                       "cols": dict(st["cols"]), "applies": st["outer_iters"]}
+                       "cols": dict(st["cols"]), "applies": st["outer_iters"], "rr_flops": 0.0}
             else:
                 for k in agg["t"]:
                     agg["t"][k] += st["t_step_s"][k]
                     agg["n_launch"][k] += st["n_launch"][k]
                     agg["cols"][k] += st["cols"][k]
                 agg["applies"] += st["outer_iters"]
+            agg["rr_flops"] += sum(rr_flops(k, b) for k in ks)
         return lat, outs, agg
 
     modes = [("fp64", lp.FP64)] + ([] if args.no_mixed else [("mixed", lp.MIXED)])
@@ -221,18 +276,29 @@ def main():
     f = results["fp64"]
     agg = f["agg"]
     steps_ms = {k: 1e3 * v / args.steps for k, v in agg["t"].items()}
-    # dominant kernel with a bandwidth or matrix-core roofline
-    cand = ["products_psi", "products_p", "residual", "gram", "block_update", "global_precond"]
-    dom = max(cand, key=lambda k: agg["t"][k])
-    bound, work = algorithmic(dom, P, fi, agg, nev, b, 8)
-    nl = max(1, agg["n_launch"][dom])
-    avg_launch_s = agg["t"][dom] / nl
-    per_launch = work / nl
-    achieved = per_launch / avg_launch_s / 1e9
-    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "launches": int(nl), "avg_launch_us": 1e6 * avg_launch_s,
-                "algorithmic_bytes_per_launch": per_launch}
+    # Roofline of the dominant kernel.  Steps that are one kernel launch each are timed
+    # per launch by the step events on the solver's stream: k_rayleigh_ritz (one per
+    # Rayleigh-Ritz step) dominates them; k_spmm_hs (the P and Psi products) is the
+    # dominant HBM-bound one.
+    nl_rr = max(1, agg["n_launch"]["rayleigh_ritz"])
+    t_rr = agg["t"]["rayleigh_ritz"] / nl_rr
+    rr_achieved = agg["rr_flops"] / nl_rr / t_rr / 1e12
+    roofline = {"bound": "mfma", "kernel": "k_rayleigh_ritz", "achieved": rr_achieved,
+                "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": rr_achieved / FP64_MFMA_PEAK_TFS,
+                "traffic": measured_traffic("k_rayleigh_ritz"),
+                "launches": int(nl_rr), "avg_launch_us": 1e6 * t_rr,
+                "algorithmic_flops_per_launch": agg["rr_flops"] / nl_rr,
+                "note": "one work-group solving the reduced pencil of order k <= %d: latency-bound "
+                        "(dependent steps and barriers), not throughput-bound" % (b + nev)}
+    nl_pp = agg["n_launch"]["products_p"] + agg["n_launch"]["products_psi"]
+    t_pp = (agg["t"]["products_p"] + agg["t"]["products_psi"]) / max(1, nl_pp)
+    bytes_pp = (agg["n_launch"]["products_p"] * spmm_bytes(P, 0) + agg["n_launch"]["products_psi"]
+                * spmm_bytes(P, 0) + 24 * P.n * (agg["cols"]["products_p"] + agg["cols"]["products_psi"]))
+    pp_achieved = bytes_pp / max(1, nl_pp) / t_pp / 1e9
+    roofline_hbm = {"bound": "hbm", "kernel": "k_spmm_hs", "achieved": pp_achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": pp_achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_spmm_hs"),
+                    "launches": int(nl_pp), "avg_launch_us": 1e6 * t_pp,
+                    "algorithmic_bytes_per_launch": bytes_pp / max(1, nl_pp)}
     line = {
         "metric": METRIC, "value": f["value"], "unit": "eigenpairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": f["ms"], "higher_is_better": True, "scaling": "weak",
@@ -250,6 +316,7 @@ def main():
         "setup_s": {"generate": t_gen, "factor_total": t_setup, "order": fi["t_order_s"],
                     "factor": fi["t_factor_s"], "upload": fi["t_upload_s"], "nnz_factor": fi["nnz_factor"]},
         "roofline": roofline,
+        "roofline_hbm": roofline_hbm,
     }
     if "mixed" in results:
         mx = results["mixed"]

@@ -258,7 +258,7 @@ class Problem:
             lam = torch.empty(nev, dtype=torch.float64, device="cuda")
             X = torch.empty((nev, n), dtype=torch.float64, device="cuda")
             out_where = MEM_DEVICE
-            hist_arg = None
+            hist_arg = torch.empty(max_outer * nev + nev, dtype=torch.float64, device="cuda")
         else:
             lam = np.zeros(nev)
             X = np.zeros((n, nev), order="F")
@@ -267,9 +267,9 @@ class Problem:
         rc = _lib.labpsd_solve(self.h, ctypes.byref(prm), _ptr(X0), _ptr(E0a), in_where, _ptr(lam), _ptr(X),
                                _ptr(hist_arg), ctypes.byref(nh), out_where, ctypes.byref(st))
         _check(rc, "labpsd_solve", allow=(OK, NOT_CONVERGED))
-        return SolveResult(status=rc, lam=lam, X=X,
-                           res_hist=hist[: nh.value * nev].reshape(nh.value, nev) if hist_arg is not None
-                           else np.zeros((0, nev)),
+        # the history is a host array, or (device_out) a device tensor view
+        src = hist_arg if hist_arg is not None else hist
+        return SolveResult(status=rc, lam=lam, X=X, res_hist=src[: nh.value * nev].reshape(nh.value, nev),
                            stats=st.as_dict())
 
     def close(self):
