@@ -132,33 +132,32 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
         F->panels32.upload(p32.data(), p32.size(), s);
         LABPSD_HIP(hipStreamSynchronize(s));
     }
-    // tasks per level and product: 64-row output tiles x 64-wide reduction chunks
-    // (triangular products skip the chunks above or below the diagonal tile)
+    // tasks: 64-row output tiles x 64-wide reduction chunks; per level the off-diagonal
+    // products (op 1: r_B -= F r_D, op 2: x_D -= F^T x_B), then one list of the diagonal
+    // products x_D = G r_D of every supernode
     constexpr int kTile = 64, kChunk = 64;
     std::vector<SnTask> tk;
     F->lev_off.assign(4 * (size_t)F->nlevels, 0);
     F->lev_count.assign(4 * (size_t)F->nlevels, 0);
+    auto add_tasks = [&](const Supernode& sn, int op) {
+        const int ncol = sn.ncol, nb = sn.nrow - sn.ncol;
+        const int nout = (op == 1) ? nb : ncol;
+        const int nred = (op == 2) ? nb : ncol;
+        for (int t = 0; t * kTile < nout; ++t)
+            for (int kc = 0; kc < nred; kc += kChunk)
+                tk.push_back(SnTask{sn.idx_off, sn.val_off, ncol, sn.nrow, t * kTile, kc});
+    };
     for (int l = 0; l < F->nlevels; ++l) {
-        for (int op = 0; op < 4; ++op) {
+        for (int op = 1; op <= 2; ++op) {
             F->lev_off[4 * l + op] = (int64_t)tk.size();
-            for (int i = 0; i < F->nsn; ++i) {
-                const Supernode& sn = H.sn[i];
-                if (sn.level != l) continue;
-                const int ncol = sn.ncol, nb = sn.nrow - sn.ncol;
-                const int nout = (op == 1) ? nb : ncol;
-                for (int t = 0; t * kTile < nout; ++t) {
-                    int k0 = 0, k1 = 0;
-                    if (op == 0) { k0 = 0; k1 = std::min(ncol, (t + 1) * kTile); }
-                    else if (op == 1) { k0 = 0; k1 = ncol; }
-                    else if (op == 2) { k0 = 0; k1 = nb; }
-                    else { k0 = t * kTile; k1 = ncol; }
-                    for (int kc = k0; kc < k1; kc += kChunk)
-                        tk.push_back(SnTask{sn.idx_off, sn.val_off, ncol, sn.nrow, t * kTile, kc});
-                }
-            }
+            for (int i = 0; i < F->nsn; ++i)
+                if (H.sn[i].level == l) add_tasks(H.sn[i], op);
             F->lev_count[4 * l + op] = (int64_t)tk.size() - F->lev_off[4 * l + op];
         }
     }
+    F->diag_off = (int64_t)tk.size();
+    for (int i = 0; i < F->nsn; ++i) add_tasks(H.sn[i], 0);
+    F->diag_count = (int64_t)tk.size() - F->diag_off;
     F->tasks.upload(tk.data(), tk.size(), s);
     LABPSD_HIP(hipStreamSynchronize(s));
     F->info.n_supernodes = F->nsn;

@@ -146,7 +146,7 @@ struct Sell {
 // metadata folded in so a work-group needs a single (scalar) load to start.
 struct SnTask {
     int64_t idx_off;   // offset of the supernode's row list in DevFactor::rows
-    int64_t val_off;   // offset of its panel [inv(L11) ; L21] (ld nrow)
+    int64_t val_off;   // offset of its panel [G ; F] (ld nrow)
     int32_t ncol;      // |D|
     int32_t nrow;      // |D| + |B|
     int32_t r0;        // first output row of the tile
@@ -162,9 +162,11 @@ struct DevFactor {
     DBuf<int32_t> rows;          // row lists (dof ids)
     DBuf<double> panels64;
     DBuf<float> panels32;
-    // work-group tasks grouped per level and per product: [level][op] with op 0 diag,
-    // 1 off-diag (forward), 2 off-diag transposed, 3 diag transposed (backward)
+    // work-group tasks: per level [level][op] with op 1 the forward off-diagonal product
+    // (r_B -= F r_D) and op 2 the backward one (x_D -= F^T x_B) (ops 0 and 3 unused),
+    // and one list of the diagonal products x_D = G r_D of all supernodes
     std::vector<int64_t> lev_off, lev_count;   // 4 * nlevels each
+    int64_t diag_off = 0, diag_count = 0;
     DBuf<SnTask> tasks;
     labpsd_factor_info info{};
 };

@@ -481,16 +481,29 @@ int factorize(const HostCSR& A, const double* kval, const double* coords, HostFa
             return;
         }
         double* panel = F.panels.data() + s.val_off;
-        // inverse of the diagonal block on top, L21 below
-        invert_lower(Fr.data(), nf, nc, panel, nt);
-        // invert_lower wrote an nc x nc block with ld nc; re-space it to ld nf
-        if (nb > 0) {
-            for (int64_t j = nc - 1; j >= 0; --j) {
-                std::memmove(panel + j * nf, panel + j * nc, sizeof(double) * nc);
+        // X = inv(L11) (lower, ld nc); the panel receives G = X^T X = (L11 L11^T)^{-1} on
+        // top (full, symmetric) and F = L21 X below
+        std::vector<double> X((size_t)nc * nc);
+        invert_lower(Fr.data(), nf, nc, X.data(), nt);
+        parallel_for(nc, nt, [&](int64_t b) {
+            // column b of G: G[a, b] = sum_{k >= max(a, b)} X[k, a] X[k, b]
+            const double* xb = X.data() + b * nc;
+            for (int64_t a = 0; a < nc; ++a) {
+                const double* xa = X.data() + a * nc;
+                double acc = 0.0;
+                for (int64_t k = std::max(a, b); k < nc; ++k) acc += xa[k] * xb[k];
+                panel[a + b * nf] = acc;
             }
-            for (int64_t j = 0; j < nc; ++j)
-                std::memcpy(panel + j * nf + nc, Fr.data() + j * nf + nc, sizeof(double) * nb);
-        }
+            // column b of F: F[i, b] = sum_{k >= b} L21[i, k] X[k, b]
+            double* fb = panel + b * nf + nc;
+            for (int64_t i = 0; i < nb; ++i) fb[i] = 0.0;
+            for (int64_t k = b; k < nc; ++k) {
+                const double xkb = xb[k];
+                if (xkb == 0.0) continue;
+                const double* l21k = Fr.data() + k * nf + nc;
+                for (int64_t i = 0; i < nb; ++i) fb[i] += l21k[i] * xkb;
+            }
+        });
         if (nb > 0) {
             auto U = std::make_unique<std::vector<double>>((size_t)nb * nb);
             for (int64_t j = 0; j < nb; ++j)
@@ -537,6 +550,15 @@ int factorize(const HostCSR& A, const double* kval, const double* coords, HostFa
 }
 
 void host_solve(const HostFactor& F, double* b) {
+    // forward: r_B -= F r_D, supernodes in postorder; then x_D = G r_D; backward:
+    // x_D -= F^T x_B, supernodes in reverse postorder
+    for (const Supernode& s : F.sn) {
+        const int32_t* r = F.rows.data() + s.idx_off;
+        const double* P = F.panels.data() + s.val_off;
+        const int64_t nc = s.ncol, nf = s.nrow;
+        for (int64_t j = 0; j < nc; ++j)
+            for (int64_t i = nc; i < nf; ++i) b[r[i]] -= P[i + j * nf] * b[r[j]];
+    }
     std::vector<double> z;
     for (const Supernode& s : F.sn) {
         const int32_t* r = F.rows.data() + s.idx_off;
@@ -544,26 +566,18 @@ void host_solve(const HostFactor& F, double* b) {
         const int64_t nc = s.ncol, nf = s.nrow;
         z.assign(nc, 0.0);
         for (int64_t j = 0; j < nc; ++j)
-            for (int64_t i = j; i < nc; ++i) z[i] += P[i + j * nf] * b[r[j]];
+            for (int64_t i = 0; i < nc; ++i) z[i] += P[i + j * nf] * b[r[j]];
         for (int64_t i = 0; i < nc; ++i) b[r[i]] = z[i];
-        for (int64_t j = 0; j < nc; ++j)
-            for (int64_t i = nc; i < nf; ++i) b[r[i]] -= P[i + j * nf] * z[j];
     }
     for (auto it = F.sn.rbegin(); it != F.sn.rend(); ++it) {
         const Supernode& s = *it;
         const int32_t* r = F.rows.data() + s.idx_off;
         const double* P = F.panels.data() + s.val_off;
         const int64_t nc = s.ncol, nf = s.nrow;
-        z.assign(nc, 0.0);
-        for (int64_t j = 0; j < nc; ++j) {
-            double acc = b[r[j]];
-            for (int64_t i = nc; i < nf; ++i) acc -= P[i + j * nf] * b[r[i]];
-            z[j] = acc;
-        }
         for (int64_t j = 0; j < nc; ++j) {
             double acc = 0.0;
-            for (int64_t i = j; i < nc; ++i) acc += P[i + j * nf] * z[i];
-            b[r[j]] = acc;
+            for (int64_t i = nc; i < nf; ++i) acc += P[i + j * nf] * b[r[i]];
+            b[r[j]] -= acc;
         }
     }
 }

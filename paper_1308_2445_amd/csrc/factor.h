@@ -18,9 +18,11 @@
 //
 // Output for the device apply: per supernode a column-major panel of nrow x ncol,
 // rows = [D (its own columns) ; B (rows in ancestors)], whose top ncol x ncol block
-// holds the explicit inverse of the diagonal Cholesky block (lower triangular) and
-// whose bottom nB x ncol block holds L21.  Row lists hold original dof indices, so
-// the symmetric permutation is folded into the gathers and scatters of the apply.
+// holds G = (L11 L11^T)^{-1} (full, symmetric) and whose bottom nB x ncol block holds
+// F = L21 L11^{-1}.  With them K^{-1} r is: r_B -= F r_D up the tree, x_D = G r_D for
+// every supernode, x_D -= F^T x_B down the tree; each supernode needs only the
+// right-hand side's own rows, so a tree level is one product.  Row lists hold original
+// dof indices, so the symmetric permutation is folded into the gathers and scatters.
 #pragma once
 
 #include <cstdint>
@@ -50,7 +52,7 @@ struct HostFactor {
     int64_t n = 0;
     std::vector<Supernode> sn;      // in postorder (children before parents)
     std::vector<int32_t> rows;      // concatenated row lists (original dof indices)
-    std::vector<double> panels;     // concatenated panels [inv(L11) ; L21], ld nrow
+    std::vector<double> panels;     // concatenated panels [G ; F], ld nrow
     std::vector<int32_t> perm;      // perm[position] = dof
     int32_t nlevels = 0;
     int64_t nnz_factor = 0;

@@ -2,23 +2,24 @@
 // supernodal Cholesky factor P^T K P = L L^T computed once on the host (eq. (ldl)).
 //
 // Each supernode t owns columns D_t (its separator or leaf) and row set D_t + B_t
-// (B_t in ancestors).  Its panel holds inv(L11) (lower) on top and L21 below, so the
-// substitutions become small dense products.  Supernodes of one tree level are
-// independent; levels run leaves to root (forward) and root to leaves (backward):
-//   forward  level l:  y[D] <- inv(L11) y[D]          (diag kernel, assign)
-//                      r[B] -= L21 y[D]               (off-diag kernel, atomic: siblings
-//                                                      share ancestor rows)
-//   backward level l:  z[D] <- y[D] - L21^T x[B]      (gather kernel)
-//                      x[D] <- inv(L11)^T z[D]        (diag kernel)
+// (B_t in ancestors).  Its panel holds G = (L11 L11^T)^{-1} on top and F = L21 L11^{-1}
+// below, which makes the two substitutions
+//   forward   r_B -= F r_D         level by level, leaves to root (atomic: siblings share
+//                                   ancestor rows)
+//   diagonal  x_D  = G r_D          every supernode at once
+//   backward  x_D -= F^T x_B       level by level, root to leaves
+// (with y = L^{-1} r and x = L^{-T} y this is x_D = L11^{-T} (L11^{-1} r_D - L21^T x_B)).
+// Every product reads only right-hand-side rows that are final when its launch starts.
 // The permutation is folded into the row lists (dof ids), so every block is read and
 // written in the caller's ordering.  Right-hand-side blocks are row-major, so a gathered
-// or updated row's 16 values are one contiguous segment.  Work-group task: 64 output rows x 16 right-hand
-// sides x one 64-wide chunk of the reduction dimension, staged through LDS in a single
-// round (every load of the task is in flight at once: the work is latency-bound at
-// these sizes); chunks of one output tile accumulate with atomics, so the large
-// separators at the top of the tree spread over many work-groups.  Outputs are zeroed
-// (or seeded) first.  T is double (FP64 mode) or float (mixed mode: FP32 panels, FP32
-// accumulation).
+// or updated row's 16 values are one contiguous segment.  The 64 x 64 by 64 x 16 product
+// of a task runs on the matrix cores (16x16x4 MFMA, one 16-row tile per wavefront).
+// Work-group task: 64 output rows x 16 right-hand sides x one 64-wide chunk of the
+// reduction dimension, staged through LDS in a single round (every load of the task is
+// in flight at once: the work is latency-bound at these sizes); chunks of one output
+// tile accumulate with atomics, so the large separators at the top of the tree spread
+// over many work-groups.  Outputs are zeroed first.  T is double (FP64 mode) or float
+// (mixed mode: FP32 panels, FP32 accumulation).
 #include <algorithm>
 
 #include "common.h"
@@ -31,14 +32,13 @@ constexpr int TR = 64;   // output rows per work-group
 constexpr int TC = 16;   // right-hand sides per work-group
 constexpr int KS = 64;   // reduction chunk per work-group (one LDS stage)
 
-enum { OP_DIAG = 0, OP_DIAG_T = 1, OP_OFFD = 2, OP_OFFD_T = 3 };
+enum { OP_DIAG = 0, OP_OFFD = 2, OP_OFFD_T = 3 };
 
-// Tiled product for one task (supernode, output tile, reduction chunk) of a level;
-// every op accumulates atomically into its output:
-//  OP_DIAG   out[D[r]] += sum_{k<=r} inv(L11)[r,k] in[D[k]]
-//  OP_DIAG_T out[D[r]] += sum_{k>=r} inv(L11)[k,r] in[D[k]]
-//  OP_OFFD   out[B[r]] -= sum_k L21[r,k] in[D[k]]
-//  OP_OFFD_T out[D[r]] -= sum_k L21[k,r] in[B[k]]
+// Tiled product for one task (supernode, output tile, reduction chunk); every op
+// accumulates atomically into its output:
+//  OP_DIAG   out[D[r]] += sum_k G[r,k] in[D[k]]
+//  OP_OFFD   out[B[r]] -= sum_k F[r,k] in[D[k]]
+//  OP_OFFD_T out[D[r]] -= sum_k F[k,r] in[B[k]]
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ tasks,
                                                     const int32_t* __restrict__ rows,
@@ -60,12 +60,11 @@ __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ t
     else { nout = ncol; nred = ncol; }
     const int r0 = tk.r0;
     const int kb = tk.k0;
-    // reduction range of the chunk (triangular blocks skip the zero half)
-    int k_end = min(nred, kb + KS);
-    if (OP == OP_DIAG) k_end = min(k_end, r0 + TR);
+    // reduction range of the chunk
+    const int k_end = min(nred, kb + KS);
 
     __shared__ T sM[KS][TR + 1];      // sM[k][r] = M(r0 + r, kb + k)
-    __shared__ T sX[KS][TC];          // sX[k][c] = in[row(kb + k), c0 + c]
+    __shared__ T sX[KS][TC + 1];      // sX[k][c] = in[row(kb + k), c0 + c]
     const int t = threadIdx.x;
     // stage M(r, k) for r in [r0, r0+TR), k in [kb, kb+KS); every load issued before any use
     T mv[TR * KS / 256];
@@ -73,20 +72,17 @@ __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ t
     for (int i = 0; i < TR * KS / 256; ++i) {
         const int e = t + 256 * i;
         T v = T(0);
-        if (OP == OP_DIAG || OP == OP_OFFD) {
+        if (OP != OP_OFFD_T) {
             // column-major panel: consecutive threads walk rows (contiguous)
             const int r = r0 + (e % TR), k = kb + e / TR;
             if (r < nout && k < k_end) {
                 const int prow = (OP == OP_OFFD) ? ncol + r : r;
-                if (OP == OP_OFFD || k <= r) v = P[prow + (int64_t)k * nrow];
+                v = P[prow + (int64_t)k * nrow];
             }
         } else {
-            // transposed: M(r, k) = panel(krow, r); consecutive threads walk k
+            // transposed: M(r, k) = F(k, r); consecutive threads walk k
             const int k = kb + (e % KS), r = r0 + e / KS;
-            if (r < nout && k < k_end) {
-                const int krow = (OP == OP_OFFD_T) ? ncol + k : k;
-                if (OP == OP_OFFD_T || k >= r) v = P[krow + (int64_t)r * nrow];
-            }
+            if (r < nout && k < k_end) v = P[(ncol + k) + (int64_t)r * nrow];
         }
         mv[i] = v;
     }
@@ -107,7 +103,7 @@ __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ t
 #pragma unroll
     for (int i = 0; i < TR * KS / 256; ++i) {
         const int e = t + 256 * i;
-        if (OP == OP_DIAG || OP == OP_OFFD) sM[e / TR][e % TR] = mv[i];
+        if (OP != OP_OFFD_T) sM[e / TR][e % TR] = mv[i];
         else sM[e % KS][e / KS] = mv[i];
     }
 #pragma unroll
@@ -116,24 +112,31 @@ __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ t
         sX[e / TC][e % TC] = xv[i];
     }
     __syncthreads();
-    // thread: right-hand side c, output rows rb, rb + 16, rb + 32, rb + 48 of the tile
-    const int c = t % TC, rb = t / TC;
-    T acc[TR / 16] = {};
+    // the 64 x 16 output tile is four 16 x 16 matrix-core tiles, one per wavefront (rows
+    // 16 w .. 16 w + 15); operands: A lane l = M(16 w + l % 16, k0 + l / 16), B lane l =
+    // X(k0 + l / 16, l % 16); staged zeros cover the chunk beyond k_end
+    const int lane = t & 63, wave = t >> 6;
     const int kn = k_end - kb;
-#pragma unroll 8
-    for (int kk = 0; kk < kn; ++kk) {
-        const T x = sX[kk][c];
-#pragma unroll
-        for (int j = 0; j < TR / 16; ++j) acc[j] = fma(sM[kk][rb + 16 * j], x, acc[j]);
+    typedef T acc_t __attribute__((ext_vector_type(4)));
+    acc_t acc = {T(0), T(0), T(0), T(0)};
+    for (int k0 = 0; k0 < kn; k0 += 4) {
+        const T a = sM[k0 + (lane >> 4)][16 * wave + (lane & 15)];
+        const T b = sX[k0 + (lane >> 4)][lane & 15];
+        if constexpr (sizeof(T) == 8) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        else acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     }
+    const int c = lane & 15;
     if (c >= nc) return;
     const bool sub = (OP == OP_OFFD || OP == OP_OFFD_T);
 #pragma unroll
-    for (int j = 0; j < TR / 16; ++j) {
-        const int r = r0 + rb + 16 * j;
+    for (int q = 0; q < 4; ++q) {
+        // accumulator layout: register q of lane l holds row 4q + l / 16 (FP64) or
+        // 4 (l / 16) + q (FP32) of the tile, column l % 16
+        const int rt = (sizeof(T) == 8) ? 4 * q + (lane >> 4) : 4 * (lane >> 4) + q;
+        const int r = r0 + 16 * wave + rt;
         if (r < nout) {
             const int64_t g = (OP == OP_OFFD) ? rl[ncol + r] : rl[r];
-            atomicAdd(&out[g * nrhs + c0 + c], sub ? -acc[j] : acc[j]);
+            atomicAdd(&out[g * nrhs + c0 + c], sub ? -acc[q] : acc[q]);
         }
     }
 }
@@ -167,30 +170,24 @@ void launch_level(const DevFactor& F, const SnTask* tasks, int64_t ntasks, const
 
 }  // namespace
 
-// Y: right-hand sides on entry (consumed); W1: forward solution; W2: result K^{-1} Y.
-// All three are n x ncols row-major.
+// Y: right-hand sides on entry (consumed); W2: result K^{-1} Y; W1 is not used.
+// All are n x ncols row-major.
 template <typename T>
 void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int ncols,
                           hipStream_t s) {
+    (void)W1;
     const T* panels;
     if constexpr (sizeof(T) == 8) panels = F.panels64.p;
     else panels = F.panels32.p;
     const int L = F.nlevels;
-    const int64_t nb = n * ncols;
-    fill_copy<T>(W1, nullptr, nb, s);
-    fill_copy<T>(W2, nullptr, nb, s);
-    for (int l = 0; l < L; ++l) {
-        const int64_t* o = &F.lev_off[4 * l];
-        launch_level<T, OP_DIAG>(F, F.tasks.p + o[0], F.lev_count[4 * l + 0], panels, Y, W1, ncols, s);
-        launch_level<T, OP_OFFD>(F, F.tasks.p + o[1], F.lev_count[4 * l + 1], panels, W1, Y, ncols, s);
-    }
-    // z = y - L21^T x accumulates into a copy of the forward solution, held in Y
-    fill_copy<T>(Y, W1, nb, s);
-    for (int l = L - 1; l >= 0; --l) {
-        const int64_t* o = &F.lev_off[4 * l];
-        launch_level<T, OP_OFFD_T>(F, F.tasks.p + o[2], F.lev_count[4 * l + 2], panels, W2, Y, ncols, s);
-        launch_level<T, OP_DIAG_T>(F, F.tasks.p + o[3], F.lev_count[4 * l + 3], panels, Y, W2, ncols, s);
-    }
+    fill_copy<T>(W2, nullptr, n * ncols, s);
+    for (int l = 0; l < L; ++l)
+        launch_level<T, OP_OFFD>(F, F.tasks.p + F.lev_off[4 * l + 1], F.lev_count[4 * l + 1], panels, Y, Y,
+                                 ncols, s);
+    launch_level<T, OP_DIAG>(F, F.tasks.p + F.diag_off, F.diag_count, panels, Y, W2, ncols, s);
+    for (int l = L - 1; l >= 0; --l)
+        launch_level<T, OP_OFFD_T>(F, F.tasks.p + F.lev_off[4 * l + 2], F.lev_count[4 * l + 2], panels, W2,
+                                   W2, ncols, s);
 }
 
 template void launch_precond_solve<double>(const DevFactor&, double*, double*, double*, int64_t, int,

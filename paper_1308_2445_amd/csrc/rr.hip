@@ -50,7 +50,7 @@ __device__ void jacobi(double* M, int r, double* V, int ldv, int vrows, double* 
     const int npair = re / 2;
     double f = 0.0;
     for (int j = 0; j < r; ++j)
-        for (int i = tid; i < r; i += nt) f += M[i + (int64_t)j * r] * M[i + (int64_t)j * r];
+        for (int i = tid; i < r; i += nt) f += M[i + j * r] * M[i + j * r];
     const double fro = sqrt(block_sum(f, red));
     if (fro == 0.0) return;
     const double skip = 1e-18 * fro;
@@ -63,7 +63,7 @@ __device__ void jacobi(double* M, int r, double* V, int ldv, int vrows, double* 
         double off = 0.0;
         for (int j = 0; j < r; ++j)
             for (int i = tid; i < r; i += nt)
-                if (i != j) off += M[i + (int64_t)j * r] * M[i + (int64_t)j * r];
+                if (i != j) off += M[i + j * r] * M[i + j * r];
         off = block_sum(off, red);
         if (sqrt(off) <= 1e-13 * fro) break;
         for (int round = 0; round < re - 1; ++round) {
@@ -81,9 +81,9 @@ __device__ void jacobi(double* M, int r, double* V, int ldv, int vrows, double* 
                 if (p > q) { const int t = p; p = q; q = t; }
                 double c = 1.0, s = 0.0;
                 if (q < r) {
-                    const double apq = M[p + (int64_t)q * r];
+                    const double apq = M[p + q * r];
                     if (fabs(apq) > skip) {
-                        const double app = M[p + (int64_t)p * r], aqq = M[q + (int64_t)q * r];
+                        const double app = M[p + p * r], aqq = M[q + q * r];
                         const double th = (aqq - app) / (2.0 * apq);
                         const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                         c = 1.0 / sqrt(t * t + 1.0);
@@ -103,10 +103,10 @@ __device__ void jacobi(double* M, int r, double* V, int ldv, int vrows, double* 
                 const int2 pqa = rpq[a], pqb = rpq[b];
                 const int pa = pqa.x, qa = pqa.y, pb = pqb.x, qb = pqb.y;
                 const bool va = qa < r, vb = qb < r;   // pa, pb always < r
-                double m00 = M[pa + (int64_t)pb * r];
-                double m01 = vb ? M[pa + (int64_t)qb * r] : 0.0;
-                double m10 = va ? M[qa + (int64_t)pb * r] : 0.0;
-                double m11 = (va && vb) ? M[qa + (int64_t)qb * r] : 0.0;
+                double m00 = M[pa + pb * r];
+                double m01 = vb ? M[pa + qb * r] : 0.0;
+                double m10 = va ? M[qa + pb * r] : 0.0;
+                double m11 = (va && vb) ? M[qa + qb * r] : 0.0;
                 // columns: (p, q) <- (c p - s q, s p + c q); then the same on rows
                 const double n00 = csb.x * m00 - csb.y * m01, n01 = csb.y * m00 + csb.x * m01;
                 const double n10 = csb.x * m10 - csb.y * m11, n11 = csb.y * m10 + csb.x * m11;
@@ -115,10 +115,10 @@ __device__ void jacobi(double* M, int r, double* V, int ldv, int vrows, double* 
                 m01 = csa.x * n01 - csa.y * n11;
                 m11 = csa.y * n01 + csa.x * n11;
                 if (a == b) { m01 = 0.0; m10 = 0.0; }
-                M[pa + (int64_t)pb * r] = m00;
-                if (vb) M[pa + (int64_t)qb * r] = m01;
-                if (va) M[qa + (int64_t)pb * r] = m10;
-                if (va && vb) M[qa + (int64_t)qb * r] = m11;
+                M[pa + pb * r] = m00;
+                if (vb) M[pa + qb * r] = m01;
+                if (va) M[qa + pb * r] = m10;
+                if (va && vb) M[qa + qb * r] = m11;
             }
             // V' = V J
             for (int e = tid; e < nvec; e += nt) {
@@ -127,9 +127,9 @@ __device__ void jacobi(double* M, int r, double* V, int ldv, int vrows, double* 
                 const double2 cs = rcs[a];
                 if (cs.y == 0.0) continue;
                 const int2 pq = rpq[a];
-                const double vp = V[i + (int64_t)pq.x * ldv], vq = V[i + (int64_t)pq.y * ldv];
-                V[i + (int64_t)pq.x * ldv] = cs.x * vp - cs.y * vq;
-                V[i + (int64_t)pq.y * ldv] = cs.y * vp + cs.x * vq;
+                const double vp = V[i + pq.x * ldv], vq = V[i + pq.y * ldv];
+                V[i + pq.x * ldv] = cs.x * vp - cs.y * vq;
+                V[i + pq.y * ldv] = cs.y * vp + cs.x * vq;
             }
             __syncthreads();
         }
@@ -139,15 +139,15 @@ __device__ void jacobi(double* M, int r, double* V, int ldv, int vrows, double* 
 // Y = X^T Z or X Z (k x k blocks, column-major, ld k; op selects the transpose of X)
 __device__ void small_gemm(const double* X, bool xt, const double* Z, bool zt, double* Y, int rows,
                            int cols, int inner, int ldx, int ldz, int ldy) {
-    for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += blockDim.x) {
+    for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
         const int i = (int)(e % rows), j = (int)(e / rows);
         double acc = 0.0;
         for (int p = 0; p < inner; ++p) {
-            const double x = xt ? X[p + (int64_t)i * ldx] : X[i + (int64_t)p * ldx];
-            const double z = zt ? Z[j + (int64_t)p * ldz] : Z[p + (int64_t)j * ldz];
+            const double x = xt ? X[p + i * ldx] : X[i + p * ldx];
+            const double z = zt ? Z[j + p * ldz] : Z[p + j * ldz];
             acc = fma(x, z, acc);
         }
-        Y[i + (int64_t)j * ldy] = acc;
+        Y[i + j * ldy] = acc;
     }
 }
 
@@ -166,6 +166,13 @@ __device__ __forceinline__ double row16_allsum(double v) {
     v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
     v += dpp_d<0x124>(v);   // row_ror 4
     v += dpp_d<0x128>(v);   // row_ror 8
+    return v;
+}
+// sum over each group of 8 lanes (half a DPP row), in every lane of the group
+__device__ __forceinline__ double row8_allsum(double v) {
+    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);   // row_half_mirror
     return v;
 }
 __device__ __forceinline__ double readlane_d(double v, int l) {
@@ -188,6 +195,11 @@ __device__ __forceinline__ double rcp_nr(double x) {
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
+}
+// one Newton step: within about 10 ulp (enough for the Sturm counts)
+__device__ __forceinline__ double rcp_nr1(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
 }
 __device__ __forceinline__ double rsq_nr(double x) {
     double r = __builtin_amdgcn_rsq(x);
@@ -212,8 +224,8 @@ __device__ void gemm_mfma(const double* A, int lda, bool ta, const double* B, in
         for (int p0 = 0; p0 < kd; p0 += 4) {
             const int pk = p0 + kq;
             double a = 0.0, b = 0.0;
-            if (ar < m && pk < kd) a = ta ? A[pk + (int64_t)ar * lda] : A[ar + (int64_t)pk * lda];
-            if (bc < n && pk < kd) b = tb ? B[bc + (int64_t)pk * ldb] : B[pk + (int64_t)bc * ldb];
+            if (ar < m && pk < kd) a = ta ? A[pk + ar * lda] : A[ar + pk * lda];
+            if (bc < n && pk < kd) b = tb ? B[bc + pk * ldb] : B[pk + bc * ldb];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
         // accumulator layout: register q of lane l holds row 4q + l / 16, column l % 16
@@ -234,27 +246,27 @@ __device__ bool cholesky_rl(double* A, int r, double* invd) {
     const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
     double il_prev = 0.0, l_prev = 0.0;
     for (int j = 0; j < r; ++j) {
-        const double piv = A[j + (int64_t)j * r];
+        const double piv = A[j + j * r];
         if (!(piv > kPivotTol)) return false;
         const double il = rsq_nr(piv);
         const double ip = il * il;
         if (j > 0) {
-            for (int i = j + tid; i < r; i += nt) A[i + (int64_t)(j - 1) * r] *= il_prev;
+            for (int i = j + tid; i < r; i += nt) A[i + (j - 1) * r] *= il_prev;
             if (tid == 0) {
-                A[(j - 1) + (int64_t)(j - 1) * r] = l_prev;
+                A[(j - 1) + (j - 1) * r] = l_prev;
                 invd[j - 1] = il_prev;
             }
         }
         for (int c = j + 1 + wave; c < r; c += nwave) {
-            const double acj = A[c + (int64_t)j * r] * ip;
-            for (int i = c + lane; i < r; i += 64) A[i + (int64_t)c * r] -= A[i + (int64_t)j * r] * acj;
+            const double acj = A[c + j * r] * ip;
+            for (int i = c + lane; i < r; i += 64) A[i + c * r] -= A[i + j * r] * acj;
         }
         il_prev = il;
         l_prev = piv * il;
         __syncthreads();
     }
     if (tid == 0) {
-        A[(r - 1) + (int64_t)(r - 1) * r] = l_prev;
+        A[(r - 1) + (r - 1) * r] = l_prev;
         invd[r - 1] = il_prev;
     }
     return true;
@@ -266,7 +278,7 @@ __device__ bool cholesky_rl(double* A, int r, double* invd) {
 __device__ void invert_lower_rl(const double* L, const double* invd, double* X, int r) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
-    for (int64_t e = tid; e < (int64_t)r * r; e += nt) {
+    for (int e = tid; e < r * r; e += nt) {
         const int i = (int)(e % r), c = (int)(e / r);
         X[e] = (i == c) ? 1.0 : 0.0;
     }
@@ -275,26 +287,26 @@ __device__ void invert_lower_rl(const double* L, const double* invd, double* X, 
         const double ij = invd[j];
         if (j > 0) {
             const double ip = invd[j - 1];
-            for (int c = tid; c < j; c += nt) X[(j - 1) + (int64_t)c * r] *= ip;
+            for (int c = tid; c < j; c += nt) X[(j - 1) + c * r] *= ip;
         }
         for (int c = wave; c <= j; c += nwave) {
-            const double xjc = X[j + (int64_t)c * r] * ij;
-            for (int i = j + 1 + lane; i < r; i += 64) X[i + (int64_t)c * r] -= L[i + (int64_t)j * r] * xjc;
+            const double xjc = X[j + c * r] * ij;
+            for (int i = j + 1 + lane; i < r; i += 64) X[i + c * r] -= L[i + j * r] * xjc;
         }
         __syncthreads();
     }
     const double ip = invd[r - 1];
-    for (int c = tid; c < r; c += nt) X[(r - 1) + (int64_t)c * r] *= ip;
+    for (int c = tid; c < r; c += nt) X[(r - 1) + c * r] *= ip;
 }
 
 // B <- (B + B^T) / 2 in place
 __device__ void symmetrize(double* B, int r) {
-    for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += blockDim.x) {
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
         const int i = (int)(e % r), j = (int)(e / r);
         if (i < j) {
-            const double m = 0.5 * (B[i + (int64_t)j * r] + B[j + (int64_t)i * r]);
-            B[i + (int64_t)j * r] = m;
-            B[j + (int64_t)i * r] = m;
+            const double m = 0.5 * (B[i + j * r] + B[j + i * r]);
+            B[i + j * r] = m;
+            B[j + i * r] = m;
         }
     }
 }
@@ -317,11 +329,14 @@ __device__ __forceinline__ void reflector(double alpha, double sigma, double& ta
 // tridiagonal form Q^T B Q = T (diagonal d, off-diagonal e), with Q = H_0 H_1 ... and
 // H_j = I - tau_j v v^T on rows j+1..r-1, v = (1, v_{j+2}, ...).  The reflectors are
 // accumulated on the right of M (r x r, row-major: M[i, c] at i r + c), M <- M H_j.
-// Two barriers per reflector: the products p = tau A22 v and M v (16 lanes per row,
-// with the terms of p . v stored per row), then the rank-2 update
-// A22 -= v w^T + w v^T, w = p - (tau/2)(p . v) v, and the rank-1 update of M.
-// Wavefront 0 owns column j + 1 in the update and builds the next reflector from it
-// right away (vb double buffer of 2 r doubles; sc[2 s], sc[2 s + 1]: tau, beta).
+// Two barriers per reflector:
+//   products  p = tau A22 v and M v, 8 lanes per row (A22 is symmetric, so row i is
+//             read as column i), the terms of p . v stored per row;
+//   updates   wavefront 0 updates column j + 1 of A22 and builds the next reflector from
+//             it (vb double buffer of 2 r doubles; sc[2 s], sc[2 s + 1]: tau, beta); the
+//             other wavefronts apply A22 -= v w^T + w v^T, w = p - (tau/2)(p . v) v, to
+//             columns j + 2.. and M -= tau (M v) v^T, two columns or rows per batch with
+//             every load issued before the stores.
 // pA, pM, pv: r doubles each.
 __device__ void tridiagonalize_acc(double* B, double* M, int r, double* d, double* e, double* vb,
                                    double* pA, double* pM, double* pv, double* sc) {
@@ -348,23 +363,24 @@ __device__ void tridiagonalize_acc(double* B, double* M, int r, double* d, doubl
         }
     }
     __syncthreads();
-    const int g = tid >> 4, sub = tid & 15, ng = nt >> 4;
+    const int g = tid >> 3, sub = tid & 7, ng = nt >> 3;
+    const int w1 = wave - 1, nw1 = nwave - 1;   // the update wavefronts other than 0
     for (int j = 0; j + 2 < r; ++j) {
         const int s0 = j & 1, s1 = s0 ^ 1;
         const double t = sc[2 * s0], beta = sc[2 * s0 + 1];
         const bool refl = t != 0.0;   // uniform: every thread read the same tau
         const double* v = vb + s0 * r;
         if (refl) {
-            // row tasks: A22 rows j+1..r-1 (p = tau A22 v; A22 symmetric, so column i),
-            // then M rows 0..r-1 (M v)
+            // row tasks: A22 rows j+1..r-1, then M rows 0..r-1
             const int na = r - j - 1;
             for (int task = g; task < na + r; task += ng) {
                 const bool isa = task < na;
                 const int i = isa ? j + 1 + task : task - na;
-                const double* src = isa ? B + (int64_t)i * r : M + (int64_t)i * r;
+                const double* src = isa ? B + i * r : M + i * r;
                 double part = 0.0;
-                for (int c = j + 1 + sub; c < r; c += 16) part = fma(src[c], v[c], part);
-                part = row16_allsum(part);
+#pragma unroll 4
+                for (int c = j + 1 + sub; c < r; c += 8) part = fma(src[c], v[c], part);
+                part = row8_allsum(part);
                 if (sub == 0) {
                     if (isa) {
                         const double pi = t * part;
@@ -377,7 +393,7 @@ __device__ void tridiagonalize_acc(double* B, double* M, int r, double* d, doubl
             }
         }
         if (tid == 0) {
-            d[j] = B[j + (int64_t)j * r];
+            d[j] = B[j + j * r];
             e[j] = beta;
         }
         __syncthreads();
@@ -387,10 +403,12 @@ __device__ void tridiagonalize_acc(double* B, double* M, int r, double* d, doubl
             for (int i = j + 1 + lane; i < r; i += 64) part += pv[i];
             K = 0.5 * t * wave_allsum(part);
         }
-        for (int c = j + 1 + wave; c < r; c += nwave) {
-            const double vc = v[c];
+        if (wave == 0) {
+            // column j + 1, then the next reflector from it
+            const int c = j + 1;
+            const double vc = 1.0;
             const double wc = refl ? pA[c] - K * vc : 0.0;
-            double* colc = B + (int64_t)c * r;
+            double* colc = B + c * r;
             double sg = 0.0, a1 = 0.0;
             for (int i = j + 1 + lane; i < r; i += 64) {
                 double x = colc[i];
@@ -402,7 +420,7 @@ __device__ void tridiagonalize_acc(double* B, double* M, int r, double* d, doubl
                 if (i >= j + 3) sg += x * x;
                 if (i == j + 2) a1 = x;
             }
-            if (c == j + 1 && j + 3 < r) {   // uniform over the wavefront (wavefront 0)
+            if (j + 3 < r) {
                 const double sigma = wave_allsum(sg), alpha = wave_allsum(a1);
                 double t2, beta2, scal2;
                 reflector(alpha, sigma, t2, beta2, scal2);
@@ -415,21 +433,54 @@ __device__ void tridiagonalize_acc(double* B, double* M, int r, double* d, doubl
                     sc[2 * s1 + 1] = beta2;
                 }
             }
-        }
-        // M <- M - tau (M v) v^T on columns j+1..r-1
-        if (refl) {
-            for (int i = wave; i < r; i += nwave) {
-                const double mi = t * pM[i];
-                double* rowi = M + (int64_t)i * r;
-                for (int c = j + 1 + lane; c < r; c += 64) rowi[c] -= mi * v[c];
+        } else if (refl) {
+            // A22 columns j+2..r-1: lanes over rows, two columns per batch
+            for (int i0 = j + 1; i0 < r; i0 += 64) {
+                const int i = i0 + lane;
+                const bool okr = i < r;
+                const double vi = okr ? v[i] : 0.0;
+                const double wi = okr ? pA[i] - K * vi : 0.0;
+                for (int c0 = j + 2 + 2 * w1; c0 < r; c0 += 2 * nw1) {
+                    double x[2], vc[2], wc[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int c = c0 + q;
+                        const bool okc = c < r;
+                        vc[q] = okc ? v[c] : 0.0;
+                        wc[q] = okc ? pA[c] - K * vc[q] : 0.0;
+                        x[q] = (okr && okc) ? B[i + c * r] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        if (okr && c0 + q < r) B[i + (c0 + q) * r] = x[q] - (vi * wc[q] + wi * vc[q]);
+                }
+            }
+            // M rows 0..r-1, columns j+1..r-1: lanes over columns, two rows per batch
+            for (int cb = j + 1; cb < r; cb += 64) {
+                const int c = cb + lane;
+                const bool okc = c < r;
+                const double tv = okc ? t * v[c] : 0.0;
+                for (int i0 = 2 * w1; i0 < r; i0 += 2 * nw1) {
+                    double x[2], mi[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int i = i0 + q;
+                        const bool oki = i < r;
+                        mi[q] = oki ? pM[i] : 0.0;
+                        x[q] = (oki && okc) ? M[i * r + c] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        if (okc && i0 + q < r) M[(i0 + q) * r + c] = x[q] - mi[q] * tv;
+                }
             }
         }
         __syncthreads();
     }
     if (tid == 0) {
-        d[r - 2] = B[(r - 2) + (int64_t)(r - 2) * r];
-        d[r - 1] = B[(r - 1) + (int64_t)(r - 1) * r];
-        e[r - 2] = B[(r - 1) + (int64_t)(r - 2) * r];
+        d[r - 2] = B[(r - 2) + (r - 2) * r];
+        d[r - 1] = B[(r - 1) + (r - 1) * r];
+        e[r - 2] = B[(r - 1) + (r - 2) * r];
     }
 }
 
@@ -443,7 +494,7 @@ __device__ int sturm_count(const double* d, const double* e2, int r, double x, d
     int cnt = q < 0.0 ? 1 : 0;
 #pragma unroll 4
     for (int i = 1; i < r; ++i) {
-        q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
+        q = (d[i] - x) - e2[i - 1] * rcp_nr1(q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0 ? 1 : 0;
     }
@@ -451,7 +502,8 @@ __device__ int sturm_count(const double* d, const double* e2, int r, double x, d
 }
 
 // Lowest nw eigenvalues of T (ascending) by multisection: G lanes per eigenvalue (a
-// power of two, at most 32, so a group never straddles a wavefront) evaluate the Sturm
+// power of two, at most 8, so a group never straddles a wavefront; more lanes make the
+// work-group's vector units, not the dependent chain, the limit) evaluate the Sturm
 // count at G interior points of the bracket, which shrinks G + 1 fold per step, down to
 // the absolute width eps ||T|| (or 2 eps |lambda| when larger).  The bracket starts from
 // the Gershgorin interval.  sc[4..7]: gl, gu, pivmin, ||T||.
@@ -487,7 +539,7 @@ __device__ void bisect_lowest(const double* d, const double* e, double* e2, int 
     const double gl = sc[4], gu = sc[5], pivmin = sc[6];
     const double atol = kEps * sc[7];
     int G = 1;
-    while (G < 32 && 2 * G * nw <= nt) G *= 2;
+    while (G < 8 && 2 * G * nw <= nt) G *= 2;
     const int ng = nt / G;
     const int g = tid % G;
     const uint64_t gmask = (1ull << G) - 1;
@@ -520,55 +572,72 @@ __device__ void bisect_lowest(const double* d, const double* e, double* e2, int 
 
 // One solve (T - lam I) x = z in place (z and the factor strided by nwp): LU with
 // partial pivoting between neighbouring rows, U with two superdiagonals (its diagonal
-// kept as reciprocals); the row operations are applied to z as they are made.  Zero
-// pivots become eps ||T||.
+// kept as reciprocals); the row operations are applied to z as they are made.  The
+// pivot choice is made with selects so lanes with different pivots do not diverge.
+// Zero pivots become eps ||T||.
 __device__ void tri_solve(const double* d, const double* e, int r, double lam, double* z, double* u,
                           int nwp, double tiny) {
-    double cd = d[0] - lam, cs1 = r > 1 ? e[0] : 0.0, cs2 = 0.0;
+    // every value a step needs is loaded one step ahead, before the step's stores (the
+    // compiler cannot move a load above a store to the same array)
+    double cd = d[0] - lam, cs1 = r > 1 ? e[0] : 0.0;
     double yc = z[0];
+    double nd = r > 1 ? e[0] : 0.0, dn = r > 1 ? d[1] : 0.0, en = r > 2 ? e[1] : 0.0;
+    double yn = r > 1 ? z[nwp] : 0.0;
 #pragma unroll 2
     for (int i = 0; i + 1 < r; ++i) {
-        const double nd = e[i];
-        const double ns1 = d[i + 1] - lam;
-        const double ns2 = (i + 2 < r) ? e[i + 1] : 0.0;
-        const double yn = z[(int64_t)(i + 1) * nwp];
-        double* ui = u + (int64_t)3 * i * nwp;
-        if (fabs(cd) >= fabs(nd)) {
-            if (cd == 0.0) cd = tiny;
-            const double icd = rcp_nr(cd);
-            const double m = nd * icd;
-            ui[0] = icd;
-            ui[nwp] = cs1;
-            ui[2 * nwp] = cs2;
-            z[(int64_t)i * nwp] = yc;
-            cd = ns1 - m * cs1;
-            cs1 = ns2 - m * cs2;
-            yc = yn - m * yc;
-        } else {
-            const double ind = rcp_nr(nd);
-            const double m = cd * ind;
-            ui[0] = ind;
-            ui[nwp] = ns1;
-            ui[2 * nwp] = ns2;
-            z[(int64_t)i * nwp] = yn;
-            cd = cs1 - m * ns1;
-            cs1 = cs2 - m * ns2;
-            yc = yc - m * yn;
-        }
-        cs2 = 0.0;
+        // current row (cd, cs1, 0 | yc), next row (nd, ns1, ns2 | yn)
+        const double ns1 = dn - lam;
+        const double ns2 = en;
+        // the step after this one
+        const double nd_n = en;
+        const double dn_n = (i + 2 < r) ? d[i + 2] : 0.0;
+        const double en_n = (i + 3 < r) ? e[i + 2] : 0.0;
+        const double yn_n = (i + 2 < r) ? z[(i + 2) * nwp] : 0.0;
+        const bool sw = fabs(cd) < fabs(nd);
+        double pv = sw ? nd : cd;
+        if (pv == 0.0) pv = tiny;
+        const double ot = sw ? cd : nd;
+        const double p1 = sw ? ns1 : cs1, p2 = sw ? ns2 : 0.0, py = sw ? yn : yc;
+        const double o1 = sw ? cs1 : ns1, o2 = sw ? 0.0 : ns2, oy = sw ? yc : yn;
+        const double ip = rcp_nr(pv);
+        const double m = ot * ip;
+        double* ui = u + 3 * i * nwp;
+        ui[0] = ip;
+        ui[nwp] = p1;
+        ui[2 * nwp] = p2;
+        z[i * nwp] = py;
+        cd = o1 - m * p1;
+        cs1 = o2 - m * p2;
+        yc = oy - m * py;
+        nd = nd_n;
+        dn = dn_n;
+        en = en_n;
+        yn = yn_n;
     }
     if (cd == 0.0) cd = tiny;
     double x1 = yc * rcp_nr(cd), x2 = 0.0;
-    z[(int64_t)(r - 1) * nwp] = x1;
-#pragma unroll 4
+    z[(r - 1) * nwp] = x1;
+    if (r < 2) return;
+    const double* un = u + 3 * (r - 2) * nwp;
+    double u0 = un[0], u1 = un[nwp], u2 = un[2 * nwp], zi = z[(r - 2) * nwp];
+#pragma unroll 2
     for (int i = r - 2; i >= 0; --i) {
-        const double* ui = u + (int64_t)3 * i * nwp;
-        double s = z[(int64_t)i * nwp] - ui[nwp] * x1;
-        if (i + 2 < r) s -= ui[2 * nwp] * x2;
-        const double xi = s * ui[0];
-        z[(int64_t)i * nwp] = xi;
+        double u0n = 0.0, u1n = 0.0, u2n = 0.0, zin = 0.0;
+        if (i > 0) {
+            const double* up = u + 3 * (i - 1) * nwp;
+            u0n = up[0];
+            u1n = up[nwp];
+            u2n = up[2 * nwp];
+            zin = z[(i - 1) * nwp];
+        }
+        const double xi = (zi - u1 * x1 - u2 * x2) * u0;
+        z[i * nwp] = xi;
         x2 = x1;
         x1 = xi;
+        u0 = u0n;
+        u1 = u1n;
+        u2 = u2n;
+        zi = zin;
     }
 }
 
@@ -610,16 +679,16 @@ __device__ void inverse_iteration(const double* d, const double* e, int r, int n
                 // start vector: a fixed, non-degenerate pattern per column
                 for (int i = 0; i < r; ++i) {
                     const uint32_t h = (uint32_t)(i + 1) * 2654435761u ^ (uint32_t)(q + 1) * 2246822519u;
-                    z[(int64_t)i * nwp] = (double)((h >> 8) & 0xffff) * (1.0 / 65536.0) + 0.25;
+                    z[i * nwp] = (double)((h >> 8) & 0xffff) * (1.0 / 65536.0) + 0.25;
                 }
             }
             tri_solve(d, e, r, sh[q], z, U3 + q, nwp, tiny);
             double s2 = 0.0;
 #pragma unroll 4
-            for (int i = 0; i < r; ++i) s2 = fma(z[(int64_t)i * nwp], z[(int64_t)i * nwp], s2);
+            for (int i = 0; i < r; ++i) s2 = fma(z[i * nwp], z[i * nwp], s2);
             const double inv = rsq_nr(s2);
 #pragma unroll 4
-            for (int i = 0; i < r; ++i) z[(int64_t)i * nwp] *= inv;
+            for (int i = 0; i < r; ++i) z[i * nwp] *= inv;
         }
         __syncthreads();
         for (int c = wave; c < nc; c += nwave) {
@@ -629,16 +698,16 @@ __device__ void inverse_iteration(const double* d, const double* e, int r, int n
                 for (int i0 = c0; i0 < jj; ++i0) {
                     double dot = 0.0;
                     for (int row = lane; row < r; row += 64)
-                        dot = fma(Zt[(int64_t)row * nwp + i0], Zt[(int64_t)row * nwp + jj], dot);
+                        dot = fma(Zt[row * nwp + i0], Zt[row * nwp + jj], dot);
                     dot = wave_allsum(dot);
                     for (int row = lane; row < r; row += 64)
-                        Zt[(int64_t)row * nwp + jj] -= dot * Zt[(int64_t)row * nwp + i0];
+                        Zt[row * nwp + jj] -= dot * Zt[row * nwp + i0];
                 }
                 double s2 = 0.0;
                 for (int row = lane; row < r; row += 64)
-                    s2 = fma(Zt[(int64_t)row * nwp + jj], Zt[(int64_t)row * nwp + jj], s2);
+                    s2 = fma(Zt[row * nwp + jj], Zt[row * nwp + jj], s2);
                 const double inv = rsq_nr(wave_allsum(s2));
-                for (int row = lane; row < r; row += 64) Zt[(int64_t)row * nwp + jj] *= inv;
+                for (int row = lane; row < r; row += 64) Zt[row * nwp + jj] *= inv;
             }
         }
         __syncthreads();
@@ -726,7 +795,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         D[i] = dd > 0.0 ? 1.0 / sqrt(dd) : 0.0;
     }
     __syncthreads();
-    for (int64_t e = tid; e < kk; e += nt) {
+    for (int e = tid; e < kk; e += nt) {
         const int i = (int)(e % k), j = (int)(e / k);
         A[e] = D[i] * SR[i + (int64_t)j * ldr] * D[j];
         B[e] = D[i] * HR[i + (int64_t)j * ldr] * D[j];
@@ -751,10 +820,10 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         invert_lower_rl(A, invd, T, k);
         __syncthreads();
         gemm_mfma(B, k, false, T, k, true, k, k, k,
-                  [&](int i, int j, double v) { A[i + (int64_t)j * k] = v; });
+                  [&](int i, int j, double v) { A[i + j * k] = v; });
         __syncthreads();
         gemm_mfma(T, k, false, A, k, false, k, k, k,
-                  [&](int i, int j, double v) { B[i + (int64_t)j * k] = v; });
+                  [&](int i, int j, double v) { B[i + j * k] = v; });
         __syncthreads();
         symmetrize(B, k);
         __syncthreads();
@@ -780,7 +849,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     double* theta = base + Lo.ftheta;
     int* sel = (int*)(base + Lo.fsel);
     // eigen-decompose the scaled S_R (V accumulates its vectors)
-    for (int64_t e = tid; e < kk; e += nt) {
+    for (int e = tid; e < kk; e += nt) {
         const int i = (int)(e % k), j = (int)(e / k);
         A[e] = D[i] * SR[i + (int64_t)j * ldr] * D[j];
         V[e] = (i == j) ? 1.0 : 0.0;
@@ -789,20 +858,20 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     jacobi(A, k, V, k, k, red, rcs, rpq);
     __syncthreads();
     double mx = 0.0;
-    for (int i = 0; i < k; ++i) mx = fmax(mx, A[i + (int64_t)i * k]);
+    for (int i = 0; i < k; ++i) mx = fmax(mx, A[i + i * k]);
     if (tid == 0) {
         int c = 0;
         for (int i = 0; i < k; ++i)
-            if (A[i + (int64_t)i * k] > kRankTol * mx) sel[c++] = i;
+            if (A[i + i * k] > kRankTol * mx) sel[c++] = i;
         flag[1] = c;
     }
     __syncthreads();
     const int r = flag[1];
     // T = Q_keep / sqrt(lambda_keep) (k x r, ld k)
-    for (int64_t e = tid; e < (int64_t)k * r; e += nt) {
+    for (int e = tid; e < k * r; e += nt) {
         const int i = (int)(e % k), c = (int)(e / k);
         const int src = sel[c];
-        T[i + (int64_t)c * k] = V[i + (int64_t)src * k] / sqrt(A[src + (int64_t)src * k]);
+        T[i + c * k] = V[i + src * k] / sqrt(A[src + src * k]);
     }
     __syncthreads();
     // C = T^T B T (r x r, ld r) into B, via U = B T (k x r)
@@ -815,19 +884,19 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         return;
     }
     // symmetrise C (r x r, ld r), V = I
-    for (int64_t e = tid; e < (int64_t)r * r; e += nt) {
+    for (int e = tid; e < r * r; e += nt) {
         const int i = (int)(e % r), j = (int)(e / r);
         if (i < j) {
-            const double a = 0.5 * (B[i + (int64_t)j * r] + B[j + (int64_t)i * r]);
-            B[i + (int64_t)j * r] = a;
-            B[j + (int64_t)i * r] = a;
+            const double a = 0.5 * (B[i + j * r] + B[j + i * r]);
+            B[i + j * r] = a;
+            B[j + i * r] = a;
         }
         V[e] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
     jacobi(B, r, V, r, r, red, rcs, rpq);
     __syncthreads();
-    for (int i = tid; i < r; i += nt) theta[i] = B[i + (int64_t)i * r];
+    for (int i = tid; i < r; i += nt) theta[i] = B[i + i * r];
     __syncthreads();
     for (int i = tid; i < r; i += nt) {
         const double ti = theta[i];
@@ -841,11 +910,11 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     __syncthreads();
     for (int q = tid; q < nwant; q += nt) gamma[q] = theta[sel[q]];
     // W = D T V(:, sel)
-    for (int64_t e = tid; e < (int64_t)k * nwant; e += nt) {
+    for (int e = tid; e < k * nwant; e += nt) {
         const int i = (int)(e % k), q = (int)(e / k);
         const int src = sel[q];
         double acc = 0.0;
-        for (int p = 0; p < r; ++p) acc = fma(T[i + (int64_t)p * k], V[p + (int64_t)src * r], acc);
+        for (int p = 0; p < r; ++p) acc = fma(T[i + p * k], V[p + src * r], acc);
         W[i + (int64_t)q * ldw] = D[i] * acc;
     }
     if (tid == 0) { info[0] = k - r; info[1] = 0; }
