@@ -61,14 +61,19 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
     bool act[CW];
     const T* xc[CW];
     T ah[CW], as[CW];
+    bool any = false;
 #pragma unroll
     for (int j = 0; j < CW; ++j) {
         const int jj = j0 + j;
         act[j] = jj < q && (MODE == 0 || !sc[jj].done);
+        any = any || act[j];
         xc[j] = act[j] ? X + (int64_t)(MODE == 0 ? xcols[jj] : jj) * ldx : X;
         ah[j] = T(0);
         as[j] = T(0);
     }
+    // a chunk whose columns have all converged has nothing to do (uniform over the
+    // work-group; the next kernels read no partial of a converged column)
+    if (!any) return;
 #pragma unroll 2
     for (int64_t e = e0 + sw * kSlice + lane; e < e1; e += kSlice * WPS) {
         const int64_t c = col[e];
