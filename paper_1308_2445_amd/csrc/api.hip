@@ -284,12 +284,14 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     tm.on = prm.timing != 0;
     tm.s = s;
 
-    Pinned<double> h_res, h_gamma;
-    Pinned<int32_t> h_int, h_its;
+    Pinned<double> h_res, h_gamma, h_dsel;
+    Pinned<int32_t> h_int, h_its, h_isel;
     h_its.alloc(m);
     h_res.alloc(2 * (size_t)m);
     h_gamma.alloc(b);
     h_int.alloc(8);
+    h_isel.alloc(2 * (size_t)m);   // [U | localised positions], copied to B.cols / B.loc
+    h_dsel.alloc(2 * (size_t)m);   // [shifts | stopping norms], copied to B.shifts / B.stopn
     int cur = 0;
     auto Z = [&](int which) { return B.Zb[cur][which]; };
 
@@ -304,7 +306,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     tm.end();
     st.n_launch[S_PROD_PSI] += 1;
     st.n_cols[S_PROD_PSI] += b;
-    auto rayleigh_ritz_update = [&](int k) -> int {
+    auto rayleigh_ritz_update = [&](int k) {
         tm.begin(S_GRAM);
         launch_gram(n, k, Z(0), Z(1), Z(2), ldz, B.HR, B.SR, kmax, B.gram_ws, P.ctx->cu_count, s);
         tm.end();
@@ -323,15 +325,25 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         st.n_launch[S_UPDATE] += 1;
         st.n_cols[S_UPDATE] += k;
         cur = nxt;
+        // the Ritz values and the rank report reach the host with the next residual
+        // read-back (rr_check), so this step adds no synchronisation
         LABPSD_HIP(hipMemcpyAsync(h_gamma.p, B.gamma, b * sizeof(double), hipMemcpyDeviceToHost, s));
         LABPSD_HIP(hipMemcpyAsync(h_int.p, B.info, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        LABPSD_HIP(hipStreamSynchronize(s));
-        st.rank_dropped += h_int.p[0];
-        return h_int.p[1];
     };
-    if (rayleigh_ritz_update(b) != 0) throw Error{LABPSD_ERANK, "start block is rank deficient"};
-
-    std::vector<double> E(h_gamma.p, h_gamma.p + b);
+    // after a synchronisation: the last Rayleigh-Ritz step's report and Ritz values
+    std::vector<double> E;
+    auto rr_check = [&](const char* what) {
+        st.rank_dropped += h_int.p[0];
+        if (h_int.p[1] != 0) throw Error{LABPSD_ERANK, what};
+        E.assign(h_gamma.p, h_gamma.p + b);
+    };
+    // MINRES iteration counts, read after the next synchronisation
+    int its_pending = 0;
+    auto its_collect = [&]() {
+        for (int j = 0; j < its_pending; ++j) st.minres_iters += h_its.p[j];
+        its_pending = 0;
+    };
+    rayleigh_ritz_update(b);
     std::vector<double> Eprev;
     if (E0) Eprev.assign(E0, E0 + m);
     bool fresh = false;
@@ -360,10 +372,11 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         tm.end();
         st.n_launch[S_RESID] += 1;
         st.n_cols[S_RESID] += m;
-        LABPSD_HIP(hipMemcpyAsync(h_res.p, B.res, m * sizeof(double), hipMemcpyDeviceToHost, s));
-        LABPSD_HIP(hipMemcpyAsync(h_res.p + m, B.rnorm, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        // Res and the norms are contiguous on the device (B.rnorm follows B.res)
+        LABPSD_HIP(hipMemcpyAsync(h_res.p, B.res, 2 * (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
         LABPSD_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < m; ++i) { res[i] = h_res.p[i]; rn[i] = h_res.p[m + i]; }
+        its_collect();
     };
     auto maxres = [&]() {
         double mx = 0.0;
@@ -374,6 +387,8 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     for (int it = 1; it <= prm.max_outer; ++it) {
         if (since_refresh >= prm.refresh_every) refresh();
         residuals();   // step 4 and eq. (res1)
+        rr_check(it == 1 ? "start block is rank deficient"
+                         : "search space [Psi P] lost rank below the block width");
         if (maxres() <= prm.tol) {   // step 5, on the true residual
             if (!fresh) {
                 refresh();
@@ -408,11 +423,15 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             }
         }
         const int q = (int)locpos.size();
-        LABPSD_HIP(hipMemcpyAsync(B.cols, U.data(), p * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        // the selections in two pinned copies (B.loc follows B.cols, B.stopn follows
+        // B.shifts); the host buffers are next written after the next synchronisation
+        std::copy(U.begin(), U.end(), h_isel.p);
+        std::copy(locpos.begin(), locpos.end(), h_isel.p + m);
+        LABPSD_HIP(hipMemcpyAsync(B.cols, h_isel.p, (q ? m + q : p) * sizeof(int32_t), hipMemcpyHostToDevice, s));
         if (q) {
-            LABPSD_HIP(hipMemcpyAsync(B.loc, locpos.data(), q * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            LABPSD_HIP(hipMemcpyAsync(B.shifts, shifts.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
-            LABPSD_HIP(hipMemcpyAsync(B.stopn, stopn.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+            std::copy(shifts.begin(), shifts.end(), h_dsel.p);
+            std::copy(stopn.begin(), stopn.end(), h_dsel.p + m);
+            LABPSD_HIP(hipMemcpyAsync(B.shifts, h_dsel.p, (m + q) * sizeof(double), hipMemcpyHostToDevice, s));
         }
         // 6(a): P = -K^{-1} R_U in the preconditioner precision
         // (the preconditioner works on row-major blocks: -R_U is cast into Y row-major)
@@ -445,8 +464,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             st.n_launch[S_LOCAL] += nl;
             st.n_cols[S_LOCAL] += q;
             LABPSD_HIP(hipMemcpyAsync(h_its.p, B.its, q * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            LABPSD_HIP(hipStreamSynchronize(s));
-            for (int j = 0; j < q; ++j) st.minres_iters += h_its.p[j];
+            its_pending = q;
             st.localized_cols += q;
         }
         // P into the search-space block, FP64
@@ -465,13 +483,16 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         st.n_cols[S_PROD_P] += p;
         // steps 8-11
         Eprev.assign(E.begin(), E.begin() + m);
-        const int rc = rayleigh_ritz_update(b + p);
-        if (rc != 0) throw Error{LABPSD_ERANK, "search space [Psi P] lost rank below the block width"};
-        E.assign(h_gamma.p, h_gamma.p + b);
+        rayleigh_ritz_update(b + p);
         fresh = false;
         ++since_refresh;
     }
     LABPSD_HIP(hipStreamSynchronize(s));
+    its_collect();
+    // a converged exit has checked the last Rayleigh-Ritz step in its final iteration
+    if (!converged)
+        rr_check(outer == 0 ? "start block is rank deficient"
+                            : "search space [Psi P] lost rank below the block width");
     tm.collect(&st);
     // keep the whole block (guards included) resident for a warm start
     P.resident_X.alloc((size_t)n * b);
