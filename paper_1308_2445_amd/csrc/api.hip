@@ -15,6 +15,25 @@
 
 namespace labpsd {
 
+void spin_event(hipEvent_t ev) {
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) LABPSD_HIP(e);
+    }
+    // a query that found the event pending may leave "not ready" as the last error
+    (void)hipGetLastError();
+}
+
+void spin_sync(hipStream_t s, hipEvent_t ev) {
+    if (!ev) {
+        LABPSD_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    LABPSD_HIP(hipEventRecord(ev, s));
+    spin_event(ev);
+}
+
 namespace {
 thread_local std::string g_err;
 
@@ -61,6 +80,15 @@ struct Pinned {
 };
 
 // Event timing of the steps (stats.t_step_s)
+// An event that lives as long as the scope that created it (no timing).
+struct ScopedEvent {
+    hipEvent_t e = nullptr;
+    ScopedEvent() { LABPSD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+    ~ScopedEvent() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
 struct StepTimer {
     bool on = false;
     hipStream_t s = nullptr;
@@ -220,7 +248,7 @@ static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T
     size_t need = 6 * (size_t)n * kmax + (size_t)n * m + 2 * (size_t)kmax * kmax +
                   (size_t)kmax * b + (size_t)b + 2 * (size_t)m +
                   std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m) + gws + 2 * (size_t)m +
-                  minres_scal_doubles(m) + 4 + rrb + 64;
+                  (2 * (size_t)m + 4) + minres_scal_doubles(m) + 4 + rrb + 64;
     P.ws64.alloc(need);
     double* p = P.ws64.p;
     for (int a = 0; a < 2; ++a)
@@ -229,13 +257,25 @@ static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T
     B.HR = p; p += (size_t)kmax * kmax;
     B.SR = p; p += (size_t)kmax * kmax;
     B.W = p; p += (size_t)kmax * b;
-    B.gamma = p; p += b;
+    // read back together once per iteration: Res, the residual norms, the Ritz values
     B.res = p; p += m;
     B.rnorm = p; p += m;
+    B.gamma = p; p += b;
     B.red = p; p += std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m);
     B.gram_ws = p; p += gws;
+    // sent together once per iteration: shifts, stopping norms and the column lists;
+    // then the MINRES counts and the Rayleigh-Ritz report, read back together
     B.shifts = p; p += m;
     B.stopn = p; p += m;
+    {
+        int32_t* ip = (int32_t*)p;
+        B.cols = ip;
+        B.loc = ip + m;
+        B.its = ip + 2 * m;
+        B.info = ip + 3 * m;
+        B.counter = B.info + 4;
+        p += 2 * (size_t)m + 4;   // 4 m + 8 int32
+    }
     B.scal = p; p += minres_scal_doubles(m) + 4;
     B.rr_ws = (void*)p; p += rrb;
     // T-precision blocks
@@ -255,12 +295,6 @@ static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T
     W.W2 = t; t += (size_t)n * m;
     W.RT = t; t += (size_t)n * m;
     W.mres = t;
-    P.iws.alloc(4 * (size_t)m + 8);
-    B.cols = P.iws.p;
-    B.loc = B.cols + m;
-    B.its = B.loc + m;
-    B.info = B.its + m;
-    B.counter = B.info + 4;
 }
 
 // ------------------------------------------------------------------ solve
@@ -284,14 +318,16 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     tm.on = prm.timing != 0;
     tm.s = s;
 
-    Pinned<double> h_res, h_gamma, h_dsel;
-    Pinned<int32_t> h_int, h_its, h_isel;
-    h_its.alloc(m);
-    h_res.alloc(2 * (size_t)m);
-    h_gamma.alloc(b);
+    // h_rb: [Res | norms | Ritz values]; h_ib: [MINRES counts | Rayleigh-Ritz report];
+    // h_sel: [shifts | stopping norms | U | localised positions] as laid out on the device
+    Pinned<double> h_rb, h_sel;
+    Pinned<int32_t> h_ib, h_int;
+    ScopedEvent ev_sync, ev_flag0, ev_flag1;
+    h_rb.alloc(2 * (size_t)m + b);
+    h_ib.alloc((size_t)m + 4);
+    h_sel.alloc(3 * (size_t)m);
     h_int.alloc(8);
-    h_isel.alloc(2 * (size_t)m);   // [U | localised positions], copied to B.cols / B.loc
-    h_dsel.alloc(2 * (size_t)m);   // [shifts | stopping norms], copied to B.shifts / B.stopn
+    int32_t* h_cols = (int32_t*)(h_sel.p + 2 * (size_t)m);
     int cur = 0;
     auto Z = [&](int which) { return B.Zb[cur][which]; };
 
@@ -327,20 +363,23 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         cur = nxt;
         // the Ritz values and the rank report reach the host with the next residual
         // read-back (rr_check), so this step adds no synchronisation
-        LABPSD_HIP(hipMemcpyAsync(h_gamma.p, B.gamma, b * sizeof(double), hipMemcpyDeviceToHost, s));
-        LABPSD_HIP(hipMemcpyAsync(h_int.p, B.info, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    };
+    // the two read-backs every synchronisation of the loop waits for
+    auto readback = [&]() {
+        LABPSD_HIP(hipMemcpyAsync(h_rb.p, B.res, (2 * (size_t)m + b) * sizeof(double), hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipMemcpyAsync(h_ib.p, B.its, ((size_t)m + 2) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     };
     // after a synchronisation: the last Rayleigh-Ritz step's report and Ritz values
     std::vector<double> E;
     auto rr_check = [&](const char* what) {
-        st.rank_dropped += h_int.p[0];
-        if (h_int.p[1] != 0) throw Error{LABPSD_ERANK, what};
-        E.assign(h_gamma.p, h_gamma.p + b);
+        st.rank_dropped += h_ib.p[m];
+        if (h_ib.p[m + 1] != 0) throw Error{LABPSD_ERANK, what};
+        E.assign(h_rb.p + 2 * m, h_rb.p + 2 * m + b);
     };
-    // MINRES iteration counts, read after the next synchronisation
+    // MINRES iteration counts of the last local refinement
     int its_pending = 0;
     auto its_collect = [&]() {
-        for (int j = 0; j < its_pending; ++j) st.minres_iters += h_its.p[j];
+        for (int j = 0; j < its_pending; ++j) st.minres_iters += h_ib.p[j];
         its_pending = 0;
     };
     rayleigh_ritz_update(b);
@@ -372,10 +411,9 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         tm.end();
         st.n_launch[S_RESID] += 1;
         st.n_cols[S_RESID] += m;
-        // Res and the norms are contiguous on the device (B.rnorm follows B.res)
-        LABPSD_HIP(hipMemcpyAsync(h_res.p, B.res, 2 * (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
-        LABPSD_HIP(hipStreamSynchronize(s));
-        for (int i = 0; i < m; ++i) { res[i] = h_res.p[i]; rn[i] = h_res.p[m + i]; }
+        readback();
+        spin_sync(s, ev_sync.e);
+        for (int i = 0; i < m; ++i) { res[i] = h_rb.p[i]; rn[i] = h_rb.p[m + i]; }
         its_collect();
     };
     auto maxres = [&]() {
@@ -423,16 +461,14 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             }
         }
         const int q = (int)locpos.size();
-        // the selections in two pinned copies (B.loc follows B.cols, B.stopn follows
-        // B.shifts); the host buffers are next written after the next synchronisation
-        std::copy(U.begin(), U.end(), h_isel.p);
-        std::copy(locpos.begin(), locpos.end(), h_isel.p + m);
-        LABPSD_HIP(hipMemcpyAsync(B.cols, h_isel.p, (q ? m + q : p) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        if (q) {
-            std::copy(shifts.begin(), shifts.end(), h_dsel.p);
-            std::copy(stopn.begin(), stopn.end(), h_dsel.p + m);
-            LABPSD_HIP(hipMemcpyAsync(B.shifts, h_dsel.p, (m + q) * sizeof(double), hipMemcpyHostToDevice, s));
-        }
+        // the selections in one pinned copy (shifts, stopping norms, U, localised
+        // positions); the host buffer is next written after the next synchronisation
+        std::copy(shifts.begin(), shifts.end(), h_sel.p);
+        std::copy(stopn.begin(), stopn.end(), h_sel.p + m);
+        std::copy(U.begin(), U.end(), h_cols);
+        std::copy(locpos.begin(), locpos.end(), h_cols + m);
+        LABPSD_HIP(hipMemcpyAsync(B.shifts, h_sel.p, 2 * (size_t)m * sizeof(double) + (m + q) * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s));
         // 6(a): P = -K^{-1} R_U in the preconditioner precision
         // (the preconditioner works on row-major blocks: -R_U is cast into Y row-major)
         tm.begin(S_CAST);
@@ -459,12 +495,12 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             tm.begin(S_LOCAL);
             int64_t nl = 0;
             run_minres<T>(P.sell, Wt.W1, n, Wt.RT, n, q, B.loc, B.shifts, B.stopn, lp.eta,
-                          lp.max_inner, B.its, Wt.mres, B.scal, h_int.p + 4, s, &nl);
+                          lp.max_inner, B.its, Wt.mres, B.scal, h_int.p + 4, s, &nl, ev_flag0.e,
+                          ev_flag1.e);
             tm.end();
             st.n_launch[S_LOCAL] += nl;
             st.n_cols[S_LOCAL] += q;
-            LABPSD_HIP(hipMemcpyAsync(h_its.p, B.its, q * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            its_pending = q;
+            its_pending = q;   // read back with the next residual
             st.localized_cols += q;
         }
         // P into the search-space block, FP64
@@ -487,6 +523,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         fresh = false;
         ++since_refresh;
     }
+    readback();
     LABPSD_HIP(hipStreamSynchronize(s));
     its_collect();
     // a converged exit has checked the last Rayleigh-Ritz step in its final iteration
@@ -584,7 +621,7 @@ static void local_refine_impl(Problem* p, DBuf<T>& arena, const double* R, int64
     launch_gather_cast<double, T>(n, q, R, ldr, cols, 1.0, RT, n, s);
     launch_colnorms<double>(n, q, R, ldr, cols, part, rn, s);
     Pinned<int32_t> flag;
-    flag.alloc(1);
+    flag.alloc(2);
     run_minres<T>(p->sell, PT, n, RT, n, q, iota, shift, rn, eta, max_inner, its, mws, scal, flag.p, s,
                   nullptr);
     launch_scatter_cast<T, double>(n, q, PT, n, cols, 1.0, Pm, ldp, s);

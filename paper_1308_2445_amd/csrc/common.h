@@ -311,6 +311,14 @@ template <typename T>
 void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q,
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
-                int32_t* flag_host_pinned, hipStream_t s, int64_t* launches);
+                int32_t* flag_host_pinned, hipStream_t s, int64_t* launches, hipEvent_t ev0 = nullptr,
+                hipEvent_t ev1 = nullptr);
+
+// Wait until everything enqueued on s so far has finished.  With an event the host polls
+// it (spins) instead of blocking, which shortens the wake-up after the small read-backs
+// the solve loop waits on; without one it falls back to hipStreamSynchronize.
+void spin_sync(hipStream_t s, hipEvent_t ev);
+// Wait for an event recorded earlier by polling it.
+void spin_event(hipEvent_t ev);
 
 }  // namespace labpsd

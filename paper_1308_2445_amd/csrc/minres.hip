@@ -354,7 +354,8 @@ template <typename T>
 void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q,
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
-                int32_t* flag_host_pinned, hipStream_t s, int64_t* launches) {
+                int32_t* flag_host_pinned, hipStream_t s, int64_t* launches, hipEvent_t ev0,
+                hipEvent_t ev1) {
     if (q <= 0 || A.n == 0) return;
     const int64_t n = A.n;
     T* V = ws;
@@ -394,9 +395,15 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     nl += 3;
     MinresScal* cur = sa;
     MinresScal* nxt = sb;
-    // the host reads the active count every few iterations; iterations issued after the
-    // last column finished find every column done and exit at once
-    constexpr int kCheckEvery = 3;
+    // The host reads the active count every kCheckEvery iterations; iterations issued
+    // after the last column finished find every column done and exit at once.  With two
+    // events (and two flag slots) the read is pipelined: after issuing a check the host
+    // waits for the previous one, so the iterations in between keep the device busy.
+    const bool piped = ev0 != nullptr && ev1 != nullptr;
+    const int kCheckEvery = piped ? 2 : 3;
+    hipEvent_t evs[2] = {ev0, ev1};
+    int slot = 0;
+    bool pending = false;
     for (int it = 0; it < max_inner; ++it) {
         launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s);
         hipLaunchKernelGGL((k_minres_axpy<T>), grow, dim3(256), 0, s, n, q, npa, (const MinresScal*)cur,
@@ -410,10 +417,21 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
         T* t0 = VP; VP = V; V = Wb; Wb = t0;
         T* t1 = D1; D1 = D2; D2 = t1;
         MinresScal* t2 = cur; cur = nxt; nxt = t2;
-        if ((it + 1) % kCheckEvery == 0 || it + 1 == max_inner) {
-            LABPSD_HIP(hipMemcpyAsync(flag_host_pinned, counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            LABPSD_HIP(hipStreamSynchronize(s));
-            if (*flag_host_pinned == 0) break;
+        if (it + 1 == max_inner) break;
+        if ((it + 1) % kCheckEvery == 0) {
+            LABPSD_HIP(hipMemcpyAsync(flag_host_pinned + slot, counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            if (!piped) {
+                LABPSD_HIP(hipStreamSynchronize(s));
+                if (flag_host_pinned[slot] == 0) break;
+                continue;
+            }
+            LABPSD_HIP(hipEventRecord(evs[slot], s));
+            if (pending) {
+                spin_event(evs[slot ^ 1]);
+                if (flag_host_pinned[slot ^ 1] == 0) break;
+            }
+            pending = true;
+            slot ^= 1;
         }
     }
     hipLaunchKernelGGL((k_minres_final<T>), gel, dim3(256), 0, s, n, q, cols_dev, (const MinresScal*)cur,
@@ -425,9 +443,9 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
 
 template void run_minres<double>(const Sell&, double*, int64_t, const double*, int64_t, int,
                                  const int32_t*, const double*, const double*, double, int, int32_t*,
-                                 double*, double*, int32_t*, hipStream_t, int64_t*);
+                                 double*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t);
 template void run_minres<float>(const Sell&, float*, int64_t, const float*, int64_t, int,
                                 const int32_t*, const double*, const double*, double, int, int32_t*,
-                                float*, double*, int32_t*, hipStream_t, int64_t*);
+                                float*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t);
 
 }  // namespace labpsd

@@ -17,6 +17,8 @@
 // C on that basis is diagonalised by cyclic Jacobi as well.
 // Everything lives in LDS when it fits the per-block limit, otherwise in a global
 // workspace.
+#include <type_traits>
+
 #include "common.h"
 
 namespace labpsd {
@@ -325,6 +327,26 @@ __device__ __forceinline__ void reflector(double alpha, double sigma, double& ta
     }
 }
 
+// The same reflector from one reciprocal square root and one reciprocal (Newton-refined
+// hardware approximations): with nrm = |(alpha, x)|, beta = -sign(alpha) nrm,
+// tau = 1 + |alpha| / nrm and scal = 1 / (alpha - beta) = sign(alpha) / (|alpha| + nrm).
+// tau matches 2 / (v^T v) for v = (1, scal x) to a few ulps.
+__device__ __forceinline__ void reflector_fast(double alpha, double sigma, double& tau, double& beta,
+                                               double& scal) {
+    tau = 0.0;
+    beta = alpha;
+    scal = 0.0;
+    if (sigma != 0.0) {
+        const double s2 = fma(alpha, alpha, sigma);
+        const double rs = rsq_nr(s2);
+        const double nrm = s2 * rs;
+        const double aa = fabs(alpha);
+        beta = -copysign(nrm, alpha);
+        tau = fma(aa, rs, 1.0);
+        scal = copysign(rcp_nr(aa + nrm), alpha);
+    }
+}
+
 // Householder reduction of the symmetric r x r matrix B (both triangles stored) to
 // tridiagonal form Q^T B Q = T (diagonal d, off-diagonal e), with Q = H_0 H_1 ... and
 // H_j = I - tau_j v v^T on rows j+1..r-1, v = (1, v_{j+2}, ...).  The reflectors are
@@ -481,6 +503,214 @@ __device__ void tridiagonalize_acc(double* B, double* M, int r, double* d, doubl
         d[r - 2] = B[(r - 2) + (r - 2) * r];
         d[r - 1] = B[(r - 1) + (r - 1) * r];
         e[r - 2] = B[(r - 1) + (r - 2) * r];
+    }
+}
+
+// ---------------------------------------------------------------- register-row routines
+// For r <= 8 NT the dense phases keep the matrix rows in registers: the 8 lanes of group
+// g = tid / 8 own row g, lane sub = tid % 8 the columns sub + 8 t (t < NT; zero at and
+// beyond r).  Only the vectors one step hands to the next pass through memory, in
+// buffers of P = 8 NT doubles whose entries at and beyond r stay zero, so that every
+// lane reads and writes its columns at fixed offsets without bounds tests.
+
+// Cholesky L L^T of D S_R D (read from S_R) fused with X = L^{-1}, right-looking: row j,
+// once updated by steps 0..j-1, gives column j of L (by symmetry of the trailing matrix)
+// and, scaled, the final row j of X; every later row then subtracts L[g, j] times both.
+// One barrier per step.  X is written column-major (ld r).  buf: 4 P doubles; piv: 2.
+// Entries of a row left of the current column are dead and take harmless updates.
+// Returns false (uniformly) at the first pivot not above kPivotTol.
+template <int NT>
+__device__ __forceinline__ bool chol_inv_regs(const double* __restrict__ SR, int64_t ldr, const double* D, int r,
+                              double* X, double* buf, double* piv) {
+    constexpr int P = 8 * NT;
+    const int tid = threadIdx.x, g = tid >> 3, sub = tid & 7;
+    const bool row = g < r;
+    double a[NT], x[NT];
+    const double dg = row ? D[g] : 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = sub + 8 * t;
+        const bool ok = row && c < r;
+        a[t] = ok ? dg * SR[c + (int64_t)g * ldr] * D[c] : 0.0;
+        x[t] = (ok && c == g) ? 1.0 : 0.0;
+    }
+    auto publish = [&](int j) {   // by the 8 lanes of group j
+        double* lb = buf + (j & 1) * P + sub;       // column j of L
+        double* xb = buf + (2 + (j & 1)) * P + sub; // row j of X
+        // the pivot sits in column j: slot j / 8 of the lane with sub = j % 8
+        double sel = a[0];
+#pragma unroll
+        for (int t = 1; t < NT; ++t)
+            if (t == (j >> 3)) sel = a[t];
+        const double p = readlane_d(sel, 8 * (j & 7) + (j & 7));
+        const double il = p > kPivotTol ? rsq_nr(p) : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            lb[8 * t] = sub + 8 * t >= j ? a[t] * il : 0.0;
+            x[t] *= il;
+            xb[8 * t] = x[t];
+        }
+        if (sub == 0) piv[j & 1] = p;
+    };
+    if (g == 0) publish(0);
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        if (!(piv[j & 1] > kPivotTol)) return false;
+        // the wavefront holding row j + 1 publishes the next step: it goes first
+        const bool lead = __builtin_amdgcn_readfirstlane((tid >> 6) == ((j + 1) >> 3) ? 1 : 0) != 0;
+        if (lead) __builtin_amdgcn_s_setprio(2);
+        if (row && g > j) {
+            const double* lb = buf + (j & 1) * P;
+            const double* xb = buf + (2 + (j & 1)) * P + sub;
+            const double lgj = lb[g];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                a[t] = fma(-lgj, lb[sub + 8 * t], a[t]);
+                x[t] = fma(-lgj, xb[8 * t], x[t]);
+            }
+        }
+        if (g == j + 1 && j + 1 < r) publish(j + 1);
+        if (lead) __builtin_amdgcn_s_setprio(0);
+        __syncthreads();
+    }
+    if (row) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = sub + 8 * t;
+            if (c < r) X[g + c * r] = x[t];
+        }
+    }
+    return true;
+}
+
+// Householder tridiagonalisation Q^T C Q = T with Q = H_0 H_1 ... accumulated onto
+// M = X^T (M <- M H_j), rows of C and M in registers.  Per reflector j (support rows
+// j+1..r-1, v = (1, v_{j+2}, ...)): each row forms its part of p = tau C v and of M v
+// (8-lane sums) and updates its row of M at once; after one barrier every row applies
+// C -= v w^T + w v^T, w = p - (tau/2)(p . v) v, and row j + 1 builds the next reflector;
+// a second barrier publishes it.  C is read column-major and symmetrised on the way
+// in; T holds X column-major on entry and M row-major on exit.  buf: 3 P doubles;
+// sc: 4 (tau, beta of the two reflector buffers).
+template <int NT>
+__device__ __forceinline__ void tridiag_regs(const double* C, double* T, int r, double* d, double* e, double* buf,
+                             double* sc) {
+    constexpr int P = 8 * NT;
+    const int tid = threadIdx.x, g = tid >> 3, sub = tid & 7, lane = tid & 63;
+    const bool row = g < r;
+    double a[NT], m[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = sub + 8 * t;
+        const bool ok = row && c < r;
+        a[t] = ok ? 0.5 * (C[c + g * r] + C[g + c * r]) : 0.0;
+        m[t] = ok ? T[c + g * r] : 0.0;   // row g of M = X^T is column g of X
+    }
+    double* pb = buf + 2 * P;   // p; buf[0..2P): the two reflector buffers
+    if (tid < P) pb[tid] = 0.0;
+    // reflector j1 from row j1 (= column j1), by the 8 lanes of that group
+    auto next_reflector = [&](int j1) {
+        const int s = j1 & 1;
+        double sg0 = 0.0, sg1 = 0.0, sel = a[0];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const double x = sub + 8 * t > j1 + 1 ? a[t] : 0.0;
+            if (t & 1) sg1 = fma(x, x, sg1);
+            else sg0 = fma(x, x, sg0);
+            if (t > 0 && t == ((j1 + 1) >> 3)) sel = a[t];
+        }
+        const double sg = row8_allsum(sg0 + sg1);
+        // alpha = C[j1, j1 + 1]: slot (j1 + 1) / 8 of the lane with sub = (j1 + 1) % 8
+        const double a1 = readlane_d(sel, 8 * (j1 & 7) + ((j1 + 1) & 7));
+        double tau, beta, scal;
+        reflector_fast(a1, sg, tau, beta, scal);
+        double* vn = buf + s * P + sub;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = sub + 8 * t;
+            vn[8 * t] = c == j1 + 1 ? 1.0 : (c > j1 + 1 ? a[t] * scal : 0.0);
+        }
+        if (sub == 0) {
+            sc[2 * s] = tau;
+            sc[2 * s + 1] = beta;
+        }
+    };
+    if (r >= 3 && g == 0) next_reflector(0);
+    __syncthreads();
+    for (int j = 0; j + 2 < r; ++j) {
+        const int s0 = j & 1;
+        const double tau = sc[2 * s0];
+        const bool refl = tau != 0.0;   // uniform
+        const double* v = buf + s0 * P;
+        if (g == j) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                if (sub + 8 * t == j) d[j] = a[t];
+            if (sub == 0) e[j] = sc[2 * s0 + 1];
+        }
+        double vt[NT];
+        double pg = 0.0;
+        // wavefronts without rows only take part in the barriers; rows up to j need only
+        // their row of M
+        if (refl && row) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) vt[t] = v[sub + 8 * t];
+            double pm0 = 0.0, pm1 = 0.0, pa0 = 0.0, pa1 = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; t += 2) {
+                pm0 = fma(m[t], vt[t], pm0);
+                pa0 = fma(a[t], vt[t], pa0);
+                if (t + 1 < NT) {
+                    pm1 = fma(m[t + 1], vt[t + 1], pm1);
+                    pa1 = fma(a[t + 1], vt[t + 1], pa1);
+                }
+            }
+            const double pa = row8_allsum(pa0 + pa1), pm = row8_allsum(pm0 + pm1);
+            if (g > j) pg = tau * pa;
+            const double tm = tau * pm;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) m[t] = fma(-tm, vt[t], m[t]);
+            if (sub == 0) pb[g] = pg;
+        }
+        __syncthreads();
+        // the wavefront holding row j + 1 builds the next reflector: it goes first
+        const bool lead = __builtin_amdgcn_readfirstlane((tid >> 6) == ((j + 1) >> 3) ? 1 : 0) != 0;
+        if (lead) __builtin_amdgcn_s_setprio(2);
+        if (refl && 8 * (tid >> 6) < r) {
+            double part = 0.0;
+#pragma unroll
+            for (int i = lane; i < P; i += 64) part = fma(pb[i], v[i], part);
+            const double K = 0.5 * tau * wave_allsum(part);
+            if (row && g > j) {
+                // C -= v w^T + w v^T = (v p^T + p v^T) - 2 K v v^T
+                const double vg = v[g];
+                const double k2 = 2.0 * K * vg;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const double u = fma(vg, pb[sub + 8 * t], pg * vt[t]);
+                    a[t] = fma(k2, vt[t], a[t] - u);
+                }
+            }
+        }
+        if (j + 3 < r && g == j + 1) next_reflector(j + 1);
+        if (lead) __builtin_amdgcn_s_setprio(0);
+        __syncthreads();
+    }
+    // the trailing 2 x 2 (or 1 x 1) block
+    if (row && g >= r - 2) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = sub + 8 * t;
+            if (c == g) d[g] = a[t];
+            if (g == r - 1 && c == r - 2) e[r - 2] = a[t];
+        }
+    }
+    __syncthreads();
+    if (row) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = sub + 8 * t;
+            if (c < r) T[g * r + c] = m[t];
+        }
     }
 }
 
@@ -719,9 +949,12 @@ __device__ void inverse_iteration(const double* d, const double* e, int r, int n
 // On the main route A holds L, then the product scratch, B holds D H_R D, then C, T
 // holds L^{-1} = M^T, then M = L^{-T} Q; the inverse-iteration factors reuse A and B
 // when they fit there.
+// register-row width for order k (8 lanes per row, NT columns per lane); 0: LDS routines
+__host__ __device__ inline int rr_nt(int k) { return k <= 40 ? 5 : k <= 72 ? 9 : k <= 128 ? 16 : 0; }
+
 struct RRLayout {
     int64_t D, flags, A, B;
-    int64_t T, Zt, U3, d, e, e2, invd, pA, pM, pv, vb, theta, sh, sc, icl, main_end;   // main route
+    int64_t T, Zt, U3, d, e, e2, invd, pA, pM, pv, vb, theta, sh, sc, icl, rb, main_end;   // main route
     int64_t V, fT, rot, ftheta, fsel, fb_end;                                      // rank-revealing
     int64_t total;
 };
@@ -747,7 +980,8 @@ __host__ __device__ inline RRLayout rr_layout(int k, int nwp) {
     L.sh = L.theta + k;
     L.sc = L.sh + k;                   // 8 doubles
     L.icl = L.sc + 8;                  // 2 k + 2 ints
-    L.main_end = L.icl + k + 1;
+    L.rb = L.icl + k + 1;              // 4 P doubles for the register-row routines
+    L.main_end = L.rb + 4 * 8 * (int64_t)rr_nt(k);
     if ((int64_t)3 * k * nwp <= 2 * kk) {
         L.U3 = L.A;
     } else {
@@ -768,7 +1002,8 @@ __host__ __device__ inline RRLayout rr_layout(int k, int nwp) {
 // ALL_LDS: the whole layout in LDS (pointers derived from the LDS base only, so the
 // compiler emits LDS instructions); otherwise in the global workspace.  The global
 // workspace always holds the k x k product scratch of the rank-revealing route.
-template <bool ALL_LDS>
+// NT > 0: the dense phases on register rows (r <= 8 NT); NT = 0: the LDS routines.
+template <bool ALL_LDS, int NT>
 __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
                                                               const double* __restrict__ HR,
                                                               const double* __restrict__ SR,
@@ -797,14 +1032,26 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     __syncthreads();
     for (int e = tid; e < kk; e += nt) {
         const int i = (int)(e % k), j = (int)(e / k);
-        A[e] = D[i] * SR[i + (int64_t)j * ldr] * D[j];
+        if (NT == 0) A[e] = D[i] * SR[i + (int64_t)j * ldr] * D[j];
         B[e] = D[i] * HR[i + (int64_t)j * ldr] * D[j];
     }
     __syncthreads();
     double* invd = base + Lo.invd;
-    if (cholesky_rl(A, k, invd)) {
+    double* T = base + Lo.T;
+    double* sc = base + Lo.sc;
+    bool spd;
+    if constexpr (NT > 0) {
+        // X = L^{-1} into T
+        spd = chol_inv_regs<NT>(SR, ldr, D, k, T, base + Lo.rb, sc + 4);
+    } else {
+        spd = cholesky_rl(A, k, invd);
+        if (spd) {
+            __syncthreads();
+            invert_lower_rl(A, invd, T, k);
+        }
+    }
+    if (spd) {
         __syncthreads();
-        double* T = base + Lo.T;
         double* Zt = base + Lo.Zt;
         double* U3 = base + Lo.U3;
         double* d = base + Lo.d;
@@ -812,23 +1059,25 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         double* e2 = base + Lo.e2;
         double* theta = base + Lo.theta;
         double* sh = base + Lo.sh;
-        double* sc = base + Lo.sc;
         int* cstart = (int*)(base + Lo.icl);
         int* csize = cstart + k;
         int* ncl = csize + k;
-        // X = L^{-1} into T; C = X B X^T via U = B X^T (into A, L is no longer needed)
-        invert_lower_rl(A, invd, T, k);
-        __syncthreads();
+        // C = X B X^T via U = B X^T (into A, L is no longer needed)
         gemm_mfma(B, k, false, T, k, true, k, k, k,
                   [&](int i, int j, double v) { A[i + j * k] = v; });
         __syncthreads();
         gemm_mfma(T, k, false, A, k, false, k, k, k,
                   [&](int i, int j, double v) { B[i + j * k] = v; });
         __syncthreads();
-        symmetrize(B, k);
-        __syncthreads();
-        // T read row-major is X^T = L^{-T}: the reflectors accumulate onto it
-        tridiagonalize_acc(B, T, k, d, e, base + Lo.vb, base + Lo.pA, base + Lo.pM, base + Lo.pv, sc);
+        if constexpr (NT > 0) {
+            // symmetrised on loading; M = X^T Q leaves row-major in T
+            tridiag_regs<NT>(B, T, k, d, e, base + Lo.rb, sc);
+        } else {
+            symmetrize(B, k);
+            __syncthreads();
+            // T read row-major is X^T = L^{-T}: the reflectors accumulate onto it
+            tridiagonalize_acc(B, T, k, d, e, base + Lo.vb, base + Lo.pA, base + Lo.pM, base + Lo.pv, sc);
+        }
         __syncthreads();
         bisect_lowest(d, e, e2, k, nwant, theta, sc);
         __syncthreads();
@@ -843,7 +1092,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     // ------------------------------------------------------------ rank-revealing route
     __syncthreads();
     double* V = base + Lo.V;
-    double* T = base + Lo.fT;
+    double* fT = base + Lo.fT;
     double2* rcs = (double2*)(base + Lo.rot);
     int2* rpq = (int2*)(rcs + (k / 2 + 1));
     double* theta = base + Lo.ftheta;
@@ -871,13 +1120,13 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     for (int e = tid; e < k * r; e += nt) {
         const int i = (int)(e % k), c = (int)(e / k);
         const int src = sel[c];
-        T[i + c * k] = V[i + src * k] / sqrt(A[src + src * k]);
+        fT[i + c * k] = V[i + src * k] / sqrt(A[src + src * k]);
     }
     __syncthreads();
     // C = T^T B T (r x r, ld r) into B, via U = B T (k x r)
-    small_gemm(B, false, T, false, U, k, r, k, k, k, k);
+    small_gemm(B, false, fT, false, U, k, r, k, k, k, k);
     __syncthreads();
-    small_gemm(T, true, U, false, B, r, r, k, k, k, r);
+    small_gemm(fT, true, U, false, B, r, r, k, k, k, r);
     __syncthreads();
     if (r < nwant) {
         if (tid == 0) { info[0] = k - r; info[1] = (int)LABPSD_ERANK; }
@@ -914,7 +1163,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         const int i = (int)(e % k), q = (int)(e / k);
         const int src = sel[q];
         double acc = 0.0;
-        for (int p = 0; p < r; ++p) acc = fma(T[i + p * k], V[p + src * r], acc);
+        for (int p = 0; p < r; ++p) acc = fma(fT[i + p * k], V[p + src * r], acc);
         W[i + (int64_t)q * ldw] = D[i] * acc;
     }
     if (tid == 0) { info[0] = k - r; info[1] = 0; }
@@ -945,19 +1194,32 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
     }
     const RRLayout L = rr_layout(k, nwant | 1);
     const size_t bytes = (size_t)L.total * sizeof(double);
+    // register-row width: 8 lanes per row, NT columns per lane
+    const int nt = rr_nt(k);
     // the static LDS of the kernel (the reduction array) stays below 1 KiB
-    if (lds_limit > 2048 && bytes <= (size_t)lds_limit - 1024) {
+    const bool all_lds = lds_limit > 2048 && bytes <= (size_t)lds_limit - 1024;
+    auto pick = [&](auto lds_tag) -> const void* {
+        constexpr bool L_ = decltype(lds_tag)::value;
+        switch (nt) {
+            case 5: return (const void*)k_rayleigh_ritz<L_, 5>;
+            case 9: return (const void*)k_rayleigh_ritz<L_, 9>;
+            case 16: return (const void*)k_rayleigh_ritz<L_, 16>;
+            default: return (const void*)k_rayleigh_ritz<L_, 0>;
+        }
+    };
+    void* args[] = {(void*)&k, (void*)&nwant, (void*)&HR, (void*)&SR, (void*)&ldr, (void*)&gamma,
+                    (void*)&W, (void*)&ldw, (void*)&info, (void*)&ws};
+    if (all_lds) {
+        const void* f = pick(std::true_type{});
         if (bytes > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)k_rayleigh_ritz<true>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         (void)hipGetLastError();
-        hipLaunchKernelGGL(k_rayleigh_ritz<true>, dim3(1), dim3(kRRThreads), bytes, s, k, nwant, HR, SR,
-                           ldr, gamma, W, ldw, info, (double*)ws);
-        if (hipGetLastError() == hipSuccess) return;
+        if (hipLaunchKernel(f, dim3(1), dim3(kRRThreads), args, bytes, s) == hipSuccess &&
+            hipGetLastError() == hipSuccess)
+            return;
         // the launch was refused (nothing ran): use the global-memory variant
     }
-    hipLaunchKernelGGL(k_rayleigh_ritz<false>, dim3(1), dim3(kRRThreads), 0, s, k, nwant, HR, SR, ldr,
-                       gamma, W, ldw, info, (double*)ws);
+    LABPSD_HIP(hipLaunchKernel(pick(std::false_type{}), dim3(1), dim3(kRRThreads), args, 0, s));
     LABPSD_HIP(hipGetLastError());
 }
 

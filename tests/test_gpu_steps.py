@@ -207,7 +207,7 @@ def _rr_case(P, k, rng, dup=0):
     return HR, SR, HR0, SR0
 
 
-@pytest.mark.parametrize("k,nwant,dup", [(8, 8, 0), (12, 6, 0), (68, 36, 0), (40, 20, 3), (100, 60, 0)])
+@pytest.mark.parametrize("k,nwant,dup", [(8, 8, 0), (12, 6, 0), (68, 36, 0), (40, 20, 3), (100, 60, 0), (140, 40, 0)])
 def test_rayleigh_ritz(prob, ctx, k, nwant, dup):
     P, pr = prob
     import paper_1308_2445_amd as lp
