@@ -186,7 +186,51 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
     F->diag_off = (int64_t)tk.size();
     for (int i = 0; i < F->nsn; ++i) add_tasks(H.sn[i], 0);
     F->diag_count = (int64_t)tk.size() - F->diag_off;
+    // the single-launch sweep: forward tasks by level from the leaves, the diagonal
+    // tasks by level, backward tasks by level from the roots (every dependency earlier
+    // in the list); counters (children, forward tasks, diagonal + backward tasks)
+    std::vector<int32_t> init(3 * (size_t)F->nsn, 0);
+    std::vector<SweepTask> sw;
+    {
+        const int nsn = F->nsn;
+        bool tree_ok = true;
+        for (int i = 0; i < nsn; ++i) {
+            const Supernode& sn = H.sn[i];
+            const int nb = sn.nrow - sn.ncol;
+            if (sn.parent >= 0) {
+                // a child counts itself off with its last forward task, so it needs one
+                if (sn.parent >= nsn || H.sn[sn.parent].level <= sn.level || nb == 0) tree_ok = false;
+                else ++init[sn.parent];
+            } else if (nb > 0) {
+                tree_ok = false;   // rows outside the supernode need a parent to own them
+            }
+        }
+        auto add_sweep = [&](int i, int op_list, int op_kernel) {
+            const size_t before = tk.size();
+            add_tasks(H.sn[i], op_list);
+            for (size_t t = before; t < tk.size(); ++t) sw.push_back(SweepTask{tk[t], op_kernel, i, H.sn[i].parent, 0});
+            const int32_t added = (int32_t)(tk.size() - before);
+            tk.resize(before);
+            if (op_list == 1) init[nsn + i] += added;
+            else init[2 * (size_t)nsn + i] += added;
+        };
+        for (int l = 0; l < F->nlevels; ++l)
+            for (int i = 0; i < nsn; ++i)
+                if (H.sn[i].level == l) add_sweep(i, 1, 2);
+        for (int l = 0; l < F->nlevels; ++l)
+            for (int i = 0; i < nsn; ++i)
+                if (H.sn[i].level == l) add_sweep(i, 0, 0);
+        for (int l = F->nlevels - 1; l >= 0; --l)
+            for (int i = 0; i < nsn; ++i)
+                if (H.sn[i].level == l) add_sweep(i, 2, 3);
+        F->use_sweep = tree_ok && !sw.empty();
+    }
+    // host vectors stay alive until the copies have finished
     F->tasks.upload(tk.data(), tk.size(), s);
+    if (F->use_sweep) {
+        F->sweep.upload(sw.data(), sw.size(), s);
+        F->sweep_init.upload(init.data(), init.size(), s);
+    }
     LABPSD_HIP(hipStreamSynchronize(s));
     F->info.n_supernodes = F->nsn;
     F->info.n_levels = F->nlevels;
@@ -525,6 +569,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     }
     readback();
     LABPSD_HIP(hipStreamSynchronize(s));
+    check_precond_sweep(*P.factor, s);
     its_collect();
     // a converged exit has checked the last Rayleigh-Ritz step in its final iteration
     if (!converged)
@@ -850,6 +895,7 @@ labpsd_status labpsd_precond_apply(labpsd_problem* p, int precision, const doubl
         }
         // the workspace is reused by the next call: finish before returning it
         LABPSD_HIP(hipStreamSynchronize(s));
+        check_precond_sweep(*p->factor, s);
         return LABPSD_OK;
     });
 }

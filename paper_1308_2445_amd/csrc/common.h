@@ -154,6 +154,17 @@ struct SnTask {
 };
 static_assert(sizeof(SnTask) == 32, "SnTask is two 16-byte words");
 
+// A task of the single-launch sweep (launch_precond_solve): a product task and its
+// place in the supernode tree; op 2 forward, 0 diagonal, 3 backward.
+struct SweepTask {
+    SnTask t;
+    int32_t op;       // which product
+    int32_t sn;       // its supernode
+    int32_t parent;   // the supernode's parent (-1 for a root)
+    int32_t pad;
+};
+static_assert(sizeof(SweepTask) == 48, "sweep task layout");
+
 struct DevFactor {
     int64_t n = 0;
     int nsn = 0;
@@ -168,8 +179,22 @@ struct DevFactor {
     std::vector<int64_t> lev_off, lev_count;   // 4 * nlevels each
     int64_t diag_off = 0, diag_count = 0;
     DBuf<SnTask> tasks;
+    // The same products as one launch: every task in dependency order (forward level by
+    // level from the leaves, the diagonal products, backward level by level from the
+    // roots), each waiting on counters of its supernode's children or parent.  The
+    // initial counters per supernode are (children, forward tasks, diagonal and backward
+    // tasks); sweep_cnt holds an error word (4 ints) and then their live copy for each
+    // group of 16 right-hand sides.
+    DBuf<SweepTask> sweep;
+    DBuf<int32_t> sweep_init;            // 3 nsn
+    mutable DBuf<int32_t> sweep_cnt;     // 4 + 3 nsn groups
+    bool use_sweep = true;
     labpsd_factor_info info{};
 };
+
+// Raise an error if a preconditioner sweep on F gave up waiting for a dependency (a
+// counter that never reached zero) since the last check; synchronises with s.
+void check_precond_sweep(const DevFactor& F, hipStream_t s);
 
 // ------------------------------------------------------------------ context / problem
 

@@ -39,18 +39,29 @@ enum { OP_DIAG = 0, OP_OFFD = 2, OP_OFFD_T = 3 };
 //  OP_DIAG   out[D[r]] += sum_k G[r,k] in[D[k]]
 //  OP_OFFD   out[B[r]] -= sum_k F[r,k] in[D[k]]
 //  OP_OFFD_T out[D[r]] -= sum_k F[k,r] in[B[k]]
-template <typename T, int OP>
-__global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ tasks,
-                                                    const int32_t* __restrict__ rows,
-                                                    const T* __restrict__ panels,
-                                                    const T* __restrict__ in, T* __restrict__ out,
-                                                    int nrhs) {
-    const SnTask tk = tasks[blockIdx.x];
+template <typename T>
+struct SnTiles {
+    T M[KS][TR + 1];   // M[k][r] = M(r0 + r, kb + k)
+    T X[KS][TC + 1];   // X[k][c] = in[row(kb + k), c0 + c]
+};
+
+struct NoWait {
+    __device__ void operator()() const {}
+};
+
+// One task on right-hand sides c0 .. c0 + 15 (in and out may be the same block).  Every
+// thread of the work-group calls it.  The panel tile and the row indices are requested
+// first; wait() (called by every thread) runs while they are in flight, and only then
+// are the right-hand-side rows read.  CO: those rows are read with device-scope
+// (coherent) loads, for rows other work-groups of the same launch have updated.
+template <typename T, int OP, bool CO = false, typename Wait = NoWait>
+__device__ __forceinline__ void sn_task(const SnTask& tk, const int32_t* __restrict__ rows,
+                                        const T* __restrict__ panels, const T* in, T* out, int nrhs,
+                                        int c0, SnTiles<T>& st, Wait wait = Wait{}) {
     const int ncol = tk.ncol, nrow = tk.nrow;
     const int nb = nrow - ncol;
     const int32_t* rl = rows + tk.idx_off;
     const T* P = panels + tk.val_off;   // nrow x ncol, ld nrow
-    const int c0 = blockIdx.y * TC;
     const int nc = min(TC, nrhs - c0);
 
     // output and reduction extents
@@ -63,8 +74,8 @@ __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ t
     // reduction range of the chunk
     const int k_end = min(nred, kb + KS);
 
-    __shared__ T sM[KS][TR + 1];      // sM[k][r] = M(r0 + r, kb + k)
-    __shared__ T sX[KS][TC + 1];      // sX[k][c] = in[row(kb + k), c0 + c]
+    auto& sM = st.M;
+    auto& sX = st.X;
     const int t = threadIdx.x;
     // stage M(r, k) for r in [r0, r0+TR), k in [kb, kb+KS); every load issued before any use
     T mv[TR * KS / 256];
@@ -87,16 +98,23 @@ __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ t
         mv[i] = v;
     }
     // gathered right-hand sides: 16 consecutive lanes read the 16 values of one row
-    T xv[KS * TC / 256];
+    int gi[KS * TC / 256];
 #pragma unroll
     for (int i = 0; i < KS * TC / 256; ++i) {
         const int e = t + 256 * i;
-        const int c = e % TC, kk = e / TC;
-        const int k = kb + kk;
+        const int c = e % TC, k = kb + e / TC;
+        gi[i] = (k < k_end && c < nc) ? ((OP == OP_OFFD_T) ? rl[ncol + k] : rl[k]) : -1;
+    }
+    wait();
+    T xv[KS * TC / 256];
+#pragma unroll
+    for (int i = 0; i < KS * TC / 256; ++i) {
+        const int c = (t + 256 * i) % TC;
         T v = T(0);
-        if (k < k_end && c < nc) {
-            const int grow = (OP == OP_OFFD_T) ? rl[ncol + k] : rl[k];
-            v = in[(int64_t)grow * nrhs + c0 + c];
+        if (gi[i] >= 0) {
+            const T* src = in + (int64_t)gi[i] * nrhs + c0 + c;
+            if constexpr (CO) v = __hip_atomic_load(const_cast<T*>(src), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else v = *src;
         }
         xv[i] = v;
     }
@@ -141,6 +159,91 @@ __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ t
     }
 }
 
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ tasks,
+                                                    const int32_t* __restrict__ rows,
+                                                    const T* __restrict__ panels,
+                                                    const T* __restrict__ in, T* __restrict__ out,
+                                                    int nrhs) {
+    __shared__ SnTiles<T> st;
+    sn_task<T, OP>(tasks[blockIdx.x], rows, panels, in, out, nrhs, blockIdx.y * TC, st);
+}
+
+// Upper bound on the polls of one dependency wait (with a short sleep between polls,
+// seconds); a wait that runs out sets the error word and goes on, so every work-group
+// finishes whatever happens.
+constexpr int kSweepSpinLimit = 1 << 20;
+
+// The whole solve in one launch.  Work-group b runs task b / groups on right-hand-side
+// group b % groups (the groups of a task side by side, so they advance together).  Before its product a task waits until (forward and diagonal) every
+// child supernode has finished its forward products, or (backward) the parent has
+// finished its diagonal and backward products; every dependency has a lower work-group
+// index, and work-groups start in index order, so the lowest unfinished one can always
+// run.  Results pass between work-groups only through device-scope atomics: a task's
+// outputs are atomic adds, which it waits for (vmcnt) before counting itself off with an
+// atomic; the last forward task of a supernode counts the supernode off at its parent;
+// a waiting task polls its counter and reads right-hand-side rows with device-scope
+// loads.  (Device-scope fences would write back or invalidate a whole L2 per task.)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sn_sweep(const SweepTask* __restrict__ tasks, int64_t ntasks,
+                                                  const int32_t* __restrict__ rows,
+                                                  const T* __restrict__ panels, T* Y, T* W2, int nrhs,
+                                                  int32_t* cnt, int nsn, int groups) {
+    __shared__ SnTiles<T> st;
+    const int64_t b = blockIdx.x;
+    const int64_t ti = b / groups;
+    const int cg = (int)(b - ti * groups);
+    const SweepTask tk = tasks[ti];
+    int32_t* err = cnt;
+    int32_t* ch_f = cnt + 4 + (int64_t)cg * 3 * nsn;   // children yet to finish forward
+    int32_t* tk_f = ch_f + nsn;                          // forward tasks left
+    int32_t* tk_b = ch_f + 2 * nsn;                      // diagonal and backward tasks left
+    auto wait = [&]() {
+        if (threadIdx.x == 0) {
+            int32_t* w = tk.op == OP_OFFD_T ? tk_b + tk.parent : ch_f + tk.sn;
+            // poll with a growing pause (waiting work-groups keep their polls off the
+            // lines the producers update)
+            int spins = 0, pause = 1;
+            while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                for (int i = 0; i < pause; ++i) __builtin_amdgcn_s_sleep(4);
+                pause = pause < 4 ? 2 * pause : 4;
+                if (++spins > kSweepSpinLimit) {
+                    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+    };
+    const int c0 = cg * TC;
+    if (tk.op == OP_OFFD) sn_task<T, OP_OFFD, true>(tk.t, rows, panels, Y, Y, nrhs, c0, st, wait);
+    else if (tk.op == OP_DIAG) sn_task<T, OP_DIAG, true>(tk.t, rows, panels, Y, W2, nrhs, c0, st, wait);
+    else sn_task<T, OP_OFFD_T, true>(tk.t, rows, panels, W2, W2, nrhs, c0, st, wait);
+    // every wavefront's atomic adds have completed (s_waitcnt vmcnt(0)) before the barrier
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (tk.op == OP_OFFD) {
+            if (__hip_atomic_fetch_add(tk_f + tk.sn, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1 &&
+                tk.parent >= 0)
+                __hip_atomic_fetch_add(ch_f + tk.parent, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_fetch_add(tk_b + tk.sn, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// W2 = 0 and the sweep counters of `groups` right-hand-side groups from their template
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep_init(int64_t count, T* __restrict__ W2,
+                                                    const int32_t* __restrict__ init, int64_t ninit,
+                                                    int32_t* __restrict__ cnt, int groups) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) W2[i] = T(0);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ninit * groups; i += stride)
+        cnt[4 + i] = init[i % ninit];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill_copy(int64_t count, T* __restrict__ dst,
                                                    const T* __restrict__ src) {
@@ -179,6 +282,24 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
     const T* panels;
     if constexpr (sizeof(T) == 8) panels = F.panels64.p;
     else panels = F.panels32.p;
+    if (F.use_sweep && F.sweep.n > 0 && ncols > 0) {
+        const int groups = (ncols + TC - 1) / TC;
+        const int64_t ninit = 3 * (int64_t)F.nsn;
+        const size_t need = 4 + (size_t)ninit * groups;
+        if (F.sweep_cnt.n < need) {
+            F.sweep_cnt.alloc(need);
+            LABPSD_HIP(hipMemsetAsync(F.sweep_cnt.p, 0, 4 * sizeof(int32_t), s));
+        }
+        const int64_t count = n * ncols;
+        const int64_t blocks = std::min<int64_t>((std::max<int64_t>(count, ninit * groups) + 255) / 256, 2048);
+        hipLaunchKernelGGL((k_sweep_init<T>), dim3((unsigned)blocks), dim3(256), 0, s, count, W2,
+                           F.sweep_init.p, ninit, F.sweep_cnt.p, groups);
+        const int64_t ntasks = (int64_t)F.sweep.n;
+        hipLaunchKernelGGL((k_sn_sweep<T>), dim3((unsigned)(ntasks * groups)), dim3(256), 0, s, F.sweep.p,
+                           ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn, groups);
+        LABPSD_HIP(hipGetLastError());
+        return;
+    }
     const int L = F.nlevels;
     fill_copy<T>(W2, nullptr, n * ncols, s);
     for (int l = 0; l < L; ++l)
@@ -188,6 +309,18 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
     for (int l = L - 1; l >= 0; --l)
         launch_level<T, OP_OFFD_T>(F, F.tasks.p + F.lev_off[4 * l + 2], F.lev_count[4 * l + 2], panels, W2,
                                    W2, ncols, s);
+}
+
+void check_precond_sweep(const DevFactor& F, hipStream_t s) {
+    if (!F.sweep_cnt.p) return;
+    int32_t e = 0;
+    LABPSD_HIP(hipMemcpyAsync(&e, F.sweep_cnt.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LABPSD_HIP(hipStreamSynchronize(s));
+    if (e != 0) {
+        LABPSD_HIP(hipMemsetAsync(F.sweep_cnt.p, 0, sizeof(int32_t), s));
+        LABPSD_HIP(hipStreamSynchronize(s));
+        throw Error{LABPSD_EHIP, "preconditioner sweep: a dependency wait ran out"};
+    }
 }
 
 template void launch_precond_solve<double>(const DevFactor&, double*, double*, double*, int64_t, int,
