@@ -6,16 +6,18 @@
 // MINRES (Paige and Saunders): Lanczos on A = H - eps_j S builds an orthonormal Krylov
 // basis with A V_k = V_{k+1} T_k; the least-squares problem with T_k is solved by one
 // Givens rotation per step, whose running product gives the residual norm for free.
-// All localised columns advance together, three kernels per iteration:
-//   spmv    w = A v - beta_k v_prev, per-slice partial sums of v.w    (one pattern pass)
-//   axpy    alpha_k = v.w; w -= alpha_k v, partial sums of ||w||^2
-//   update  beta_{k+1} = ||w||, the new rotation, tau_k and |phibar_k|;
+// All localised columns advance together, two kernels per iteration:
+//   spmv    u = A v - beta_k v_prev, per-slice FP64 partial sums of v.u, u.u and v.v
+//           (one pattern pass)
+//   update  alpha_k = v.u; w = u - alpha_k v, whose norm follows from the sums without
+//           another pass: ||w||^2 = u.u - 2 alpha_k v.u + alpha_k^2 v.v; beta_{k+1} = ||w||,
+//           the new rotation, tau_k and |phibar_k|;
 //           d = (v - delta_k d1 - eps_k d2) / gamma_k, x += tau_k d, v_next = w / beta_{k+1}
 // Every block recomputes the column's scalars from the partial sums (identical values);
 // block 0 of the column stores the new scalar state into the other half of a double
 // buffer, so no block reads a state that another block of the same kernel writes.
 // The host checks the count of active columns every few iterations.  T = double (FP64)
-// or float (mixed: FP32 vectors, FP32 products and FP32 per-slice sums).
+// or float (mixed: FP32 vectors and products; the per-slice sums are FP64 in both).
 #include "common.h"
 
 namespace labpsd {
@@ -45,10 +47,12 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
     const T* __restrict__ sv, int64_t n, int64_t nslices, const T* __restrict__ X, int64_t ldx,
     const int32_t* __restrict__ xcols, const T* __restrict__ aux, int64_t ldaux,
     const int32_t* __restrict__ auxcols, const double* __restrict__ shift,
-    const MinresScal* __restrict__ sc, T* __restrict__ out, T* __restrict__ partial, int q) {
+    const MinresScal* __restrict__ sc, T* __restrict__ out, double* __restrict__ partial,
+    int64_t npart, int q, int32_t* __restrict__ active) {
     constexpr int SPB = 4 / WPS;   // slices per work-group
+    constexpr int NS = MODE == 0 ? 1 : 3;   // partial sums per column
     __shared__ T sred[WPS > 1 ? 256 * 2 * CW : 1];
-    __shared__ T red[kWaves][CW];
+    __shared__ double red[kWaves][NS][CW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t nblk = (nslices + SPB - 1) / SPB;
     const int64_t sb = xcd_block(blockIdx.x, nblk);
@@ -71,6 +75,9 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
         ah[j] = T(0);
         as[j] = T(0);
     }
+    // the active-column count of this iteration starts at zero (the previous
+    // iteration's count has been read by now: the read is ordered before this kernel)
+    if (MODE == 1 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *active = 0;
     // a chunk whose columns have all converged has nothing to do (uniform over the
     // work-group; the next kernels read no partial of a converged column)
     if (!any) return;
@@ -92,32 +99,41 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
 #pragma unroll
     for (int j = 0; j < CW; ++j) {
         const int jj = j0 + j;
-        T contrib = T(0);
+        double c[NS];
+#pragma unroll
+        for (int w = 0; w < NS; ++w) c[w] = 0.0;
         if (act[j] && lead && row < n) {
             const T y = ah[j] - (T)shift[jj] * as[j];
             T v;
-            if (MODE == 0) {
+            if constexpr (MODE == 0) {
                 v = -(y + aux[row + (int64_t)auxcols[jj] * ldaux]);
-                contrib = v * v;
+                c[0] = (double)v * (double)v;
             } else {
                 v = y - (T)sc[jj].beta * aux[row + (int64_t)jj * ldaux];
-                contrib = xc[j][row] * v;
+                const double xv = (double)xc[j][row];
+                c[0] = xv * (double)v;
+                c[1] = (double)v * (double)v;
+                c[2] = xv * xv;
             }
             out[row + (int64_t)jj * n] = v;
         }
-        contrib = wave_sum_t(contrib);
-        if (lane == 0) red[wave][j] = contrib;
+#pragma unroll
+        for (int w = 0; w < NS; ++w) {
+            const double t = wave_allsum(c[w]);
+            if (lane == 0) red[wave][w][j] = t;
+        }
     }
     __syncthreads();
-    // one partial per work-group and column (the slice block sb owns slot sb); the
+    // one partial per work-group, column and sum (the slice block sb owns slot sb); the
     // wavefronts that only helped a slice contributed zeros
-    if (threadIdx.x < CW) {
-        const int jj = j0 + threadIdx.x;
+    if (threadIdx.x < NS * CW) {
+        const int w = threadIdx.x / CW, jl = threadIdx.x % CW;
+        const int jj = j0 + jl;
         if (jj < q) {
-            T t = T(0);
+            double t = 0.0;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) t += red[w][threadIdx.x];
-            partial[sb * q + jj] = (MODE == 0 || !sc[jj].done) ? t : T(0);
+            for (int v = 0; v < kWaves; ++v) t += red[v][w][jl];
+            partial[((int64_t)w * npart + sb) * q + jj] = (MODE == 0 || !sc[jj].done) ? t : 0.0;
         }
     }
 }
@@ -132,16 +148,19 @@ __device__ double column_sum(const T* partial, int64_t np, int q, int j) {
     return __shfl(s, 0, 64);
 }
 
-// the same sum for a whole work-group: wavefront 0 computes it, LDS broadcasts it
-template <typename T>
-__device__ double block_column_sum(const T* partial, int64_t np, int q, int j) {
-    __shared__ double bc;
-    if (threadIdx.x < 64) {
-        const double v = column_sum(partial, np, q, j);
-        if (threadIdx.x == 0) bc = v;
+// the three sums (stride np q apart) for a whole work-group: wavefronts 0, 1 and 2 each
+// compute one, LDS broadcasts them; called once per kernel
+__device__ void block_column_sums3(const double* partial, int64_t np, int q, int j, double out[3]) {
+    __shared__ double bc[3];
+    const int w = threadIdx.x >> 6;
+    if (w < 3) {
+        const double v = column_sum(partial + (int64_t)w * np * q, np, q, j);
+        if ((threadIdx.x & 63) == 0) bc[w] = v;
     }
     __syncthreads();
-    return bc;
+    out[0] = bc[0];
+    out[1] = bc[1];
+    out[2] = bc[2];
 }
 
 // sum over the work-group, valid in thread 0
@@ -154,8 +173,7 @@ __device__ T block_sum(T v) {
     return w[0] + w[1] + w[2] + w[3];
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_minres_init_finish(const T* __restrict__ partial,
+__global__ __launch_bounds__(256) void k_minres_init_finish(const double* __restrict__ partial,
                                                             int64_t nslices, int q,
                                                             const double* __restrict__ rnorm,
                                                             double eta, int max_inner,
@@ -195,34 +213,6 @@ __global__ __launch_bounds__(256) void k_minres_init_vectors(int64_t n, int q,
     }
 }
 
-// alpha = v.w (from the spmv partials); w -= alpha v; one partial of ||w||^2 per
-// work-group.  Grid (G, q): work-group x of column j strides over rows x*256 + G*256*i.
-template <typename T>
-__global__ __launch_bounds__(256) void k_minres_axpy(int64_t n, int q, int64_t npa,
-                                                     const MinresScal* __restrict__ sc,
-                                                     const T* __restrict__ pa, double* __restrict__ alpha,
-                                                     const T* __restrict__ V, T* __restrict__ Wb,
-                                                     T* __restrict__ pw, int32_t* __restrict__ active) {
-    const int j = blockIdx.y;
-    if (blockIdx.x == 0 && j == 0 && threadIdx.x == 0) *active = 0;
-    if (sc[j].done) {   // uniform over the work-group
-        if (threadIdx.x == 0) pw[(int64_t)blockIdx.x * q + j] = T(0);
-        return;
-    }
-    const double a = block_column_sum(pa, npa, q, j);
-    if (blockIdx.x == 0 && threadIdx.x == 0) alpha[j] = a;
-    const T ta = (T)a;
-    T c = T(0);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int64_t o = i + (int64_t)j * n;
-        const T w = Wb[o] - ta * V[o];
-        Wb[o] = w;
-        c += w * w;
-    }
-    c = block_sum(c);
-    if (threadIdx.x == 0) pw[(int64_t)blockIdx.x * q + j] = c;
-}
-
 // Scalar recurrences of the tridiagonal QR, computed identically by every work-group of
 // the column, then the vector updates of its rows.  Work-group 0 of the column stores
 // the new state in sc_out (the host swaps sc_in and sc_out between iterations).
@@ -230,8 +220,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max_inner,
                                                        const MinresScal* __restrict__ sc_in,
                                                        MinresScal* __restrict__ sc_out,
-                                                       const T* __restrict__ pw,
-                                                       const double* __restrict__ alpha,
+                                                       const double* __restrict__ part, int64_t npa,
                                                        const T* __restrict__ V, T* __restrict__ Wb,
                                                        const T* __restrict__ D1, T* __restrict__ D2,
                                                        T* __restrict__ Xs, int32_t* __restrict__ active) {
@@ -242,8 +231,10 @@ __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max
         if (lead) sc_out[j] = s;
         return;
     }
-    const double bnext = sqrt(block_column_sum(pw, (int64_t)gridDim.x, q, j));
-    const double al = alpha[j];
+    double sums[3];   // v.u, u.u, v.v
+    block_column_sums3(part, npa, q, j, sums);
+    const double al = sums[0];
+    const double bnext = sqrt(fmax(sums[1] - al * (2.0 * sums[0] - al * sums[2]), 0.0));
     const int k = s.its + 1;
     // rotation k-2 maps (0, beta_k) to (eps_k, t1); column 1 has no entry above the diagonal
     const double epsk = k > 1 ? s.spp * s.beta : 0.0;
@@ -266,12 +257,14 @@ __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max
     const double phibar = -sn * s.phibar;
     const T ig = (T)(1.0 / gamma), de = (T)delta, ep = (T)epsk, ta = (T)tau;
     const T ib = bnext > 0.0 ? (T)(1.0 / bnext) : T(0);
+    const T tal = (T)al;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int64_t o = i + (int64_t)j * n;
-        const T d = (V[o] - de * D1[o] - ep * D2[o]) * ig;
+        const T v = V[o];
+        const T d = (v - de * D1[o] - ep * D2[o]) * ig;
         D2[o] = d;
         Xs[o] += ta * d;
-        Wb[o] *= ib;
+        Wb[o] = (Wb[o] - tal * v) * ib;
     }
     if (lead) {
         MinresScal t = s;
@@ -305,13 +298,14 @@ __global__ __launch_bounds__(256) void k_minres_final(int64_t n, int q, const in
 template <typename T, int MODE, int CW, int WPS>
 int64_t launch_spmv_s(const Sell& A, const T* hv, const T* sv, const T* X, int64_t ldx,
                       const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
-                      const double* shift, const MinresScal* sc, T* out, T* partial, int q,
-                      hipStream_t s) {
+                      const double* shift, const MinresScal* sc, T* out, double* partial, int q,
+                      int32_t* active, hipStream_t s) {
     constexpr int SPB = 4 / WPS;
     const int64_t nblk = (A.nslices + SPB - 1) / SPB;
     const dim3 g((unsigned)nblk, (unsigned)((q + CW - 1) / CW));
     hipLaunchKernelGGL((k_minres_spmv<T, MODE, CW, WPS>), g, dim3(256), 0, s, A.slice_off.p, A.col.p, hv,
-                       sv, A.n, A.nslices, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q);
+                       sv, A.n, A.nslices, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, nblk,
+                       q, active);
     return nblk;
 }
 
@@ -320,9 +314,11 @@ int64_t launch_spmv_s(const Sell& A, const T* hv, const T* sv, const T* X, int64
 template <typename T, int MODE>
 int64_t launch_spmv(const Sell& A, SellShape sh, const T* hv, const T* sv, const T* X, int64_t ldx,
                     const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
-                    const double* shift, const MinresScal* sc, T* out, T* partial, int q, hipStream_t s) {
+                    const double* shift, const MinresScal* sc, T* out, double* partial, int q,
+                    int32_t* active, hipStream_t s) {
 #define LABPSD_SPMV(CW, WPS) \
-    launch_spmv_s<T, MODE, CW, WPS>(A, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q, s)
+    launch_spmv_s<T, MODE, CW, WPS>(A, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q, \
+                                    active, s)
     if (sh.wps == 4) {
         if (sh.cw >= 4) return LABPSD_SPMV(4, 4);
         if (sh.cw == 2) return LABPSD_SPMV(2, 4);
@@ -337,7 +333,8 @@ int64_t launch_spmv(const Sell& A, SellShape sh, const T* hv, const T* sv, const
 }  // namespace
 
 size_t minres_ws_elems(int64_t n, int q) {
-    return (size_t)6 * n * q + 2 * (size_t)((n + 63) / 64 + 1) * q;
+    // six vectors, then 3 FP64 partial sums per slice and column (as T elements)
+    return (size_t)6 * n * q + 3 * (8 / sizeof(float)) * (size_t)((n + 63) / 64 + 1) * q;
 }
 
 size_t minres_scal_doubles(int q) {
@@ -366,9 +363,10 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     T* Xs = D2 + n * q;
     const SellShape sh = sell_shape(A.nslices, q, 4);
     const unsigned G = rowwise_groups(n);
-    T* pa = Xs + n * q;                          // spmv partials (v.w, or b.b)
-    T* pw = pa + (A.nslices + 1) * q;            // axpy partials of ||w||^2, G per column
-    // scalar state double buffer, alpha, and the active-column counter
+    // spmv partials: 3 sets of at most nslices per column, FP64 (6 n q T elements precede,
+    // an even count, so the address is 8-byte aligned)
+    double* pa = (double*)(Xs + n * q);
+    // scalar state double buffer, one spare double per column, and the active-column counter
     constexpr size_t kScalDoubles = sizeof(MinresScal) / 8;
     MinresScal* sa = (MinresScal*)scal_ws;
     MinresScal* sb = (MinresScal*)(scal_ws + kScalDoubles * q);
@@ -385,9 +383,9 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     int64_t nl = 0;
     // b = -((H - eps S) p + r); beta1 = ||b||
     // spmv partials: one per work-group and column (at most nslices)
-    const int64_t npa =
-        launch_spmv<T, 0>(A, sh, hv, sv, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev, sa, V, pa, q, s);
-    hipLaunchKernelGGL((k_minres_init_finish<T>), gcol, dim3(256), 0, s, (const T*)pa, npa, q, rnorm_dev,
+    const int64_t npa = launch_spmv<T, 0>(A, sh, hv, sv, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev, sa, V,
+                                          pa, q, counter, s);
+    hipLaunchKernelGGL(k_minres_init_finish, gcol, dim3(256), 0, s, (const double*)pa, npa, q, rnorm_dev,
                        eta, max_inner, sa);
     hipLaunchKernelGGL((k_minres_init_vectors<T>), gel, dim3(256), 0, s, n, q, (const MinresScal*)sa, V,
                        VP, D1, D2, Xs);
@@ -405,14 +403,12 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     int slot = 0;
     bool pending = false;
     for (int it = 0; it < max_inner; ++it) {
-        launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s);
-        hipLaunchKernelGGL((k_minres_axpy<T>), grow, dim3(256), 0, s, n, q, npa, (const MinresScal*)cur,
-                           (const T*)pa, alpha, (const T*)V, Wb, pw, counter);
+        launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, counter, s);
         hipLaunchKernelGGL((k_minres_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
-                           (const MinresScal*)cur, nxt, (const T*)pw, (const double*)alpha, (const T*)V, Wb,
+                           (const MinresScal*)cur, nxt, (const double*)pa, npa, (const T*)V, Wb,
                            (const T*)D1, D2, Xs, counter);
         LABPSD_HIP(hipGetLastError());
-        nl += 3;
+        nl += 2;
         // rotate: v_prev <- v, v <- w (now scaled), w <- old v_prev; d1 <- new d, d2 <- old d1
         T* t0 = VP; VP = V; V = Wb; Wb = t0;
         T* t1 = D1; D1 = D2; D2 = t1;

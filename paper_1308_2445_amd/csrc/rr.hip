@@ -153,42 +153,6 @@ __device__ void small_gemm(const double* X, bool xt, const double* Z, bool zt, d
     }
 }
 
-// Cross-lane sums with DPP moves (VALU latency, no LDS round trip).  A DPP source lane
-// that is inactive contributes 0.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
-}
-// sum over the 16 lanes of a DPP row, in every lane of the row
-__device__ __forceinline__ double row16_allsum(double v) {
-    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-    v += dpp_d<0x124>(v);   // row_ror 4
-    v += dpp_d<0x128>(v);   // row_ror 8
-    return v;
-}
-// sum over each group of 8 lanes (half a DPP row), in every lane of the group
-__device__ __forceinline__ double row8_allsum(double v) {
-    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-    v += dpp_d<0x141>(v);   // row_half_mirror
-    return v;
-}
-__device__ __forceinline__ double readlane_d(double v, int l) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
-}
-// sum over the wavefront, in every lane; all 64 lanes must be active
-__device__ __forceinline__ double wave_allsum(double v) {
-    v = row16_allsum(v);
-    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
-}
-
 // 1 / x and 1 / sqrt(x) from the hardware approximations with two Newton steps
 // (within an ulp or two, without the long IEEE division sequence)
 __device__ __forceinline__ double rcp_nr(double x) {
