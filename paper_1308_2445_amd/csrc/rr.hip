@@ -764,11 +764,58 @@ __device__ void bisect_lowest(const double* d, const double* e, double* e2, int 
     }
 }
 
+// Row-swap flag and multiplier of elimination step i, kept in one double: the flag in the
+// lowest mantissa bit (the multiplier moves by at most an ulp).
+__device__ __forceinline__ double pack_step(double m, bool sw) {
+    const uint64_t b = (__builtin_bit_cast(uint64_t, m) & ~1ull) | (sw ? 1ull : 0ull);
+    return __builtin_bit_cast(double, b);
+}
+__device__ __forceinline__ double unpack_step(double v, bool& sw) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    sw = (b & 1ull) != 0;
+    return __builtin_bit_cast(double, b & ~1ull);
+}
+
+// Back substitution with U (reciprocal diagonal in slot 0, first superdiagonal in slot 1;
+// the second superdiagonal is e[i + 1] where step i swapped rows, else 0) from row r - 2
+// up, x1 = x[r - 1] already in z.
+__device__ __forceinline__ void tri_back(const double* e, int r, double* z, const double* u, int nwp,
+                                         double x1) {
+    if (r < 2) return;
+    double x2 = 0.0;
+    auto load = [&](int i, double& u0, double& u1, double& u2, double& zi) {
+        const double* ui = u + 3 * i * nwp;
+        bool sw;
+        (void)unpack_step(ui[2 * nwp], sw);
+        u0 = ui[0];
+        u1 = ui[nwp];
+        u2 = (sw && i + 2 < r) ? e[i + 1] : 0.0;
+        zi = z[i * nwp];
+    };
+    double u0, u1, u2, zi;
+    load(r - 2, u0, u1, u2, zi);
+#pragma unroll 2
+    for (int i = r - 2; i >= 0; --i) {
+        double u0n = 0.0, u1n = 0.0, u2n = 0.0, zin = 0.0;
+        if (i > 0) load(i - 1, u0n, u1n, u2n, zin);
+        const double xi = (zi - u1 * x1 - u2 * x2) * u0;
+        z[i * nwp] = xi;
+        x2 = x1;
+        x1 = xi;
+        u0 = u0n;
+        u1 = u1n;
+        u2 = u2n;
+        zi = zin;
+    }
+}
+
 // One solve (T - lam I) x = z in place (z and the factor strided by nwp): LU with
-// partial pivoting between neighbouring rows, U with two superdiagonals (its diagonal
-// kept as reciprocals); the row operations are applied to z as they are made.  The
-// pivot choice is made with selects so lanes with different pivots do not diverge.
-// Zero pivots become eps ||T||.
+// partial pivoting between neighbouring rows, U with two superdiagonals; the row
+// operations are applied to z as they are made.  The factor u (3 r x nwp) keeps, per
+// step, 1 / pivot, the first superdiagonal and the packed multiplier and swap flag (the
+// second superdiagonal follows from the flag), and 1 / pivot of the last row, so that
+// tri_resolve can repeat the solve.  The pivot choice is made with selects so lanes with
+// different pivots do not diverge.  Zero pivots become eps ||T||.
 __device__ void tri_solve(const double* d, const double* e, int r, double lam, double* z, double* u,
                           int nwp, double tiny) {
     // every value a step needs is loaded one step ahead, before the step's stores (the
@@ -798,7 +845,7 @@ __device__ void tri_solve(const double* d, const double* e, int r, double lam, d
         double* ui = u + 3 * i * nwp;
         ui[0] = ip;
         ui[nwp] = p1;
-        ui[2 * nwp] = p2;
+        ui[2 * nwp] = pack_step(m, sw);
         z[i * nwp] = py;
         cd = o1 - m * p1;
         cs1 = o2 - m * p2;
@@ -809,37 +856,38 @@ __device__ void tri_solve(const double* d, const double* e, int r, double lam, d
         yn = yn_n;
     }
     if (cd == 0.0) cd = tiny;
-    double x1 = yc * rcp_nr(cd), x2 = 0.0;
+    const double il = rcp_nr(cd);
+    u[3 * (r - 1) * nwp] = il;
+    const double x1 = yc * il;
     z[(r - 1) * nwp] = x1;
-    if (r < 2) return;
-    const double* un = u + 3 * (r - 2) * nwp;
-    double u0 = un[0], u1 = un[nwp], u2 = un[2 * nwp], zi = z[(r - 2) * nwp];
-#pragma unroll 2
-    for (int i = r - 2; i >= 0; --i) {
-        double u0n = 0.0, u1n = 0.0, u2n = 0.0, zin = 0.0;
-        if (i > 0) {
-            const double* up = u + 3 * (i - 1) * nwp;
-            u0n = up[0];
-            u1n = up[nwp];
-            u2n = up[2 * nwp];
-            zin = z[(i - 1) * nwp];
-        }
-        const double xi = (zi - u1 * x1 - u2 * x2) * u0;
-        z[i * nwp] = xi;
-        x2 = x1;
-        x1 = xi;
-        u0 = u0n;
-        u1 = u1n;
-        u2 = u2n;
-        zi = zin;
-    }
+    tri_back(e, r, z, u, nwp, x1);
 }
 
-// Eigenvectors of T for theta[0..nw) by two steps of inverse iteration, every vector in
-// its own thread; eigenvalues closer than 1e-3 ||T|| form a cluster whose vectors are
-// orthonormalised by modified Gram-Schmidt (one wavefront per cluster) after every
-// step, and whose equal shifts are separated by a few ulps.  Zt: r x nwp row-major
-// (vector q in column q); U3: 3 r x nwp.
+// The solve of the last tri_solve with the same factor on a new z: the stored row
+// swaps and multipliers, then the same back substitution.
+__device__ void tri_resolve(const double* e, int r, double* z, const double* u, int nwp) {
+    double yc = z[0];
+    double yn = r > 1 ? z[nwp] : 0.0;
+#pragma unroll 2
+    for (int i = 0; i + 1 < r; ++i) {
+        const double yn_n = (i + 2 < r) ? z[(i + 2) * nwp] : 0.0;
+        bool sw;
+        const double m = unpack_step(u[(3 * i + 2) * nwp], sw);
+        const double py = sw ? yn : yc, oy = sw ? yc : yn;
+        z[i * nwp] = py;
+        yc = oy - m * py;
+        yn = yn_n;
+    }
+    const double x1 = yc * u[3 * (r - 1) * nwp];
+    z[(r - 1) * nwp] = x1;
+    tri_back(e, r, z, u, nwp, x1);
+}
+
+// Eigenvectors of T for theta[0..nw) by two steps of inverse iteration (the second with
+// the first step's factorisation), every vector in its own thread; eigenvalues closer
+// than 1e-3 ||T|| form a cluster whose vectors are orthonormalised by modified
+// Gram-Schmidt (one wavefront per cluster) after every step, and whose equal shifts are
+// separated by a few ulps.  Zt: r x nwp row-major (vector q in column q); U3: 3 r x nwp.
 __device__ void inverse_iteration(const double* d, const double* e, int r, int nw, int nwp,
                                   const double* theta, double* sh, double* Zt, double* U3,
                                   int* cstart, int* csize, int* ncl, double tnorm) {
@@ -876,7 +924,8 @@ __device__ void inverse_iteration(const double* d, const double* e, int r, int n
                     z[i * nwp] = (double)((h >> 8) & 0xffff) * (1.0 / 65536.0) + 0.25;
                 }
             }
-            tri_solve(d, e, r, sh[q], z, U3 + q, nwp, tiny);
+            if (it == 0) tri_solve(d, e, r, sh[q], z, U3 + q, nwp, tiny);
+            else tri_resolve(e, r, z, U3 + q, nwp);
             double s2 = 0.0;
 #pragma unroll 4
             for (int i = 0; i < r; ++i) s2 = fma(z[i * nwp], z[i * nwp], s2);
