@@ -9,7 +9,9 @@
 //   diagonal  x_D  = G r_D          every supernode at once
 //   backward  x_D -= F^T x_B       level by level, root to leaves
 // (with y = L^{-1} r and x = L^{-T} y this is x_D = L11^{-T} (L11^{-1} r_D - L21^T x_B)).
-// Every product reads only right-hand-side rows that are final when its launch starts.
+// Every product reads only right-hand-side rows that are final when it starts: either
+// all tasks run in one launch ordered by dependency (k_sn_sweep, the default), or one
+// launch per level and phase (k_sn_product).
 // The permutation is folded into the row lists (dof ids), so every block is read and
 // written in the caller's ordering.  Right-hand-side blocks are row-major, so a gathered
 // or updated row's 16 values are one contiguous segment.  The 64 x 64 by 64 x 16 product
