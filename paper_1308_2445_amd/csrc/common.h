@@ -136,6 +136,47 @@ struct SellShape {
 };
 SellShape sell_shape(int64_t nslices, int w, int max_cw);
 
+// Accumulate ah[j] += H(row, :) x_j and as[j] += S(row, :) x_j over this lane's slots
+// e = e_first, e_first + stride, ... < e1 of a slice, for the CW columns whose bases
+// xp[j] gives.  U slots at a time: their indices and values, then every gather, then the
+// products, so one wait covers U slots.  The slot count of a slice is the same for all
+// its rows (padded slot-major), so the bound test is uniform; slots past the end read the
+// first slot and contribute zero.  Callers point unused columns at a valid column and
+// discard their sums, which keeps the loop free of branches.
+template <typename T, int CW>
+__device__ __forceinline__ void sell_accumulate(const int32_t* __restrict__ col, const T* __restrict__ hv,
+                                                const T* __restrict__ sv, int64_t e_first, int64_t e1,
+                                                int64_t stride, const T* const (&xp)[CW], T (&ah)[CW],
+                                                T (&as)[CW]) {
+    constexpr int U = 4;
+    for (int64_t e = e_first; e < e1; e += stride * U) {
+        int32_t c[U];
+        T h[U], s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t idx = e + (int64_t)u * stride;
+            const bool ok = idx < e1;
+            const int64_t ic = ok ? idx : e;
+            c[u] = col[ic];
+            const T hh = hv[ic], ss = sv[ic];
+            h[u] = ok ? hh : T(0);
+            s[u] = ok ? ss : T(0);
+        }
+        T x[U][CW];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < CW; ++j) x[u][j] = xp[j][c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                ah[j] = fma(h[u], x[u][j], ah[j]);
+                as[j] = fma(s[u], x[u][j], as[j]);
+            }
+    }
+}
+
 // Sum the per-lane accumulators of the WPS wavefronts that share a slice; the sums are
 // valid in the slice's first wavefront.  red: LDS of 256 * 2 * CW elements.  Every
 // thread of the work-group must call it.

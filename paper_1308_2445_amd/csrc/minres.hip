@@ -81,19 +81,10 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
     // a chunk whose columns have all converged has nothing to do (uniform over the
     // work-group; the next kernels read no partial of a converged column)
     if (!any) return;
-#pragma unroll 2
-    for (int64_t e = e0 + sw * kSlice + lane; e < e1; e += kSlice * WPS) {
-        const int64_t c = col[e];
-        const T h = hv[e], s = sv[e];
+    const T* xp[CW];
 #pragma unroll
-        for (int j = 0; j < CW; ++j) {
-            if (act[j]) {
-                const T x = xc[j][c];
-                ah[j] = fma(h, x, ah[j]);
-                as[j] = fma(s, x, as[j]);
-            }
-        }
-    }
+    for (int j = 0; j < CW; ++j) xp[j] = xc[j];
+    sell_accumulate<T, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
     slice_reduce<T, CW, WPS>(ah, as, sred);
     const bool lead = valid && sw == 0;
 #pragma unroll

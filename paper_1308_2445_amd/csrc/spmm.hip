@@ -41,19 +41,10 @@ __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off
 #pragma unroll
     for (int j = 0; j < CW; ++j) { ah[j] = 0.0; as[j] = 0.0; }
     const double* Xj = X + (int64_t)j0 * ldx;
-#pragma unroll 2
-    for (int64_t e = e0 + sw * kSlice + lane; e < e1; e += kSlice * WPS) {
-        const int64_t c = col[e];
-        const double h = hv[e], s = sv[e];
+    const double* xp[CW];
 #pragma unroll
-        for (int j = 0; j < CW; ++j) {
-            if (j < nc) {
-                const double x = Xj[c + j * ldx];
-                ah[j] = fma(h, x, ah[j]);
-                as[j] = fma(s, x, as[j]);
-            }
-        }
-    }
+    for (int j = 0; j < CW; ++j) xp[j] = Xj + (j < nc ? (int64_t)j * ldx : 0);
+    sell_accumulate<double, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
     slice_reduce<double, CW, WPS>(ah, as, red);
     if (valid && sw == 0 && row < n) {
 #pragma unroll
@@ -92,19 +83,10 @@ __global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ 
 #pragma unroll
     for (int j = 0; j < CW; ++j) { ah[j] = T(0); as[j] = T(0); }
     const T* Xj = X + (int64_t)j0 * ldx;
-#pragma unroll 2
-    for (int64_t e = e0 + sw * kSlice + lane; e < e1; e += kSlice * WPS) {
-        const int64_t c = col[e];
-        const T h = hv[e], s = sv[e];
+    const T* xp[CW];
 #pragma unroll
-        for (int j = 0; j < CW; ++j) {
-            if (j < nc) {
-                const T x = Xj[c + j * ldx];
-                ah[j] = fma(h, x, ah[j]);
-                as[j] = fma(s, x, as[j]);
-            }
-        }
-    }
+    for (int j = 0; j < CW; ++j) xp[j] = Xj + (j < nc ? (int64_t)j * ldx : 0);
+    sell_accumulate<T, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
     slice_reduce<T, CW, WPS>(ah, as, red);
     if (valid && sw == 0 && row < n) {
 #pragma unroll
