@@ -197,19 +197,39 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int k, const double* __
     double4_t accS = {0.0, 0.0, 0.0, 0.0};
     const int64_t rb = (int64_t)blockIdx.y * rows_per_chunk;
     const int64_t re = min(n, rb + rows_per_chunk);
-    for (int64_t r0 = rb; r0 < re; r0 += GR) {
+    // a stage's loads are all issued before any is used (out-of-range elements read a
+    // valid one and are zeroed), and the next stage is fetched into registers while the
+    // current one is multiplied
+    constexpr int NQ = (GT * GR) / 256;
+    double vz[NQ], vh[NQ], vs[NQ];
+    auto load_stage = [&](int64_t r0) {
 #pragma unroll
-        for (int q = 0; q < (GT * GR) / 256; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const int e = t + 256 * q;
             const int rr = e & (GR - 1), cc = e / GR;
             const int64_t row = r0 + rr;
-            const bool okr = row < re;
-            sZ[cc][rr] = (okr && i0 + cc < k) ? Z[row + (int64_t)(i0 + cc) * ld] : 0.0;
-            const bool okc = okr && j0 + cc < k;
-            sH[cc][rr] = okc ? ZH[row + (int64_t)(j0 + cc) * ld] : 0.0;
-            sS[cc][rr] = okc ? ZS[row + (int64_t)(j0 + cc) * ld] : 0.0;
+            const bool okr = row < re, okz = okr && i0 + cc < k, okc = okr && j0 + cc < k;
+            const int64_t rowc = okr ? row : rb;
+            const double z = Z[rowc + (int64_t)(i0 + cc < k ? i0 + cc : 0) * ld];
+            const int64_t hcol = (int64_t)(j0 + cc < k ? j0 + cc : 0) * ld;
+            const double h = ZH[rowc + hcol], sv = ZS[rowc + hcol];
+            vz[q] = okz ? z : 0.0;
+            vh[q] = okc ? h : 0.0;
+            vs[q] = okc ? sv : 0.0;
+        }
+    };
+    if (rb < re) load_stage(rb);
+    for (int64_t r0 = rb; r0 < re; r0 += GR) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = t + 256 * q;
+            const int rr = e & (GR - 1), cc = e / GR;
+            sZ[cc][rr] = vz[q];
+            sH[cc][rr] = vh[q];
+            sS[cc][rr] = vs[q];
         }
         __syncthreads();
+        if (r0 + GR < re) load_stage(r0 + GR);
 #pragma unroll 4
         for (int kk = 0; kk < GR; kk += 4) {
             const double a = sZ[ti * 16 + (lane & 15)][kk + (lane >> 4)];
@@ -233,37 +253,34 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int k, const double* __
     }
 }
 
-// sum the chunk partials of the upper triangle (i <= j) and mirror it
+// sum the chunk partials of the upper triangle (i <= j) and mirror it: eight lanes per
+// element, lane u summing chunks u, u + 8, ..., then a fixed-order 8-lane sum (the same
+// result on every run)
 __global__ __launch_bounds__(256) void k_gram_reduce(int k, int kp, int nchunk,
                                                      const double* __restrict__ part,
                                                      double* __restrict__ HR,
                                                      double* __restrict__ SR, int64_t ldr) {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)k * k) return;
-    const int i = (int)(idx % k), j = (int)(idx / k);
-    if (i > j) return;
-    // eight independent partial sums keep several loads in flight
-    double h8[8] = {0, 0, 0, 0, 0, 0, 0, 0}, s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t idx = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
+    const int u = threadIdx.x & 7;
+    const bool in = idx < (int64_t)k * k;
+    const int i = in ? (int)(idx % k) : 0, j = in ? (int)(idx / k) : 0;
+    const bool act = in && i <= j;
     const int64_t stride = (int64_t)kp * kp, off = i + (int64_t)j * kp;
-    int c = 0;
-    for (; c + 8 <= nchunk; c += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            h8[u] += part[((int64_t)(c + u) * 2 + 0) * stride + off];
-            s8[u] += part[((int64_t)(c + u) * 2 + 1) * stride + off];
-        }
-    }
-    for (; c < nchunk; ++c) {
-        h8[0] += part[((int64_t)c * 2 + 0) * stride + off];
-        s8[0] += part[((int64_t)c * 2 + 1) * stride + off];
-    }
     double h = 0.0, s = 0.0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) { h += h8[u]; s += s8[u]; }
-    HR[i + (int64_t)j * ldr] = h;
-    HR[j + (int64_t)i * ldr] = h;
-    SR[i + (int64_t)j * ldr] = s;
-    SR[j + (int64_t)i * ldr] = s;
+    if (act)
+        for (int c = u; c < nchunk; c += 8) {
+            h += part[((int64_t)c * 2 + 0) * stride + off];
+            s += part[((int64_t)c * 2 + 1) * stride + off];
+        }
+    // the 8 lanes of an element share a DPP half-row; every lane takes part
+    h = row8_allsum(h);
+    s = row8_allsum(s);
+    if (act && u == 0) {
+        HR[i + (int64_t)j * ldr] = h;
+        HR[j + (int64_t)i * ldr] = h;
+        SR[i + (int64_t)j * ldr] = s;
+        SR[j + (int64_t)i * ldr] = s;
+    }
 }
 
 // ------------------------------------------------------------------ block update on MFMA
@@ -456,7 +473,7 @@ void launch_gram(int64_t n, int k, const double* Z, const double* ZH, const doub
                        ws, kp);
     LABPSD_HIP(hipGetLastError());
     const int64_t tot = (int64_t)k * k;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, k, kp,
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((8 * tot + 255) / 256)), dim3(256), 0, s, k, kp,
                        nchunk, ws, HR, SR, ldr);
     LABPSD_HIP(hipGetLastError());
 }
