@@ -362,7 +362,8 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     tm.on = prm.timing != 0;
     tm.s = s;
 
-    // h_rb: [Res | norms | Ritz values]; h_ib: [MINRES counts | Rayleigh-Ritz report];
+    // h_rb: [Res | norms | Ritz values]; h_ib: [unused m | Rayleigh-Ritz report]; the
+    // residual and Rayleigh-Ritz kernels write them directly (device-mapped pinned memory);
     // h_sel: [shifts | stopping norms | U | localised positions] as laid out on the device
     Pinned<double> h_rb, h_sel;
     Pinned<int32_t> h_ib, h_int;
@@ -370,8 +371,15 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     h_rb.alloc(2 * (size_t)m + b);
     h_ib.alloc((size_t)m + 4);
     h_sel.alloc(3 * (size_t)m);
-    h_int.alloc(8);
+    h_int.alloc(2 * (size_t)m);   // MINRES done flags: two slots of up to m columns
     int32_t* h_cols = (int32_t*)(h_sel.p + 2 * (size_t)m);
+    double* d_rb = nullptr;
+    int32_t* d_ib = nullptr;
+    LABPSD_HIP(hipHostGetDevicePointer((void**)&d_rb, h_rb.p, 0));
+    LABPSD_HIP(hipHostGetDevicePointer((void**)&d_ib, h_ib.p, 0));
+    // MINRES iterations of the whole solve, summed on the device (a spare scalar word)
+    auto* its_total = (unsigned long long*)(B.scal + minres_scal_doubles(m));
+    LABPSD_HIP(hipMemsetAsync(its_total, 0, sizeof(unsigned long long), s));
     int cur = 0;
     auto Z = [&](int which) { return B.Zb[cur][which]; };
 
@@ -393,7 +401,8 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         st.n_launch[S_GRAM] += 1;
         st.n_cols[S_GRAM] += k;
         tm.begin(S_RR);
-        launch_rayleigh_ritz(k, b, B.HR, B.SR, kmax, B.gamma, B.W, kmax, B.info, B.rr_ws, s);
+        launch_rayleigh_ritz(k, b, B.HR, B.SR, kmax, B.gamma, B.W, kmax, B.info, B.rr_ws, s, d_rb + 2 * m,
+                             d_ib + m);
         tm.end();
         st.n_launch[S_RR] += 1;
         st.n_cols[S_RR] += k;
@@ -408,23 +417,12 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         // the Ritz values and the rank report reach the host with the next residual
         // read-back (rr_check), so this step adds no synchronisation
     };
-    // the two read-backs every synchronisation of the loop waits for
-    auto readback = [&]() {
-        LABPSD_HIP(hipMemcpyAsync(h_rb.p, B.res, (2 * (size_t)m + b) * sizeof(double), hipMemcpyDeviceToHost, s));
-        LABPSD_HIP(hipMemcpyAsync(h_ib.p, B.its, ((size_t)m + 2) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    };
     // after a synchronisation: the last Rayleigh-Ritz step's report and Ritz values
     std::vector<double> E;
     auto rr_check = [&](const char* what) {
         st.rank_dropped += h_ib.p[m];
         if (h_ib.p[m + 1] != 0) throw Error{LABPSD_ERANK, what};
         E.assign(h_rb.p + 2 * m, h_rb.p + 2 * m + b);
-    };
-    // MINRES iteration counts of the last local refinement
-    int its_pending = 0;
-    auto its_collect = [&]() {
-        for (int j = 0; j < its_pending; ++j) st.minres_iters += h_ib.p[j];
-        its_pending = 0;
     };
     rayleigh_ritz_update(b);
     std::vector<double> Eprev;
@@ -451,14 +449,12 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     auto residuals = [&]() {
         tm.begin(S_RESID);
         launch_residual(n, m, Z(1), Z(2), ldz, B.gamma, prm.sigma0, B.R, n, B.red, nblk, s);
-        launch_residual_finish(m, B.red, nblk, B.res, B.rnorm, s);
+        launch_residual_finish(m, B.red, nblk, B.res, B.rnorm, s, d_rb);
         tm.end();
         st.n_launch[S_RESID] += 1;
         st.n_cols[S_RESID] += m;
-        readback();
         spin_sync(s, ev_sync.e);
         for (int i = 0; i < m; ++i) { res[i] = h_rb.p[i]; rn[i] = h_rb.p[m + i]; }
-        its_collect();
     };
     auto maxres = [&]() {
         double mx = 0.0;
@@ -539,12 +535,11 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             tm.begin(S_LOCAL);
             int64_t nl = 0;
             run_minres<T>(P.sell, Wt.W1, n, Wt.RT, n, q, B.loc, B.shifts, B.stopn, lp.eta,
-                          lp.max_inner, B.its, Wt.mres, B.scal, h_int.p + 4, s, &nl, ev_flag0.e,
-                          ev_flag1.e);
+                          lp.max_inner, B.its, Wt.mres, B.scal, h_int.p, s, &nl, ev_flag0.e,
+                          ev_flag1.e, its_total);
             tm.end();
             st.n_launch[S_LOCAL] += nl;
             st.n_cols[S_LOCAL] += q;
-            its_pending = q;   // read back with the next residual
             st.localized_cols += q;
         }
         // P into the search-space block, FP64
@@ -567,10 +562,11 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         fresh = false;
         ++since_refresh;
     }
-    readback();
+    unsigned long long its_sum = 0;
+    LABPSD_HIP(hipMemcpyAsync(&its_sum, its_total, sizeof(its_sum), hipMemcpyDeviceToHost, s));
     LABPSD_HIP(hipStreamSynchronize(s));
+    st.minres_iters += (int64_t)its_sum;
     check_precond_sweep(*P.factor, s);
-    its_collect();
     // a converged exit has checked the last Rayleigh-Ritz step in its final iteration
     if (!converged)
         rr_check(outer == 0 ? "start block is rank deficient"
@@ -666,7 +662,7 @@ static void local_refine_impl(Problem* p, DBuf<T>& arena, const double* R, int64
     launch_gather_cast<double, T>(n, q, R, ldr, cols, 1.0, RT, n, s);
     launch_colnorms<double>(n, q, R, ldr, cols, part, rn, s);
     Pinned<int32_t> flag;
-    flag.alloc(2);
+    flag.alloc(2 * (size_t)q);
     run_minres<T>(p->sell, PT, n, RT, n, q, iota, shift, rn, eta, max_inner, its, mws, scal, flag.p, s,
                   nullptr);
     launch_scatter_cast<T, double>(n, q, PT, n, cols, 1.0, Pm, ldp, s);

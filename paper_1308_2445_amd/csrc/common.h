@@ -352,8 +352,9 @@ void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const doub
 void launch_residual(int64_t n, int m, const double* PsiH, const double* PsiS, int64_t ld,
                      const double* E, double sigma0, double* R, int64_t ldr, double* partial,
                      int nblk, hipStream_t s);
+// host: optional device-mapped pinned memory that also receives [Res | norms] (2 m)
 void launch_residual_finish(int m, const double* partial, int nblk, double* res, double* rnorm,
-                            hipStream_t s);
+                            hipStream_t s, double* host = nullptr);
 int residual_blocks(int64_t n);
 
 // Gram: HR = Z^T ZH, SR = Z^T ZS (symmetric parts); partial workspace sized by gram_ws
@@ -369,9 +370,11 @@ void launch_block_update(int64_t n, int k, int b, const double* Z, const double*
 // Rayleigh-Ritz (single work-group, k <= kRRMax)
 constexpr int kRRMax = 4096;
 size_t rr_ws_bytes(int k);
+// gamma_host, info_host: optional device-mapped pinned memory that also receives the
+// nwant Ritz values and the two report words
 void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, int64_t ldr,
                           double* gamma, double* W, int64_t ldw, int32_t* info, void* ws,
-                          hipStream_t s);
+                          hipStream_t s, double* gamma_host = nullptr, int32_t* info_host = nullptr);
 
 // Gathers / casts
 // row-major blocks (the ncols values of a row contiguous) for the global preconditioner:
@@ -409,12 +412,14 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
 // minres_ws_elems(n, q) elements of T, scal_ws minres_scal_doubles(q) doubles.
 size_t minres_ws_elems(int64_t n, int q);
 size_t minres_scal_doubles(int q);
+// flag_host_pinned: pinned host memory of 2 q ints (the done flags of the checked
+// iterations); ev0, ev1: two events for pipelined checks (else a synchronisation per check)
 template <typename T>
 void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q,
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
                 int32_t* flag_host_pinned, hipStream_t s, int64_t* launches, hipEvent_t ev0 = nullptr,
-                hipEvent_t ev1 = nullptr);
+                hipEvent_t ev1 = nullptr, unsigned long long* its_total = nullptr);
 
 // Wait until everything enqueued on s so far has finished.  With an event the host polls
 // it (spins) instead of blocking, which shortens the wake-up after the small read-backs

@@ -59,7 +59,8 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, const double* __res
 }
 
 __global__ void k_residual_finish(int m, const double* __restrict__ partial, int nblk,
-                                  double* __restrict__ res, double* __restrict__ rnorm) {
+                                  double* __restrict__ res, double* __restrict__ rnorm,
+                                  double* __restrict__ host) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     double a = 0.0, b = 0.0;
@@ -67,8 +68,13 @@ __global__ void k_residual_finish(int m, const double* __restrict__ partial, int
         a += partial[((int64_t)j * nblk + k) * 2 + 0];
         b += partial[((int64_t)j * nblk + k) * 2 + 1];
     }
-    rnorm[j] = sqrt(a);
-    res[j] = b > 0.0 ? sqrt(a / b) : (a > 0.0 ? INFINITY : 0.0);
+    const double rn = sqrt(a), r = b > 0.0 ? sqrt(a / b) : (a > 0.0 ? INFINITY : 0.0);
+    rnorm[j] = rn;
+    res[j] = r;
+    if (host) {   // pinned host memory, device-mapped: [Res | norms]
+        host[j] = r;
+        host[m + j] = rn;
+    }
 }
 
 // ------------------------------------------------------------------ gather / cast
@@ -339,10 +345,10 @@ void launch_residual(int64_t n, int m, const double* PsiH, const double* PsiS, i
 }
 
 void launch_residual_finish(int m, const double* partial, int nblk, double* res, double* rnorm,
-                            hipStream_t s) {
+                            hipStream_t s, double* host) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_residual_finish, dim3((m + 255) / 256), dim3(256), 0, s, m, partial, nblk,
-                       res, rnorm);
+                       res, rnorm, host);
     LABPSD_HIP(hipGetLastError());
 }
 

@@ -16,7 +16,8 @@
 // Every block recomputes the column's scalars from the partial sums (identical values);
 // block 0 of the column stores the new scalar state into the other half of a double
 // buffer, so no block reads a state that another block of the same kernel writes.
-// The host checks the count of active columns every few iterations.  T = double (FP64)
+// The host checks the columns' done flags every few iterations (the update kernel writes
+// them straight into pinned host memory on those iterations).  T = double (FP64)
 // or float (mixed: FP32 vectors and products; the per-slice sums are FP64 in both).
 #include "common.h"
 
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
     const int32_t* __restrict__ xcols, const T* __restrict__ aux, int64_t ldaux,
     const int32_t* __restrict__ auxcols, const double* __restrict__ shift,
     const MinresScal* __restrict__ sc, T* __restrict__ out, double* __restrict__ partial,
-    int64_t npart, int q, int32_t* __restrict__ active) {
+    int64_t npart, int q) {
     constexpr int SPB = 4 / WPS;   // slices per work-group
     constexpr int NS = MODE == 0 ? 1 : 3;   // partial sums per column
     __shared__ T sred[WPS > 1 ? 256 * 2 * CW : 1];
@@ -75,9 +76,6 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
         ah[j] = T(0);
         as[j] = T(0);
     }
-    // the active-column count of this iteration starts at zero (the previous
-    // iteration's count has been read by now: the read is ordered before this kernel)
-    if (MODE == 1 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *active = 0;
     // a chunk whose columns have all converged has nothing to do (uniform over the
     // work-group; the next kernels read no partial of a converged column)
     if (!any) return;
@@ -214,12 +212,15 @@ __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max
                                                        const double* __restrict__ part, int64_t npa,
                                                        const T* __restrict__ V, T* __restrict__ Wb,
                                                        const T* __restrict__ D1, T* __restrict__ D2,
-                                                       T* __restrict__ Xs, int32_t* __restrict__ active) {
+                                                       T* __restrict__ Xs, int32_t* __restrict__ done_out) {
     const int j = blockIdx.y;
     const MinresScal s = sc_in[j];
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (s.done) {
-        if (lead) sc_out[j] = s;
+        if (lead) {
+            sc_out[j] = s;
+            if (done_out) done_out[j] = 1;
+        }
         return;
     }
     double sums[3];   // v.u, u.u, v.v
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max
         t.beta = bnext;
         t.done = (fabs(phibar) <= s.stop || bnext == 0.0 || k >= max_inner) ? 1 : 0;
         sc_out[j] = t;
-        if (!t.done) atomicAdd(active, 1);
+        if (done_out) done_out[j] = t.done;
     }
 }
 
@@ -276,27 +277,31 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_minres_final(int64_t n, int q, const int32_t* __restrict__ cols,
                                                       const MinresScal* __restrict__ sc,
                                                       const T* __restrict__ Xs, T* __restrict__ P,
-                                                      int64_t ldp, int32_t* __restrict__ its) {
+                                                      int64_t ldp, int32_t* __restrict__ its,
+                                                      unsigned long long* __restrict__ its_total) {
     const int j = blockIdx.y;
     T* p = P + (int64_t)cols[j] * ldp;
     const T* x = Xs + (int64_t)j * n;
     if (sc[j].its > 0)
         for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
             p[i] += x[i];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && its) its[j] = sc[j].its;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (its) its[j] = sc[j].its;
+        if (its_total) atomicAdd(its_total, (unsigned long long)sc[j].its);
+    }
 }
 
 template <typename T, int MODE, int CW, int WPS>
 int64_t launch_spmv_s(const Sell& A, const T* hv, const T* sv, const T* X, int64_t ldx,
                       const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
                       const double* shift, const MinresScal* sc, T* out, double* partial, int q,
-                      int32_t* active, hipStream_t s) {
+                      hipStream_t s) {
     constexpr int SPB = 4 / WPS;
     const int64_t nblk = (A.nslices + SPB - 1) / SPB;
     const dim3 g((unsigned)nblk, (unsigned)((q + CW - 1) / CW));
     hipLaunchKernelGGL((k_minres_spmv<T, MODE, CW, WPS>), g, dim3(256), 0, s, A.slice_off.p, A.col.p, hv,
                        sv, A.n, A.nslices, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, nblk,
-                       q, active);
+                       q);
     return nblk;
 }
 
@@ -306,10 +311,10 @@ template <typename T, int MODE>
 int64_t launch_spmv(const Sell& A, SellShape sh, const T* hv, const T* sv, const T* X, int64_t ldx,
                     const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
                     const double* shift, const MinresScal* sc, T* out, double* partial, int q,
-                    int32_t* active, hipStream_t s) {
+                    hipStream_t s) {
 #define LABPSD_SPMV(CW, WPS) \
     launch_spmv_s<T, MODE, CW, WPS>(A, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q, \
-                                    active, s)
+                                    s)
     if (sh.wps == 4) {
         if (sh.cw >= 4) return LABPSD_SPMV(4, 4);
         if (sh.cw == 2) return LABPSD_SPMV(2, 4);
@@ -343,7 +348,7 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
                 int32_t* flag_host_pinned, hipStream_t s, int64_t* launches, hipEvent_t ev0,
-                hipEvent_t ev1) {
+                hipEvent_t ev1, unsigned long long* its_total) {
     if (q <= 0 || A.n == 0) return;
     const int64_t n = A.n;
     T* V = ws;
@@ -357,12 +362,20 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     // spmv partials: 3 sets of at most nslices per column, FP64 (6 n q T elements precede,
     // an even count, so the address is 8-byte aligned)
     double* pa = (double*)(Xs + n * q);
-    // scalar state double buffer, one spare double per column, and the active-column counter
+    // scalar state double buffer (the rest of the scalar workspace is spare)
     constexpr size_t kScalDoubles = sizeof(MinresScal) / 8;
     MinresScal* sa = (MinresScal*)scal_ws;
     MinresScal* sb = (MinresScal*)(scal_ws + kScalDoubles * q);
-    double* alpha = scal_ws + 2 * kScalDoubles * q;
-    int32_t* counter = (int32_t*)(alpha + q);
+    // the done flags of a check iteration are written by the device into pinned host
+    // memory: two slots of q flags (flag_host_pinned holds 2 q ints)
+    int32_t* flag_dev = nullptr;
+    LABPSD_HIP(hipHostGetDevicePointer((void**)&flag_dev, flag_host_pinned, 0));
+    auto all_done = [&](int sl) {
+        const volatile int32_t* f = flag_host_pinned + (size_t)sl * q;
+        for (int j = 0; j < q; ++j)
+            if (f[j] == 0) return false;
+        return true;
+    };
     const T* hv;
     const T* sv;
     if constexpr (sizeof(T) == 8) { hv = A.hv.p; sv = A.sv.p; }
@@ -375,7 +388,7 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     // b = -((H - eps S) p + r); beta1 = ||b||
     // spmv partials: one per work-group and column (at most nslices)
     const int64_t npa = launch_spmv<T, 0>(A, sh, hv, sv, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev, sa, V,
-                                          pa, q, counter, s);
+                                          pa, q, s);
     hipLaunchKernelGGL(k_minres_init_finish, gcol, dim3(256), 0, s, (const double*)pa, npa, q, rnorm_dev,
                        eta, max_inner, sa);
     hipLaunchKernelGGL((k_minres_init_vectors<T>), gel, dim3(256), 0, s, n, q, (const MinresScal*)sa, V,
@@ -394,10 +407,12 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     int slot = 0;
     bool pending = false;
     for (int it = 0; it < max_inner; ++it) {
-        launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, counter, s);
+        // on a check iteration the done flags go to host slot `slot`
+        const bool check = it + 1 < max_inner && (it + 1) % kCheckEvery == 0;
+        launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s);
         hipLaunchKernelGGL((k_minres_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
                            (const MinresScal*)cur, nxt, (const double*)pa, npa, (const T*)V, Wb,
-                           (const T*)D1, D2, Xs, counter);
+                           (const T*)D1, D2, Xs, check ? flag_dev + (size_t)slot * q : nullptr);
         LABPSD_HIP(hipGetLastError());
         nl += 2;
         // rotate: v_prev <- v, v <- w (now scaled), w <- old v_prev; d1 <- new d, d2 <- old d1
@@ -405,24 +420,23 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
         T* t1 = D1; D1 = D2; D2 = t1;
         MinresScal* t2 = cur; cur = nxt; nxt = t2;
         if (it + 1 == max_inner) break;
-        if ((it + 1) % kCheckEvery == 0) {
-            LABPSD_HIP(hipMemcpyAsync(flag_host_pinned + slot, counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (check) {
             if (!piped) {
                 LABPSD_HIP(hipStreamSynchronize(s));
-                if (flag_host_pinned[slot] == 0) break;
+                if (all_done(slot)) break;
                 continue;
             }
             LABPSD_HIP(hipEventRecord(evs[slot], s));
             if (pending) {
                 spin_event(evs[slot ^ 1]);
-                if (flag_host_pinned[slot ^ 1] == 0) break;
+                if (all_done(slot ^ 1)) break;
             }
             pending = true;
             slot ^= 1;
         }
     }
     hipLaunchKernelGGL((k_minres_final<T>), gel, dim3(256), 0, s, n, q, cols_dev, (const MinresScal*)cur,
-                       Xs, P, ldp, its_dev);
+                       Xs, P, ldp, its_dev, its_total);
     LABPSD_HIP(hipGetLastError());
     nl += 1;
     if (launches) *launches += nl;
@@ -430,9 +444,11 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
 
 template void run_minres<double>(const Sell&, double*, int64_t, const double*, int64_t, int,
                                  const int32_t*, const double*, const double*, double, int, int32_t*,
-                                 double*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t);
+                                 double*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t,
+                                 unsigned long long*);
 template void run_minres<float>(const Sell&, float*, int64_t, const float*, int64_t, int,
                                 const int32_t*, const double*, const double*, double, int, int32_t*,
-                                float*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t);
+                                float*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t,
+                                unsigned long long*);
 
 }  // namespace labpsd

@@ -1023,7 +1023,8 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
                                                               int64_t ldr, double* __restrict__ gamma,
                                                               double* __restrict__ W, int64_t ldw,
                                                               int32_t* __restrict__ info,
-                                                              double* gws) {
+                                                              double* gws, double* gamma_host,
+                                                              int32_t* info_host) {
     extern __shared__ double lds[];
     __shared__ double red[kRRThreads / 64];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -1098,8 +1099,15 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         // W = D M Z (M row-major in T, Z row-major in Zt with ld nwp)
         gemm_mfma(T, k, true, Zt, nwp, true, k, nwant, k,
                   [&](int i, int q, double v) { W[i + (int64_t)q * ldw] = D[i] * v; });
-        for (int q = tid; q < nwant; q += nt) gamma[q] = theta[q];
-        if (tid == 0) { info[0] = 0; info[1] = 0; }
+        for (int q = tid; q < nwant; q += nt) {
+            gamma[q] = theta[q];
+            if (gamma_host) gamma_host[q] = theta[q];
+        }
+        if (tid == 0) {
+            info[0] = 0;
+            info[1] = 0;
+            if (info_host) { info_host[0] = 0; info_host[1] = 0; }
+        }
         return;
     }
     // ------------------------------------------------------------ rank-revealing route
@@ -1142,7 +1150,11 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     small_gemm(fT, true, U, false, B, r, r, k, k, k, r);
     __syncthreads();
     if (r < nwant) {
-        if (tid == 0) { info[0] = k - r; info[1] = (int)LABPSD_ERANK; }
+        if (tid == 0) {
+            info[0] = k - r;
+            info[1] = (int)LABPSD_ERANK;
+            if (info_host) { info_host[0] = k - r; info_host[1] = (int)LABPSD_ERANK; }
+        }
         return;
     }
     // symmetrise C (r x r, ld r), V = I
@@ -1170,7 +1182,10 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         if (rank < nwant) sel[rank] = i;
     }
     __syncthreads();
-    for (int q = tid; q < nwant; q += nt) gamma[q] = theta[sel[q]];
+    for (int q = tid; q < nwant; q += nt) {
+        gamma[q] = theta[sel[q]];
+        if (gamma_host) gamma_host[q] = theta[sel[q]];
+    }
     // W = D T V(:, sel)
     for (int e = tid; e < k * nwant; e += nt) {
         const int i = (int)(e % k), q = (int)(e / k);
@@ -1179,7 +1194,11 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
         for (int p = 0; p < r; ++p) acc = fma(fT[i + p * k], V[p + src * r], acc);
         W[i + (int64_t)q * ldw] = D[i] * acc;
     }
-    if (tid == 0) { info[0] = k - r; info[1] = 0; }
+    if (tid == 0) {
+        info[0] = k - r;
+        info[1] = 0;
+        if (info_host) { info_host[0] = k - r; info_host[1] = 0; }
+    }
 }
 
 }  // namespace
@@ -1192,7 +1211,7 @@ size_t rr_ws_bytes(int k) {
 
 void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, int64_t ldr,
                           double* gamma, double* W, int64_t ldw, int32_t* info, void* ws,
-                          hipStream_t s) {
+                          hipStream_t s, double* gamma_host, int32_t* info_host) {
     if (k <= 0 || nwant <= 0) return;
     LABPSD_REQUIRE(k <= kRRMax, "Rayleigh-Ritz order exceeds the supported maximum");
     LABPSD_REQUIRE(nwant <= k, "more Ritz pairs requested than the search space holds");
@@ -1220,8 +1239,9 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
             default: return (const void*)k_rayleigh_ritz<L_, 0>;
         }
     };
-    void* args[] = {(void*)&k, (void*)&nwant, (void*)&HR, (void*)&SR, (void*)&ldr, (void*)&gamma,
-                    (void*)&W, (void*)&ldw, (void*)&info, (void*)&ws};
+    void* args[] = {(void*)&k,    (void*)&nwant, (void*)&HR, (void*)&SR, (void*)&ldr,
+                    (void*)&gamma, (void*)&W,    (void*)&ldw, (void*)&info, (void*)&ws,
+                    (void*)&gamma_host, (void*)&info_host};
     if (all_lds) {
         const void* f = pick(std::true_type{});
         if (bytes > 64 * 1024)
