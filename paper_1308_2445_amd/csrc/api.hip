@@ -62,32 +62,8 @@ labpsd_status guarded(F&& f) {
 }
 
 // pinned host staging buffer
-template <typename T>
-struct Pinned {
-    T* p = nullptr;
-    size_t n = 0;
-    ~Pinned() {
-        if (p) (void)hipHostFree(p);
-    }
-    void alloc(size_t count) {
-        if (count <= n && p) return;
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-        n = 0;
-        LABPSD_HIP(hipHostMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
-        n = count;
-    }
-};
 
 // Event timing of the steps (stats.t_step_s)
-// An event that lives as long as the scope that created it (no timing).
-struct ScopedEvent {
-    hipEvent_t e = nullptr;
-    ScopedEvent() { LABPSD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
-    ~ScopedEvent() {
-        if (e) (void)hipEventDestroy(e);
-    }
-};
 
 struct StepTimer {
     bool on = false;
@@ -365,13 +341,16 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     // h_rb: [Res | norms | Ritz values]; h_ib: [unused m | Rayleigh-Ritz report]; the
     // residual and Rayleigh-Ritz kernels write them directly (device-mapped pinned memory);
     // h_sel: [shifts | stopping norms | U | localised positions] as laid out on the device
-    Pinned<double> h_rb, h_sel;
-    Pinned<int32_t> h_ib, h_int;
-    ScopedEvent ev_sync, ev_flag0, ev_flag1;
+    HBuf<double>& h_rb = P.h_rb;
+    HBuf<double>& h_sel = P.h_sel;
+    HBuf<int32_t>& h_ib = P.h_ib;
+    HBuf<int32_t>& h_int = P.h_flags;
     h_rb.alloc(2 * (size_t)m + b);
     h_ib.alloc((size_t)m + 4);
     h_sel.alloc(3 * (size_t)m);
     h_int.alloc(2 * (size_t)m);   // MINRES done flags: two slots of up to m columns
+    P.events.ensure();
+    hipEvent_t ev_sync = P.events.e[0], ev_flag0 = P.events.e[1], ev_flag1 = P.events.e[2];
     int32_t* h_cols = (int32_t*)(h_sel.p + 2 * (size_t)m);
     double* d_rb = nullptr;
     int32_t* d_ib = nullptr;
@@ -453,7 +432,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         tm.end();
         st.n_launch[S_RESID] += 1;
         st.n_cols[S_RESID] += m;
-        spin_sync(s, ev_sync.e);
+        spin_sync(s, ev_sync);
         for (int i = 0; i < m; ++i) { res[i] = h_rb.p[i]; rn[i] = h_rb.p[m + i]; }
     };
     auto maxres = [&]() {
@@ -535,8 +514,8 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             tm.begin(S_LOCAL);
             int64_t nl = 0;
             run_minres<T>(P.sell, Wt.W1, n, Wt.RT, n, q, B.loc, B.shifts, B.stopn, lp.eta,
-                          lp.max_inner, B.its, Wt.mres, B.scal, h_int.p, s, &nl, ev_flag0.e,
-                          ev_flag1.e, its_total);
+                          lp.max_inner, B.its, Wt.mres, B.scal, h_int.p, s, &nl, ev_flag0,
+                          ev_flag1, its_total);
             tm.end();
             st.n_launch[S_LOCAL] += nl;
             st.n_cols[S_LOCAL] += q;
@@ -661,7 +640,7 @@ static void local_refine_impl(Problem* p, DBuf<T>& arena, const double* R, int64
     launch_gather_cast<double, T>(n, q, Pm, ldp, cols, 1.0, PT, n, s);
     launch_gather_cast<double, T>(n, q, R, ldr, cols, 1.0, RT, n, s);
     launch_colnorms<double>(n, q, R, ldr, cols, part, rn, s);
-    Pinned<int32_t> flag;
+    HBuf<int32_t> flag;
     flag.alloc(2 * (size_t)q);
     run_minres<T>(p->sell, PT, n, RT, n, q, iota, shift, rn, eta, max_inner, its, mws, scal, flag.p, s,
                   nullptr);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include <cstdint>
 #include <functional>
@@ -103,6 +104,43 @@ __device__ __forceinline__ double wave_allsum(double v) {
     v = row16_allsum(v);
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
+
+// Pinned (page-locked, device-mapped) host memory that only grows.
+template <typename T>
+struct HBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    HBuf() = default;
+    HBuf(const HBuf&) = delete;
+    HBuf& operator=(const HBuf&) = delete;
+    ~HBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void alloc(size_t count) {
+        if (count <= n && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        LABPSD_HIP(hipHostMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
+        n = count;
+    }
+};
+
+// A few events without timing, created on first use.
+struct EventSet {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    EventSet() = default;
+    EventSet(const EventSet&) = delete;
+    EventSet& operator=(const EventSet&) = delete;
+    ~EventSet() {
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    void ensure() {
+        for (auto& x : e)
+            if (!x) LABPSD_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    }
+};
 
 // ------------------------------------------------------------------ sliced ELL
 
@@ -310,6 +348,11 @@ struct Problem {
     DBuf<float> ws32;
     DBuf<double> red;            // FP64 preconditioner arena
     DBuf<int32_t> iws;
+    // host side of the solve loop (kept between solves): read-back blocks, the selection
+    // upload block, the MINRES done flags, and the loop's events
+    HBuf<double> h_rb, h_sel;
+    HBuf<int32_t> h_ib, h_flags;
+    EventSet events;
     // the last solve's full block (n x b, all Ritz vectors incl. guards) and Ritz
     // values, kept resident for warm starts of the next GHEP of the sequence
     DBuf<double> resident_X;

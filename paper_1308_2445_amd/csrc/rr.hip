@@ -162,11 +162,6 @@ __device__ __forceinline__ double rcp_nr(double x) {
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
 }
-// one Newton step: within about 10 ulp (enough for the Sturm counts)
-__device__ __forceinline__ double rcp_nr1(double x) {
-    const double r = __builtin_amdgcn_rcp(x);
-    return fma(r, fma(-x, r, 1.0), r);
-}
 __device__ __forceinline__ double rsq_nr(double x) {
     double r = __builtin_amdgcn_rsq(x);
     r = r * fma(-0.5 * x * r, r, 1.5);
@@ -681,16 +676,35 @@ __device__ __forceinline__ void tridiag_regs(const double* C, double* T, int r, 
 constexpr double kEps = 1.1102230246251565e-16;      // 2^-53
 constexpr double kSafmin = 2.2250738585072014e-308;
 
-// number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots)
+// number of eigenvalues of T below x: sign changes of the Sturm sequence p_0 = 1,
+// p_1 = d_0 - x, p_i = (d_{i-1} - x) p_{i-1} - e_{i-2}^2 p_{i-2} (the leading principal
+// minors of T - x I; p_i / p_{i-1} is the i-th pivot of its LDL^T, so a sign change is a
+// negative pivot).  One fused multiply-add per step is on the dependent chain, with no
+// division; every fourth step p_{i-1}, p_{i-2} are rescaled by the same power of two to
+// keep them in range.  An exact zero is replaced by a value of the opposite sign to its
+// predecessor, tiny relative to it (the zero-pivot convention: it counts as negative).
 __device__ int sturm_count(const double* d, const double* e2, int r, double x, double pivmin) {
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int cnt = q < 0.0 ? 1 : 0;
+    (void)pivmin;
+    constexpr double kZeroRel = 0x1p-80;
+    double p2 = 1.0, p1 = d[0] - x;
+    if (p1 == 0.0) p1 = -kZeroRel;
+    int cnt = p1 < 0.0 ? 1 : 0;
 #pragma unroll 4
     for (int i = 1; i < r; ++i) {
-        q = (d[i] - x) - e2[i - 1] * rcp_nr1(q);
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0 ? 1 : 0;
+        double p = fma(d[i] - x, p1, -(e2[i - 1] * p2));
+        if (p == 0.0) p = -kZeroRel * p1;
+        cnt += (__builtin_bit_cast(int64_t, p) ^ __builtin_bit_cast(int64_t, p1)) < 0 ? 1 : 0;
+        p2 = p1;
+        p1 = p;
+        if ((i & 3) == 0) {
+            // the larger of the two is brought to [0.5, 1)
+            int ea, eb;
+            (void)frexp(p1, &ea);
+            (void)frexp(p2, &eb);
+            const int ex = ea > eb ? ea : eb;
+            p1 = ldexp(p1, -ex);
+            p2 = ldexp(p2, -ex);
+        }
     }
     return cnt;
 }
