@@ -172,12 +172,12 @@ struct SellShape {
     int cw;
     int wps;
 };
-SellShape sell_shape(int64_t nslices, int w, int max_cw);
+SellShape sell_shape(int64_t nslices, int w, int max_cw, int64_t want_waves);
 
 // Accumulate ah[j] += H(row, :) x_j and as[j] += S(row, :) x_j over this lane's slots
 // e = e_first, e_first + stride, ... < e1 of a slice, for the CW columns whose bases
-// xp[j] gives.  U slots at a time: their indices and values, then every gather, then the
-// products, so one wait covers U slots.  The slot count of a slice is the same for all
+// xp[j] gives.  U slots at a time (4, or 2 for 8 columns): their indices and values, then
+// every gather, then the products, so one wait covers U slots.  The slot count of a slice is the same for all
 // its rows (padded slot-major), so the bound test is uniform; slots past the end read the
 // first slot and contribute zero.  Callers point unused columns at a valid column and
 // discard their sums, which keeps the loop free of branches.
@@ -186,7 +186,7 @@ __device__ __forceinline__ void sell_accumulate(const int32_t* __restrict__ col,
                                                 const T* __restrict__ sv, int64_t e_first, int64_t e1,
                                                 int64_t stride, const T* const (&xp)[CW], T (&ah)[CW],
                                                 T (&as)[CW]) {
-    constexpr int U = 4;
+    constexpr int U = CW >= 8 ? 2 : 4;
     for (int64_t e = e_first; e < e1; e += stride * U) {
         int32_t c[U];
         T h[U], s[U];

@@ -357,7 +357,8 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     T* D1 = Wb + n * q;
     T* D2 = D1 + n * q;
     T* Xs = D2 + n * q;
-    const SellShape sh = sell_shape(A.nslices, q, 4);
+    // the MINRES products are latency-bound at these sizes: more, narrower chunks
+    const SellShape sh = sell_shape(A.nslices, q, 4, 4096);
     const unsigned G = rowwise_groups(n);
     // spmv partials: 3 sets of at most nslices per column, FP64 (6 n q T elements precede,
     // an even count, so the address is 8-byte aligned)

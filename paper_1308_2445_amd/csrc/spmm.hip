@@ -162,10 +162,10 @@ void refresh_sell_h(Sell& S, const double* hv, hipStream_t s) {
 }
 
 // Launch shape: the widest column chunk (fewest passes over the pattern) that, with 1
-// or 4 wavefronts per slice, gives at least kWantWaves wavefronts to hide the gathers'
+// or 4 wavefronts per slice, gives at least want_waves wavefronts to hide the gathers'
 // latency; failing that the shape with the most wavefronts.
-SellShape sell_shape(int64_t nslices, int w, int max_cw) {
-    constexpr int64_t kWantWaves = 4096;
+SellShape sell_shape(int64_t nslices, int w, int max_cw, int64_t want_waves) {
+    const int64_t kWantWaves = want_waves;
     SellShape best{1, 4};
     int64_t best_waves = -1;
     for (int cw : {8, 4, 2, 1}) {
@@ -202,7 +202,7 @@ static void spmm_hs_w(const Sell& A, int wps, const double* X, int64_t ldx, int 
 void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
                     int64_t ldy, hipStream_t s) {
     if (w <= 0 || A.n == 0) return;
-    const SellShape sh = sell_shape(A.nslices, w, 8);
+    const SellShape sh = sell_shape(A.nslices, w, 8, 2048);
     switch (sh.cw) {
         case 8: spmm_hs_w<8>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
         case 4: spmm_hs_w<4>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
@@ -241,7 +241,7 @@ template <typename T>
 void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
                        int64_t ldy, hipStream_t s) {
     if (w <= 0 || A.n == 0) return;
-    const SellShape sh = sell_shape(A.nslices, w, 8);
+    const SellShape sh = sell_shape(A.nslices, w, 8, 2048);
     switch (sh.cw) {
         case 8: spmm_shift_w<T, 8>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
         case 4: spmm_shift_w<T, 4>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
