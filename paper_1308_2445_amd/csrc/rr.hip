@@ -679,19 +679,20 @@ constexpr double kSafmin = 2.2250738585072014e-308;
 // number of eigenvalues of T below x: sign changes of the Sturm sequence p_0 = 1,
 // p_1 = d_0 - x, p_i = (d_{i-1} - x) p_{i-1} - e_{i-2}^2 p_{i-2} (the leading principal
 // minors of T - x I; p_i / p_{i-1} is the i-th pivot of its LDL^T, so a sign change is a
-// negative pivot).  One fused multiply-add per step is on the dependent chain, with no
-// division; every fourth step p_{i-1}, p_{i-2} are rescaled by the same power of two to
+// negative pivot).  The sequence is that of s T (s a power of two near 1 / ||T||, e2s
+// holding (s e)^2), so every step changes the magnitude by a factor of order one.  One
+// fused multiply-add per step is on the dependent chain, with no division; every fourth
+// step p_{i-1}, p_{i-2} are rescaled by the same power of two (the larger to [0.5, 1)) to
 // keep them in range.  An exact zero is replaced by a value of the opposite sign to its
 // predecessor, tiny relative to it (the zero-pivot convention: it counts as negative).
-__device__ int sturm_count(const double* d, const double* e2, int r, double x, double pivmin) {
-    (void)pivmin;
+__device__ int sturm_count(const double* d, const double* e2s, int r, double x, double s) {
     constexpr double kZeroRel = 0x1p-80;
-    double p2 = 1.0, p1 = d[0] - x;
+    double p2 = 1.0, p1 = (d[0] - x) * s;
     if (p1 == 0.0) p1 = -kZeroRel;
     int cnt = p1 < 0.0 ? 1 : 0;
 #pragma unroll 4
     for (int i = 1; i < r; ++i) {
-        double p = fma(d[i] - x, p1, -(e2[i - 1] * p2));
+        double p = fma((d[i] - x) * s, p1, -(e2s[i - 1] * p2));
         if (p == 0.0) p = -kZeroRel * p1;
         cnt += (__builtin_bit_cast(int64_t, p) ^ __builtin_bit_cast(int64_t, p1)) < 0 ? 1 : 0;
         p2 = p1;
@@ -714,12 +715,12 @@ __device__ int sturm_count(const double* d, const double* e2, int r, double x, d
 // work-group's vector units, not the dependent chain, the limit) evaluate the Sturm
 // count at G interior points of the bracket, which shrinks G + 1 fold per step, down to
 // the absolute width eps ||T|| (or 2 eps |lambda| when larger).  The bracket starts from
-// the Gershgorin interval.  sc[4..7]: gl, gu, pivmin, ||T||.
+// the Gershgorin interval.  sc[3..7]: the Sturm scale, gl, gu, pivmin, ||T||; e2 receives
+// the scaled squared off-diagonal.
 __device__ void bisect_lowest(const double* d, const double* e, double* e2, int r, int nw,
                               double* theta, double* sc) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i + 1 < r; i += nt) e2[i] = e[i] * e[i];
     if (wave == 0) {
         double lo = 1.0 / 0.0, hi = -1.0 / 0.0, emax = 0.0;
         for (int i = lane; i < r; i += 64) {
@@ -741,7 +742,16 @@ __device__ void bisect_lowest(const double* d, const double* e, double* e2, int 
             sc[5] = hi + pad;
             sc[6] = pivmin;
             sc[7] = tnorm;
+            int ex;
+            (void)frexp(tnorm, &ex);
+            sc[3] = ldexp(1.0, -ex);   // the Sturm counts' scale
         }
+    }
+    __syncthreads();
+    const double ts = sc[3];
+    for (int i = tid; i + 1 < r; i += nt) {
+        const double es = e[i] * ts;
+        e2[i] = es * es;
     }
     __syncthreads();
     const double gl = sc[4], gu = sc[5], pivmin = sc[6];
@@ -763,7 +773,7 @@ __device__ void bisect_lowest(const double* d, const double* e, double* e2, int 
             if (__all(done)) break;
             const double w = hi - lo;
             const double x = lo + w * (double)(g + 1) * inv_g1;
-            const int cnt = act ? sturm_count(d, e2, r, x, pivmin) : 0;
+            const int cnt = act ? sturm_count(d, e2, r, x, ts) : 0;
             const uint64_t bal = __ballot(cnt > j);
             const uint64_t gm = (bal >> gbase) & gmask;
             const int f = gm ? __builtin_ctzll(gm) : G;   // first point with lambda_j below it

@@ -207,13 +207,18 @@ def _rr_case(P, k, rng, dup=0):
     return HR, SR, HR0, SR0
 
 
-@pytest.mark.parametrize("k,nwant,dup", [(8, 8, 0), (12, 6, 0), (68, 36, 0), (40, 20, 3), (100, 60, 0), (140, 40, 0)])
-def test_rayleigh_ritz(prob, ctx, k, nwant, dup):
+@pytest.mark.parametrize("k,nwant,dup,hscale", [(8, 8, 0, 1.0), (12, 6, 0, 1.0), (68, 36, 0, 1.0), (40, 20, 3, 1.0),
+                                                (100, 60, 0, 1.0), (140, 40, 0, 1.0), (68, 36, 0, 1e100),
+                                                (68, 36, 0, 1e-100)])
+def test_rayleigh_ritz(prob, ctx, k, nwant, dup, hscale):
+    """hscale scales H_R (so every Ritz value) far from 1, which the eigenvalue counts of
+    the small solve have to survive."""
     P, pr = prob
     import paper_1308_2445_amd as lp
     torch = _torch()
     rng = np.random.default_rng(16 + k)
     HR, SR, HR0, SR0 = _rr_case(P, k, rng, dup)
+    HR, HR0 = HR * hscale, HR0 * hscale
     gam = torch.empty(nwant, dtype=torch.float64, device="cuda")
     W = torch.empty((nwant, k), dtype=torch.float64, device="cuda")
     info = torch.zeros(2, dtype=torch.int32, device="cuda")
