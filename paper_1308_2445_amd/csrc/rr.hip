@@ -16,7 +16,8 @@
 // Jacobi) and only its eigen-directions above 1e-14 of the largest eigenvalue are kept;
 // C on that basis is diagonalised by cyclic Jacobi as well.
 // Everything lives in LDS when it fits the per-block limit, otherwise in a global
-// workspace.
+// workspace.  Orders above 128 take the same steps on many work-groups (the "large
+// orders" section below), with the one-work-group kernel as their fallback.
 #include <type_traits>
 
 #include "common.h"
@@ -909,16 +910,18 @@ __device__ void tri_resolve(const double* e, int r, double* z, const double* u, 
 
 // Eigenvectors of T for theta[0..nw) by two steps of inverse iteration (the second with
 // the first step's factorisation), every vector in its own thread; eigenvalues closer
-// than 1e-3 ||T|| form a cluster whose vectors are orthonormalised by modified
+// than clrel ||T|| form a cluster whose vectors are orthonormalised by modified
 // Gram-Schmidt (one wavefront per cluster) after every step, and whose equal shifts are
-// separated by a few ulps.  Zt: r x nwp row-major (vector q in column q); U3: 3 r x nwp.
+// separated by a few ulps.  Vectors of eigenvalues further apart are orthogonal to
+// about eps / clrel without it.  Zt: r x nwp row-major (vector q in column q); U3:
+// 3 r x nwp.
 __device__ void inverse_iteration(const double* d, const double* e, int r, int nw, int nwp,
                                   const double* theta, double* sh, double* Zt, double* U3,
-                                  int* cstart, int* csize, int* ncl, double tnorm) {
+                                  int* cstart, int* csize, int* ncl, double tnorm, double clrel = 1e-3) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
     if (tid == 0) {
-        const double ortol = 1e-3 * tnorm;
+        const double ortol = clrel * tnorm;
         int c = -1;
         for (int j = 0; j < nw; ++j) {
             double s = theta[j];
@@ -1048,10 +1051,17 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
                                                               double* __restrict__ W, int64_t ldw,
                                                               int32_t* __restrict__ info,
                                                               double* gws, double* gamma_host,
-                                                              int32_t* info_host) {
+                                                              int32_t* info_host, const int32_t* run_if) {
     extern __shared__ double lds[];
     __shared__ double red[kRRThreads / 64];
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (run_if) {
+        // the fallback of the many-work-group route: run only if it set its flag (read
+        // by every thread before any store, since the flag lies in the workspace)
+        const bool run = __hip_atomic_load(run_if, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        __syncthreads();
+        if (!run) return;
+    }
     const int64_t kk = (int64_t)k * k;
     const int nwp = nwant | 1;
     const RRLayout Lo = rr_layout(k, nwp);
@@ -1225,13 +1235,569 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
     }
 }
 
+// ---------------------------------------------------------------- large orders
+// Above the register-row range the O(k^3) phases run on many work-groups, each phase
+// its own launch (the launch boundary orders them), except the tridiagonal reduction:
+//   prep      D, A = D S_R D and B = D H_R D, padded to kp = 16 ceil(k / 16) (A with
+//             the identity, B with zeros, so the padding stays decoupled);
+//   chol      blocked Cholesky A = L L^T, one launch per 16-column panel: every
+//             work-group takes one 16 x 16 tile of the panel, forms it and the diagonal
+//             tile from the finished panels with MFMA, factors the diagonal tile itself
+//             (the same arithmetic in every work-group) and solves its tile; L^T's
+//             tiles go to the unused upper blocks of A;
+//   fwd (x2)  Y = L^{-1} B, then C = L^{-1} Y^T, one 16-column slice per work-group,
+//             blocked forward substitution with MFMA; slices are kept row-major per
+//             slice ((row, j) at row 16 + j) so the MFMA operands load contiguously;
+//   sym       C <- (C + C^T) / 2, column-major;
+//   tridiag   Householder reduction of C (order k) on G co-resident work-groups, column
+//             c owned by work-group c mod G, two grid barriers per reflector (after the
+//             products p = tau C v, after the rank-2 update, whose owner of the next
+//             column builds the next reflector); vectors shared between work-groups are
+//             written and read with device-scope atomics;
+//   teig      eigenvalues by multisection and eigenvectors by inverse iteration (one
+//             work-group, as in the one-work-group kernel);
+//   back      per 16-column slice of Z: X = Q Z (reflectors in reverse order), then
+//             W = D L^{-T} X by blocked back substitution with MFMA.
+// A pivot of the scaled S_R at or below 1e-14, or a barrier wait that runs out, sets a
+// flag: the kernels after it return at once and the one-work-group kernel solves the
+// pencil instead (rank-revealing route included).
+
+constexpr int kRRLargeMin = 129;
+constexpr int kLT = 16;
+constexpr int kLThreads = 256;
+constexpr int kRRSpinLimit = 1 << 20;
+
+__host__ __device__ inline int rrl_kp(int k) { return (k + kLT - 1) / kLT * kLT; }
+
+struct RRLLayout {
+    int64_t ctl, D, A, L, B, Y, d, e, e2, tau, theta, sh, vb, p, part, sc, icl, Zt, U3, total;
+};
+
+// offsets in doubles; everything before Zt is independent of nwp
+__host__ __device__ inline RRLLayout rrl_layout(int k, int nwp) {
+    const int64_t kp = rrl_kp(k), kk = kp * kp;
+    RRLLayout L{};
+    L.ctl = 0;                 // 16 int32: [0] fallback flag, [1] barrier counter
+    L.D = 8;
+    L.A = L.D + kp;
+    L.L = L.A + kk;
+    L.B = L.L + kk;
+    L.Y = L.B + kk;
+    L.d = L.Y + kk;
+    L.e = L.d + kp;
+    L.e2 = L.e + kp;
+    L.tau = L.e2 + kp;
+    L.theta = L.tau + kp;
+    L.sh = L.theta + kp;
+    L.vb = L.sh + kp;          // 2 kp
+    L.p = L.vb + 2 * kp;
+    L.part = L.p + kp;         // 256
+    L.sc = L.part + 256;       // 8
+    L.icl = L.sc + 8;          // 2 kp + 4 int32
+    L.Zt = L.icl + kp + 2;
+    L.U3 = L.Zt + (int64_t)k * nwp;
+    L.total = L.U3 + 3 * (int64_t)k * nwp;
+    return L;
+}
+
+__device__ __forceinline__ bool rrl_failed(const double* base) {
+    return __hip_atomic_load((const int*)base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// acc += sum over kc in [kb, ke) of X(i, kc) Y(kc, j) (16 x 16 tile, 4 columns of kc per
+// MFMA step, the steps dealt round-robin to nwave wavefronts, loads issued 8 steps at a
+// time); xa(i, kc) and yb(kc, j) return the operands.  ke - kb is a multiple of 4.
+template <typename FA, typename FB>
+__device__ __forceinline__ rr_double4 mfma_tile(FA xa, FB yb, int kb, int ke, int wave, int nwave,
+                                                rr_double4 acc) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nst = (ke - kb) >> 2;
+    int s = wave;
+    for (; s + 7 * nwave < nst; s += 8 * nwave) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int kc = kb + 4 * (s + u * nwave) + lk;
+            a[u] = xa(li, kc);
+            b[u] = yb(kc, li);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+    for (; s < nst; s += nwave) {
+        const int kc = kb + 4 * s + lk;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa(li, kc), yb(kc, li), acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// the four wavefronts' accumulators into red[w][i * 16 + j] (accumulator register q of
+// lane l holds row 4 q + l / 16, column l % 16)
+__device__ __forceinline__ void tile_to_lds(const rr_double4& acc, double (*red)[256]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[wave][(4 * q + (lane >> 4)) * 16 + (lane & 15)] = acc[q];
+}
+
+__global__ __launch_bounds__(kLThreads) void k_rrl_prep(int k, const double* __restrict__ HR,
+                                                        const double* __restrict__ SR, int64_t ldr,
+                                                        double* __restrict__ base) {
+    const RRLLayout Lo = rrl_layout(k, 1);
+    const int64_t kp = rrl_kp(k), kk = kp * kp;
+    double* D = base + Lo.D;
+    double* A = base + Lo.A;
+    double* B = base + Lo.B;
+    const int64_t stride = (int64_t)gridDim.x * kLThreads;
+    const int64_t t0 = (int64_t)blockIdx.x * kLThreads + threadIdx.x;
+    if (t0 < 16) ((int*)(base + Lo.ctl))[t0] = 0;
+    for (int64_t i = t0; i < kp; i += stride) {
+        double di = 0.0;
+        if (i < k) {
+            const double sd = SR[i + i * ldr];
+            di = sd > 0.0 ? 1.0 / sqrt(sd) : 0.0;
+        }
+        D[i] = di;
+    }
+    for (int64_t e = t0; e < kk; e += stride) {
+        const int64_t i = e % kp, j = e / kp;
+        double a = (i == j) ? 1.0 : 0.0, b = 0.0;
+        if (i < k && j < k) {
+            const double si = SR[i + i * ldr], sj = SR[j + j * ldr];
+            const double di = si > 0.0 ? 1.0 / sqrt(si) : 0.0, dj = sj > 0.0 ? 1.0 / sqrt(sj) : 0.0;
+            a = di * SR[i + j * ldr] * dj;
+            b = di * HR[i + j * ldr] * dj;
+        }
+        A[e] = a;
+        B[e] = b;
+    }
+}
+
+// panel p of the blocked Cholesky; work-group b takes row tile r = p + b
+__global__ __launch_bounds__(kLThreads) void k_rrl_chol(int k, int p, double* __restrict__ base) {
+    if (rrl_failed(base)) return;
+    const RRLLayout Lo = rrl_layout(k, 1);
+    const int64_t kp = rrl_kp(k);
+    double* A = base + Lo.A;
+    double* L = base + Lo.L;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int r = p + blockIdx.x, r0 = r * kLT, p0 = p * kLT;
+    __shared__ double red[2][4][256];
+    __shared__ double tD[16][17], tR[16][17];
+    auto lr = [&](int i, int kc) { return L[(r0 + i) + (int64_t)kc * kp]; };
+    auto lp = [&](int i, int kc) { return L[(p0 + i) + (int64_t)kc * kp]; };
+    auto lpt = [&](int kc, int j) { return L[(p0 + j) + (int64_t)kc * kp]; };
+    rr_double4 accR = {0.0, 0.0, 0.0, 0.0}, accD = {0.0, 0.0, 0.0, 0.0};
+    accR = mfma_tile(lr, lpt, 0, p0, wave, 4, accR);
+    if (r != p) accD = mfma_tile(lp, lpt, 0, p0, wave, 4, accD);
+    tile_to_lds(accR, red[0]);
+    tile_to_lds(accD, red[1]);
+    __syncthreads();
+    const int i = tid >> 4, j = tid & 15;
+    {
+        const double sR = red[0][0][tid] + red[0][1][tid] + red[0][2][tid] + red[0][3][tid];
+        const double sD = r == p ? sR : red[1][0][tid] + red[1][1][tid] + red[1][2][tid] + red[1][3][tid];
+        tR[i][j] = A[(r0 + i) + (int64_t)(p0 + j) * kp] - sR;
+        tD[i][j] = A[(p0 + i) + (int64_t)(p0 + j) * kp] - sD;
+    }
+    __syncthreads();
+    // the diagonal tile, one entry per thread (identical in every work-group)
+    for (int c = 0; c < 16; ++c) {
+        const double piv = tD[c][c];
+        if (!(piv > kPivotTol)) {
+            if (tid == 0) __hip_atomic_fetch_or((int*)base, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;   // uniform: every thread read the same pivot
+        }
+        const double lc = sqrt(piv);
+        const double lic = i > c ? tD[i][c] / lc : 0.0;
+        const double ljc = j > c ? tD[j][c] / lc : 0.0;
+        __syncthreads();
+        if (j == c) {
+            if (i == c) tD[i][j] = lc;
+            else if (i > c) tD[i][j] = lic;
+        } else if (j > c && i >= j) {
+            tD[i][j] -= lic * ljc;
+        }
+        __syncthreads();
+    }
+    if (r == p) {
+        L[(p0 + i) + (int64_t)(p0 + j) * kp] = i >= j ? tD[i][j] : 0.0;
+        return;
+    }
+    // L(r, p) = T_R L_pp^{-T}: row i of the tile by forward substitution
+    if (tid < 16) {
+        for (int c = 0; c < 16; ++c) {
+            double v = tR[tid][c];
+            for (int c2 = 0; c2 < c; ++c2) v -= tR[tid][c2] * tD[c][c2];
+            tR[tid][c] = v / tD[c][c];
+        }
+    }
+    __syncthreads();
+    const double x = tR[i][j];
+    L[(r0 + i) + (int64_t)(p0 + j) * kp] = x;
+    A[(p0 + j) + (int64_t)(r0 + i) * kp] = x;   // L^T into the upper block (p, r) of A
+}
+
+// Y = L^{-1} X for the 16-column slice blockIdx.x; X(a, b) = xsr ? the slice-row-major
+// matrix X at (row b, column a) : X[a + b kp]; Y slice-row-major.
+__global__ __launch_bounds__(kLThreads) void k_rrl_fwd(int k, const double* X, int xsr, double* Ys,
+                                                       double* __restrict__ base) {
+    if (rrl_failed(base)) return;
+    const RRLLayout Lo = rrl_layout(k, 1);
+    const int64_t kp = rrl_kp(k);
+    const int nrb = (int)(kp / kLT);
+    const double* L = base + Lo.L;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int c0 = blockIdx.x * kLT;
+    double* Y = Ys + (int64_t)blockIdx.x * kp * kLT;
+    __shared__ double red[4][256];
+    __shared__ double t[16][17], lpp[16][17];
+    const int i = tid >> 4, j = tid & 15;
+    for (int p = 0; p < nrb; ++p) {
+        const int p0 = p * kLT;
+        rr_double4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mfma_tile([&](int a, int kc) { return L[(p0 + a) + (int64_t)kc * kp]; },
+                        [&](int kc, int b) { return Y[(int64_t)kc * kLT + b]; }, 0, p0, wave, 4, acc);
+        tile_to_lds(acc, red);
+        const double xv = xsr ? X[(int64_t)p * kp * kLT + (int64_t)(c0 + j) * kLT + i]
+                              : X[(p0 + i) + (int64_t)(c0 + j) * kp];
+        lpp[i][j] = L[(p0 + i) + (int64_t)(p0 + j) * kp];
+        __syncthreads();
+        t[i][j] = xv - (red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]);
+        __syncthreads();
+        if (tid < 16) {
+            for (int a = 0; a < 16; ++a) {
+                double v = t[a][tid];
+                for (int b2 = 0; b2 < a; ++b2) v -= lpp[a][b2] * t[b2][tid];
+                t[a][tid] = v / lpp[a][a];
+            }
+        }
+        __syncthreads();
+        Y[(int64_t)(p0 + i) * kLT + j] = t[i][j];
+        __syncthreads();
+    }
+}
+
+// C (slice-row-major in B) -> (C + C^T) / 2, column-major in Y
+__global__ __launch_bounds__(kLThreads) void k_rrl_sym(int k, double* __restrict__ base) {
+    if (rrl_failed(base)) return;
+    const RRLLayout Lo = rrl_layout(k, 1);
+    const int64_t kp = rrl_kp(k), kk = kp * kp;
+    const double* Cs = base + Lo.B;
+    double* C = base + Lo.Y;
+    auto at = [&](int64_t a, int64_t b) { return Cs[(b >> 4) * kp * kLT + a * kLT + (b & 15)]; };
+    const int64_t stride = (int64_t)gridDim.x * kLThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kLThreads + threadIdx.x; e < kk; e += stride) {
+        const int64_t i = e % kp, j = e / kp;
+        C[e] = (i < k && j < k) ? 0.5 * (at(i, j) + at(j, i)) : 0.0;
+    }
+}
+
+// Householder tridiagonalisation of C (column-major, ld kp, order k) on gridDim.x
+// co-resident work-groups: d, e, tau; reflector j = I - tau_j v v^T with v_{j+1} = 1 and
+// v_i (i > j + 1) kept in C[i, j].  Dynamic LDS: 2 kp doubles.
+__global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __restrict__ base) {
+    if (rrl_failed(base)) return;
+    const RRLLayout Lo = rrl_layout(k, 1);
+    const int64_t kp = rrl_kp(k);
+    int* fail = (int*)(base + Lo.ctl);
+    int* bar = fail + 1;
+    double* C = base + Lo.Y;
+    double* d = base + Lo.d;
+    double* e = base + Lo.e;
+    double* tau = base + Lo.tau;
+    double* vb = base + Lo.vb;
+    double* pg = base + Lo.p;
+    double* part = base + Lo.part;
+    extern __shared__ double sm[];
+    double* sv = sm;
+    double* sp = sm + kp;
+    __shared__ double red[4];
+    __shared__ int sok;
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int nbar = 0;
+    // grid-wide barrier: this thread's stores and atomics have completed before the
+    // work-group counts itself in; false once any work-group has given up
+    auto gsync = [&]() -> bool {
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();
+        ++nbar;
+        if (tid == 0) {
+            __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int target = nbar * G;
+            int ok = 1, spins = 0;
+            while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                ++spins;
+                if ((spins & 63) == 0 &&
+                    (spins > kRRSpinLimit ||
+                     __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                    __hip_atomic_fetch_or(fail, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            sok = ok;
+        }
+        __syncthreads();
+        return sok != 0;
+    };
+    // reflector of column c from its rows c + 1.. (one wavefront, after the column's
+    // last update): v to the shared buffer of parity c and into C, tau, d[c], e[c]
+    auto reflect = [&](int c) {
+        double* col = C + (int64_t)c * kp;
+        double sg = 0.0, a1 = 0.0;
+        for (int i = c + 1 + lane; i < k; i += 64) {
+            const double x = col[i];
+            if (i == c + 1) a1 = x;
+            else sg = fma(x, x, sg);
+        }
+        const double sigma = wave_allsum(sg), alpha = wave_allsum(a1);
+        double t, beta, scal;
+        reflector(alpha, sigma, t, beta, scal);
+        double* vn = vb + (c & 1) * kp;
+        for (int i = c + 1 + lane; i < k; i += 64) {
+            const double vi = (i == c + 1) ? 1.0 : col[i] * scal;
+            if (i > c + 1) col[i] = vi;
+            __hip_atomic_store(vn + i, vi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) {
+            d[c] = col[c];
+            e[c] = beta;
+            __hip_atomic_store(tau + c, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    };
+    // the first column >= cmin owned by this wavefront (columns g + t G, t = wave mod 4)
+    auto first_own = [&](int cmin) {
+        int t = cmin > g ? (cmin - g + G - 1) / G : 0;
+        t += ((wave - t) % 4 + 4) % 4;
+        return g + t * G;
+    };
+    if (g == 0 && wave == 0) reflect(0);
+    if (!gsync()) return;
+    for (int j = 0; j + 2 < k; ++j) {
+        const double* vsh = vb + (j & 1) * kp;
+        for (int i = j + 1 + tid; i < k; i += kLThreads)
+            sv[i] = __hip_atomic_load(vsh + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double tj = __hip_atomic_load(tau + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        // p_c = tau (C v)_c for the owned columns, and this work-group's part of p . v
+        double mp = 0.0;
+        for (int c = first_own(j + 1); c < k; c += 4 * G) {
+            const double* col = C + (int64_t)c * kp;
+            double dot = 0.0;
+            for (int i = j + 1 + lane; i < k; i += 64) dot = fma(col[i], sv[i], dot);
+            dot = tj * wave_allsum(dot);
+            if (lane == 0) __hip_atomic_store(pg + c, dot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            mp = fma(dot, sv[c], mp);
+        }
+        if (lane == 0) red[wave] = mp;
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(part + g, red[0] + red[1] + red[2] + red[3], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (!gsync()) return;
+        // C <- C - v w^T - w v^T with w = p - K v, K = tau (p . v) / 2
+        for (int i = j + 1 + tid; i < k; i += kLThreads)
+            sp[i] = __hip_atomic_load(pg + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double ps = 0.0;
+        for (int q = lane; q < G; q += 64) ps += __hip_atomic_load(part + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double K = 0.5 * tj * wave_allsum(ps);
+        __syncthreads();
+        for (int c = first_own(j + 1); c < k; c += 4 * G) {
+            double* col = C + (int64_t)c * kp;
+            const double vc = sv[c], wc = sp[c] - K * vc;
+            for (int i = j + 1 + lane; i < k; i += 64) {
+                const double vi = sv[i];
+                col[i] -= vi * wc + (sp[i] - K * vi) * vc;
+            }
+            if (c == j + 1) {
+                if (j + 3 < k) {
+                    reflect(j + 1);
+                } else if (lane == 0) {   // j + 1 = k - 2: the last off-diagonal
+                    d[k - 2] = col[k - 2];
+                    e[k - 2] = col[k - 1];
+                }
+            }
+            if (c == k - 1 && j + 3 == k && lane == 0) d[k - 1] = col[k - 1];
+        }
+        if (j + 3 < k && !gsync()) return;
+    }
+}
+
+// eigenvalues and vectors of the tridiagonal matrix (one work-group of kRRThreads)
+__global__ __launch_bounds__(kRRThreads) void k_rrl_teig(int k, int nwant, double* __restrict__ base,
+                                                         double* __restrict__ gamma, int32_t* __restrict__ info,
+                                                         double* gamma_host, int32_t* info_host) {
+    if (rrl_failed(base)) return;
+    const int nwp = nwant | 1;
+    const RRLLayout Lo = rrl_layout(k, nwp);
+    double* d = base + Lo.d;
+    double* e = base + Lo.e;
+    double* theta = base + Lo.theta;
+    double* sc = base + Lo.sc;
+    int* cstart = (int*)(base + Lo.icl);
+    int* csize = cstart + k;
+    int* ncl = csize + k;
+    bisect_lowest(d, e, base + Lo.e2, k, nwant, theta, sc);
+    __syncthreads();
+    // LABPSD's wanted Ritz values lie dense in a narrow band: clusters at 1e-3 ||T|| chain
+    // into hundreds of vectors, at 1e-5 ||T|| (vectors orthogonal to ~1e-11 outside
+    // them) they stay a few wide
+    inverse_iteration(d, e, k, nwant, nwp, theta, base + Lo.sh, base + Lo.Zt, base + Lo.U3, cstart, csize, ncl,
+                      sc[7], 1e-5);
+    const int tid = threadIdx.x;
+    for (int q = tid; q < nwant; q += blockDim.x) {
+        gamma[q] = theta[q];
+        if (gamma_host) gamma_host[q] = theta[q];
+    }
+    if (tid == 0) {
+        info[0] = 0;
+        info[1] = 0;
+        if (info_host) { info_host[0] = 0; info_host[1] = 0; }
+    }
+}
+
+// W(:, slice) = D L^{-T} Q Z(:, slice) for the 16-column slice blockIdx.x
+__global__ __launch_bounds__(kLThreads) void k_rrl_back(int k, int nwant, double* __restrict__ base,
+                                                        double* __restrict__ W, int64_t ldw) {
+    if (rrl_failed(base)) return;
+    const int nwp = nwant | 1;
+    const RRLLayout Lo = rrl_layout(k, nwp);
+    const int64_t kp = rrl_kp(k);
+    const int nrb = (int)(kp / kLT);
+    const double* C = base + Lo.Y;
+    const double* tau = base + Lo.tau;
+    const double* Zt = base + Lo.Zt;
+    const double* L = base + Lo.L;
+    const double* At = base + Lo.A;
+    const double* D = base + Lo.D;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q0 = blockIdx.x * kLT;
+    double* X = base + Lo.B + (int64_t)blockIdx.x * kp * kLT;
+    __shared__ double part[4][16];
+    __shared__ double red[4][256];
+    __shared__ double t[16][17], lpp[16][17];
+    for (int64_t el = tid; el < kp * kLT; el += kLThreads) {
+        const int64_t row = el >> 4;
+        const int q = q0 + (int)(el & 15);
+        X[el] = (row < k && q < nwant) ? Zt[row * nwp + q] : 0.0;
+    }
+    __syncthreads();
+    // X <- H_j X for j = k - 3 down to 0; thread (ro, jc) takes column jc, rows j + 1 + ro + 16 m
+    const int jc = tid & 15, ro = tid >> 4;
+    for (int jr = k - 3; jr >= 0; --jr) {
+        const double tj = tau[jr];
+        if (tj == 0.0) continue;   // uniform
+        const double* v = C + (int64_t)jr * kp;
+        double sacc = 0.0;
+        for (int i = jr + 1 + ro; i < k; i += 16) {
+            const double vi = (i == jr + 1) ? 1.0 : v[i];
+            sacc = fma(vi, X[(int64_t)i * kLT + jc], sacc);
+        }
+        sacc += __shfl_xor(sacc, 16, 64);
+        sacc += __shfl_xor(sacc, 32, 64);
+        if (lane < 16) part[wave][lane] = sacc;
+        __syncthreads();
+        const double sq = tj * (part[0][jc] + part[1][jc] + part[2][jc] + part[3][jc]);
+        for (int i = jr + 1 + ro; i < k; i += 16) {
+            const double vi = (i == jr + 1) ? 1.0 : v[i];
+            X[(int64_t)i * kLT + jc] -= sq * vi;
+        }
+        __syncthreads();
+    }
+    // L^T Y = X, row tiles from the bottom; Y overwrites X
+    const int i = tid >> 4, j = tid & 15;
+    for (int p = nrb - 1; p >= 0; --p) {
+        const int p0 = p * kLT;
+        rr_double4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mfma_tile([&](int a, int kc) { return At[(p0 + a) + (int64_t)kc * kp]; },
+                        [&](int kc, int b) { return X[(int64_t)kc * kLT + b]; }, p0 + kLT, (int)kp, wave, 4, acc);
+        tile_to_lds(acc, red);
+        const double xv = X[(int64_t)(p0 + i) * kLT + j];
+        lpp[i][j] = L[(p0 + i) + (int64_t)(p0 + j) * kp];
+        __syncthreads();
+        t[i][j] = xv - (red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]);
+        __syncthreads();
+        if (tid < 16) {
+            for (int a = 15; a >= 0; --a) {
+                double v = t[a][tid];
+                for (int b2 = a + 1; b2 < 16; ++b2) v -= lpp[b2][a] * t[b2][tid];
+                t[a][tid] = v / lpp[a][a];
+            }
+        }
+        __syncthreads();
+        const double y = t[i][j];
+        X[(int64_t)(p0 + i) * kLT + j] = y;
+        if (p0 + i < k && q0 + j < nwant) W[(p0 + i) + (int64_t)(q0 + j) * ldw] = D[p0 + i] * y;
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 size_t rr_ws_bytes(int k) {
-    // the layout at the widest nwant (= k) plus the k x k product scratch and alignment
+    // the layout at the widest nwant (= k) plus the k x k product scratch and alignment;
+    // large orders also run the many-work-group route in the same workspace
     const RRLayout L = rr_layout(k, k | 1);
-    return sizeof(double) * ((size_t)L.total + (size_t)k * k + 4);
+    size_t n = (size_t)L.total + (size_t)k * k + 4;
+    if (k >= kRRLargeMin) n = std::max(n, (size_t)rrl_layout(k, k | 1).total + 4);
+    return sizeof(double) * n;
 }
+
+namespace {
+
+// the many-work-group route for k >= kRRLargeMin; the one-work-group kernel follows it
+// and runs only if the route gave up (or runs in its place if the cooperative launch
+// is refused)
+void launch_rr_large(int k, int nwant, const double* HR, const double* SR, int64_t ldr, double* gamma,
+                     double* W, int64_t ldw, int32_t* info, void* ws, hipStream_t s, double* gamma_host,
+                     int32_t* info_host) {
+    double* gws = (double*)ws;
+    double* base = gws + (((uintptr_t)gws & 15) ? 1 : 0);
+    const int kp = rrl_kp(k), nrb = kp / kLT;
+    const int64_t kk = (int64_t)kp * kp;
+    const int prep_blocks = (int)std::min<int64_t>(2048, (kk + kLThreads - 1) / kLThreads);
+    hipLaunchKernelGGL(k_rrl_prep, dim3(prep_blocks), dim3(kLThreads), 0, s, k, HR, SR, ldr, base);
+    for (int p = 0; p < nrb; ++p)
+        hipLaunchKernelGGL(k_rrl_chol, dim3(nrb - p), dim3(kLThreads), 0, s, k, p, base);
+    const RRLLayout Lo = rrl_layout(k, 1);
+    hipLaunchKernelGGL(k_rrl_fwd, dim3(nrb), dim3(kLThreads), 0, s, k, (const double*)(base + Lo.B), 0,
+                       base + Lo.Y, base);
+    hipLaunchKernelGGL(k_rrl_fwd, dim3(nrb), dim3(kLThreads), 0, s, k, (const double*)(base + Lo.Y), 1,
+                       base + Lo.B, base);
+    hipLaunchKernelGGL(k_rrl_sym, dim3(prep_blocks), dim3(kLThreads), 0, s, k, base);
+    LABPSD_HIP(hipGetLastError());
+    // about eight columns per work-group
+    const int G = std::min(128, std::max(8, (k + 7) / 8));
+    const size_t lds = 2 * (size_t)kp * sizeof(double);
+    if (lds + 1024 > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)k_rrl_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+    int kk_arg = k;
+    double* base_arg = base;
+    void* targs[] = {(void*)&kk_arg, (void*)&base_arg};
+    const int32_t* run_if = (const int32_t*)base;
+    if (hipLaunchCooperativeKernel((const void*)k_rrl_tridiag, dim3(G), dim3(kLThreads), targs,
+                                   (unsigned)lds, s) == hipSuccess &&
+        hipGetLastError() == hipSuccess) {
+        hipLaunchKernelGGL(k_rrl_teig, dim3(1), dim3(kRRThreads), 0, s, k, nwant, base, gamma, info, gamma_host,
+                           info_host);
+        hipLaunchKernelGGL(k_rrl_back, dim3((nwant + kLT - 1) / kLT), dim3(kLThreads), 0, s, k, nwant, base, W,
+                           ldw);
+        LABPSD_HIP(hipGetLastError());
+    } else {
+        (void)hipGetLastError();
+        run_if = nullptr;   // nothing ran: the one-work-group kernel solves the pencil
+    }
+    void* args[] = {(void*)&k,    (void*)&nwant, (void*)&HR, (void*)&SR, (void*)&ldr,
+                    (void*)&gamma, (void*)&W,    (void*)&ldw, (void*)&info, (void*)&ws,
+                    (void*)&gamma_host, (void*)&info_host, (void*)&run_if};
+    LABPSD_HIP(hipLaunchKernel((const void*)k_rayleigh_ritz<false, 0>, dim3(1), dim3(kRRThreads), args, 0, s));
+    LABPSD_HIP(hipGetLastError());
+}
+
+}  // namespace
 
 void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, int64_t ldr,
                           double* gamma, double* W, int64_t ldw, int32_t* info, void* ws,
@@ -1239,6 +1805,10 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
     if (k <= 0 || nwant <= 0) return;
     LABPSD_REQUIRE(k <= kRRMax, "Rayleigh-Ritz order exceeds the supported maximum");
     LABPSD_REQUIRE(nwant <= k, "more Ritz pairs requested than the search space holds");
+    if (k >= kRRLargeMin) {
+        launch_rr_large(k, nwant, HR, SR, ldr, gamma, W, ldw, info, ws, s, gamma_host, info_host);
+        return;
+    }
     static int lds_limit = -1;
     if (lds_limit < 0) {
         int dev = 0, v = 0;
@@ -1263,9 +1833,10 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
             default: return (const void*)k_rayleigh_ritz<L_, 0>;
         }
     };
+    const int32_t* run_if = nullptr;
     void* args[] = {(void*)&k,    (void*)&nwant, (void*)&HR, (void*)&SR, (void*)&ldr,
                     (void*)&gamma, (void*)&W,    (void*)&ldw, (void*)&info, (void*)&ws,
-                    (void*)&gamma_host, (void*)&info_host};
+                    (void*)&gamma_host, (void*)&info_host, (void*)&run_if};
     if (all_lds) {
         const void* f = pick(std::true_type{});
         if (bytes > 64 * 1024)

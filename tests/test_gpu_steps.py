@@ -209,7 +209,7 @@ def _rr_case(P, k, rng, dup=0):
 
 @pytest.mark.parametrize("k,nwant,dup,hscale", [(8, 8, 0, 1.0), (12, 6, 0, 1.0), (68, 36, 0, 1.0), (40, 20, 3, 1.0),
                                                 (100, 60, 0, 1.0), (140, 40, 0, 1.0), (68, 36, 0, 1e100),
-                                                (68, 36, 0, 1e-100)])
+                                                (68, 36, 0, 1e-100), (129, 129, 0, 1.0), (200, 100, 5, 1.0)])
 def test_rayleigh_ritz(prob, ctx, k, nwant, dup, hscale):
     """hscale scales H_R (so every Ritz value) far from 1, which the eigenvalue counts of
     the small solve have to survive."""
@@ -234,6 +234,43 @@ def test_rayleigh_ritz(prob, ctx, k, nwant, dup, hscale):
     scale = np.abs(gr).max()
     assert np.abs(g - gr).max() <= 1e-11 * scale
     assert np.abs(Wh.T @ SR @ Wh - np.eye(nwant)).max() <= 1e-9
+    assert np.abs(Wh.T @ HR @ Wh - np.diag(g)).max() <= 1e-9 * scale
+
+
+@pytest.fixture(scope="module")
+def c2_pencil():
+    return pufe.workload("c2", 0)
+
+
+@pytest.mark.parametrize("k,nwant,dup,hscale", [(300, 150, 0, 1e100), (538, 282, 0, 1.0), (1076, 564, 0, 1.0),
+                                                (300, 150, 20, 1.0)])
+def test_rayleigh_ritz_large(c2_pencil, ctx, k, nwant, dup, hscale):
+    """Orders of the 128k- and 296k-dof cells (k up to 538 and 1076) on pencils of the
+    16k-dof cell; with repeated directions the Cholesky of S_R fails and the
+    rank-revealing route takes over."""
+    P = c2_pencil
+    import paper_1308_2445_amd as lp
+    torch = _torch()
+    rng = np.random.default_rng(16 + k)
+    HR, SR, HR0, SR0 = _rr_case(P, k, rng, dup)
+    HR, HR0 = HR * hscale, HR0 * hscale
+    gam = torch.empty(nwant, dtype=torch.float64, device="cuda")
+    W = torch.empty((nwant, k), dtype=torch.float64, device="cuda")
+    info = torch.zeros(2, dtype=torch.int32, device="cuda")
+    print("\n[case] rayleigh_ritz k=%d nwant=%d dup=%d" % (k, nwant, dup), flush=True)
+    lp.labpsd_rayleigh_ritz(ctx, k, nwant, dev(HR), dev(SR), gam, W, info)
+    g = gam.cpu().numpy()
+    Wh = host(W)
+    gr, Wr, dropped = orr.rayleigh_ritz(HR0, SR0, nwant)
+    inf = info.cpu().numpy()
+    assert inf[1] == 0
+    if dup:
+        assert inf[0] >= dup
+    scale = np.abs(gr).max()
+    orth = np.abs(Wh.T @ SR @ Wh - np.eye(nwant)).max()
+    print("[rr] k=%d eig err %.2e orth %.2e" % (k, np.abs(g - gr).max() / scale, orth), flush=True)
+    assert np.abs(g - gr).max() <= 1e-11 * scale
+    assert orth <= 1e-10
     assert np.abs(Wh.T @ HR @ Wh - np.diag(g)).max() <= 1e-9 * scale
 
 

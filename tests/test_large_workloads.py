@@ -1,0 +1,89 @@
+"""Full-size mixed-precision solve: the 48^3-element, 64-atom PUFE cell (about 128k dofs,
+nev = 256), mixed precision against FP64 and against the oracle's eigenvalues.
+
+At this size the oracle's eigenpairs come from its own LABPSD run (stored by
+tests/golden/make_golden.py); the GPU results are checked against them, against each
+other, and against properties that hold at any size: every returned pair's relative
+residual (eq. (res1), computed here with SciPy sparse products), S-orthonormality of X
+and ascending Ritz values.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import pufe
+from oracle import eigs as oeig
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-8
+
+
+def _lp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1308_2445_amd as lp
+    return lp
+
+
+@pytest.fixture(scope="module")
+def c3():
+    lp = _lp()
+    path = os.path.join(GOLDEN, "c3_eigs.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle eigenvalues for the 128k-dof cell (tests/golden/make_golden.py c3)")
+    P = pufe.workload("c3", 0)
+    with open(path) as f:
+        g = json.load(f)
+    assert g["n"] == P.n and g["nnz"] == P.nnz and g["converged"]
+    ctx = lp.Context(0)
+    pr = lp.Problem.from_pencil(ctx, P)
+    pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P))
+    return P, pr, g, {}
+
+
+def _solve(c3, precision):
+    P, pr, g, cache = c3
+    if precision not in cache:
+        m, m0 = g["nev"], g["m0"]
+        print("\n[case] c3 n=%d nev=%d m0=%d precision=%d" % (P.n, m, m0, precision), flush=True)
+        cache[precision] = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=TOL, sigma0=P.sigma0,
+                                    precision=precision)
+    return cache[precision]
+
+
+def _rel(lam, ref, sigma0):
+    return np.abs(np.asarray(lam) - np.asarray(ref)) / np.abs(np.asarray(ref) - sigma0)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", [1, 0])
+def test_c3_full_size_matches_oracle(c3, precision):
+    P, pr, g, _ = c3
+    out = _solve(c3, precision)
+    m = g["nev"]
+    assert out.converged, out.stats
+    err = _rel(out.lam, g["lam"], P.sigma0)
+    print("[c3] precision=%d iters=%d minres=%d max rel eig err vs oracle %.2e (median %.2e)"
+          % (precision, out.stats["outer_iters"], out.stats["minres_iters"], err.max(), np.median(err)),
+          flush=True)
+    assert err.max() < 1e-10
+    H, S = P.H(), P.S()
+    res = oeig.relative_residuals(H, S, out.lam, out.X, P.sigma0)
+    assert res.max() <= TOL * 1.01
+    assert np.abs(out.X.T @ (S @ out.X) - np.eye(m)).max() < 1e-10
+    assert np.all(np.diff(out.lam) >= 0)
+    assert out.res_hist.shape[1] == m and out.res_hist[-1].max() <= TOL
+
+
+@pytest.mark.timeout(600)
+def test_c3_mixed_agrees_with_fp64(c3):
+    P, _, g, _ = c3
+    mixed, fp64 = _solve(c3, 1), _solve(c3, 0)
+    d = _rel(mixed.lam, fp64.lam, P.sigma0)
+    print("[c3] per-eigenpair |lam_mixed - lam_fp64| / |lam_fp64 - sigma0|: max %.2e median %.2e"
+          % (d.max(), np.median(d)), flush=True)
+    assert d.max() < 1e-10
