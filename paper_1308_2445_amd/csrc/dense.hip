@@ -331,6 +331,85 @@ __global__ __launch_bounds__(256) void k_block_update(int64_t n, int k, int b,
     }
 }
 
+// The same product for wide blocks (large k or b): each wavefront accumulates 16 rows x
+// 16 CT columns (CT MFMA tiles), so Z is re-read b / (16 CT) times instead of b / 32; W
+// passes through LDS in 16-row chunks (double-buffered, shared by the four wavefronts)
+// and the next chunk's Z operands and W entries are loaded while the current chunk's
+// MFMAs run.
+template <int CT>
+__global__ __launch_bounds__(256) void k_block_update_wide(int64_t n, int k, int b,
+                                                           const double* __restrict__ Z0,
+                                                           const double* __restrict__ Z1,
+                                                           const double* __restrict__ Z2, int64_t ldz,
+                                                           const double* __restrict__ W, int64_t ldw,
+                                                           double* __restrict__ O0,
+                                                           double* __restrict__ O1,
+                                                           double* __restrict__ O2, int64_t ldo) {
+    constexpr int NC = 16 * CT;               // columns per work-group
+    constexpr int WL = 16 * NC / 256;         // W entries per thread per chunk
+    __shared__ double Wl[2][16][NC];
+    const double* Zm = blockIdx.z == 0 ? Z0 : (blockIdx.z == 1 ? Z1 : Z2);
+    double* O = blockIdx.z == 0 ? O0 : (blockIdx.z == 1 ? O1 : O2);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int c0 = blockIdx.y * NC;
+    const int64_t arow = r0 + (lane & 15);
+    const bool rin = arow < n;
+    const int kq = lane >> 4;
+    const int nchunk = (k + 15) / 16;
+    double an[4], wn[WL];
+    auto load = [&](int ch) {
+        const int kb = ch * 16;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int kr = kb + 4 * s4 + kq;
+            an[s4] = (rin && kr < k) ? Zm[arow + (int64_t)kr * ldz] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < WL; ++u) {
+            const int r = tid & 15, c = (tid >> 4) + 16 * u;
+            const int kr = kb + r;
+            wn[u] = (kr < k && c0 + c < b) ? W[kr + (int64_t)(c0 + c) * ldw] : 0.0;
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < WL; ++u) Wl[buf][tid & 15][(tid >> 4) + 16 * u] = wn[u];
+    };
+    double4_t acc[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = double4_t{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    stage(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        double a[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) a[s4] = an[s4];
+        const bool more = ch + 1 < nchunk;
+        if (more) load(ch + 1);
+        const int buf = ch & 1;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], Wl[buf][4 * s4 + kq][16 * ct + (lane & 15)],
+                                                               acc[ct], 0, 0, 0);
+        }
+        if (more) stage(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = c0 + 16 * ct + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = r0 + 4 * q + (lane >> 4);
+            if (row < n && col < b) O[row + (int64_t)col * ldo] = acc[ct][q];
+        }
+    }
+}
+
 }  // namespace
 
 int residual_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kResRows - 1) / kResRows); }
@@ -489,6 +568,14 @@ void launch_block_update(int64_t n, int k, int b, const double* Z, const double*
                          double* PsiH, double* PsiS, int64_t ldo, hipStream_t s) {
     if (n <= 0 || b <= 0) return;
     dim3 grid((unsigned)((n + 63) / 64), (unsigned)((b + 31) / 32), 3);
+    if (k >= 128 || b >= 96) {
+        // wide blocks: 128 columns per work-group
+        const dim3 gw((unsigned)((n + 63) / 64), (unsigned)((b + 127) / 128), 3);
+        hipLaunchKernelGGL(k_block_update_wide<8>, gw, dim3(256), 0, s, n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi,
+                           PsiH, PsiS, ldo);
+        LABPSD_HIP(hipGetLastError());
+        return;
+    }
     hipLaunchKernelGGL(k_block_update, grid, dim3(256), 0, s, n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi,
                        PsiH, PsiS, ldo);
     LABPSD_HIP(hipGetLastError());

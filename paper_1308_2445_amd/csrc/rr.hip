@@ -1675,39 +1675,85 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_back(int k, int nwant, double
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q0 = blockIdx.x * kLT;
     double* X = base + Lo.B + (int64_t)blockIdx.x * kp * kLT;
-    __shared__ double part[4][16];
     __shared__ double red[4][256];
-    __shared__ double t[16][17], lpp[16][17];
+    __shared__ double t[16][17], lpp[16][17], tm[16][17], w2[16][17];
     for (int64_t el = tid; el < kp * kLT; el += kLThreads) {
         const int64_t row = el >> 4;
         const int q = q0 + (int)(el & 15);
         X[el] = (row < k && q < nwant) ? Zt[row * nwp + q] : 0.0;
     }
     __syncthreads();
-    // X <- H_j X for j = k - 3 down to 0; thread (ro, jc) takes column jc, rows j + 1 + ro + 16 m
-    const int jc = tid & 15, ro = tid >> 4;
-    for (int jr = k - 3; jr >= 0; --jr) {
-        const double tj = tau[jr];
-        if (tj == 0.0) continue;   // uniform
-        const double* v = C + (int64_t)jr * kp;
-        double sacc = 0.0;
-        for (int i = jr + 1 + ro; i < k; i += 16) {
-            const double vi = (i == jr + 1) ? 1.0 : v[i];
-            sacc = fma(vi, X[(int64_t)i * kLT + jc], sacc);
-        }
-        sacc += __shfl_xor(sacc, 16, 64);
-        sacc += __shfl_xor(sacc, 32, 64);
-        if (lane < 16) part[wave][lane] = sacc;
+    // X <- H_j0 ... H_j0+15 X for the blocks of 16 reflectors from the last one down, in
+    // compact WY form I - V T V^T (V: the block's reflectors, rows j0.. kp; T upper
+    // triangular from tau and V^T V): X -= V (T (V^T X))
+    const int i = tid >> 4, j = tid & 15;
+    const int nref = k - 2;
+    for (int j0 = (nref - 1) / kLT * kLT; j0 >= 0; j0 -= kLT) {
+        const int nb = min(kLT, nref - j0);
+        // V(row, c): 0 above row j0 + c + 1, 1 there, the stored entries below
+        auto vv = [&](int row, int c) -> double {
+            const int top = j0 + c + 1;
+            if (c >= nb || row < top || row >= k) return 0.0;
+            return row == top ? 1.0 : C[row + (int64_t)(j0 + c) * kp];
+        };
+        rr_double4 accW = {0.0, 0.0, 0.0, 0.0}, accG = {0.0, 0.0, 0.0, 0.0};
+        accW = mfma_tile([&](int c, int row) { return vv(row, c); },
+                         [&](int row, int b) { return X[(int64_t)row * kLT + b]; }, j0, (int)kp, wave, 4, accW);
+        accG = mfma_tile([&](int c, int row) { return vv(row, c); },
+                         [&](int row, int b) { return vv(row, b); }, j0, (int)kp, wave, 4, accG);
+        tile_to_lds(accW, red);
         __syncthreads();
-        const double sq = tj * (part[0][jc] + part[1][jc] + part[2][jc] + part[3][jc]);
-        for (int i = jr + 1 + ro; i < k; i += 16) {
-            const double vi = (i == jr + 1) ? 1.0 : v[i];
-            X[(int64_t)i * kLT + jc] -= sq * vi;
+        t[i][j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];   // V^T X
+        __syncthreads();
+        tile_to_lds(accG, red);
+        __syncthreads();
+        lpp[i][j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];   // V^T V
+        __syncthreads();
+        // T into part-free LDS: Tm[r][c] for r <= c < nb (column c from columns < c)
+        if (tid < 16) {
+            const int r = tid;
+            for (int c = 0; c < 16; ++c) {
+                double v = 0.0;
+                if (c < nb && r <= c) {
+                    const double tc = tau[j0 + c];
+                    if (r == c) {
+                        v = tc;
+                    } else {
+                        double acc = 0.0;
+                        for (int m = r; m < c; ++m) acc = fma(tm[r][m], lpp[m][c], acc);
+                        v = -tc * acc;
+                    }
+                }
+                tm[r][c] = v;
+            }
+        }
+        __syncthreads();
+        // W2 = T (V^T X)
+        {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) acc = fma(tm[i][m], t[m][j], acc);
+            w2[i][j] = acc;
+        }
+        __syncthreads();
+        // X(rows, :) -= V(rows, :) W2, one 16-row tile per wavefront at a time
+        for (int rt = j0 / kLT + wave; rt < (int)(kp / kLT); rt += 4) {
+            const int row0 = rt * kLT;
+            rr_double4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int c = 4 * s4 + (lane >> 4);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vv(row0 + (lane & 15), c), w2[c][lane & 15], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t el = (int64_t)(row0 + 4 * q + (lane >> 4)) * kLT + (lane & 15);
+                X[el] -= acc[q];
+            }
         }
         __syncthreads();
     }
     // L^T Y = X, row tiles from the bottom; Y overwrites X
-    const int i = tid >> 4, j = tid & 15;
     for (int p = nrb - 1; p >= 0; --p) {
         const int p0 = p * kLT;
         rr_double4 acc = {0.0, 0.0, 0.0, 0.0};

@@ -279,7 +279,8 @@ def test_block_update(prob, ctx):
     import paper_1308_2445_amd as lp
     torch = _torch()
     rng = np.random.default_rng(17)
-    for k, b in ((8, 5), (45, 33), (70, 36)):
+    # the last four shapes take the wide kernel (128 columns per work-group)
+    for k, b in ((8, 5), (45, 33), (70, 36), (129, 40), (60, 130), (300, 150), (538, 282)):
         Zs = [rng.standard_normal((P.n, k)) for _ in range(3)]
         W = rng.standard_normal((k, b))
         outs = [torch.empty((b, P.n), dtype=torch.float64, device="cuda") for _ in range(3)]
