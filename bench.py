@@ -288,8 +288,11 @@ def main():
                 "traffic": measured_traffic("k_rayleigh_ritz"),
                 "launches": int(nl_rr), "avg_launch_us": 1e6 * t_rr,
                 "algorithmic_flops_per_launch": agg["rr_flops"] / nl_rr,
-                "note": "one work-group solving the reduced pencil of order k <= %d: latency-bound "
-                        "(dependent steps and barriers), not throughput-bound" % (b + nev)}
+                "note": ("one work-group solving the reduced pencil of order k <= %d: latency-bound "
+                         "(dependent steps and barriers), not throughput-bound" % (b + nev)) if b + nev <= 128 else
+                        ("reduced pencil of order k <= %d: orders above 128 run as a sequence of "
+                         "many-work-group kernels (blocked Cholesky and substitutions on MFMA, cooperative "
+                         "tridiagonalisation with two grid barriers per reflector): latency-bound" % (b + nev))}
     nl_pp = agg["n_launch"]["products_p"] + agg["n_launch"]["products_psi"]
     t_pp = (agg["t"]["products_p"] + agg["t"]["products_psi"]) / max(1, nl_pp)
     bytes_pp = (agg["n_launch"]["products_p"] * spmm_bytes(P, 0) + agg["n_launch"]["products_psi"]

@@ -1,11 +1,11 @@
-"""Full-size mixed-precision solve: the 48^3-element, 64-atom PUFE cell (about 128k dofs,
-nev = 256), mixed precision against FP64 and against the oracle's eigenvalues.
+"""Full-size solves of the two large cells, mixed precision against FP64.
 
-At this size the oracle's eigenpairs come from its own LABPSD run (stored by
-tests/golden/make_golden.py); the GPU results are checked against them, against each
-other, and against properties that hold at any size: every returned pair's relative
-residual (eq. (res1), computed here with SciPy sparse products), S-orthonormality of X
-and ascending Ritz values.
+The 48^3-element, 64-atom cell (about 128k dofs, nev = 256): the oracle's eigenpairs come
+from its own LABPSD run (stored by tests/golden/make_golden.py); the GPU results are
+checked against them, against each other, and against properties that hold at any size:
+every returned pair's relative residual (eq. (res1), computed here with SciPy sparse
+products), S-orthonormality of X and ascending Ritz values.  The 64^3-element, 128-atom
+cell (about 297k dofs, nev = 512) is checked by the same properties only.
 """
 import json
 import os
@@ -86,4 +86,41 @@ def test_c3_mixed_agrees_with_fp64(c3):
     d = _rel(mixed.lam, fp64.lam, P.sigma0)
     print("[c3] per-eigenpair |lam_mixed - lam_fp64| / |lam_fp64 - sigma0|: max %.2e median %.2e"
           % (d.max(), np.median(d)), flush=True)
+    assert d.max() < 1e-10
+
+
+@pytest.fixture(scope="module")
+def c5():
+    """The 64^3-element, 128-atom cell (about 297k dofs, nev = 512): too large for the
+    oracle's run, so checked by properties that hold at any size."""
+    lp = _lp()
+    P = pufe.workload("c5", 0)
+    ctx = lp.Context(0)
+    pr = lp.Problem.from_pencil(ctx, P)
+    pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P))
+    return P, pr
+
+
+@pytest.mark.timeout(900)
+def test_c5_full_size_properties(c5):
+    P, pr = c5
+    m = pufe.WORKLOADS["c5"]["nev"]
+    m0 = pufe.guard_vectors(m)
+    X0 = pufe.start_block(P.n, m + m0, 0)
+    outs = {}
+    for precision in (1, 0):
+        print("\n[case] c5 n=%d nev=%d m0=%d precision=%d" % (P.n, m, m0, precision), flush=True)
+        out = pr.solve(m, m0, X0, tol=TOL, sigma0=P.sigma0, precision=precision)
+        assert out.converged, out.stats
+        H, S = P.H(), P.S()
+        res = oeig.relative_residuals(H, S, out.lam, out.X, P.sigma0)
+        orth = np.abs(out.X.T @ (S @ out.X) - np.eye(m)).max()
+        print("[c5] precision=%d iters=%d max res %.2e orth %.2e" % (precision, out.stats["outer_iters"],
+                                                                     res.max(), orth), flush=True)
+        assert res.max() <= TOL * 1.01
+        assert orth < 1e-10
+        assert np.all(np.diff(out.lam) >= 0)
+        outs[precision] = out
+    d = _rel(outs[1].lam, outs[0].lam, P.sigma0)
+    print("[c5] per-eigenpair mixed vs FP64: max %.2e median %.2e" % (d.max(), np.median(d)), flush=True)
     assert d.max() < 1e-10
