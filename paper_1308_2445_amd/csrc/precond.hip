@@ -32,6 +32,8 @@ namespace {
 
 constexpr int TR = 64;   // output rows per work-group
 constexpr int TC = 16;   // right-hand sides per work-group
+constexpr int TCW = 64;  // the same for wide blocks (at least kWideCols columns)
+constexpr int kWideCols = 128;
 constexpr int KS = 64;   // reduction chunk per work-group (one LDS stage)
 
 enum { OP_DIAG = 0, OP_OFFD = 2, OP_OFFD_T = 3 };
@@ -41,30 +43,30 @@ enum { OP_DIAG = 0, OP_OFFD = 2, OP_OFFD_T = 3 };
 //  OP_DIAG   out[D[r]] += sum_k G[r,k] in[D[k]]
 //  OP_OFFD   out[B[r]] -= sum_k F[r,k] in[D[k]]
 //  OP_OFFD_T out[D[r]] -= sum_k F[k,r] in[B[k]]
-template <typename T>
+template <typename T, int NC = TC>
 struct SnTiles {
     T M[KS][TR + 1];   // M[k][r] = M(r0 + r, kb + k)
-    T X[KS][TC + 1];   // X[k][c] = in[row(kb + k), c0 + c]
+    T X[KS][NC + 1];   // X[k][c] = in[row(kb + k), c0 + c]
 };
 
 struct NoWait {
     __device__ void operator()() const {}
 };
 
-// One task on right-hand sides c0 .. c0 + 15 (in and out may be the same block).  Every
-// thread of the work-group calls it.  The panel tile and the row indices are requested
+// One task on right-hand sides c0 .. c0 + NC - 1 (in and out may be the same block).
+// Every thread of the work-group calls it.  The panel tile and the row indices are requested
 // first; wait() (called by every thread) runs while they are in flight, and only then
 // are the right-hand-side rows read.  CO: those rows are read with device-scope
 // (coherent) loads, for rows other work-groups of the same launch have updated.
-template <typename T, int OP, bool CO = false, typename Wait = NoWait>
+template <typename T, int OP, bool CO = false, typename Wait = NoWait, int NC = TC>
 __device__ __forceinline__ void sn_task(const SnTask& tk, const int32_t* __restrict__ rows,
                                         const T* __restrict__ panels, const T* in, T* out, int nrhs,
-                                        int c0, SnTiles<T>& st, Wait wait = Wait{}) {
+                                        int c0, SnTiles<T, NC>& st, Wait wait = Wait{}) {
     const int ncol = tk.ncol, nrow = tk.nrow;
     const int nb = nrow - ncol;
     const int32_t* rl = rows + tk.idx_off;
     const T* P = panels + tk.val_off;   // nrow x ncol, ld nrow
-    const int nc = min(TC, nrhs - c0);
+    const int nc = min(NC, nrhs - c0);
 
     // output and reduction extents
     int nout, nred;
@@ -100,18 +102,18 @@ __device__ __forceinline__ void sn_task(const SnTask& tk, const int32_t* __restr
         mv[i] = v;
     }
     // gathered right-hand sides: 16 consecutive lanes read the 16 values of one row
-    int gi[KS * TC / 256];
+    int gi[KS * NC / 256];
 #pragma unroll
-    for (int i = 0; i < KS * TC / 256; ++i) {
+    for (int i = 0; i < KS * NC / 256; ++i) {
         const int e = t + 256 * i;
-        const int c = e % TC, k = kb + e / TC;
+        const int c = e % NC, k = kb + e / NC;
         gi[i] = (k < k_end && c < nc) ? ((OP == OP_OFFD_T) ? rl[ncol + k] : rl[k]) : -1;
     }
     wait();
-    T xv[KS * TC / 256];
+    T xv[KS * NC / 256];
 #pragma unroll
-    for (int i = 0; i < KS * TC / 256; ++i) {
-        const int c = (t + 256 * i) % TC;
+    for (int i = 0; i < KS * NC / 256; ++i) {
+        const int c = (t + 256 * i) % NC;
         T v = T(0);
         if (gi[i] >= 0) {
             const T* src = in + (int64_t)gi[i] * nrhs + c0 + c;
@@ -127,26 +129,30 @@ __device__ __forceinline__ void sn_task(const SnTask& tk, const int32_t* __restr
         else sM[e % KS][e / KS] = mv[i];
     }
 #pragma unroll
-    for (int i = 0; i < KS * TC / 256; ++i) {
+    for (int i = 0; i < KS * NC / 256; ++i) {
         const int e = t + 256 * i;
-        sX[e / TC][e % TC] = xv[i];
+        sX[e / NC][e % NC] = xv[i];
     }
     __syncthreads();
-    // the 64 x 16 output tile is four 16 x 16 matrix-core tiles, one per wavefront (rows
-    // 16 w .. 16 w + 15); operands: A lane l = M(16 w + l % 16, k0 + l / 16), B lane l =
-    // X(k0 + l / 16, l % 16); staged zeros cover the chunk beyond k_end
+    // the 64 x NC output tile: wavefront w takes rows 16 w .. 16 w + 15, one 16 x 16
+    // matrix-core tile per 16 columns; operands: A lane l = M(16 w + l % 16, k0 + l / 16),
+    // B lane l = X(k0 + l / 16, 16 j + l % 16); staged zeros cover the chunk beyond k_end
     const int lane = t & 63, wave = t >> 6;
     const int kn = k_end - kb;
+    constexpr int NJ = NC / 16;
     typedef T acc_t __attribute__((ext_vector_type(4)));
-    acc_t acc = {T(0), T(0), T(0), T(0)};
+    acc_t acc[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = acc_t{T(0), T(0), T(0), T(0)};
     for (int k0 = 0; k0 < kn; k0 += 4) {
         const T a = sM[k0 + (lane >> 4)][16 * wave + (lane & 15)];
-        const T b = sX[k0 + (lane >> 4)][lane & 15];
-        if constexpr (sizeof(T) == 8) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        else acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const T b = sX[k0 + (lane >> 4)][16 * j + (lane & 15)];
+            if constexpr (sizeof(T) == 8) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+            else acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+        }
     }
-    const int c = lane & 15;
-    if (c >= nc) return;
     const bool sub = (OP == OP_OFFD || OP == OP_OFFD_T);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -156,7 +162,11 @@ __device__ __forceinline__ void sn_task(const SnTask& tk, const int32_t* __restr
         const int r = r0 + 16 * wave + rt;
         if (r < nout) {
             const int64_t g = (OP == OP_OFFD) ? rl[ncol + r] : rl[r];
-            atomicAdd(&out[g * nrhs + c0 + c], sub ? -acc[q] : acc[q]);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int c = 16 * j + (lane & 15);
+                if (c < nc) atomicAdd(&out[g * nrhs + c0 + c], sub ? -acc[j][q] : acc[j][q]);
+            }
         }
     }
 }
@@ -186,12 +196,12 @@ constexpr int kSweepSpinLimit = 1 << 20;
 // atomic; the last forward task of a supernode counts the supernode off at its parent;
 // a waiting task polls its counter and reads right-hand-side rows with device-scope
 // loads.  (Device-scope fences would write back or invalidate a whole L2 per task.)
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_sn_sweep(const SweepTask* __restrict__ tasks, int64_t ntasks,
                                                   const int32_t* __restrict__ rows,
                                                   const T* __restrict__ panels, T* Y, T* W2, int nrhs,
                                                   int32_t* cnt, int nsn, int groups) {
-    __shared__ SnTiles<T> st;
+    __shared__ SnTiles<T, NC> st;
     const int64_t b = blockIdx.x;
     const int64_t ti = b / groups;
     const int cg = (int)(b - ti * groups);
@@ -217,10 +227,10 @@ __global__ __launch_bounds__(256) void k_sn_sweep(const SweepTask* __restrict__ 
         }
         __syncthreads();
     };
-    const int c0 = cg * TC;
-    if (tk.op == OP_OFFD) sn_task<T, OP_OFFD, true>(tk.t, rows, panels, Y, Y, nrhs, c0, st, wait);
-    else if (tk.op == OP_DIAG) sn_task<T, OP_DIAG, true>(tk.t, rows, panels, Y, W2, nrhs, c0, st, wait);
-    else sn_task<T, OP_OFFD_T, true>(tk.t, rows, panels, W2, W2, nrhs, c0, st, wait);
+    const int c0 = cg * NC;
+    if (tk.op == OP_OFFD) sn_task<T, OP_OFFD, true, decltype(wait), NC>(tk.t, rows, panels, Y, Y, nrhs, c0, st, wait);
+    else if (tk.op == OP_DIAG) sn_task<T, OP_DIAG, true, decltype(wait), NC>(tk.t, rows, panels, Y, W2, nrhs, c0, st, wait);
+    else sn_task<T, OP_OFFD_T, true, decltype(wait), NC>(tk.t, rows, panels, W2, W2, nrhs, c0, st, wait);
     // every wavefront's atomic adds have completed (s_waitcnt vmcnt(0)) before the barrier
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
@@ -285,7 +295,11 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
     if constexpr (sizeof(T) == 8) panels = F.panels64.p;
     else panels = F.panels32.p;
     if (F.use_sweep && F.sweep.n > 0 && ncols > 0) {
-        const int groups = (ncols + TC - 1) / TC;
+        // wide blocks: 64 right-hand sides per task, so each panel chunk is read a quarter
+        // as often
+        const bool wide = ncols >= kWideCols;
+        const int nc = wide ? TCW : TC;
+        const int groups = (ncols + nc - 1) / nc;
         const int64_t ninit = 3 * (int64_t)F.nsn;
         const size_t need = 4 + (size_t)ninit * groups;
         if (F.sweep_cnt.n < need) {
@@ -297,8 +311,12 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
         hipLaunchKernelGGL((k_sweep_init<T>), dim3((unsigned)blocks), dim3(256), 0, s, count, W2,
                            F.sweep_init.p, ninit, F.sweep_cnt.p, groups);
         const int64_t ntasks = (int64_t)F.sweep.n;
-        hipLaunchKernelGGL((k_sn_sweep<T>), dim3((unsigned)(ntasks * groups)), dim3(256), 0, s, F.sweep.p,
-                           ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn, groups);
+        if (wide)
+            hipLaunchKernelGGL((k_sn_sweep<T, TCW>), dim3((unsigned)(ntasks * groups)), dim3(256), 0, s,
+                               F.sweep.p, ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn, groups);
+        else
+            hipLaunchKernelGGL((k_sn_sweep<T, TC>), dim3((unsigned)(ntasks * groups)), dim3(256), 0, s,
+                               F.sweep.p, ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn, groups);
         LABPSD_HIP(hipGetLastError());
         return;
     }

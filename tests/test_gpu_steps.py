@@ -114,12 +114,13 @@ def test_residual(prob, ctx):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_global_precond_apply(prob, precision):
+@pytest.mark.parametrize("p", [21, 150])
+def test_global_precond_apply(prob, precision, p):
+    """p = 150 takes the wide tasks (64 right-hand sides each, the last group ragged)."""
     P, pr = prob
     import paper_1308_2445_amd as lp
     torch = _torch()
     rng = np.random.default_rng(14)
-    p = 21
     R = rng.standard_normal((P.n, p))
     Pd = torch.empty((p, P.n), dtype=torch.float64, device="cuda")
     lp.labpsd_precond_apply(pr, precision, dev(R), Pd)
