@@ -179,6 +179,39 @@ def test_local_refine(prob, precision):
     assert np.array_equal(got[:, others], P0[:, others]) if precision == 0 else True
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_local_refine_wide(prob, precision):
+    """130 localised columns at once (33 four-column chunks per product, the last ragged)."""
+    P, pr = prob
+    import paper_1308_2445_amd as lp
+    torch = _torch()
+    H, S = P.H(), P.S()
+    rng = np.random.default_rng(19)
+    q = 130
+    R = rng.standard_normal((P.n, q))
+    K = oprec.GlobalPreconditioner(H, S, P.eps_bar)
+    P0 = K.apply(R)
+    cols = np.arange(q, dtype=np.int32)
+    shifts = P.eps_bar + np.abs(P.eps_bar) * rng.uniform(0.1, 0.6, q)
+    eta, cap = 0.25, 20
+    Pd = dev(P0)
+    its = torch.zeros(q, dtype=torch.int32, device="cuda")
+    lp.labpsd_local_refine(pr, precision, dev(R), Pd, torch.from_numpy(cols).cuda(),
+                           torch.from_numpy(shifts).cuda(), eta, cap, its)
+    torch.cuda.synchronize()
+    got = host(Pd)
+    itg = its.cpu().numpy()
+    for c in range(0, q, 13):
+        pref, itref = olab.local_refine(H, S, P0[:, c], R[:, c], float(shifts[c]), eta, cap)
+        if precision == 0:
+            assert int(itg[c]) == itref
+            assert np.linalg.norm(got[:, c] - pref) <= 1e-9 * np.linalg.norm(pref)
+        else:
+            a = H @ got[:, c] - shifts[c] * (S @ got[:, c]) + R[:, c]
+            assert abs(int(itg[c]) - itref) <= 2
+            assert np.linalg.norm(a) <= 1.5 * eta * np.linalg.norm(R[:, c]) or int(itg[c]) == cap
+
+
 def test_gram(prob, ctx):
     P, pr = prob
     import paper_1308_2445_amd as lp
