@@ -139,7 +139,8 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
     // tasks: 64-row output tiles x 64-wide reduction chunks; per level the off-diagonal
     // products (op 1: r_B -= F r_D, op 2: x_D -= F^T x_B), then one list of the diagonal
     // products x_D = G r_D of every supernode
-    constexpr int kTile = 64, kChunk = 64;
+    constexpr int kTile = 64;
+    int kChunk = 64;
     std::vector<SnTask> tk;
     F->lev_off.assign(4 * (size_t)F->nlevels, 0);
     F->lev_count.assign(4 * (size_t)F->nlevels, 0);
@@ -165,9 +166,11 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
     // the single-launch sweep: forward tasks by level from the leaves, the diagonal
     // tasks by level, backward tasks by level from the roots (every dependency earlier
     // in the list); counters (children, forward tasks, diagonal + backward tasks)
-    std::vector<int32_t> init(3 * (size_t)F->nsn, 0);
-    std::vector<SweepTask> sw;
-    {
+    std::vector<int32_t> init, init_deep;
+    std::vector<SweepTask> sw, sw_deep;
+    auto build_sweep = [&](int chunk, std::vector<SweepTask>& sw, std::vector<int32_t>& init) {
+        kChunk = chunk;
+        init.assign(3 * (size_t)F->nsn, 0);
         const int nsn = F->nsn;
         bool tree_ok = true;
         for (int i = 0; i < nsn; ++i) {
@@ -199,13 +202,19 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
         for (int l = F->nlevels - 1; l >= 0; --l)
             for (int i = 0; i < nsn; ++i)
                 if (H.sn[i].level == l) add_sweep(i, 2, 3);
-        F->use_sweep = tree_ok && !sw.empty();
-    }
+        return tree_ok && !sw.empty();
+    };
+    // the single-launch sweep twice: 64-deep reductions per task, and kDeepChunk-deep ones
+    // for wide right-hand-side blocks (fewer tasks per supernode, same order)
+    F->use_sweep = build_sweep(kDeepChunk, sw_deep, init_deep) && build_sweep(64, sw, init);
+    kChunk = 64;
     // host vectors stay alive until the copies have finished
     F->tasks.upload(tk.data(), tk.size(), s);
     if (F->use_sweep) {
         F->sweep.upload(sw.data(), sw.size(), s);
         F->sweep_init.upload(init.data(), init.size(), s);
+        F->sweep_deep.upload(sw_deep.data(), sw_deep.size(), s);
+        F->sweep_init_deep.upload(init_deep.data(), init_deep.size(), s);
     }
     LABPSD_HIP(hipStreamSynchronize(s));
     F->info.n_supernodes = F->nsn;

@@ -259,6 +259,9 @@ struct Sell {
 // One work-group task of the supernodal apply: a 64-row output tile of one supernode's
 // product and one 64-wide chunk of its reduction dimension, with the supernode's
 // metadata folded in so a work-group needs a single (scalar) load to start.
+// reduction depth of a task in the sweep over wide right-hand-side blocks
+constexpr int kDeepChunk = 256;
+
 struct SnTask {
     int64_t idx_off;   // offset of the supernode's row list in DevFactor::rows
     int64_t val_off;   // offset of its panel [G ; F] (ld nrow)
@@ -302,6 +305,8 @@ struct DevFactor {
     // group of 16 right-hand sides.
     DBuf<SweepTask> sweep;
     DBuf<int32_t> sweep_init;            // 3 nsn
+    DBuf<SweepTask> sweep_deep;          // the same sweep with kDeepChunk-deep reductions
+    DBuf<int32_t> sweep_init_deep;
     mutable DBuf<int32_t> sweep_cnt;     // 4 + 3 nsn groups
     bool use_sweep = true;
     labpsd_factor_info info{};

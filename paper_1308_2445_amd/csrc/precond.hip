@@ -34,6 +34,7 @@ constexpr int TR = 64;   // output rows per work-group
 constexpr int TC = 16;   // right-hand sides per work-group
 constexpr int TCW = 64;  // the same for wide blocks (at least kWideCols columns)
 constexpr int kWideCols = 128;
+static_assert(kDeepChunk % 64 == 0, "deep tasks stage 64 reduction indices at a time");
 constexpr int KS = 64;   // reduction chunk per work-group (one LDS stage)
 
 enum { OP_DIAG = 0, OP_OFFD = 2, OP_OFFD_T = 3 };
@@ -58,7 +59,7 @@ struct NoWait {
 // first; wait() (called by every thread) runs while they are in flight, and only then
 // are the right-hand-side rows read.  CO: those rows are read with device-scope
 // (coherent) loads, for rows other work-groups of the same launch have updated.
-template <typename T, int OP, bool CO = false, typename Wait = NoWait, int NC = TC>
+template <typename T, int OP, bool CO = false, typename Wait = NoWait, int NC = TC, int KD = KS>
 __device__ __forceinline__ void sn_task(const SnTask& tk, const int32_t* __restrict__ rows,
                                         const T* __restrict__ panels, const T* in, T* out, int nrhs,
                                         int c0, SnTiles<T, NC>& st, Wait wait = Wait{}) {
@@ -74,83 +75,87 @@ __device__ __forceinline__ void sn_task(const SnTask& tk, const int32_t* __restr
     else if (OP == OP_OFFD_T) { nout = ncol; nred = nb; }
     else { nout = ncol; nred = ncol; }
     const int r0 = tk.r0;
-    const int kb = tk.k0;
-    // reduction range of the chunk
-    const int k_end = min(nred, kb + KS);
+    // the task's reduction range, staged KS at a time
+    const int kb0 = tk.k0;
+    const int k_all = min(nred, kb0 + KD);
 
     auto& sM = st.M;
     auto& sX = st.X;
     const int t = threadIdx.x;
-    // stage M(r, k) for r in [r0, r0+TR), k in [kb, kb+KS); every load issued before any use
-    T mv[TR * KS / 256];
-#pragma unroll
-    for (int i = 0; i < TR * KS / 256; ++i) {
-        const int e = t + 256 * i;
-        T v = T(0);
-        if (OP != OP_OFFD_T) {
-            // column-major panel: consecutive threads walk rows (contiguous)
-            const int r = r0 + (e % TR), k = kb + e / TR;
-            if (r < nout && k < k_end) {
-                const int prow = (OP == OP_OFFD) ? ncol + r : r;
-                v = P[prow + (int64_t)k * nrow];
-            }
-        } else {
-            // transposed: M(r, k) = F(k, r); consecutive threads walk k
-            const int k = kb + (e % KS), r = r0 + e / KS;
-            if (r < nout && k < k_end) v = P[(ncol + k) + (int64_t)r * nrow];
-        }
-        mv[i] = v;
-    }
-    // gathered right-hand sides: 16 consecutive lanes read the 16 values of one row
-    int gi[KS * NC / 256];
-#pragma unroll
-    for (int i = 0; i < KS * NC / 256; ++i) {
-        const int e = t + 256 * i;
-        const int c = e % NC, k = kb + e / NC;
-        gi[i] = (k < k_end && c < nc) ? ((OP == OP_OFFD_T) ? rl[ncol + k] : rl[k]) : -1;
-    }
-    wait();
-    T xv[KS * NC / 256];
-#pragma unroll
-    for (int i = 0; i < KS * NC / 256; ++i) {
-        const int c = (t + 256 * i) % NC;
-        T v = T(0);
-        if (gi[i] >= 0) {
-            const T* src = in + (int64_t)gi[i] * nrhs + c0 + c;
-            if constexpr (CO) v = __hip_atomic_load(const_cast<T*>(src), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else v = *src;
-        }
-        xv[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < TR * KS / 256; ++i) {
-        const int e = t + 256 * i;
-        if (OP != OP_OFFD_T) sM[e / TR][e % TR] = mv[i];
-        else sM[e % KS][e / KS] = mv[i];
-    }
-#pragma unroll
-    for (int i = 0; i < KS * NC / 256; ++i) {
-        const int e = t + 256 * i;
-        sX[e / NC][e % NC] = xv[i];
-    }
-    __syncthreads();
-    // the 64 x NC output tile: wavefront w takes rows 16 w .. 16 w + 15, one 16 x 16
-    // matrix-core tile per 16 columns; operands: A lane l = M(16 w + l % 16, k0 + l / 16),
-    // B lane l = X(k0 + l / 16, 16 j + l % 16); staged zeros cover the chunk beyond k_end
     const int lane = t & 63, wave = t >> 6;
-    const int kn = k_end - kb;
     constexpr int NJ = NC / 16;
     typedef T acc_t __attribute__((ext_vector_type(4)));
     acc_t acc[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[j] = acc_t{T(0), T(0), T(0), T(0)};
-    for (int k0 = 0; k0 < kn; k0 += 4) {
-        const T a = sM[k0 + (lane >> 4)][16 * wave + (lane & 15)];
+    for (int kb = kb0; kb < k_all; kb += KS) {
+        const int k_end = min(k_all, kb + KS);
+        // stage M(r, k) for r in [r0, r0+TR), k in [kb, kb+KS); every load issued before any use
+        T mv[TR * KS / 256];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const T b = sX[k0 + (lane >> 4)][16 * j + (lane & 15)];
-            if constexpr (sizeof(T) == 8) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
-            else acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+        for (int i = 0; i < TR * KS / 256; ++i) {
+            const int e = t + 256 * i;
+            T v = T(0);
+            if (OP != OP_OFFD_T) {
+                // column-major panel: consecutive threads walk rows (contiguous)
+                const int r = r0 + (e % TR), k = kb + e / TR;
+                if (r < nout && k < k_end) {
+                    const int prow = (OP == OP_OFFD) ? ncol + r : r;
+                    v = P[prow + (int64_t)k * nrow];
+                }
+            } else {
+                // transposed: M(r, k) = F(k, r); consecutive threads walk k
+                const int k = kb + (e % KS), r = r0 + e / KS;
+                if (r < nout && k < k_end) v = P[(ncol + k) + (int64_t)r * nrow];
+            }
+            mv[i] = v;
+        }
+        // gathered right-hand sides: 16 consecutive lanes read 16 values of one row
+        int gi[KS * NC / 256];
+#pragma unroll
+        for (int i = 0; i < KS * NC / 256; ++i) {
+            const int e = t + 256 * i;
+            const int c = e % NC, k = kb + e / NC;
+            gi[i] = (k < k_end && c < nc) ? ((OP == OP_OFFD_T) ? rl[ncol + k] : rl[k]) : -1;
+        }
+        if (kb == kb0) wait();   // the dependencies, once per task (uniform)
+        T xv[KS * NC / 256];
+#pragma unroll
+        for (int i = 0; i < KS * NC / 256; ++i) {
+            const int c = (t + 256 * i) % NC;
+            T v = T(0);
+            if (gi[i] >= 0) {
+                const T* src = in + (int64_t)gi[i] * nrhs + c0 + c;
+                if constexpr (CO) v = __hip_atomic_load(const_cast<T*>(src), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else v = *src;
+            }
+            xv[i] = v;
+        }
+        if (kb != kb0) __syncthreads();   // the previous stage's products have read the tiles
+#pragma unroll
+        for (int i = 0; i < TR * KS / 256; ++i) {
+            const int e = t + 256 * i;
+            if (OP != OP_OFFD_T) sM[e / TR][e % TR] = mv[i];
+            else sM[e % KS][e / KS] = mv[i];
+        }
+#pragma unroll
+        for (int i = 0; i < KS * NC / 256; ++i) {
+            const int e = t + 256 * i;
+            sX[e / NC][e % NC] = xv[i];
+        }
+        __syncthreads();
+        // the 64 x NC output tile: wavefront w takes rows 16 w .. 16 w + 15, one 16 x 16
+        // matrix-core tile per 16 columns; operands: A lane l = M(16 w + l % 16, k0 + l / 16),
+        // B lane l = X(k0 + l / 16, 16 j + l % 16); staged zeros cover the chunk beyond k_end
+        const int kn = k_end - kb;
+        for (int k0 = 0; k0 < kn; k0 += 4) {
+            const T a = sM[k0 + (lane >> 4)][16 * wave + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const T b = sX[k0 + (lane >> 4)][16 * j + (lane & 15)];
+                if constexpr (sizeof(T) == 8) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+                else acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+            }
         }
     }
     const bool sub = (OP == OP_OFFD || OP == OP_OFFD_T);
@@ -196,7 +201,7 @@ constexpr int kSweepSpinLimit = 1 << 20;
 // atomic; the last forward task of a supernode counts the supernode off at its parent;
 // a waiting task polls its counter and reads right-hand-side rows with device-scope
 // loads.  (Device-scope fences would write back or invalidate a whole L2 per task.)
-template <typename T, int NC>
+template <typename T, int NC, int KD>
 __global__ __launch_bounds__(256) void k_sn_sweep(const SweepTask* __restrict__ tasks, int64_t ntasks,
                                                   const int32_t* __restrict__ rows,
                                                   const T* __restrict__ panels, T* Y, T* W2, int nrhs,
@@ -228,9 +233,12 @@ __global__ __launch_bounds__(256) void k_sn_sweep(const SweepTask* __restrict__ 
         __syncthreads();
     };
     const int c0 = cg * NC;
-    if (tk.op == OP_OFFD) sn_task<T, OP_OFFD, true, decltype(wait), NC>(tk.t, rows, panels, Y, Y, nrhs, c0, st, wait);
-    else if (tk.op == OP_DIAG) sn_task<T, OP_DIAG, true, decltype(wait), NC>(tk.t, rows, panels, Y, W2, nrhs, c0, st, wait);
-    else sn_task<T, OP_OFFD_T, true, decltype(wait), NC>(tk.t, rows, panels, W2, W2, nrhs, c0, st, wait);
+    if (tk.op == OP_OFFD)
+        sn_task<T, OP_OFFD, true, decltype(wait), NC, KD>(tk.t, rows, panels, Y, Y, nrhs, c0, st, wait);
+    else if (tk.op == OP_DIAG)
+        sn_task<T, OP_DIAG, true, decltype(wait), NC, KD>(tk.t, rows, panels, Y, W2, nrhs, c0, st, wait);
+    else
+        sn_task<T, OP_OFFD_T, true, decltype(wait), NC, KD>(tk.t, rows, panels, W2, W2, nrhs, c0, st, wait);
     // every wavefront's atomic adds have completed (s_waitcnt vmcnt(0)) before the barrier
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
@@ -295,9 +303,10 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
     if constexpr (sizeof(T) == 8) panels = F.panels64.p;
     else panels = F.panels32.p;
     if (F.use_sweep && F.sweep.n > 0 && ncols > 0) {
-        // wide blocks: 64 right-hand sides per task, so each panel chunk is read a quarter
-        // as often
-        const bool wide = ncols >= kWideCols;
+        // wide blocks: 64 right-hand sides and a 256-deep reduction per task (the second
+        // task list), so each panel chunk is read a quarter as often and each output tile
+        // takes a quarter of the atomic adds
+        const bool wide = ncols >= kWideCols && F.sweep_deep.n > 0;
         const int nc = wide ? TCW : TC;
         const int groups = (ncols + nc - 1) / nc;
         const int64_t ninit = 3 * (int64_t)F.nsn;
@@ -309,13 +318,14 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
         const int64_t count = n * ncols;
         const int64_t blocks = std::min<int64_t>((std::max<int64_t>(count, ninit * groups) + 255) / 256, 2048);
         hipLaunchKernelGGL((k_sweep_init<T>), dim3((unsigned)blocks), dim3(256), 0, s, count, W2,
-                           F.sweep_init.p, ninit, F.sweep_cnt.p, groups);
-        const int64_t ntasks = (int64_t)F.sweep.n;
+                           wide ? F.sweep_init_deep.p : F.sweep_init.p, ninit, F.sweep_cnt.p, groups);
+        const int64_t ntasks = (int64_t)(wide ? F.sweep_deep.n : F.sweep.n);
         if (wide)
-            hipLaunchKernelGGL((k_sn_sweep<T, TCW>), dim3((unsigned)(ntasks * groups)), dim3(256), 0, s,
-                               F.sweep.p, ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn, groups);
+            hipLaunchKernelGGL((k_sn_sweep<T, TCW, kDeepChunk>), dim3((unsigned)(ntasks * groups)), dim3(256), 0,
+                               s, F.sweep_deep.p, ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn,
+                               groups);
         else
-            hipLaunchKernelGGL((k_sn_sweep<T, TC>), dim3((unsigned)(ntasks * groups)), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_sn_sweep<T, TC, KS>), dim3((unsigned)(ntasks * groups)), dim3(256), 0, s,
                                F.sweep.p, ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn, groups);
         LABPSD_HIP(hipGetLastError());
         return;
