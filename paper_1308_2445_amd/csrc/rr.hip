@@ -1250,10 +1250,10 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
 //             slice ((row, j) at row 16 + j) so the MFMA operands load contiguously;
 //   sym       C <- (C + C^T) / 2, column-major;
 //   tridiag   Householder reduction of C (order k) on G co-resident work-groups, column
-//             c owned by work-group c mod G, two grid barriers per reflector (after the
-//             products p = tau C v, after the rank-2 update, whose owner of the next
-//             column builds the next reflector); vectors shared between work-groups are
-//             written and read with device-scope atomics;
+//             c owned by work-group c mod G, one grid barrier per reflector (after the
+//             products p = tau C v; every work-group then updates its columns and builds
+//             the next reflector itself from the published next column); vectors shared
+//             between work-groups are written and read with device-scope atomics;
 //   teig      eigenvalues by multisection and eigenvectors by inverse iteration (one
 //             work-group, as in the one-work-group kernel);
 //   back      per 16-column slice of Z: X = Q Z (reflectors in reverse order), then
@@ -1290,9 +1290,9 @@ __host__ __device__ inline RRLLayout rrl_layout(int k, int nwp) {
     L.theta = L.tau + kp;
     L.sh = L.theta + kp;
     L.vb = L.sh + kp;          // 2 kp
-    L.p = L.vb + 2 * kp;
-    L.part = L.p + kp;         // 256
-    L.sc = L.part + 256;       // 8
+    L.p = L.vb + 2 * kp;       // 2 kp
+    L.part = L.p + 2 * kp;     // 2 x 256
+    L.sc = L.part + 512;       // 8
     L.icl = L.sc + 8;          // 2 kp + 4 int32
     L.Zt = L.icl + kp + 2;
     L.U3 = L.Zt + (int64_t)k * nwp;
@@ -1495,7 +1495,15 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_sym(int k, double* __restrict
 
 // Householder tridiagonalisation of C (column-major, ld kp, order k) on gridDim.x
 // co-resident work-groups: d, e, tau; reflector j = I - tau_j v v^T with v_{j+1} = 1 and
-// v_i (i > j + 1) kept in C[i, j].  Dynamic LDS: 2 kp doubles.
+// v_i (i > j + 1) kept in C[i, j].  Column c belongs to work-group c mod G.  One grid
+// barrier per reflector: before it, every work-group forms its part of p = tau C v and
+// of p . v, and the owner of column j + 1 publishes that column; after it, every
+// work-group applies the rank-2 update to its own columns and, redundantly and with the
+// same arithmetic, to the published column, from which it builds the next reflector
+// itself.  Vectors shared between work-groups (p, the partial sums, the published
+// column; double-buffered by parity, so a work-group running one step ahead never
+// overwrites what another still reads) go through device-scope atomics.
+// Dynamic LDS: 4 kp doubles.
 __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __restrict__ base) {
     if (rrl_failed(base)) return;
     const RRLLayout Lo = rrl_layout(k, 1);
@@ -1506,13 +1514,15 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
     double* d = base + Lo.d;
     double* e = base + Lo.e;
     double* tau = base + Lo.tau;
-    double* vb = base + Lo.vb;
-    double* pg = base + Lo.p;
-    double* part = base + Lo.part;
+    double* colb = base + Lo.vb;     // 2 kp: the published column, by parity
+    double* pg = base + Lo.p;        // 2 kp: p, by parity
+    double* part = base + Lo.part;   // 2 x 256: the work-groups' parts of p . v, by parity
     extern __shared__ double sm[];
-    double* sv = sm;
-    double* sp = sm + kp;
-    __shared__ double red[4];
+    double* sv = sm;                 // v_j
+    double* svn = sm + kp;           // v_{j+1}
+    double* sp = sm + 2 * kp;        // p_j
+    double* sy = sm + 3 * kp;        // the published column, updated
+    __shared__ double red[2][4];
     __shared__ int sok;
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int nbar = 0;
@@ -1542,29 +1552,33 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
         __syncthreads();
         return sok != 0;
     };
-    // reflector of column c from its rows c + 1.. (one wavefront, after the column's
-    // last update): v to the shared buffer of parity c and into C, tau, d[c], e[c]
-    auto reflect = [&](int c) {
-        double* col = C + (int64_t)c * kp;
+    // reflector of column c from y (LDS, rows c + 1.., final): v into vn, tau, beta; the
+    // same result in every work-group (same data, same reduction order); keep: also store
+    // v below the subdiagonal of C's column c.  The caller syncs before vn is read.
+    auto make_reflector = [&](const double* y, int c, double* vn, double& t, double& beta, bool keep) {
         double sg = 0.0, a1 = 0.0;
-        for (int i = c + 1 + lane; i < k; i += 64) {
-            const double x = col[i];
+        for (int i = c + 1 + tid; i < k; i += kLThreads) {
+            const double x = y[i];
             if (i == c + 1) a1 = x;
             else sg = fma(x, x, sg);
         }
-        const double sigma = wave_allsum(sg), alpha = wave_allsum(a1);
-        double t, beta, scal;
-        reflector(alpha, sigma, t, beta, scal);
-        double* vn = vb + (c & 1) * kp;
-        for (int i = c + 1 + lane; i < k; i += 64) {
-            const double vi = (i == c + 1) ? 1.0 : col[i] * scal;
-            if (i > c + 1) col[i] = vi;
-            __hip_atomic_store(vn + i, vi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        sg = wave_allsum(sg);
+        a1 = wave_allsum(a1);
         if (lane == 0) {
-            d[c] = col[c];
-            e[c] = beta;
-            __hip_atomic_store(tau + c, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            red[0][wave] = sg;
+            red[1][wave] = a1;
+        }
+        __syncthreads();
+        const double sigma = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        const double alpha = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        __syncthreads();
+        double scal;
+        reflector(alpha, sigma, t, beta, scal);
+        double* col = C + (int64_t)c * kp;
+        for (int i = c + 1 + tid; i < k; i += kLThreads) {
+            const double vi = (i == c + 1) ? 1.0 : y[i] * scal;
+            vn[i] = vi;
+            if (keep && i > c + 1) col[i] = vi;
         }
     };
     // the first column >= cmin owned by this wavefront (columns g + t G, t = wave mod 4)
@@ -1573,14 +1587,28 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
         t += ((wave - t) % 4 + 4) % 4;
         return g + t * G;
     };
-    if (g == 0 && wave == 0) reflect(0);
-    if (!gsync()) return;
+    // reflector 0 from column 0, in every work-group
+    for (int i = tid; i < k; i += kLThreads) sy[i] = C[i];
+    __syncthreads();
+    double tj, beta0;
+    make_reflector(sy, 0, sv, tj, beta0, g == 0);
+    if (g == 0 && tid == 0) {
+        d[0] = sy[0];
+        e[0] = beta0;
+        tau[0] = tj;
+    }
+    __syncthreads();
     for (int j = 0; j + 2 < k; ++j) {
-        const double* vsh = vb + (j & 1) * kp;
-        for (int i = j + 1 + tid; i < k; i += kLThreads)
-            sv[i] = __hip_atomic_load(vsh + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double tj = __hip_atomic_load(tau + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
+        const int par = j & 1;
+        double* pgj = pg + par * kp;
+        double* partj = part + par * 256;
+        double* cbj = colb + ((j + 1) & 1) * kp;
+        // the owner of column j + 1 publishes it (its updates up to reflector j - 1 are in)
+        if (g == (j + 1) % G) {
+            const double* col = C + (int64_t)(j + 1) * kp;
+            for (int i = j + 1 + tid; i < k; i += kLThreads)
+                __hip_atomic_store(cbj + i, col[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         // p_c = tau (C v)_c for the owned columns, and this work-group's part of p . v
         double mp = 0.0;
         for (int c = first_own(j + 1); c < k; c += 4 * G) {
@@ -1588,40 +1616,60 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
             double dot = 0.0;
             for (int i = j + 1 + lane; i < k; i += 64) dot = fma(col[i], sv[i], dot);
             dot = tj * wave_allsum(dot);
-            if (lane == 0) __hip_atomic_store(pg + c, dot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0) __hip_atomic_store(pgj + c, dot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             mp = fma(dot, sv[c], mp);
         }
-        if (lane == 0) red[wave] = mp;
+        if (lane == 0) red[0][wave] = mp;
         __syncthreads();
         if (tid == 0)
-            __hip_atomic_store(part + g, red[0] + red[1] + red[2] + red[3], __ATOMIC_RELAXED,
+            __hip_atomic_store(partj + g, red[0][0] + red[0][1] + red[0][2] + red[0][3], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         if (!gsync()) return;
         // C <- C - v w^T - w v^T with w = p - K v, K = tau (p . v) / 2
-        for (int i = j + 1 + tid; i < k; i += kLThreads)
-            sp[i] = __hip_atomic_load(pg + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int i = j + 1 + tid; i < k; i += kLThreads) {
+            sp[i] = __hip_atomic_load(pgj + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sy[i] = __hip_atomic_load(cbj + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         double ps = 0.0;
-        for (int q = lane; q < G; q += 64) ps += __hip_atomic_load(part + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int q = lane; q < G; q += 64) ps += __hip_atomic_load(partj + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double K = 0.5 * tj * wave_allsum(ps);
         __syncthreads();
-        for (int c = first_own(j + 1); c < k; c += 4 * G) {
+        for (int c = first_own(j + 2); c < k; c += 4 * G) {
             double* col = C + (int64_t)c * kp;
             const double vc = sv[c], wc = sp[c] - K * vc;
             for (int i = j + 1 + lane; i < k; i += 64) {
                 const double vi = sv[i];
                 col[i] -= vi * wc + (sp[i] - K * vi) * vc;
             }
-            if (c == j + 1) {
-                if (j + 3 < k) {
-                    reflect(j + 1);
-                } else if (lane == 0) {   // j + 1 = k - 2: the last off-diagonal
-                    d[k - 2] = col[k - 2];
-                    e[k - 2] = col[k - 1];
-                }
-            }
             if (c == k - 1 && j + 3 == k && lane == 0) d[k - 1] = col[k - 1];
         }
-        if (j + 3 < k && !gsync()) return;
+        {
+            // column j + 1, from its published copy
+            const int c = j + 1;
+            const double vc = sv[c], wc = sp[c] - K * vc;
+            for (int i = j + 1 + tid; i < k; i += kLThreads) {
+                const double vi = sv[i];
+                sy[i] -= vi * wc + (sp[i] - K * vi) * vc;
+            }
+        }
+        __syncthreads();
+        if (j + 3 < k) {
+            double tn, bn;
+            make_reflector(sy, j + 1, svn, tn, bn, g == (j + 1) % G);
+            if (g == 0 && tid == 0) {
+                d[j + 1] = sy[j + 1];
+                e[j + 1] = bn;
+                tau[j + 1] = tn;
+            }
+            tj = tn;
+            double* tsw = sv;
+            sv = svn;
+            svn = tsw;
+            __syncthreads();
+        } else if (g == 0 && tid == 0) {   // j + 1 = k - 2: the last off-diagonal
+            d[k - 2] = sy[k - 2];
+            e[k - 2] = sy[k - 1];
+        }
     }
 }
 
@@ -1816,7 +1864,7 @@ void launch_rr_large(int k, int nwant, const double* HR, const double* SR, int64
     LABPSD_HIP(hipGetLastError());
     // about eight columns per work-group
     const int G = std::min(128, std::max(8, (k + 7) / 8));
-    const size_t lds = 2 * (size_t)kp * sizeof(double);
+    const size_t lds = 4 * (size_t)kp * sizeof(double);
     if (lds + 1024 > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)k_rrl_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
