@@ -1254,8 +1254,10 @@ __global__ __launch_bounds__(kRRThreads) void k_rayleigh_ritz(int k, int nwant,
 //             products p = tau C v; every work-group then updates its columns and builds
 //             the next reflector itself from the published next column); vectors shared
 //             between work-groups are written and read with device-scope atomics;
-//   teig      eigenvalues by multisection and eigenvectors by inverse iteration (one
-//             work-group, as in the one-work-group kernel);
+//   bisect    the wanted eigenvalues by multisection, one wavefront (64 points per step)
+//             per eigenvalue;
+//   teig      eigenvectors by inverse iteration (one work-group, as in the one-work-group
+//             kernel);
 //   back      per 16-column slice of Z: X = Q Z (reflectors in reverse order), then
 //             W = D L^{-T} X by blocked back substitution with MFMA.
 // A pivot of the scaled S_R at or below 1e-14, or a barrier wait that runs out, sets a
@@ -1673,7 +1675,88 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
     }
 }
 
-// eigenvalues and vectors of the tridiagonal matrix (one work-group of kRRThreads)
+// The wanted eigenvalues of T by multisection, one wavefront per eigenvalue: the 64
+// lanes evaluate the Sturm count at 64 interior points of the bracket, which shrinks
+// 65-fold per step (about nine steps from the Gershgorin interval to the width eps ||T||).
+// Every work-group forms the bounds, the Sturm scale and the scaled e^2 itself (d and
+// e^2 in LDS, 2 kp doubles); work-group 0 also stores sc[3..7] for the inverse iteration.
+__global__ __launch_bounds__(kLThreads) void k_rrl_bisect(int k, int nwant, double* __restrict__ base) {
+    if (rrl_failed(base)) return;
+    const RRLLayout Lo = rrl_layout(k, 1);
+    const int64_t kp = rrl_kp(k);
+    const double* dg = base + Lo.d;
+    const double* eg = base + Lo.e;
+    double* theta = base + Lo.theta;
+    double* sc = base + Lo.sc;
+    extern __shared__ double bl[];
+    double* d = bl;
+    double* e2 = bl + kp;
+    __shared__ double red[3][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double lo = 1.0 / 0.0, hi = -1.0 / 0.0, emax = 0.0;
+    for (int i = tid; i < k; i += kLThreads) {
+        const double di = dg[i];
+        d[i] = di;
+        const double em = i > 0 ? eg[i - 1] : 0.0, ei = i + 1 < k ? eg[i] : 0.0;
+        const double rad = fabs(em) + fabs(ei);
+        lo = fmin(lo, di - rad);
+        hi = fmax(hi, di + rad);
+        if (i + 1 < k) emax = fmax(emax, ei * ei);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+        emax = fmax(emax, __shfl_xor(emax, o, 64));
+    }
+    if (lane == 0) {
+        red[0][wave] = lo;
+        red[1][wave] = hi;
+        red[2][wave] = emax;
+    }
+    __syncthreads();
+    lo = fmin(fmin(red[0][0], red[0][1]), fmin(red[0][2], red[0][3]));
+    hi = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+    emax = fmax(fmax(red[2][0], red[2][1]), fmax(red[2][2], red[2][3]));
+    const double tnorm = fmax(fabs(lo), fabs(hi));
+    const double pivmin = kSafmin * fmax(1.0, emax);
+    const double pad = 2.0 * kEps * tnorm * k + 2.0 * pivmin;
+    const double gl = lo - pad, gu = hi + pad;
+    int ex;
+    (void)frexp(tnorm, &ex);
+    const double ts = ldexp(1.0, -ex);   // the Sturm counts' scale
+    if (blockIdx.x == 0 && tid == 0) {
+        sc[3] = ts;
+        sc[4] = gl;
+        sc[5] = gu;
+        sc[6] = pivmin;
+        sc[7] = tnorm;
+    }
+    for (int i = tid; i + 1 < k; i += kLThreads) {
+        const double es = eg[i] * ts;
+        e2[i] = es * es;
+    }
+    __syncthreads();
+    const int j = blockIdx.x * (kLThreads / 64) + wave;
+    if (j >= nwant) return;
+    const double atol = kEps * tnorm;
+    double a = gl, b = gu;
+    for (int it = 0; it < 40; ++it) {
+        if (b - a <= fmax(atol, 2.0 * kEps * fmax(fabs(a), fabs(b))) + 2.0 * pivmin) break;   // uniform
+        const double w = b - a;
+        const double x = a + w * (double)(lane + 1) * (1.0 / 65.0);
+        const int cnt = sturm_count(d, e2, k, x, ts);
+        const uint64_t bal = __ballot(cnt > j);
+        const int f = bal ? __builtin_ctzll(bal) : 64;   // first point with lambda_j below it
+        const double na = f > 0 ? a + w * (double)f * (1.0 / 65.0) : a;
+        const double nb = f < 64 ? a + w * (double)(f + 1) * (1.0 / 65.0) : b;
+        a = na;
+        b = nb;
+    }
+    if (lane == 0) theta[j] = 0.5 * (a + b);
+}
+
+// eigenvectors of the tridiagonal matrix for the eigenvalues k_rrl_bisect found (one
+// work-group of kRRThreads)
 __global__ __launch_bounds__(kRRThreads) void k_rrl_teig(int k, int nwant, double* __restrict__ base,
                                                          double* __restrict__ gamma, int32_t* __restrict__ info,
                                                          double* gamma_host, int32_t* info_host) {
@@ -1687,8 +1770,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rrl_teig(int k, int nwant, doubl
     int* cstart = (int*)(base + Lo.icl);
     int* csize = cstart + k;
     int* ncl = csize + k;
-    bisect_lowest(d, e, base + Lo.e2, k, nwant, theta, sc);
-    __syncthreads();
+    // theta and sc[3..7] come from k_rrl_bisect
     // LABPSD's wanted Ritz values lie dense in a narrow band: clusters at 1e-3 ||T|| chain
     // into hundreds of vectors, at 1e-5 ||T|| (vectors orthogonal to ~1e-11 outside
     // them) they stay a few wide
@@ -1875,6 +1957,11 @@ void launch_rr_large(int k, int nwant, const double* HR, const double* SR, int64
     if (hipLaunchCooperativeKernel((const void*)k_rrl_tridiag, dim3(G), dim3(kLThreads), targs,
                                    (unsigned)lds, s) == hipSuccess &&
         hipGetLastError() == hipSuccess) {
+        const size_t bl = 2 * (size_t)kp * sizeof(double);
+        if (bl + 1024 > 64 * 1024)
+            (void)hipFuncSetAttribute((const void*)k_rrl_bisect, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bl);
+        (void)hipGetLastError();
+        hipLaunchKernelGGL(k_rrl_bisect, dim3((nwant + 3) / 4), dim3(kLThreads), bl, s, k, nwant, base);
         hipLaunchKernelGGL(k_rrl_teig, dim3(1), dim3(kRRThreads), 0, s, k, nwant, base, gamma, info, gamma_host,
                            info_host);
         hipLaunchKernelGGL(k_rrl_back, dim3((nwant + kLT - 1) / kLT), dim3(kLThreads), 0, s, k, nwant, base, W,
