@@ -217,7 +217,7 @@ def test_gram(prob, ctx):
     import paper_1308_2445_amd as lp
     torch = _torch()
     rng = np.random.default_rng(15)
-    for k in (5, 33, 70):
+    for k in (5, 33, 70, 300, 538):
         Z = rng.standard_normal((P.n, k))
         ZH, ZS = P.H() @ Z, P.S() @ Z
         HR = torch.empty((k, k), dtype=torch.float64, device="cuda")
