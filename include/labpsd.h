@@ -218,7 +218,10 @@ labpsd_status labpsd_gram(labpsd_ctx* ctx, int64_t n, int k, const double* Z, co
  * eigen-decomposed and directions below 1e-14 of its largest eigenvalue are
  * dropped (the rank-revealing step the conclusions call for).  info: device
  * int32[2] = {directions dropped, status (0 ok, -5 rank below nwant)}.
- * k <= 4096.                                                                   */
+ * k <= 4096.  Orders above 128 run on many work-groups, one of the kernels a
+ * cooperative launch (all its work-groups resident at once); if the runtime
+ * refuses that launch, or one of its bounded waits runs out, the same result
+ * comes from a one-work-group kernel instead.                                  */
 labpsd_status labpsd_rayleigh_ritz(labpsd_ctx* ctx, int k, int nwant, const double* HR,
                                    const double* SR, int64_t ldr, double* gamma, double* W,
                                    int64_t ldw, int32_t* info);

@@ -1272,7 +1272,7 @@ constexpr int kRRSpinLimit = 1 << 20;
 __host__ __device__ inline int rrl_kp(int k) { return (k + kLT - 1) / kLT * kLT; }
 
 struct RRLLayout {
-    int64_t ctl, D, A, L, B, Y, d, e, e2, tau, theta, sh, vb, p, part, sc, icl, Zt, U3, total;
+    int64_t ctl, D, A, L, B, Y, d, e, tau, theta, sh, vb, p, part, sc, icl, Zt, U3, total;
 };
 
 // offsets in doubles; everything before Zt is independent of nwp
@@ -1287,8 +1287,7 @@ __host__ __device__ inline RRLLayout rrl_layout(int k, int nwp) {
     L.Y = L.B + kk;
     L.d = L.Y + kk;
     L.e = L.d + kp;
-    L.e2 = L.e + kp;
-    L.tau = L.e2 + kp;
+    L.tau = L.e + kp;
     L.theta = L.tau + kp;
     L.sh = L.theta + kp;
     L.vb = L.sh + kp;          // 2 kp
