@@ -168,9 +168,9 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
     // in the list); counters (children, forward tasks, diagonal + backward tasks)
     std::vector<int32_t> init, init_deep;
     std::vector<SweepTask> sw, sw_deep;
-    auto build_sweep = [&](int chunk, std::vector<SweepTask>& sw, std::vector<int32_t>& init) {
+    auto build_sweep = [&](int chunk, std::vector<SweepTask>& list, std::vector<int32_t>& counts) {
         kChunk = chunk;
-        init.assign(3 * (size_t)F->nsn, 0);
+        counts.assign(3 * (size_t)F->nsn, 0);
         const int nsn = F->nsn;
         bool tree_ok = true;
         for (int i = 0; i < nsn; ++i) {
@@ -179,7 +179,7 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
             if (sn.parent >= 0) {
                 // a child counts itself off with its last forward task, so it needs one
                 if (sn.parent >= nsn || H.sn[sn.parent].level <= sn.level || nb == 0) tree_ok = false;
-                else ++init[sn.parent];
+                else ++counts[sn.parent];
             } else if (nb > 0) {
                 tree_ok = false;   // rows outside the supernode need a parent to own them
             }
@@ -187,11 +187,11 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
         auto add_sweep = [&](int i, int op_list, int op_kernel) {
             const size_t before = tk.size();
             add_tasks(H.sn[i], op_list);
-            for (size_t t = before; t < tk.size(); ++t) sw.push_back(SweepTask{tk[t], op_kernel, i, H.sn[i].parent, 0});
+            for (size_t t = before; t < tk.size(); ++t) list.push_back(SweepTask{tk[t], op_kernel, i, H.sn[i].parent, 0});
             const int32_t added = (int32_t)(tk.size() - before);
             tk.resize(before);
-            if (op_list == 1) init[nsn + i] += added;
-            else init[2 * (size_t)nsn + i] += added;
+            if (op_list == 1) counts[nsn + i] += added;
+            else counts[2 * (size_t)nsn + i] += added;
         };
         for (int l = 0; l < F->nlevels; ++l)
             for (int i = 0; i < nsn; ++i)
@@ -202,7 +202,7 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
         for (int l = F->nlevels - 1; l >= 0; --l)
             for (int i = 0; i < nsn; ++i)
                 if (H.sn[i].level == l) add_sweep(i, 2, 3);
-        return tree_ok && !sw.empty();
+        return tree_ok && !list.empty();
     };
     // the single-launch sweep twice: 64-deep reductions per task, and kDeepChunk-deep ones
     // for wide right-hand-side blocks (fewer tasks per supernode, same order)
