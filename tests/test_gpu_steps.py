@@ -277,7 +277,7 @@ def c2_pencil():
 
 
 @pytest.mark.parametrize("k,nwant,dup,hscale", [(300, 150, 0, 1e100), (538, 282, 0, 1.0), (1076, 564, 0, 1.0),
-                                                (300, 150, 20, 1.0)])
+                                                (300, 150, 20, 1.0), (144, 1, 0, 1.0), (161, 161, 0, 1e-100)])
 def test_rayleigh_ritz_large(c2_pencil, ctx, k, nwant, dup, hscale):
     """Orders of the 128k- and 296k-dof cells (k up to 538 and 1076) on pencils of the
     16k-dof cell; with repeated directions the Cholesky of S_R fails and the
