@@ -134,6 +134,10 @@ typedef struct {
     int precision;        /* labpsd_precision                                             */
     int refresh_every;    /* recompute H Psi, S Psi from H and S every this many iterations */
     int timing;           /* nonzero: time every step with HIP events (stats.t_step_s)      */
+    double reorth_tol;    /* at every refresh, Psi^T S Psi is formed from the fresh products;
+                           * if max |Psi^T S Psi - I| exceeds this (0: the default 1e-10;
+                           * negative: always), Psi is S-orthonormalised again by a
+                           * Rayleigh-Ritz step on span(Psi) (Cholesky of Psi^T S Psi) */
 } labpsd_solve_params;
 
 typedef struct {
@@ -151,6 +155,7 @@ typedef struct {
     double t_step_s[12];
     int64_t n_launch[12];
     int64_t n_cols[12];       /* columns processed by each step, summed over its launches */
+    int reorths;              /* S-orthonormality restorations (see reorth_tol)            */
 } labpsd_stats;
 
 /* Run LABPSD (Section 3 outline) from the start block X0 (n x (nev+m0),

@@ -52,7 +52,7 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int), ("m0", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("sigma0", ctypes.c_double),
                 ("precision", ctypes.c_int), ("refresh_every", ctypes.c_int),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("reorth_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -60,7 +60,8 @@ class Stats(ctypes.Structure):
                 ("localized_cols", ctypes.c_int64), ("rank_dropped", ctypes.c_int),
                 ("refreshes", ctypes.c_int), ("hp", ctypes.c_double), ("la", ctypes.c_double),
                 ("t_solve_s", ctypes.c_double), ("t_step_s", ctypes.c_double * 12),
-                ("n_launch", ctypes.c_int64 * 12), ("n_cols", ctypes.c_int64 * 12)]
+                ("n_launch", ctypes.c_int64 * 12), ("n_cols", ctypes.c_int64 * 12),
+                ("reorths", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("t_step_s", "n_launch", "n_cols")}
@@ -236,8 +237,9 @@ class Problem:
         return {f: getattr(fi, f) for f, _ in fi._fields_}
 
     def solve(self, nev: int, m0: int, X0, *, tol=1e-8, max_outer=200, sigma0=0.0,
-              precision=FP64, refresh_every=10, timing=False, E0=None, device_out=False):
-        """Run LABPSD from X0 (numpy n x b Fortran array, or torch (b, n) device tensor)."""
+              precision=FP64, refresh_every=10, timing=False, E0=None, device_out=False, reorth_tol=0.0):
+        """Run LABPSD from X0 (numpy n x b Fortran array, or torch (b, n) device tensor).
+        reorth_tol: threshold on max |Psi^T S Psi - I| at a refresh (0: 1e-10; negative: always)."""
         import torch
         b = nev + m0
         n = self.n
@@ -250,7 +252,8 @@ class Problem:
             assert tuple(X0.shape) == (b, n) and X0.is_contiguous() and X0.dtype == torch.float64
             in_where = MEM_DEVICE
         E0a = None if E0 is None else np.ascontiguousarray(E0, dtype=np.float64)
-        prm = SolveParams(nev, m0, tol, max_outer, sigma0, precision, refresh_every, 1 if timing else 0)
+        prm = SolveParams(nev, m0, tol, max_outer, sigma0, precision, refresh_every, 1 if timing else 0,
+                          reorth_tol)
         hist = np.zeros(max_outer * nev + nev)
         nh = ctypes.c_int(0)
         st = Stats()

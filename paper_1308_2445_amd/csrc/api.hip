@@ -354,7 +354,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     HBuf<double>& h_sel = P.h_sel;
     HBuf<int32_t>& h_ib = P.h_ib;
     HBuf<int32_t>& h_int = P.h_flags;
-    h_rb.alloc(2 * (size_t)m + b);
+    h_rb.alloc(2 * (size_t)m + b + 1);
     h_ib.alloc((size_t)m + 4);
     h_sel.alloc(3 * (size_t)m);
     h_int.alloc(2 * (size_t)m);   // MINRES done flags: two slots of up to m columns
@@ -424,6 +424,12 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     std::vector<double> shifts, stopn;
     const LocalParams& lp = P.local;
 
+    // S-orthonormality of Psi (row a8's safeguard): at every refresh, Psi^T S Psi from the
+    // fresh products; max |Psi^T S Psi - I| reaches the host with the next residual read
+    // (slot 2m + b of h_rb), and above reorth_tol a Rayleigh-Ritz step on span(Psi) (the
+    // Cholesky of Psi^T S Psi, then the rotation to its Ritz basis) restores it
+    const double reorth_tol = prm.reorth_tol > 0.0 ? prm.reorth_tol : (prm.reorth_tol < 0.0 ? -1.0 : 1e-10);
+    bool orth_pending = false;
     auto refresh = [&]() {
         tm.begin(S_PROD_PSI);
         launch_spmm_hs(P.sell, Z(0), ldz, b, Z(1), Z(2), ldz, s);
@@ -433,6 +439,37 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         fresh = true;
         since_refresh = 0;
         st.refreshes += 1;
+        tm.begin(S_GRAM);
+        launch_gram(n, b, Z(0), Z(1), Z(2), ldz, B.HR, B.SR, kmax, B.gram_ws, P.ctx->cu_count, s);
+        launch_orth_deviation(b, B.SR, kmax, d_rb + 2 * m + b, s);
+        tm.end();
+        st.n_launch[S_GRAM] += 1;
+        st.n_cols[S_GRAM] += b;
+        orth_pending = true;
+    };
+    // after a synchronisation: true if Psi had to be S-orthonormalised again (the caller
+    // recomputes the residuals and reads the new Ritz values)
+    auto restore_orth = [&]() -> bool {
+        if (!orth_pending) return false;
+        orth_pending = false;
+        const double dev = h_rb.p[2 * (size_t)m + b];
+        if (reorth_tol >= 0.0 && dev <= reorth_tol) return false;
+        tm.begin(S_RR);
+        launch_rayleigh_ritz(b, b, B.HR, B.SR, kmax, B.gamma, B.W, kmax, B.info, B.rr_ws, s, d_rb + 2 * m,
+                             d_ib + m);
+        tm.end();
+        st.n_launch[S_RR] += 1;
+        st.n_cols[S_RR] += b;
+        tm.begin(S_UPDATE);
+        const int nxt = 1 - cur;
+        launch_block_update(n, b, b, Z(0), Z(1), Z(2), ldz, B.W, kmax, B.Zb[nxt][0], B.Zb[nxt][1],
+                            B.Zb[nxt][2], ldz, s);
+        tm.end();
+        st.n_launch[S_UPDATE] += 1;
+        st.n_cols[S_UPDATE] += b;
+        cur = nxt;
+        st.reorths += 1;
+        return true;
     };
     auto residuals = [&]() {
         tm.begin(S_RESID);
@@ -455,10 +492,18 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         residuals();   // step 4 and eq. (res1)
         rr_check(it == 1 ? "start block is rank deficient"
                          : "search space [Psi P] lost rank below the block width");
+        if (restore_orth()) {
+            residuals();
+            rr_check("Psi lost rank below the block width");
+        }
         if (maxres() <= prm.tol) {   // step 5, on the true residual
             if (!fresh) {
                 refresh();
                 residuals();
+                if (restore_orth()) {
+                    residuals();
+                    rr_check("Psi lost rank below the block width");
+                }
             }
             if (maxres() <= prm.tol) {
                 converged = true;

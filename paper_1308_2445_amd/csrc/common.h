@@ -407,6 +407,8 @@ int residual_blocks(int64_t n);
 
 // Gram: HR = Z^T ZH, SR = Z^T ZS (symmetric parts); partial workspace sized by gram_ws
 size_t gram_ws_doubles(int64_t n, int k, int cu_count);
+// out (device-visible) = max |SR - I| over the b x b matrix SR (ld ld)
+void launch_orth_deviation(int b, const double* SR, int64_t ld, double* out, hipStream_t s);
 void launch_gram(int64_t n, int k, const double* Z, const double* ZH, const double* ZS, int64_t ldz,
                  double* HR, double* SR, int64_t ldr, double* ws, int cu_count, hipStream_t s);
 

@@ -410,6 +410,22 @@ __global__ __launch_bounds__(256) void k_block_update_wide(int64_t n, int k, int
     }
 }
 
+// max |SR - I| over the b x b matrix SR (ld ld), one work-group; a NaN counts as infinite
+__global__ __launch_bounds__(256) void k_orth_deviation(int b, const double* __restrict__ SR, int64_t ld,
+                                                        double* __restrict__ out) {
+    __shared__ double red[4];
+    double mx = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)b * b; e += 256) {
+        const int64_t i = e % b, j = e / b;
+        const double dv = fabs(SR[i + j * ld] - (i == j ? 1.0 : 0.0));
+        mx = (dv == dv) ? fmax(mx, dv) : INFINITY;
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 }  // namespace
 
 int residual_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kResRows - 1) / kResRows); }
@@ -578,6 +594,12 @@ void launch_block_update(int64_t n, int k, int b, const double* Z, const double*
     }
     hipLaunchKernelGGL(k_block_update, grid, dim3(256), 0, s, n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi,
                        PsiH, PsiS, ldo);
+    LABPSD_HIP(hipGetLastError());
+}
+
+void launch_orth_deviation(int b, const double* SR, int64_t ld, double* out, hipStream_t s) {
+    if (b <= 0) return;
+    hipLaunchKernelGGL(k_orth_deviation, dim3(1), dim3(256), 0, s, b, SR, ld, out);
     LABPSD_HIP(hipGetLastError());
 }
 

@@ -159,6 +159,30 @@ def test_modes_and_minimal_block(ctx):
     assert out.converged and _rel_err(out.lam, lam[:1], P.sigma0).max() < 1e-10
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_orthonormality_restoration(ctx, precision):
+    """The S-orthonormality safeguard: max |Psi^T S Psi - I| is measured at every refresh;
+    the default threshold (1e-10) leaves a well-conditioned run alone, a negative one
+    restores S-orthonormality at every refresh without changing the result."""
+    P = pufe.workload("c1", 0)
+    pr = _problem(ctx, P)
+    m, m0 = 4, pufe.guard_vectors(4)
+    X0 = pufe.start_block(P.n, m + m0, 0)
+    lam, _ = oeig.dense_eigs(P.H(), P.S(), m)
+    print("\n[case] c1 reorth precision=%d" % precision, flush=True)
+    a = pr.solve(m, m0, X0, tol=1e-10, sigma0=P.sigma0, precision=precision, refresh_every=3)
+    b = pr.solve(m, m0, X0, tol=1e-10, sigma0=P.sigma0, precision=precision, refresh_every=3, reorth_tol=-1.0)
+    assert a.converged and b.converged
+    assert a.stats["reorths"] == 0 and a.stats["refreshes"] >= 2
+    assert b.stats["reorths"] == b.stats["refreshes"]
+    assert _rel_err(b.lam, lam, P.sigma0).max() < 1e-10
+    assert _rel_err(b.lam, a.lam, P.sigma0).max() < 1e-10
+    S = P.S()
+    assert np.abs(b.X.T @ (S @ b.X) - np.eye(m)).max() < 1e-10
+    res = oeig.relative_residuals(P.H(), S, b.lam, b.X, P.sigma0)
+    assert res.max() <= 1e-10 * 1.01
+
+
 def test_not_converged_keeps_valid_outputs(ctx):
     lp = _lp()
     P = pufe.workload("c1", 0)
