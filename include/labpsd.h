@@ -165,13 +165,15 @@ typedef struct {
  * Outputs (host or device per out_where, caller-allocated):
  *   lambda[nev] ascending; X n x nev (ld n), S-orthonormal;
  *   res_hist[max_outer * nev] (may be NULL): Res_i at the start of every
- *   iteration, iteration-major; *n_hist = iterations recorded (may be NULL).
- *   stats may be NULL.
+ *   iteration, iteration-major; ritz_hist[max_outer * (nev+m0)] (may be NULL):
+ *   the Ritz values those Res_i belong to, iteration-major;
+ *   *n_hist = iterations recorded (may be NULL).  stats may be NULL.
  * Returns OK, NOT_CONVERGED (outputs hold the last iterate) or an error.
  * Requires labpsd_set_global_precond first (ESTATE otherwise).              */
 labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* params, const double* X0,
                            const double* E0, labpsd_mem in_where, double* lambda, double* X,
-                           double* res_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats);
+                           double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where,
+                           labpsd_stats* stats);
 
 /* ------------------------------------------------------------------ hot-path steps
  * The steps of one LABPSD iteration, each callable on its own for testing and

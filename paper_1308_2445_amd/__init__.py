@@ -96,7 +96,7 @@ _SIGS = {
     "labpsd_set_global_precond": ([_p, _d, _p], _i32),
     "labpsd_set_local_precond": ([_p, _d, _d, _d, _i32, _i32], _i32),
     "labpsd_get_factor_info": ([_p, ctypes.POINTER(FactorInfo)], _i32),
-    "labpsd_solve": ([_p, ctypes.POINTER(SolveParams), _p, _p, _i32, _p, _p, _p,
+    "labpsd_solve": ([_p, ctypes.POINTER(SolveParams), _p, _p, _i32, _p, _p, _p, _p,
                       ctypes.POINTER(ctypes.c_int), _i32, ctypes.POINTER(Stats)], _i32),
     "labpsd_spmm": ([_p, _p, _i64, _i32, _p, _p, _i64], _i32),
     "labpsd_spmm_shifted": ([_p, _i32, _p, _i64, _i32, _p, _p, _i64], _i32),
@@ -191,6 +191,7 @@ class SolveResult:
     X: object
     res_hist: np.ndarray
     stats: dict
+    ritz_hist: object = None   # Ritz values at the start of every iteration (iterations x b)
 
     @property
     def converged(self) -> bool:
@@ -255,6 +256,7 @@ class Problem:
         prm = SolveParams(nev, m0, tol, max_outer, sigma0, precision, refresh_every, 1 if timing else 0,
                           reorth_tol)
         hist = np.zeros(max_outer * nev + nev)
+        rhist = np.zeros((max_outer + 1) * b)
         nh = ctypes.c_int(0)
         st = Stats()
         if device_out:
@@ -262,18 +264,20 @@ class Problem:
             X = torch.empty((nev, n), dtype=torch.float64, device="cuda")
             out_where = MEM_DEVICE
             hist_arg = torch.empty(max_outer * nev + nev, dtype=torch.float64, device="cuda")
+            rhist_arg = torch.empty((max_outer + 1) * b, dtype=torch.float64, device="cuda")
         else:
             lam = np.zeros(nev)
             X = np.zeros((n, nev), order="F")
             out_where = MEM_HOST
             hist_arg = hist
+            rhist_arg = rhist
         rc = _lib.labpsd_solve(self.h, ctypes.byref(prm), _ptr(X0), _ptr(E0a), in_where, _ptr(lam), _ptr(X),
-                               _ptr(hist_arg), ctypes.byref(nh), out_where, ctypes.byref(st))
+                               _ptr(hist_arg), _ptr(rhist_arg), ctypes.byref(nh), out_where, ctypes.byref(st))
         _check(rc, "labpsd_solve", allow=(OK, NOT_CONVERGED))
         # the history is a host array, or (device_out) a device tensor view
         src = hist_arg if hist_arg is not None else hist
         return SolveResult(status=rc, lam=lam, X=X, res_hist=src[: nh.value * nev].reshape(nh.value, nev),
-                           stats=st.as_dict())
+                           stats=st.as_dict(), ritz_hist=rhist_arg[: nh.value * b].reshape(nh.value, b))
 
     def close(self):
         if getattr(self, "h", None):

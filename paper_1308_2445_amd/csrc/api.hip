@@ -331,7 +331,7 @@ static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T
 template <typename T>
 static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, const double* X0,
                                 const double* E0, labpsd_mem in_where, double* lambda, double* X,
-                                double* res_hist, int* n_hist, labpsd_mem out_where,
+                                double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where,
                                 labpsd_stats* stats, hipStream_t s) {
     const double t_start = wall();
     const int64_t n = P.n;
@@ -486,7 +486,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         for (double r : res) mx = std::max(mx, std::isnan(r) ? INFINITY : r);
         return mx;
     };
-    std::vector<double> hist;
+    std::vector<double> hist, rhist;   // Res and the Ritz values at the start of every iteration
     for (int it = 1; it <= prm.max_outer; ++it) {
         if (since_refresh >= prm.refresh_every) refresh();
         residuals();   // step 4 and eq. (res1)
@@ -508,11 +508,13 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             if (maxres() <= prm.tol) {
                 converged = true;
                 hist.insert(hist.end(), res.begin(), res.end());
+                rhist.insert(rhist.end(), E.begin(), E.end());
                 ++nh;
                 break;
             }
         }
         hist.insert(hist.end(), res.begin(), res.end());
+        rhist.insert(rhist.end(), E.begin(), E.end());
         ++nh;
         outer = it;
         // step 6: directions for the unconverged pairs
@@ -624,6 +626,13 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         else
             std::memcpy(res_hist, hist.data(), hist.size() * sizeof(double));
     }
+    if (ritz_hist && nh > 0) {
+        if (out_where == LABPSD_MEM_DEVICE)
+            LABPSD_HIP(hipMemcpyAsync(ritz_hist, rhist.data(), rhist.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, s));
+        else
+            std::memcpy(ritz_hist, rhist.data(), rhist.size() * sizeof(double));
+    }
     LABPSD_HIP(hipStreamSynchronize(s));
     if (n_hist) *n_hist = nh;
     st.outer_iters = outer;
@@ -636,12 +645,12 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
 
 labpsd_status run_solve(Problem& P, const labpsd_solve_params& prm, const double* X0,
                         const double* E0, labpsd_mem in_where, double* lambda, double* X,
-                        double* res_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats,
+                        double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats,
                         hipStream_t stream) {
     if (prm.precision == LABPSD_MIXED)
-        return solve_impl<float>(P, prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where,
+        return solve_impl<float>(P, prm, X0, E0, in_where, lambda, X, res_hist, ritz_hist, n_hist, out_where,
                                  stats, stream);
-    return solve_impl<double>(P, prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where,
+    return solve_impl<double>(P, prm, X0, E0, in_where, lambda, X, res_hist, ritz_hist, n_hist, out_where,
                               stats, stream);
 }
 
@@ -839,7 +848,7 @@ labpsd_status labpsd_get_factor_info(const labpsd_problem* p, labpsd_factor_info
 
 labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* prm, const double* X0,
                            const double* E0, labpsd_mem in_where, double* lambda, double* X,
-                           double* res_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats) {
+                           double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats) {
     return guarded([&]() -> labpsd_status {
         LABPSD_REQUIRE(p && prm && X0 && lambda && X, "NULL argument");
         if (!p->factor) throw Error{LABPSD_ESTATE, "labpsd_set_global_precond must come first"};
@@ -851,7 +860,7 @@ labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* prm, co
         LABPSD_REQUIRE(prm->precision == LABPSD_FP64 || prm->precision == LABPSD_MIXED,
                        "invalid precision");
         LABPSD_HIP(hipSetDevice(p->ctx->device));
-        return run_solve(*p, *prm, X0, E0, in_where, lambda, X, res_hist, n_hist, out_where, stats,
+        return run_solve(*p, *prm, X0, E0, in_where, lambda, X, res_hist, ritz_hist, n_hist, out_where, stats,
                          p->ctx->stream);
     });
 }

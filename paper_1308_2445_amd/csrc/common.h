@@ -375,7 +375,7 @@ namespace labpsd {
 // Run one LABPSD solve of P on `stream` (the driver of labpsd_solve).
 labpsd_status run_solve(Problem& P, const labpsd_solve_params& prm, const double* X0,
                         const double* E0, labpsd_mem in_where, double* lambda, double* X,
-                        double* res_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats,
+                        double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats,
                         hipStream_t stream);
 // Device bytes one solve reserves beyond the resident problem.
 size_t solve_footprint_bytes(int64_t n, int nev, int m0, int precision, int cu_count);

@@ -110,7 +110,7 @@ struct Server {
             X0 = start.p;
         }
         r.status = run_solve(P, r.prm, X0, E0.empty() ? nullptr : E0.data(), where, r.lambda.data(),
-                             r.X.data(), nullptr, nullptr, LABPSD_MEM_HOST, &r.stats, stream);
+                             r.X.data(), nullptr, nullptr, nullptr, LABPSD_MEM_HOST, &r.stats, stream);
     }
 
     void worker() {

@@ -85,6 +85,25 @@ def test_c2_eigenvalues_match_oracle(c2, precision):
     assert out.res_hist.shape[1] == m and out.res_hist[-1].max() <= 1e-8
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_ritz_history_monotone_and_bounded(c2, precision):
+    """The recorded Ritz values never increase from one iteration to the next (the new
+    search space contains the old block) and stay above the pencil's eigenvalues
+    (Courant-Fischer; the oracle's eigenvalues at tol 1e-11 stand in for them)."""
+    P, pr, g = c2
+    m, m0 = g["nev"], g["m0"]
+    out = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-8, sigma0=P.sigma0, precision=precision)
+    assert out.converged
+    Eh = np.asarray(out.ritz_hist)
+    assert Eh.shape == (out.res_hist.shape[0], m + m0)
+    scale = np.abs(Eh - P.sigma0)
+    assert np.all(np.diff(Eh, axis=0) <= 1e-12 * scale[1:])
+    lam = np.asarray(g["lam"])
+    assert np.all(Eh[:, :m] >= lam[None, :] - 1e-10 * np.abs(lam - P.sigma0)[None, :])
+    assert np.all(np.diff(Eh, axis=1) >= 0)   # ascending within an iteration
+    assert _rel_err(Eh[-1, :m], out.lam, P.sigma0).max() < 1e-13
+
+
 @pytest.fixture(scope="module")
 def c2_oracle(c2):
     P, pr, g = c2
