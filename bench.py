@@ -102,6 +102,43 @@ def measured_traffic(kernel):
     return None
 
 
+def measured_peaks():
+    """Peaks measured on this GPU beside the published ones: a 1 GiB device copy (bytes
+    read + written per second) and an FP64 8192^3 matrix product (the vendor library's
+    DGEMM on the matrix cores).  Outside every timed region."""
+    import torch
+    out = {}
+    n = 2 ** 30 // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_copy_GBps"] = 10 * 2 * 8 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    m = 8192
+    a = torch.rand((m, m), dtype=torch.float64, device="cuda")
+    b = torch.rand((m, m), dtype=torch.float64, device="cuda")
+    c = a @ b
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(3):
+        c = a @ b
+    e1.record()
+    torch.cuda.synchronize()
+    out["fp64_dgemm_TFLOPs"] = 3 * 2.0 * m ** 3 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    out["note"] = ("torch device copy of 1 GiB (read + write) and torch FP64 matmul 8192^3 on this GPU; "
+                   "'frac' uses the published peaks, 'frac_of_measured' these")
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration():
     """Plain device-to-device copies of a known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -331,6 +368,13 @@ def main():
                          "iterations": mx["outs"][0].stats["outer_iters"],
                          "max_rel_eig_diff_vs_fp64": float(np.max(np.abs(lam32 - lam64) /
                                                                   np.abs(lam64 - P.sigma0)))}
+    try:
+        mp = measured_peaks()
+        line["measured_peaks"] = mp
+        line["roofline"]["frac_of_measured"] = rr_achieved / mp["fp64_dgemm_TFLOPs"]
+        line["roofline_hbm"]["frac_of_measured"] = pp_achieved / mp["hbm_copy_GBps"]
+    except Exception as exc:   # the peaks are context; the line is printed regardless
+        line["measured_peaks"] = {"error": str(exc)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(P, nev, m0, args.tol)
     print(json.dumps(line), flush=True)
