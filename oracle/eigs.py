@@ -62,8 +62,29 @@ def clusters(lam, sigma0: float, rel_gap: float = 1e-6):
     return out
 
 
+def _s_sines(S, C):
+    """Singular values of C in the S norm (ascending), each to about rounding of
+    C's entries in absolute terms: the eigenvalues of C^T S C give the squares; the
+    ones far below the largest are recomputed from the Gram matrix of their own
+    directions, where no large value dilutes them."""
+    G = C.T @ (S @ C)
+    w, V = np.linalg.eigh(0.5 * (G + G.T))
+    w = np.clip(w, 0.0, None)
+    small = w < 1e-4 * w.max()
+    if small.any() and not small.all():
+        w[small] = _s_sines(S, C @ V[:, small]) ** 2
+    return np.sqrt(np.sort(w))
+
+
 def s_principal_angles(S, X, Y):
-    """Principal angles between span(X) and span(Y) in the S inner product."""
+    """Principal angles between span(X) and span(Y) in the S inner product, ascending.
+
+    Both bases are S-orthonormalised (Qx, Qy).  The cosines are the singular values
+    of Qx^T S Qy; the sines are the S-norm singular values of the part of Qy that is
+    S-orthogonal to span(Qx), B = Qy - Qx (Qx^T S Qy).  Angles whose sine is below
+    1/sqrt(2) are taken from the sine (arccos of a cosine near 1 resolves nothing
+    below about 1e-8), the others from the cosine (the sine-cosine rule of Knyazev and
+    Argentati, SIAM J. Sci. Comput. 23 (2002)).  Requires dim span(X) <= dim span(Y)."""
     def sorth(A):
         G = A.T @ (S @ A)
         G = 0.5 * (G + G.T)
@@ -71,6 +92,26 @@ def s_principal_angles(S, X, Y):
         return A @ (V / np.sqrt(w)[None, :])
     Qx, Qy = sorth(X), sorth(Y)
     M = Qx.T @ (S @ Qy)
-    sv = np.linalg.svd(M, compute_uv=False)
-    sv = np.clip(sv, -1.0, 1.0)
-    return np.arccos(sv)
+    cos = np.sort(np.clip(np.linalg.svd(M, compute_uv=False), 0.0, 1.0))[::-1]
+    sin = np.clip(_s_sines(S, Qy - Qx @ M), 0.0, 1.0)[: cos.shape[0]]
+    return np.where(sin < np.sqrt(0.5), np.arcsin(sin), np.arccos(cos))
+
+
+def shift_invert_eigs(H, S, m: int, sigma: float, tol: float = 1e-13):
+    """Lowest m eigenpairs of (H, S) by a library route that shares nothing with LABPSD:
+    ARPACK's implicitly restarted Lanczos on the shift-inverted operator
+    (H - sigma S)^{-1} S (SciPy ``eigsh`` in shift-invert mode), with sigma below the
+    spectrum so that the eigenvalues closest to sigma are the lowest ones (eq. (ghep)).
+    (H - sigma S) is factorised once by SuperLU with a symmetric ordering.
+    Returns (lambda ascending, X S-orthonormal)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    A = (sp.csc_matrix(H) - sigma * sp.csc_matrix(S)).tocsc()
+    lu = spla.splu(A, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+    n = A.shape[0]
+    op = spla.LinearOperator((n, n), matvec=lu.solve, dtype=np.float64)
+    ncv = min(n, max(2 * m + 1, m + 64))
+    lam, X = spla.eigsh(sp.csr_matrix(H), k=m, M=sp.csr_matrix(S), sigma=sigma, which="LM", OPinv=op,
+                        ncv=ncv, tol=tol)
+    order = np.argsort(lam)
+    return lam[order], X[:, order]
