@@ -77,21 +77,26 @@ const char* labpsd_version(void);
 
 /* ------------------------------------------------------------------ problem */
 
-/* Upload the pencil (H, S) (Section 2, eq. (ghep)).  Host arrays: rowptr
- * int64[n+1], col int32[nnz] (per row strictly increasing; the pattern must be
- * structurally symmetric), h_val and s_val float64[nnz] on that one pattern.
- * The library copies everything (a sliced-ELL device layout plus FP32 value
- * copies for the mixed-precision preconditioner); the caller may free on
- * return.  EINVAL on n < 1, nnz < n, unsorted/duplicate/out-of-range columns
- * or a pattern that is not structurally symmetric.                          */
+/* Upload the pencil (H, S) (Section 2, eq. (ghep)).  rowptr int64[n+1],
+ * col int32[nnz] (per row strictly increasing; the pattern must be structurally
+ * symmetric), h_val and s_val float64[nnz] on that one pattern.  `where` says
+ * whether the four arrays are host memory or device memory of the context's
+ * device (device arrays are read with a synchronous copy on the context's stream:
+ * the pattern is validated, the sliced-ELL layout built and, later, the global
+ * factorisation computed on the host).  The library copies everything (a
+ * sliced-ELL device layout plus FP32 value copies for the mixed-precision
+ * preconditioner); the caller may free on return.  EINVAL on n < 1, nnz < n,
+ * unsorted/duplicate/out-of-range columns, an empty row or a pattern that is not
+ * structurally symmetric.                                                     */
 labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz,
                                     const int64_t* rowptr, const int32_t* col,
-                                    const double* h_val, const double* s_val,
+                                    const double* h_val, const double* s_val, labpsd_mem where,
                                     labpsd_problem** out);
-/* Replace the values of H (host float64[nnz], same pattern) for the next GHEP of
- * an SCF-like sequence (Section 2).  S and the global factorisation are kept:
- * the paper builds the global preconditioner once, from the first H (Section 4). */
-labpsd_status labpsd_problem_update_h(labpsd_problem* p, const double* h_val);
+/* Replace the values of H (float64[nnz] on the same pattern, host or device per
+ * `where`) for the next GHEP of an SCF-like sequence (Section 2).  S and the
+ * global factorisation are kept: the paper builds the global preconditioner once,
+ * from the first H (Section 4).                                               */
+labpsd_status labpsd_problem_update_h(labpsd_problem* p, const double* h_val, labpsd_mem where);
 void labpsd_problem_destroy(labpsd_problem* p);
 int64_t labpsd_problem_n(const labpsd_problem* p);
 
@@ -99,11 +104,17 @@ int64_t labpsd_problem_n(const labpsd_problem* p);
  * Factorises H - eps_bar S once on the host (FP64 supernodal Cholesky after a
  * nested-dissection ordering; eq. (ldl) with 1x1 pivots only, since eps_bar
  * below lambda_1 makes the matrix positive definite) and uploads the factor
- * panels in FP64 and FP32.  `coords` (host float64[n*3], row-major x,y,z per
- * dof, or NULL) guides the ordering by coordinate bisection; with NULL a
- * breadth-first level-structure bisection of the graph is used.
- * ENOTSPD if a pivot is not positive (eps_bar too high).                    */
-labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const double* coords);
+ * panels in the precisions that `precisions` selects: LABPSD_PANELS_FP64 (the
+ * apply of LABPSD_FP64 solves), LABPSD_PANELS_FP32 (the apply of LABPSD_MIXED
+ * solves), or their OR; 0 means both.  A solve or apply in a precision whose
+ * panels were not uploaded returns ESTATE.  `coords` (host float64[n*3],
+ * row-major x,y,z per dof, or NULL) guides the ordering by coordinate
+ * bisection; with NULL a breadth-first level-structure bisection of the graph
+ * is used.  ENOTSPD if a pivot is not positive (eps_bar too high); EINVAL for a
+ * mask with other bits set.                                                  */
+enum { LABPSD_PANELS_FP64 = 1, LABPSD_PANELS_FP32 = 2 };
+labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const double* coords,
+                                        unsigned precisions);
 
 /* Locally accelerated preconditioner parameters (Section 3 remark 4, Section 5):
  * a pair is localised when Res_i <= tau1 and |eps_i - eps_i^prev| <= tau2
@@ -138,6 +149,9 @@ typedef struct {
                            * if max |Psi^T S Psi - I| exceeds this (0: the default 1e-10;
                            * negative: always), Psi is S-orthonormalised again by a
                            * Rayleigh-Ritz step on span(Psi) (Cholesky of Psi^T S Psi) */
+    uint64_t seed;        /* start block when X0 is NULL: entry (i, j) is a standard normal
+                           * drawn from counter i + n j of this seed (splitmix64 hash,
+                           * Box-Muller); the same seed gives the same block           */
 } labpsd_solve_params;
 
 typedef struct {
@@ -159,7 +173,9 @@ typedef struct {
 } labpsd_stats;
 
 /* Run LABPSD (Section 3 outline) from the start block X0 (n x (nev+m0),
- * column-major, ld n; host or device per in_where).  E0 (nev+m0 values or
+ * column-major, ld n; host or device per in_where), or, with X0 NULL, from the
+ * seeded random block that params->seed selects (a cold start: step 1 of the
+ * outline with no previous SCF iteration).  E0 (nev+m0 values or
  * NULL) are the previous Ritz values of a warm start; they serve as the
  * previous-iteration values of the first localisation test.
  * Outputs (host or device per out_where, caller-allocated):

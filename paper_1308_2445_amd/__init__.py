@@ -30,6 +30,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, NOT_CONVERGED, PENDING = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ENOTSPD, ERANK, ESTATE = -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
+PANELS_FP64, PANELS_FP32 = 1, 2
 HYBRID, GLOBAL_ONLY, LOCAL_ONLY = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 
@@ -52,7 +53,7 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int), ("m0", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("sigma0", ctypes.c_double),
                 ("precision", ctypes.c_int), ("refresh_every", ctypes.c_int),
-                ("timing", ctypes.c_int), ("reorth_tol", ctypes.c_double)]
+                ("timing", ctypes.c_int), ("reorth_tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -89,11 +90,11 @@ _SIGS = {
     "labpsd_ctx_set_stream": ([_p, _p], _i32),
     "labpsd_last_error": ([], ctypes.c_char_p),
     "labpsd_version": ([], ctypes.c_char_p),
-    "labpsd_problem_create": ([_p, _i64, _i64, _p, _p, _p, _p, ctypes.POINTER(_p)], _i32),
-    "labpsd_problem_update_h": ([_p, _p], _i32),
+    "labpsd_problem_create": ([_p, _i64, _i64, _p, _p, _p, _p, _i32, ctypes.POINTER(_p)], _i32),
+    "labpsd_problem_update_h": ([_p, _p, _i32], _i32),
     "labpsd_problem_destroy": ([_p], None),
     "labpsd_problem_n": ([_p], _i64),
-    "labpsd_set_global_precond": ([_p, _d, _p], _i32),
+    "labpsd_set_global_precond": ([_p, _d, _p, ctypes.c_uint], _i32),
     "labpsd_set_local_precond": ([_p, _d, _d, _d, _i32, _i32], _i32),
     "labpsd_get_factor_info": ([_p, ctypes.POINTER(FactorInfo)], _i32),
     "labpsd_solve": ([_p, ctypes.POINTER(SolveParams), _p, _p, _i32, _p, _p, _p, _p,
@@ -202,17 +203,27 @@ class Problem:
     """The pencil (H, S) on one shared CSR pattern, resident on the device."""
 
     def __init__(self, ctx: Context, n, rowptr, col, h_val, s_val):
+        """rowptr int64[n+1], col int32[nnz], h_val / s_val float64[nnz]: numpy arrays (host)
+        or torch device tensors (all four on the same side)."""
         self.ctx = ctx
         self.n = int(n)
-        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
-        col = np.ascontiguousarray(col, dtype=np.int32)
-        h_val = np.ascontiguousarray(h_val, dtype=np.float64)
-        s_val = np.ascontiguousarray(s_val, dtype=np.float64)
+        if isinstance(rowptr, np.ndarray) or not hasattr(rowptr, "is_cuda"):
+            rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            h_val = np.ascontiguousarray(h_val, dtype=np.float64)
+            s_val = np.ascontiguousarray(s_val, dtype=np.float64)
+            where = MEM_HOST
+        else:
+            import torch
+            for t, dt in ((rowptr, torch.int64), (col, torch.int32), (h_val, torch.float64),
+                          (s_val, torch.float64)):
+                assert t.is_cuda and t.dtype == dt and t.is_contiguous()
+            where = MEM_DEVICE
         self.nnz = int(col.shape[0])
         h = _p()
         ctx.sync_stream()
         _check(_lib.labpsd_problem_create(ctx.h, self.n, self.nnz, _ptr(rowptr), _ptr(col), _ptr(h_val),
-                                          _ptr(s_val), ctypes.byref(h)), "labpsd_problem_create")
+                                          _ptr(s_val), where, ctypes.byref(h)), "labpsd_problem_create")
         self.h = h
 
     @classmethod
@@ -220,13 +231,23 @@ class Problem:
         return cls(ctx, P.n, P.rowptr, P.col, P.h_val, P.s_val)
 
     def update_h(self, h_val):
-        h_val = np.ascontiguousarray(h_val, dtype=np.float64)
-        _check(_lib.labpsd_problem_update_h(self.h, _ptr(h_val)), "labpsd_problem_update_h")
+        """New H values on the same pattern: numpy array or torch device tensor."""
+        if isinstance(h_val, np.ndarray) or not hasattr(h_val, "is_cuda"):
+            h_val = np.ascontiguousarray(h_val, dtype=np.float64)
+            where = MEM_HOST
+        else:
+            import torch
+            assert h_val.is_cuda and h_val.dtype == torch.float64 and h_val.is_contiguous()
+            where = MEM_DEVICE
+        self.ctx.sync_stream()
+        _check(_lib.labpsd_problem_update_h(self.h, _ptr(h_val), where), "labpsd_problem_update_h")
 
-    def set_global_precond(self, eps_bar: float, coords=None):
+    def set_global_precond(self, eps_bar: float, coords=None, panels: int = 0):
+        """panels: PANELS_FP64 | PANELS_FP32 mask of the factor copies to upload (0: both)."""
         c = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64).reshape(-1, 3)
         self.ctx.sync_stream()
-        _check(_lib.labpsd_set_global_precond(self.h, float(eps_bar), _ptr(c)), "labpsd_set_global_precond")
+        _check(_lib.labpsd_set_global_precond(self.h, float(eps_bar), _ptr(c), int(panels)),
+               "labpsd_set_global_precond")
 
     def set_local_precond(self, tau1=0.1, tau2=0.1, eta=0.25, max_inner=20, mode=HYBRID):
         _check(_lib.labpsd_set_local_precond(self.h, tau1, tau2, eta, max_inner, mode),
@@ -238,14 +259,18 @@ class Problem:
         return {f: getattr(fi, f) for f, _ in fi._fields_}
 
     def solve(self, nev: int, m0: int, X0, *, tol=1e-8, max_outer=200, sigma0=0.0,
-              precision=FP64, refresh_every=10, timing=False, E0=None, device_out=False, reorth_tol=0.0):
-        """Run LABPSD from X0 (numpy n x b Fortran array, or torch (b, n) device tensor).
+              precision=FP64, refresh_every=10, timing=False, E0=None, device_out=False, reorth_tol=0.0,
+              seed=0):
+        """Run LABPSD from X0 (numpy n x b Fortran array, torch (b, n) device tensor, or None for
+        the library's seeded random start).
         reorth_tol: threshold on max |Psi^T S Psi - I| at a refresh (0: 1e-10; negative: always)."""
         import torch
         b = nev + m0
         n = self.n
         self.ctx.sync_stream()
-        if isinstance(X0, np.ndarray):
+        if X0 is None:
+            in_where = MEM_HOST
+        elif isinstance(X0, np.ndarray):
             X0 = np.asfortranarray(X0, dtype=np.float64)
             assert X0.shape == (n, b)
             in_where = MEM_HOST
@@ -254,7 +279,7 @@ class Problem:
             in_where = MEM_DEVICE
         E0a = None if E0 is None else np.ascontiguousarray(E0, dtype=np.float64)
         prm = SolveParams(nev, m0, tol, max_outer, sigma0, precision, refresh_every, 1 if timing else 0,
-                          reorth_tol)
+                          reorth_tol, seed)
         hist = np.zeros(max_outer * nev + nev)
         rhist = np.zeros((max_outer + 1) * b)
         nh = ctypes.c_int(0)

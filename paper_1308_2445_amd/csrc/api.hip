@@ -121,7 +121,7 @@ Problem::~Problem() { delete factor; }
 
 // ------------------------------------------------------------------ factor upload
 
-static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
+static void upload_factor(Problem& P, const HostFactor& H, double eps_bar, unsigned panels) {
     hipStream_t s = P.ctx->stream;
     auto F = std::make_unique<DevFactor>();
     F->n = H.n;
@@ -129,8 +129,8 @@ static void upload_factor(Problem& P, const HostFactor& H, double eps_bar) {
     F->nlevels = H.nlevels;
     F->eps_bar = eps_bar;
     F->rows.upload(H.rows.data(), H.rows.size(), s);
-    F->panels64.upload(H.panels.data(), H.panels.size(), s);
-    {
+    if (panels & LABPSD_PANELS_FP64) F->panels64.upload(H.panels.data(), H.panels.size(), s);
+    if (panels & LABPSD_PANELS_FP32) {
         std::vector<float> p32(H.panels.size());
         for (size_t i = 0; i < p32.size(); ++i) p32[i] = (float)H.panels[i];
         F->panels32.upload(p32.data(), p32.size(), s);
@@ -371,12 +371,16 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     int cur = 0;
     auto Z = [&](int which) { return B.Zb[cur][which]; };
 
-    // steps 1-3: start block, its products and one Rayleigh-Ritz step on span(X0)
-    LABPSD_HIP(hipMemcpy2DAsync(Z(0), ldz * sizeof(double), X0, n * sizeof(double),
-                                n * sizeof(double), b,
-                                in_where == LABPSD_MEM_DEVICE ? hipMemcpyDeviceToDevice
-                                                              : hipMemcpyHostToDevice,
-                                s));
+    // steps 1-3: start block (given, or the seeded random block of a cold start), its
+    // products and one Rayleigh-Ritz step on span(X0)
+    if (X0)
+        LABPSD_HIP(hipMemcpy2DAsync(Z(0), ldz * sizeof(double), X0, n * sizeof(double),
+                                    n * sizeof(double), b,
+                                    in_where == LABPSD_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                                  : hipMemcpyHostToDevice,
+                                    s));
+    else
+        launch_random_block(n, b, prm.seed, Z(0), ldz, s);
     tm.begin(S_PROD_PSI);
     launch_spmm_hs(P.sell, Z(0), ldz, b, Z(1), Z(2), ldz, s);
     tm.end();
@@ -713,6 +717,31 @@ static void local_refine_impl(Problem* p, DBuf<T>& arena, const double* R, int64
 
 }  // namespace labpsd
 
+namespace labpsd {
+// Host copies of caller arrays that may live on the device (read synchronously on the
+// context's stream) or on the host (used in place).
+template <typename T>
+static const T* host_view(labpsd_ctx* ctx, const T* a, size_t count, labpsd_mem where,
+                          std::vector<T>& keep) {
+    if (where == LABPSD_MEM_HOST) return a;
+    LABPSD_REQUIRE(where == LABPSD_MEM_DEVICE, "invalid memory kind");
+    keep.resize(count);
+    if (count) {
+        LABPSD_HIP(hipMemcpyAsync(keep.data(), a, count * sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+        LABPSD_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    return keep.data();
+}
+
+// ESTATE unless the global factor's panels for this solve precision were uploaded
+static void require_panels(const Problem& P, int precision) {
+    if (precision == LABPSD_MIXED && !P.factor->panels32.p)
+        throw Error{LABPSD_ESTATE, "FP32 factor panels were not uploaded (precision mask)"};
+    if (precision == LABPSD_FP64 && !P.factor->panels64.p)
+        throw Error{LABPSD_ESTATE, "FP64 factor panels were not uploaded (precision mask)"};
+}
+}  // namespace labpsd
+
 extern "C" {
 
 const char* labpsd_last_error(void) { return labpsd::get_error(); }
@@ -747,15 +776,23 @@ labpsd_status labpsd_ctx_set_stream(labpsd_ctx* ctx, void* stream) {
     });
 }
 
-labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
-                                    const int32_t* col, const double* h_val, const double* s_val,
-                                    labpsd_problem** out) {
+labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr_in,
+                                    const int32_t* col_in, const double* h_in, const double* s_in,
+                                    labpsd_mem where, labpsd_problem** out) {
     return guarded([&]() -> labpsd_status {
-        LABPSD_REQUIRE(ctx && out && rowptr && col && h_val && s_val, "NULL argument");
+        LABPSD_REQUIRE(ctx && out && rowptr_in && col_in && h_in && s_in, "NULL argument");
         *out = nullptr;
         LABPSD_REQUIRE(n >= 1 && n < (int64_t)INT32_MAX, "n out of range");
         LABPSD_REQUIRE(nnz >= n, "nnz smaller than n");
+        LABPSD_HIP(hipSetDevice(ctx->device));
+        std::vector<int64_t> rp_keep;
+        const int64_t* rowptr = host_view(ctx, rowptr_in, (size_t)n + 1, where, rp_keep);
         LABPSD_REQUIRE(rowptr[0] == 0 && rowptr[n] == nnz, "rowptr does not span [0, nnz]");
+        std::vector<int32_t> col_keep;
+        std::vector<double> h_keep, s_keep;
+        const int32_t* col = host_view(ctx, col_in, (size_t)nnz, where, col_keep);
+        const double* h_val = host_view(ctx, h_in, (size_t)nnz, where, h_keep);
+        const double* s_val = host_view(ctx, s_in, (size_t)nnz, where, s_keep);
         for (int64_t i = 0; i < n; ++i) {
             LABPSD_REQUIRE(rowptr[i + 1] > rowptr[i], "empty row " + std::to_string(i));
             for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
@@ -773,7 +810,6 @@ labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz, con
                                "pattern not structurally symmetric at (" + std::to_string(i) + "," +
                                    std::to_string(j) + ")");
             }
-        LABPSD_HIP(hipSetDevice(ctx->device));
         auto p = std::make_unique<labpsd_problem>();
         p->ctx = ctx;
         p->n = n;
@@ -790,9 +826,12 @@ labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz, con
     });
 }
 
-labpsd_status labpsd_problem_update_h(labpsd_problem* p, const double* h_val) {
+labpsd_status labpsd_problem_update_h(labpsd_problem* p, const double* h_in, labpsd_mem where) {
     return guarded([&]() -> labpsd_status {
-        LABPSD_REQUIRE(p && h_val, "NULL argument");
+        LABPSD_REQUIRE(p && h_in, "NULL argument");
+        LABPSD_HIP(hipSetDevice(p->ctx->device));
+        std::vector<double> keep;
+        const double* h_val = host_view(p->ctx, h_in, (size_t)p->nnz, where, keep);
         p->h_val.assign(h_val, h_val + p->nnz);
         refresh_sell_h(p->sell, h_val, p->ctx->stream);
         return LABPSD_OK;
@@ -803,10 +842,15 @@ void labpsd_problem_destroy(labpsd_problem* p) { delete p; }
 
 int64_t labpsd_problem_n(const labpsd_problem* p) { return p ? p->n : -1; }
 
-labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const double* coords) {
+labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const double* coords,
+                                        unsigned precisions) {
     return guarded([&]() -> labpsd_status {
         LABPSD_REQUIRE(p != nullptr, "problem is NULL");
         LABPSD_REQUIRE(std::isfinite(eps_bar), "eps_bar must be finite");
+        LABPSD_REQUIRE((precisions & ~(unsigned)(LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32)) == 0,
+                       "precision mask has unknown bits");
+        const unsigned panels = precisions ? precisions : (LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32);
+        LABPSD_HIP(hipSetDevice(p->ctx->device));
         std::vector<double> kval(p->nnz);
         for (int64_t e = 0; e < p->nnz; ++e) kval[e] = p->h_val[e] - eps_bar * p->s_val[e];
         HostFactor F;
@@ -815,7 +859,7 @@ labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const
         if (rc == -4) throw Error{LABPSD_ENOTSPD, msg};
         if (rc != 0) throw Error{LABPSD_EINVAL, msg};
         const double t0 = wall();
-        upload_factor(*p, F, eps_bar);
+        upload_factor(*p, F, eps_bar, panels);
         p->factor->info.t_upload_s = wall() - t0;
         return LABPSD_OK;
     });
@@ -850,8 +894,9 @@ labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* prm, co
                            const double* E0, labpsd_mem in_where, double* lambda, double* X,
                            double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats) {
     return guarded([&]() -> labpsd_status {
-        LABPSD_REQUIRE(p && prm && X0 && lambda && X, "NULL argument");
+        LABPSD_REQUIRE(p && prm && lambda && X, "NULL argument");
         if (!p->factor) throw Error{LABPSD_ESTATE, "labpsd_set_global_precond must come first"};
+        require_panels(*p, prm->precision);
         LABPSD_REQUIRE(prm->nev >= 1 && prm->m0 >= 0, "nev must be >= 1 and m0 >= 0");
         LABPSD_REQUIRE((int64_t)(2 * prm->nev + prm->m0) <= p->n, "n < 2 nev + m0");
         LABPSD_REQUIRE(prm->nev + prm->m0 + prm->nev <= kRRMax, "block too wide");
@@ -913,6 +958,7 @@ labpsd_status labpsd_precond_apply(labpsd_problem* p, int precision, const doubl
         LABPSD_REQUIRE(p && R && Pout, "NULL argument");
         if (!p->factor) throw Error{LABPSD_ESTATE, "no global preconditioner set"};
         LABPSD_REQUIRE(ncols >= 0 && ldr >= p->n && ldp >= p->n, "bad sizes");
+        require_panels(*p, precision);
         if (ncols == 0) return LABPSD_OK;
         hipStream_t s = p->ctx->stream;
         const int64_t n = p->n;

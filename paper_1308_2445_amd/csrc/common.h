@@ -396,6 +396,9 @@ template <typename T>
 void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
                        int64_t ldy, hipStream_t s);
 
+// X (n x b, ld ldx) := i.i.d. standard normals, entry (i, j) from counter i + n j of `seed`
+void launch_random_block(int64_t n, int b, uint64_t seed, double* X, int64_t ldx, hipStream_t s);
+
 // residual and per-column norms (partials reduced by launch_residual_finish)
 void launch_residual(int64_t n, int m, const double* PsiH, const double* PsiS, int64_t ld,
                      const double* E, double sigma0, double* R, int64_t ldr, double* partial,

@@ -77,6 +77,30 @@ __global__ void k_residual_finish(int m, const double* __restrict__ partial, int
     }
 }
 
+// ------------------------------------------------------------------ seeded start block
+
+// splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014) applied to a
+// counter: the k-th output of the generator started at `seed`.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// X(i, j) = Box-Muller normal from outputs 2c and 2c + 1, c = i + n j
+__global__ __launch_bounds__(256) void k_random_block(int64_t n, int64_t total, uint64_t seed,
+                                                      double* __restrict__ X, int64_t ldx) {
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
+        const uint64_t a = splitmix64_at(seed, 2 * (uint64_t)c), b = splitmix64_at(seed, 2 * (uint64_t)c + 1);
+        const double u1 = (double)((a >> 11) + 1) * 0x1.0p-53;   // (0, 1]
+        const double u2 = (double)(b >> 11) * 0x1.0p-53;         // [0, 1)
+        const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+        const int64_t i = c % n, j = c / n;
+        X[i + j * ldx] = z;
+    }
+}
+
 // ------------------------------------------------------------------ gather / cast
 
 template <typename TS, typename TD>
@@ -427,6 +451,14 @@ __global__ __launch_bounds__(256) void k_orth_deviation(int b, const double* __r
 }
 
 }  // namespace
+
+void launch_random_block(int64_t n, int b, uint64_t seed, double* X, int64_t ldx, hipStream_t s) {
+    const int64_t total = n * (int64_t)b;
+    if (total <= 0) return;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_random_block, dim3((unsigned)blocks), dim3(256), 0, s, n, total, seed, X, ldx);
+    LABPSD_HIP(hipGetLastError());
+}
 
 int residual_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kResRows - 1) / kResRows); }
 
