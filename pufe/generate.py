@@ -166,8 +166,14 @@ def _potential_at(elem_ijk: np.ndarray, xi: np.ndarray, h: float,
 
 
 def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
-             atoms: np.ndarray | None = None) -> Problem:
-    """Assemble the PUFE-shaped pencil for a periodic cube (see module docstring)."""
+             atoms: np.ndarray | None = None, alpha: float = ENRICH_ALPHA) -> Problem:
+    """Assemble the PUFE-shaped pencil for a periodic cube (see module docstring).
+
+    alpha is the exponent of the enrichment g(r) = exp(-alpha |r - R|^2).  The named
+    workloads use 1.0; a smaller alpha makes g flatter over a node's support, so each
+    enriched function approaches a multiple of its hat function and S approaches
+    singularity (cond(S) grows roughly like 1/alpha^2), the regime of Section 2's
+    Table 1 where enrichment drives cond(S) to 1e8 and beyond."""
     h = L / ne
     nnode = ne ** 3
     if atoms is None:
@@ -287,8 +293,8 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
                 dd -= L * np.round(dd / L)
                 Rstar = xnode - dd                                      # nearest image to the node
                 u = rq - Rstar[:, None, :]                              # (e,nq,3)
-                g = np.exp(-ENRICH_ALPHA * np.einsum("eqd,eqd->eq", u, u))
-                dg = -2.0 * ENRICH_ALPHA * u * g[..., None]
+                g = np.exp(-alpha * np.einsum("eqd,eqd->eq", u, u))
+                dg = -2.0 * alpha * u * g[..., None]
                 m = has[:, None]
                 phi[:, :, slot] = np.where(m, N4[None, :, a] * g, 0.0)
                 gr = g[..., None] * (dN4[None, :, a, :] / h) + N4[None, :, a, None] * dg
@@ -379,6 +385,9 @@ WORKLOADS = {
     "c2": dict(L=12.0, ne=24, natoms=8, nev=32),
     "c3": dict(L=24.0, ne=48, natoms=64, nev=256),
     "c5": dict(L=32.0, ne=64, natoms=128, nev=512),
+    # the 250- and 16k-dof cells with flat enrichments: cond(S) above 1e8
+    "c1i": dict(L=6.0, ne=6, natoms=1, nev=4, alpha=1e-3),
+    "c2i": dict(L=12.0, ne=24, natoms=8, nev=32, alpha=1e-2),
 }
 
 
@@ -389,6 +398,8 @@ def guard_vectors(nev: int) -> int:
 
 def workload(name: str, seed: int = 0, **kw) -> Problem:
     w = WORKLOADS[name]
+    if "alpha" in w:
+        kw.setdefault("alpha", w["alpha"])
     return generate(w["L"], w["ne"], w["natoms"], seed, **kw)
 
 

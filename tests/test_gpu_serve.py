@@ -59,6 +59,8 @@ def _run(ctx, pencils, slots, budget, precision):
     r1 = [srv.wait(r) for r in first]
     r2 = [srv.wait(r) for r in second]
     srv.close()
+    for pr in systems:
+        pr.close()
     return r1, r2
 
 

@@ -37,8 +37,11 @@ def host(t):
 @pytest.fixture(scope="module")
 def ctx():
     import paper_1308_2445_amd as lp
-    _torch()
-    return lp.Context(0)
+    torch = _torch()
+    c = lp.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
 
 
 @pytest.fixture(scope="module", params=["c1", "c2"])
@@ -48,7 +51,8 @@ def prob(request, ctx):
     print("\n[case] workload=%s n=%d nnz=%d" % (request.param, P.n, P.nnz), flush=True)
     pr = lp.Problem.from_pencil(ctx, P)
     pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P))
-    return P, pr
+    yield P, pr
+    pr.close()
 
 
 def test_spmm_fused(prob):

@@ -42,7 +42,9 @@ def c3():
     ctx = lp.Context(0)
     pr = lp.Problem.from_pencil(ctx, P)
     pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P))
-    return P, pr, g, {}
+    yield P, pr, g, {}
+    pr.close()
+    ctx.close()
 
 
 def _solve(c3, precision):
@@ -98,7 +100,9 @@ def c5():
     ctx = lp.Context(0)
     pr = lp.Problem.from_pencil(ctx, P)
     pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P))
-    return P, pr
+    yield P, pr
+    pr.close()
+    ctx.close()
 
 
 @pytest.mark.timeout(900)
@@ -124,3 +128,114 @@ def test_c5_full_size_properties(c5):
     d = _rel(outs[1].lam, outs[0].lam, P.sigma0)
     print("[c5] per-eigenpair mixed vs FP64: max %.2e median %.2e" % (d.max(), np.median(d)), flush=True)
     assert d.max() < 1e-10
+
+
+def _golden_eigsh(name):
+    path = os.path.join(GOLDEN, "%s_eigs.json" % name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    return g if "lam_eigsh" in g else None
+
+
+@pytest.mark.timeout(900)
+def test_c5_eigenvalues_match_shift_invert_route(c5):
+    """The 296k-dof cell's 512 eigenvalues against an independent CPU route, ARPACK
+    shift-invert Lanczos on (H - eps_bar S)^-1 S (stored by tests/golden/make_golden.py
+    --eigsh c5), in both precisions: this pins that the returned pairs are the LOWEST 512,
+    which residual and orthonormality checks alone cannot."""
+    g = _golden_eigsh("c5")
+    if g is None:
+        pytest.skip("no stored shift-invert eigenvalues for the 296k-dof cell")
+    P, pr = c5
+    assert g["n"] == P.n and g["nnz"] == P.nnz
+    m = g["nev"]
+    m0 = pufe.guard_vectors(m)
+    for precision in (0, 1):
+        print("\n[case] c5 vs eigsh precision=%d" % precision, flush=True)
+        out = pr.solve(m, m0, None, tol=TOL, sigma0=P.sigma0, precision=precision, seed=3)
+        assert out.converged, out.stats
+        err = _rel(out.lam, g["lam_eigsh"], P.sigma0)
+        print("[c5] precision=%d max rel eig err vs eigsh %.2e (median %.2e)"
+              % (precision, err.max(), np.median(err)), flush=True)
+        assert err.max() < 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_c3_matches_shift_invert_route(c3):
+    g = _golden_eigsh("c3")
+    if g is None:
+        pytest.skip("no stored shift-invert eigenvalues for the 128k-dof cell")
+    P, _, _, _ = c3
+    for precision in (1, 0):
+        out = _solve(c3, precision)
+        err = _rel(out.lam, g["lam_eigsh"], P.sigma0)
+        print("[c3] precision=%d max rel eig err vs eigsh %.2e" % (precision, err.max()), flush=True)
+        assert err.max() < 1e-10
+
+
+def _fourier_shells(ne):
+    """Exact invariant subspaces of the periodic trilinear pencil with V = 0 and no
+    enrichment, for its four lowest eigenvalues: the separable modes f(i) g(j) h(k) with
+    each factor 1, cos(2 pi x / ne) or sin(2 pi x / ne); shell s has s factors of wave
+    number 1 (C(3, s) 2^s modes: 1, 6, 12, 8).  Vector index i + ne j + ne^2 k."""
+    x = np.arange(ne)
+    one = [np.ones(ne)]
+    wave = [np.cos(2 * np.pi * x / ne), np.sin(2 * np.pi * x / ne)]
+    shells = [[], [], [], []]
+    import itertools
+    for ti in range(2):
+        for tj in range(2):
+            for tk in range(2):
+                for fi in (wave if ti else one):
+                    for fj in (wave if tj else one):
+                        for fk in (wave if tk else one):
+                            v = (fk[:, None, None] * fj[None, :, None] * fi[None, None, :]).ravel()
+                            shells[ti + tj + tk].append(v)
+    return [np.stack(s, axis=1) for s in shells]
+
+
+@pytest.mark.timeout(900)
+def test_free_particle_64cubed_shells():
+    """The 64^3-element cell with no atoms (262,144 dofs, the largest cell's mesh): V = 0,
+    so the spectrum and the eigenvectors are known in closed form.  nev = 27 ends exactly
+    at a shell boundary (1 + 6 + 12 + 8; the next shell is 6-fold and separated), so every
+    shell's invariant subspace is well posed: eigenvalues to 1e-10 relative and each
+    shell's S-principal angles to the exact Fourier modes below 1e-7."""
+    lp = _lp()
+    ne, L = 64, 32.0
+    P = pufe.generate(L, ne, 0, 0)
+    assert P.n == ne ** 3
+    ctx = lp.Context(0)
+    pr = lp.Problem.from_pencil(ctx, P)
+    pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P))
+    ref = pufe.free_particle_eigs(ne, L, 33)
+    shells = _fourier_shells(ne)
+    sizes = [s.shape[1] for s in shells]
+    assert sizes == [1, 6, 12, 8]
+    # the closed-form modes are eigenvectors of the assembled pencil (a check of the
+    # formula itself): H v = lambda S v with lambda the shell's value
+    H, S = P.H(), P.S()
+    starts = np.cumsum([0] + sizes)
+    for s, V in enumerate(shells):
+        lam_s = ref[starts[s]]
+        Rm = H @ V - lam_s * (S @ V)
+        assert np.abs(Rm).max() <= 1e-12 * abs(H).max()
+    assert ref[27] - ref[26] > 0.1 * ref[26]            # the wanted set ends at a gap
+    for precision in (0, 1):
+        print("\n[case] free particle 64^3 nev=27 precision=%d" % precision, flush=True)
+        out = pr.solve(27, 4, None, tol=1e-10, sigma0=P.sigma0, precision=precision, seed=11)
+        assert out.converged, out.stats
+        err = _rel(out.lam, ref[:27], P.sigma0)
+        assert err.max() < 1e-10, err.max()
+        worst = 0.0
+        for s, V in enumerate(shells):
+            cols = list(range(starts[s], starts[s + 1]))
+            ang = oeig.s_principal_angles(S, out.X[:, cols], V)
+            worst = max(worst, float(ang.max()))
+        print("[free] precision=%d iters=%d max eig err %.2e max shell angle %.2e"
+              % (precision, out.stats["outer_iters"], err.max(), worst), flush=True)
+        assert worst < 1e-7
+    pr.close()
+    ctx.close()
