@@ -215,6 +215,17 @@ labpsd_status labpsd_residual(labpsd_ctx* ctx, int64_t n, int m, const double* P
                               const double* PsiS, int64_t ld, const double* E, double sigma0,
                               double* R, int64_t ldr, double* res, double* rnorm);
 
+/* As labpsd_residual, but allocates nothing: for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc).
+ * Its partial sums go to a static device array of 2^17 doubles (1 MiB) that each GPU
+ * holds for the life of the process; sizes with 2 * ceil(n / 4096) * m above that
+ * return EINVAL.  Every call on one GPU shares the array: calls that overlap on one GPU
+ * race.  Pointers and layouts as labpsd_residual; nothing needs clearing first.       */
+labpsd_status labpsd_residual_noalloc(labpsd_ctx* ctx, int64_t n, int m, const double* PsiH,
+                                      const double* PsiS, int64_t ld, const double* E,
+                                      double sigma0, double* R, int64_t ldr, double* res,
+                                      double* rnorm);
+
 /* Step 6(a), eq. (k1p): P = -(H - eps_bar S)^{-1} R for p columns (R, P n x p).
  * precision LABPSD_MIXED runs the substitutions in FP32 on FP32 factor panels. */
 labpsd_status labpsd_precond_apply(labpsd_problem* p, int precision, const double* R, int64_t ldr,

@@ -102,6 +102,7 @@ _SIGS = {
     "labpsd_spmm": ([_p, _p, _i64, _i32, _p, _p, _i64], _i32),
     "labpsd_spmm_shifted": ([_p, _i32, _p, _i64, _i32, _p, _p, _i64], _i32),
     "labpsd_residual": ([_p, _i64, _i32, _p, _p, _i64, _p, _d, _p, _i64, _p, _p], _i32),
+    "labpsd_residual_noalloc": ([_p, _i64, _i32, _p, _p, _i64, _p, _d, _p, _i64, _p, _p], _i32),
     "labpsd_precond_apply": ([_p, _i32, _p, _i64, _i32, _p, _i64], _i32),
     "labpsd_local_refine": ([_p, _i32, _p, _i64, _p, _i64, _i32, _p, _p, _d, _i32, _p], _i32),
     "labpsd_gram": ([_p, _i64, _i32, _p, _p, _p, _i64, _p, _p, _i64], _i32),
@@ -334,6 +335,12 @@ def labpsd_residual(ctx: Context, n: int, m: int, PsiH, PsiS, E, sigma0: float, 
     ctx.sync_stream()
     _check(_lib.labpsd_residual(ctx.h, n, m, _ptr(PsiH), _ptr(PsiS), _ld(PsiH), _ptr(E), sigma0, _ptr(R),
                                 _ld(R), _ptr(res), _ptr(rnorm)), "labpsd_residual")
+
+
+def labpsd_residual_noalloc(ctx: Context, n: int, m: int, PsiH, PsiS, E, sigma0: float, R, res, rnorm):
+    ctx.sync_stream()
+    _check(_lib.labpsd_residual_noalloc(ctx.h, n, m, _ptr(PsiH), _ptr(PsiS), _ld(PsiH), _ptr(E), sigma0,
+                                        _ptr(R), _ld(R), _ptr(res), _ptr(rnorm)), "labpsd_residual_noalloc")
 
 
 def labpsd_precond_apply(prob: Problem, precision: int, R, P):

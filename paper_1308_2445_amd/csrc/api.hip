@@ -761,6 +761,7 @@ labpsd_status labpsd_ctx_create(int device, void* stream, labpsd_ctx** out) {
         hipDeviceProp_t prop;
         LABPSD_HIP(hipGetDeviceProperties(&prop, device));
         c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        noalloc_setup(device);
         *out = c.release();
         return LABPSD_OK;
     });

@@ -372,6 +372,11 @@ struct labpsd_problem : labpsd::Problem {};
 
 namespace labpsd {
 
+// Resolve the device address of the allocation-free entry points' static scratch array
+// on `device` (must be the current device); idempotent.
+void noalloc_setup(int device);
+size_t noalloc_scratch_doubles();
+
 // Run one LABPSD solve of P on `stream` (the driver of labpsd_solve).
 labpsd_status run_solve(Problem& P, const labpsd_solve_params& prm, const double* X0,
                         const double* E0, labpsd_mem in_where, double* lambda, double* X,
