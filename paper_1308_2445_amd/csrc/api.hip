@@ -478,11 +478,13 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     auto residuals = [&]() {
         tm.begin(S_RESID);
         launch_residual(n, m, Z(1), Z(2), ldz, B.gamma, prm.sigma0, B.R, n, B.red, nblk, s);
-        launch_residual_finish(m, B.red, nblk, B.res, B.rnorm, s, d_rb);
+        // the global apply's error word (a dependency wait that ran out) comes back with Res
+        launch_residual_finish(m, B.red, nblk, B.res, B.rnorm, s, d_rb, P.factor->sweep_cnt.p, d_ib + m + 2);
         tm.end();
         st.n_launch[S_RESID] += 1;
         st.n_cols[S_RESID] += m;
         spin_sync(s, ev_sync);
+        if (h_ib.p[m + 2] != 0) check_precond_sweep(*P.factor, s);   // raises EHIP
         for (int i = 0; i < m; ++i) { res[i] = h_rb.p[i]; rn[i] = h_rb.p[m + i]; }
     };
     auto maxres = [&]() {

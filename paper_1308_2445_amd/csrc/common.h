@@ -408,9 +408,11 @@ void launch_random_block(int64_t n, int b, uint64_t seed, double* X, int64_t ldx
 void launch_residual(int64_t n, int m, const double* PsiH, const double* PsiS, int64_t ld,
                      const double* E, double sigma0, double* R, int64_t ldr, double* partial,
                      int nblk, hipStream_t s);
-// host: optional device-mapped pinned memory that also receives [Res | norms] (2 m)
+// host: optional device-mapped pinned memory that also receives [Res | norms] (2 m);
+// flag_dst (optional, device-visible) receives *flag_src (0 if flag_src is null)
 void launch_residual_finish(int m, const double* partial, int nblk, double* res, double* rnorm,
-                            hipStream_t s, double* host = nullptr);
+                            hipStream_t s, double* host = nullptr, const int32_t* flag_src = nullptr,
+                            int32_t* flag_dst = nullptr);
 int residual_blocks(int64_t n);
 
 // Gram: HR = Z^T ZH, SR = Z^T ZS (symmetric parts); partial workspace sized by gram_ws

@@ -60,8 +60,11 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, const double* __res
 
 __global__ void k_residual_finish(int m, const double* __restrict__ partial, int nblk,
                                   double* __restrict__ res, double* __restrict__ rnorm,
-                                  double* __restrict__ host) {
+                                  double* __restrict__ host, const int32_t* __restrict__ flag_src,
+                                  int32_t* __restrict__ flag_dst) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (flag_dst && j == 0)   // an error word of earlier work, carried to the host with Res
+        flag_dst[0] = flag_src ? __hip_atomic_load(flag_src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     if (j >= m) return;
     double a = 0.0, b = 0.0;
     for (int k = 0; k < nblk; ++k) {
@@ -472,10 +475,10 @@ void launch_residual(int64_t n, int m, const double* PsiH, const double* PsiS, i
 }
 
 void launch_residual_finish(int m, const double* partial, int nblk, double* res, double* rnorm,
-                            hipStream_t s, double* host) {
+                            hipStream_t s, double* host, const int32_t* flag_src, int32_t* flag_dst) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_residual_finish, dim3((m + 255) / 256), dim3(256), 0, s, m, partial, nblk,
-                       res, rnorm, host);
+                       res, rnorm, host, flag_src, flag_dst);
     LABPSD_HIP(hipGetLastError());
 }
 

@@ -191,12 +191,17 @@ __global__ __launch_bounds__(256) void k_sn_product(const SnTask* __restrict__ t
 // finishes whatever happens.
 constexpr int kSweepSpinLimit = 1 << 20;
 
-// The whole solve in one launch.  Work-group b runs task b / groups on right-hand-side
-// group b % groups (the groups of a task side by side, so they advance together).  Before its product a task waits until (forward and diagonal) every
-// child supernode has finished its forward products, or (backward) the parent has
-// finished its diagonal and backward products; every dependency has a lower work-group
-// index, and work-groups start in index order, so the lowest unfinished one can always
-// run.  Results pass between work-groups only through device-scope atomics: a task's
+// The whole solve in one launch.  A work-group's logical index b is a ticket it takes
+// from a counter when it starts; it runs task b / groups on right-hand-side group
+// b % groups (the groups of a task side by side, so they advance together).  Before its
+// product a task waits until (forward and diagonal) every child supernode has finished
+// its forward products, or (backward) the parent has finished its diagonal and backward
+// products.  Every dependency has a lower task index, and a work-group holding ticket b
+// started after every holder of a lower ticket had started, so those are resident and
+// the lowest unfinished one can always run -- whatever order the XCDs dispatch the grid
+// in and whatever other kernels share the device (the hardware index order gives no such
+// guarantee on a multi-XCD part).  Results pass between work-groups only through
+// device-scope atomics: a task's
 // outputs are atomic adds, which it waits for (vmcnt) before counting itself off with an
 // atomic; the last forward task of a supernode counts the supernode off at its parent;
 // a waiting task polls its counter and reads right-hand-side rows with device-scope
@@ -207,7 +212,11 @@ __global__ __launch_bounds__(256) void k_sn_sweep(const SweepTask* __restrict__ 
                                                   const T* __restrict__ panels, T* Y, T* W2, int nrhs,
                                                   int32_t* cnt, int nsn, int groups) {
     __shared__ SnTiles<T, NC> st;
-    const int64_t b = blockIdx.x;
+    __shared__ int32_t s_ticket;
+    if (threadIdx.x == 0)
+        s_ticket = __hip_atomic_fetch_add(cnt + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t b = s_ticket;
     const int64_t ti = b / groups;
     const int cg = (int)(b - ti * groups);
     const SweepTask tk = tasks[ti];
@@ -253,12 +262,14 @@ __global__ __launch_bounds__(256) void k_sn_sweep(const SweepTask* __restrict__ 
     }
 }
 
-// W2 = 0 and the sweep counters of `groups` right-hand-side groups from their template
+// W2 = 0, the ticket counter = 0 and the sweep counters of `groups` right-hand-side
+// groups from their template (the error word, cnt[0], is left for the host to read)
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweep_init(int64_t count, T* __restrict__ W2,
                                                     const int32_t* __restrict__ init, int64_t ninit,
                                                     int32_t* __restrict__ cnt, int groups) {
     const int64_t stride = (int64_t)gridDim.x * 256;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[1] = 0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) W2[i] = T(0);
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ninit * groups; i += stride)
         cnt[4 + i] = init[i % ninit];
