@@ -45,6 +45,7 @@ class Params:
     eta: float = 0.25              # inexact local solve (eq. (approxp)), Section 5
     max_inner: int = 20            # MINRES cap (Section 5)
     mode: str = "hybrid"           # "hybrid" | "global" | "local"
+    refine: str = "minres"         # "minres" (Section 4) | "onestep" (the conclusions' variant)
     refresh_every: int = 10
 
     @property
@@ -119,6 +120,34 @@ def local_refine(H, S, p, r, eps: float, eta: float, max_inner: int):
     return p + dp, its
 
 
+def one_step_refine(H, S, p, r, eps: float, eta: float, max_inner: int):
+    """The first-order one-step refinement the conclusions propose in place of MINRES:
+    p <- p - alpha [(H - eps S) p + r], alpha chosen to minimise the residual norm of
+    eq. (idealp), ||(H - eps S) p_new + r||, for that step.  (The printed update has
+    '- r_i' inside the bracket, which would minimise ||(H - eps S) p - r||; with eq.
+    (idealp)'s right-hand side -r_i the bracket is that equation's residual, + r_i.)
+    Each step recomputes rho = (H - eps S) p + r from p; alpha = rho.A rho / ||A rho||^2
+    is the minimiser of ||rho - alpha A rho|| over alpha.  Stops when ||rho|| <= eta ||r||
+    (eq. (approxp)) or after max_inner steps.  Returns (p_new, steps)."""
+    def A(v):
+        return H @ v - eps * (S @ v)
+    target = eta * float(np.linalg.norm(r))
+    p = np.array(p, dtype=np.float64, copy=True)
+    steps = 0
+    for _ in range(max_inner):
+        rho = A(p) + r
+        if float(np.linalg.norm(rho)) <= target:
+            break
+        Arho = A(rho)
+        den = float(Arho @ Arho)
+        if den == 0.0:
+            break
+        alpha = float(rho @ Arho) / den
+        p = p - alpha * rho
+        steps += 1
+    return p, steps
+
+
 def initial_rr(H, S, X0, b: int):
     """Rayleigh-Ritz on span(X0): the start block becomes S-orthonormal Ritz vectors."""
     XH = H @ X0
@@ -178,10 +207,10 @@ def solve(H, S, params: Params, X0: np.ndarray, E0: np.ndarray | None = None,
                 P[:, np.searchsorted(U, i)] = 0.0
         # 6(b) local refinement of localised pairs
         its = np.zeros(loc.shape[0], dtype=np.int64)
+        refine = one_step_refine if params.refine == "onestep" else local_refine
         for j, i in enumerate(loc):
             c = int(np.searchsorted(U, i))
-            P[:, c], its[j] = local_refine(H, S, P[:, c], R[:, i], float(E[i]), params.eta,
-                                           params.max_inner)
+            P[:, c], its[j] = refine(H, S, P[:, c], R[:, i], float(E[i]), params.eta, params.max_inner)
         minres_total += int(its.sum())
         # step 7: products of P
         PH, PS = H @ P, S @ P
