@@ -124,6 +124,15 @@ labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const
 labpsd_status labpsd_set_local_precond(labpsd_problem* p, double tau1, double tau2, double eta,
                                        int max_inner, labpsd_precond_mode mode);
 
+/* How localised directions are refined (step 6(b)).  LABPSD_REFINE_MINRES: MINRES on
+ * eq. (indls) (Section 4; the default).  LABPSD_REFINE_ONESTEP: the first-order one-step
+ * method the conclusions propose instead, p <- p - alpha [(H - eps_i S) p + r_i] with
+ * alpha minimising ||(H - eps_i S) p + r_i|| at every step (the bracket read as eq.
+ * (idealp)'s residual, + r_i), under the same stopping test (eq. (approxp)) and cap.
+ * Applies to labpsd_solve and labpsd_local_refine of this problem.                  */
+typedef enum { LABPSD_REFINE_MINRES = 0, LABPSD_REFINE_ONESTEP = 1 } labpsd_refine_method;
+labpsd_status labpsd_set_refine_method(labpsd_problem* p, int method);
+
 /* Factor statistics: supernodes, levels, nnz(L), host factorisation seconds. */
 typedef struct {
     int64_t n_supernodes;
@@ -233,8 +242,8 @@ labpsd_status labpsd_precond_apply(labpsd_problem* p, int precision, const doubl
 
 /* Step 6(b): refine the columns cols[0..q) of P (n x *, ld ldp) in place so that
  * ||(H - shift_j S) p + r|| <= eta ||r||, r the matching column of R (ld ldr),
- * by MINRES on (H - shift_j S) dp = -((H - shift_j S) p + r) (eq. (indls)),
- * at most max_inner iterations.  cols: device int32[q] column indices into
+ * by MINRES on (H - shift_j S) dp = -((H - shift_j S) p + r) (eq. (indls)), or by
+ * the one-step method (labpsd_set_refine_method), at most max_inner iterations.  cols: device int32[q] column indices into
  * both P and R; shift: device float64[q]; its: device int32[q] iterations used.
  * precision LABPSD_MIXED runs MINRES in FP32.                                 */
 labpsd_status labpsd_local_refine(labpsd_problem* p, int precision, const double* R, int64_t ldr,

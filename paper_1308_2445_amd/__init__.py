@@ -32,6 +32,7 @@ EINVAL, ENOMEM, EHIP, ENOTSPD, ERANK, ESTATE = -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 PANELS_FP64, PANELS_FP32 = 1, 2
 HYBRID, GLOBAL_ONLY, LOCAL_ONLY = 0, 1, 2
+REFINE_MINRES, REFINE_ONESTEP = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 
 _STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
@@ -97,6 +98,7 @@ _SIGS = {
     "labpsd_set_global_precond": ([_p, _d, _p, ctypes.c_uint], _i32),
     "labpsd_set_local_precond": ([_p, _d, _d, _d, _i32, _i32], _i32),
     "labpsd_get_factor_info": ([_p, ctypes.POINTER(FactorInfo)], _i32),
+    "labpsd_set_refine_method": ([_p, _i32], _i32),
     "labpsd_solve": ([_p, ctypes.POINTER(SolveParams), _p, _p, _i32, _p, _p, _p, _p,
                       ctypes.POINTER(ctypes.c_int), _i32, ctypes.POINTER(Stats)], _i32),
     "labpsd_spmm": ([_p, _p, _i64, _i32, _p, _p, _i64], _i32),
@@ -253,6 +255,10 @@ class Problem:
     def set_local_precond(self, tau1=0.1, tau2=0.1, eta=0.25, max_inner=20, mode=HYBRID):
         _check(_lib.labpsd_set_local_precond(self.h, tau1, tau2, eta, max_inner, mode),
                "labpsd_set_local_precond")
+
+    def set_refine_method(self, method: int):
+        """REFINE_MINRES (Section 4) or REFINE_ONESTEP (the conclusions' one-step method)."""
+        _check(_lib.labpsd_set_refine_method(self.h, int(method)), "labpsd_set_refine_method")
 
     def factor_info(self) -> dict:
         fi = FactorInfo()

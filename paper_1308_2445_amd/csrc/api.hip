@@ -577,7 +577,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             int64_t nl = 0;
             run_minres<T>(P.sell, Wt.W1, n, Wt.RT, n, q, B.loc, B.shifts, B.stopn, lp.eta,
                           lp.max_inner, B.its, Wt.mres, B.scal, h_int.p, s, &nl, ev_flag0,
-                          ev_flag1, its_total);
+                          ev_flag1, its_total, lp.method);
             tm.end();
             st.n_launch[S_LOCAL] += nl;
             st.n_cols[S_LOCAL] += q;
@@ -712,7 +712,7 @@ static void local_refine_impl(Problem* p, DBuf<T>& arena, const double* R, int64
     HBuf<int32_t> flag;
     flag.alloc(2 * (size_t)q);
     run_minres<T>(p->sell, PT, n, RT, n, q, iota, shift, rn, eta, max_inner, its, mws, scal, flag.p, s,
-                  nullptr);
+                  nullptr, nullptr, nullptr, nullptr, p->local.method);
     launch_scatter_cast<T, double>(n, q, PT, n, cols, 1.0, Pm, ldp, s);
     LABPSD_HIP(hipStreamSynchronize(s));
 }
@@ -880,6 +880,16 @@ labpsd_status labpsd_set_local_precond(labpsd_problem* p, double tau1, double ta
         p->local.eta = eta;
         p->local.max_inner = max_inner;
         p->local.mode = mode;
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_set_refine_method(labpsd_problem* p, int method) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p != nullptr, "problem is NULL");
+        LABPSD_REQUIRE(method == LABPSD_REFINE_MINRES || method == LABPSD_REFINE_ONESTEP,
+                       "invalid refinement method");
+        p->local.method = method;
         return LABPSD_OK;
     });
 }

@@ -330,6 +330,7 @@ struct LocalParams {
     double tau1 = 0.1, tau2 = 0.1, eta = 0.25;
     int max_inner = 20;
     int mode = LABPSD_HYBRID;
+    int method = LABPSD_REFINE_MINRES;
 };
 
 struct Problem;
@@ -479,7 +480,8 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
                 int32_t* flag_host_pinned, hipStream_t s, int64_t* launches, hipEvent_t ev0 = nullptr,
-                hipEvent_t ev1 = nullptr, unsigned long long* its_total = nullptr);
+                hipEvent_t ev1 = nullptr, unsigned long long* its_total = nullptr,
+                int method = LABPSD_REFINE_MINRES);
 
 // Wait until everything enqueued on s so far has finished.  With an event the host polls
 // it (spins) instead of blocking, which shortens the wake-up after the small read-backs

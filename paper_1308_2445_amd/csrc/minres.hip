@@ -16,6 +16,8 @@
 // Every block recomputes the column's scalars from the partial sums (identical values);
 // block 0 of the column stores the new scalar state into the other half of a double
 // buffer, so no block reads a state that another block of the same kernel writes.
+// The one-step variant (the conclusions' first-order method) shares the SpMV and the
+// host loop; see k_onestep_update.
 // The host checks the columns' done flags every few iterations (the update kernel writes
 // them straight into pinned host memory on those iterations).  T = double (FP64)
 // or float (mixed: FP32 vectors and products; the per-slice sums are FP64 in both).
@@ -273,6 +275,85 @@ __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max
     }
 }
 
+// ---- the conclusions' first-order one-step refinement: g = -rho, rho = (H - eps S) p + r;
+// each step u = A g (the SpMV above with beta = 0 gives u and the sums g.u, u.u, g.g),
+// alpha = g.u / u.u minimises ||g - alpha u||, p += alpha g (accumulated in Xs),
+// g -= alpha u, ||g||^2 = g.g - (g.u)^2 / u.u.  The scalar state reuses MinresScal:
+// beta = 0 always, phibar = ||g||.
+
+__global__ __launch_bounds__(256) void k_onestep_init_finish(const double* __restrict__ partial,
+                                                             int64_t nslices, int q,
+                                                             const double* __restrict__ rnorm,
+                                                             double eta, int max_inner,
+                                                             MinresScal* __restrict__ sc) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= q) return;
+    const double g2 = column_sum(partial, nslices, q, j);
+    if ((threadIdx.x & 63) != 0) return;
+    MinresScal s{};
+    s.beta = 0.0;
+    s.cprev = 1.0; s.sprev = 0.0; s.cpp = 1.0; s.spp = 0.0;
+    s.phibar = sqrt(g2);
+    s.stop = eta * rnorm[j];
+    s.done = (s.phibar == 0.0 || s.phibar <= s.stop || max_inner <= 0) ? 1 : 0;
+    s.its = 0;
+    sc[j] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_cols(int64_t n, T* __restrict__ Xs) {
+    const int j = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        Xs[i + (int64_t)j * n] = T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_onestep_update(int64_t n, int q, int max_inner,
+                                                        const MinresScal* __restrict__ sc_in,
+                                                        MinresScal* __restrict__ sc_out,
+                                                        const double* __restrict__ part, int64_t npa,
+                                                        T* __restrict__ G, const T* __restrict__ U,
+                                                        T* __restrict__ Xs, int32_t* __restrict__ done_out) {
+    const int j = blockIdx.y;
+    const MinresScal s = sc_in[j];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (s.done) {
+        if (lead) {
+            sc_out[j] = s;
+            if (done_out) done_out[j] = 1;
+        }
+        return;
+    }
+    double sums[3];   // g.u, u.u, g.g
+    block_column_sums3(part, npa, q, j, sums);
+    if (!(sums[1] > 0.0)) {   // A g = 0: no step reduces the residual
+        if (lead) {
+            MinresScal t = s;
+            t.done = 1;
+            sc_out[j] = t;
+            if (done_out) done_out[j] = 1;
+        }
+        return;
+    }
+    const double alpha = sums[0] / sums[1];
+    const double g2 = fmax(sums[2] - sums[0] * alpha, 0.0);
+    const T a = (T)alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t o = i + (int64_t)j * n;
+        const T g = G[o];
+        Xs[o] += a * g;
+        G[o] = g - a * U[o];
+    }
+    if (lead) {
+        MinresScal t = s;
+        t.its = s.its + 1;
+        t.phibar = sqrt(g2);
+        t.done = (t.phibar <= s.stop || t.its >= max_inner) ? 1 : 0;
+        sc_out[j] = t;
+        if (done_out) done_out[j] = t.done;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_minres_final(int64_t n, int q, const int32_t* __restrict__ cols,
                                                       const MinresScal* __restrict__ sc,
@@ -348,8 +429,9 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
                 int32_t* flag_host_pinned, hipStream_t s, int64_t* launches, hipEvent_t ev0,
-                hipEvent_t ev1, unsigned long long* its_total) {
+                hipEvent_t ev1, unsigned long long* its_total, int method) {
     if (q <= 0 || A.n == 0) return;
+    const bool onestep = method == LABPSD_REFINE_ONESTEP;
     const int64_t n = A.n;
     T* V = ws;
     T* VP = V + n * q;
@@ -390,10 +472,16 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     // spmv partials: one per work-group and column (at most nslices)
     const int64_t npa = launch_spmv<T, 0>(A, sh, hv, sv, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev, sa, V,
                                           pa, q, s);
-    hipLaunchKernelGGL(k_minres_init_finish, gcol, dim3(256), 0, s, (const double*)pa, npa, q, rnorm_dev,
-                       eta, max_inner, sa);
-    hipLaunchKernelGGL((k_minres_init_vectors<T>), gel, dim3(256), 0, s, n, q, (const MinresScal*)sa, V,
-                       VP, D1, D2, Xs);
+    if (onestep) {
+        hipLaunchKernelGGL(k_onestep_init_finish, gcol, dim3(256), 0, s, (const double*)pa, npa, q, rnorm_dev,
+                           eta, max_inner, sa);
+        hipLaunchKernelGGL((k_zero_cols<T>), gel, dim3(256), 0, s, n, Xs);
+    } else {
+        hipLaunchKernelGGL(k_minres_init_finish, gcol, dim3(256), 0, s, (const double*)pa, npa, q, rnorm_dev,
+                           eta, max_inner, sa);
+        hipLaunchKernelGGL((k_minres_init_vectors<T>), gel, dim3(256), 0, s, n, q, (const MinresScal*)sa, V,
+                           VP, D1, D2, Xs);
+    }
     LABPSD_HIP(hipGetLastError());
     nl += 3;
     MinresScal* cur = sa;
@@ -410,6 +498,16 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     for (int it = 0; it < max_inner; ++it) {
         // on a check iteration the done flags go to host slot `slot`
         const bool check = it + 1 < max_inner && (it + 1) % kCheckEvery == 0;
+        if (onestep) {
+            // u = A g (beta is 0 in the one-step state), then the step
+            launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, V, n, nullptr, shift_dev, cur, Wb, pa, q, s);
+            hipLaunchKernelGGL((k_onestep_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
+                               (const MinresScal*)cur, nxt, (const double*)pa, npa, V, (const T*)Wb, Xs,
+                               check ? flag_dev + (size_t)slot * q : nullptr);
+            LABPSD_HIP(hipGetLastError());
+            nl += 2;
+            MinresScal* t2 = cur; cur = nxt; nxt = t2;
+        } else {
         launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s);
         hipLaunchKernelGGL((k_minres_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
                            (const MinresScal*)cur, nxt, (const double*)pa, npa, (const T*)V, Wb,
@@ -420,6 +518,7 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
         T* t0 = VP; VP = V; V = Wb; Wb = t0;
         T* t1 = D1; D1 = D2; D2 = t1;
         MinresScal* t2 = cur; cur = nxt; nxt = t2;
+        }
         if (it + 1 == max_inner) break;
         if (check) {
             if (!piped) {
@@ -446,10 +545,10 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
 template void run_minres<double>(const Sell&, double*, int64_t, const double*, int64_t, int,
                                  const int32_t*, const double*, const double*, double, int, int32_t*,
                                  double*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t,
-                                 unsigned long long*);
+                                 unsigned long long*, int);
 template void run_minres<float>(const Sell&, float*, int64_t, const float*, int64_t, int,
                                 const int32_t*, const double*, const double*, double, int, int32_t*,
                                 float*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t,
-                                unsigned long long*);
+                                unsigned long long*, int);
 
 }  // namespace labpsd

@@ -260,7 +260,7 @@ def test_ill_conditioned_overlap(ctx, name, precision):
     refs = [g[k] for k in ("lam_mp", "lam", "lam_eigsh") if k in g]
     assert len(refs) >= 2
     for ref in refs:
-        assert _rel(out.lam, ref, P.sigma0).max() < 1e-10
+        assert _rel_err(out.lam, ref, P.sigma0).max() < 1e-10
     S = P.S()
     assert np.abs(out.X.T @ (S @ out.X) - np.eye(m)).max() < 1e-10
     res = oeig.relative_residuals(P.H(), S, out.lam, out.X, P.sigma0)
@@ -268,3 +268,24 @@ def test_ill_conditioned_overlap(ctx, name, precision):
     print("[%s] precision=%d iters=%d rank drops=%d" % (name, precision, out.stats["outer_iters"],
                                                          out.stats["rank_dropped"]), flush=True)
     pr.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_one_step_refinement(c2, precision):
+    """Whole solves with the one-step refinement in place of MINRES reach the stored
+    eigenvalues (oracle LABPSD and ARPACK routes) to 1e-10."""
+    lp = _lp()
+    P, pr, g = c2
+    m, m0 = g["nev"], g["m0"]
+    pr.set_refine_method(lp.REFINE_ONESTEP)
+    try:
+        out = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-8, sigma0=P.sigma0, precision=precision)
+    finally:
+        pr.set_refine_method(lp.REFINE_MINRES)
+    assert out.converged, out.stats
+    assert out.stats["minres_iters"] > 0
+    for ref in (g["lam"], g["lam_eigsh"]):
+        assert _rel_err(out.lam, ref, P.sigma0).max() < 1e-10
+    res = oeig.relative_residuals(P.H(), P.S(), out.lam, out.X, P.sigma0)
+    assert res.max() <= 1e-8 * 1.01
+    print("[c2 one-step] precision=%d iters=%d La=%.2f" % (precision, out.stats["outer_iters"], out.stats["la"]))

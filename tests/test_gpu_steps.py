@@ -328,3 +328,53 @@ def test_block_update(prob, ctx):
             ref = Z @ W
             bound = np.abs(Z) @ np.abs(W)
             assert np.all(np.abs(host(o) - ref) <= 1e-14 * bound)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_local_refine_one_step(prob, precision):
+    """The conclusions' one-step refinement (labpsd_set_refine_method) against the oracle's
+    one_step_refine per column: the same step counts and directions in FP64 (up to the
+    rounding of the recurred residual norm near the stopping threshold), eq. (approxp) met
+    or the cap reached in both precisions; 70 columns, the last chunk ragged."""
+    P, pr = prob
+    import paper_1308_2445_amd as lp
+    torch = _torch()
+    H, S = P.H(), P.S()
+    rng = np.random.default_rng(23)
+    q = 70
+    # residual-like right-hand sides and shifts inside the spectrum, as in refinement
+    m = 4 if P.n < 1000 else 8
+    prm = olab.Params(nev=m, m0=pufe.guard_vectors(m), tol=1e-14, max_outer=6, sigma0=P.sigma0,
+                      eps_bar=P.eps_bar)
+    res = olab.solve(H, S, prm, pufe.start_block(P.n, m + prm.m0, 0))
+    R0, _ = olab.residual_block(H @ res.Psi, S @ res.Psi, res.E, m, P.sigma0)
+    R = R0[:, rng.integers(0, m, q)] + 1e-3 * rng.standard_normal((P.n, q)) * np.abs(R0).max()
+    shifts = res.E[rng.integers(0, m, q)] * (1 + 1e-3 * rng.standard_normal(q))
+    K = oprec.GlobalPreconditioner(H, S, P.eps_bar)
+    P0 = K.apply(R)
+    cols = np.arange(q, dtype=np.int32)
+    eta, cap = 0.25, 20
+    pr.set_refine_method(lp.REFINE_ONESTEP)
+    try:
+        Pd = dev(P0)
+        its = torch.zeros(q, dtype=torch.int32, device="cuda")
+        lp.labpsd_local_refine(pr, precision, dev(R), Pd, torch.from_numpy(cols).cuda(),
+                               torch.from_numpy(shifts).cuda(), eta, cap, its)
+        torch.cuda.synchronize()
+    finally:
+        pr.set_refine_method(lp.REFINE_MINRES)
+    got = host(Pd)
+    itg = its.cpu().numpy()
+    assert itg.max() >= 2                                 # the refinement does work here
+    for c in range(0, q, 7):
+        pref, itref = olab.one_step_refine(H, S, P0[:, c], R[:, c], float(shifts[c]), eta, cap)
+        a = H @ got[:, c] - shifts[c] * (S @ got[:, c]) + R[:, c]
+        rn = np.linalg.norm(R[:, c])
+        if precision == 0:
+            assert abs(int(itg[c]) - itref) <= 1
+            if int(itg[c]) == itref:
+                assert np.linalg.norm(got[:, c] - pref) <= 1e-9 * np.linalg.norm(pref)
+            assert np.linalg.norm(a) <= eta * rn * (1 + 1e-8) or int(itg[c]) == cap
+        else:
+            assert abs(int(itg[c]) - itref) <= 2
+            assert np.linalg.norm(a) <= 1.5 * eta * rn or int(itg[c]) == cap
