@@ -115,3 +115,14 @@ def shift_invert_eigs(H, S, m: int, sigma: float, tol: float = 1e-13):
                         ncv=ncv, tol=tol)
     order = np.argsort(lam)
     return lam[order], X[:, order]
+
+
+def full_hamiltonian(H_loc, F, G):
+    """H = H_loc + H_nl with the nonlocal part in its low-rank form H_nl = F G F^T
+    (Section 4, eq. (fgf); real at the Gamma point), as one explicit sparse matrix: the
+    plain definition the oracle's solves use.  F: n x k sparse, G: k x k."""
+    import scipy.sparse as sp
+    Fs = sp.csr_matrix(F)
+    Hnl = Fs @ sp.csr_matrix(G) @ Fs.T
+    Hnl = 0.5 * (Hnl + Hnl.T)
+    return (sp.csr_matrix(H_loc) + Hnl).tocsr()

@@ -57,6 +57,9 @@ class Problem:
     dof_atom: np.ndarray     # int64[n] enrichment atom (-1 for standard dofs)
     seed: int
     k_val: np.ndarray | None = None   # kinetic part 1/2 int grad.grad on the pattern (h_val - k_val is V)
+    alpha: float = ENRICH_ALPHA       # enrichment exponent the pencil was built with
+    F: object = None                  # nonlocal projectors (n x k CSC) or None
+    G: np.ndarray | None = None       # their k x k coupling
 
     def h_scaled(self, scale: float) -> np.ndarray:
         """H values with every potential amplitude multiplied by ``scale``."""
@@ -335,7 +338,91 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
     return Problem(n=n, rowptr=pat.indptr.astype(np.int64), col=pat.indices.astype(np.int32),
                    h_val=Hc, s_val=Sc, v_min=vmin, sigma0=vmin - 1.0, eps_bar=vmin - 0.1,
                    L=float(L), ne=int(ne), atoms=atoms, amplitudes=amps, dof_node=dof_node,
-                   dof_atom=dof_atom, seed=int(seed), k_val=Kc)
+                   dof_atom=dof_atom, seed=int(seed), k_val=Kc, alpha=float(alpha))
+
+
+# ------------------------------------------------------------------ nonlocal projectors
+
+PROJ_RC = 0.35               # bohr: projector width, beta(r) ~ exp(-|r - R|^2 / (2 rc^2))
+PROJ_CUT = 1e-6              # projectors are cut where beta_s falls below this (r = 5.26 rc)
+PROJ_ENERGY = (4.0, 2.0)     # hartree: G entries of the s and p projectors
+
+
+def nonlocal_projectors(P: Problem, per_atom: int = 4, rc: float = PROJ_RC,
+                        energies=PROJ_ENERGY):
+    """The low-rank nonlocal term H_nl = F G F^T of a separable (Kleinman-Bylander-like)
+    pseudopotential for the cell of P (Section 4, eq. (fgf)): per atom an s projector
+    beta_s = exp(-d^2 / (2 rc^2)) and, with per_atom = 4, three p projectors
+    beta_x = (d_x / rc) beta_s, ...  (d = r minus the nearest image of the atom), cut off
+    where beta_s < PROJ_CUT (a core radius of 5.26 rc) or at half the cell.  F[i, c] = integral of phi_i beta_c over the
+    cell by 4^3 Gauss points per element, phi_i the basis function of dof i (hat, or hat
+    times the enrichment g); G = diag(energies[s], energies[p] x 3) per atom.
+    Returns (F as an n x k CSC matrix, G as a k x k dense array), k = per_atom * atoms."""
+    assert per_atom in (1, 4)
+    ne, L = P.ne, P.L
+    h = L / ne
+    natoms = P.atoms.shape[0]
+    n = P.n
+    # dof numbering: first dof of every node, then its enriched dofs in atom order
+    first_dof = np.zeros(ne ** 3 + 1, dtype=np.int64)
+    np.add.at(first_dof, P.dof_node + 1, 1)
+    first_dof = np.cumsum(first_dof)
+    cut = min(rc * math.sqrt(2.0 * math.log(1.0 / PROJ_CUT)), 0.5 * L)
+    xi, w = _quad3d(4)
+    N, _ = _shape(xi)
+    rows_all, cols_all, vals_all = [], [], []
+    reach = int(math.ceil(cut / h)) + 1
+    for a in range(natoms):
+        R = P.atoms[a]
+        base = np.floor(R / h).astype(np.int64)
+        rng_ = np.arange(-reach, reach + 1)
+        I, J, K = np.meshgrid(base[0] + rng_, base[1] + rng_, base[2] + rng_, indexing="ij")
+        org = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1) * h      # unwrapped element origins
+        # keep elements with a point within the cut-off
+        cen = org + 0.5 * h
+        keep = np.linalg.norm(cen - R, axis=1) <= cut + 0.5 * math.sqrt(3.0) * h
+        org = org[keep]
+        eijk = np.round(org / h).astype(np.int64) % ne
+        xq = org[:, None, :] + h * xi[None, :, :]                           # (e, nq, 3)
+        d = xq - R
+        d -= L * np.round(d / L)
+        r2 = np.einsum("eqd,eqd->eq", d, d)
+        bs = np.exp(-r2 / (2.0 * rc * rc)) * (r2 <= cut * cut)
+        betas = [bs] if per_atom == 1 else [bs, d[..., 0] / rc * bs, d[..., 1] / rc * bs, d[..., 2] / rc * bs]
+        wq = w * h ** 3
+        for loc in range(8):
+            o = _LOCAL_OFF[loc]
+            nd = ((eijk[:, 0] + o[0]) % ne) + ne * (((eijk[:, 1] + o[1]) % ne) + ne * ((eijk[:, 2] + o[2]) % ne))
+            xnode = org + o * h
+            # the hat function of the node, then its enriched functions
+            funcs = [(first_dof[nd], N[None, :, loc] * np.ones((org.shape[0], 1)))]
+            nen = first_dof[nd + 1] - first_dof[nd] - 1
+            for rr in range(int(nen.max()) if nen.size else 0):
+                has = nen > rr
+                pdof = np.where(has, first_dof[nd] + 1 + rr, 0)
+                at = np.where(has, P.dof_atom[pdof], 0)
+                dd = xnode - P.atoms[at]
+                dd -= L * np.round(dd / L)
+                u = xq - (xnode - dd)[:, None, :]
+                g = np.exp(-P.alpha * np.einsum("eqd,eqd->eq", u, u))
+                funcs.append((np.where(has, pdof, -1), N[None, :, loc] * g * has[:, None]))
+            for dof, phi in funcs:
+                for l, be in enumerate(betas):
+                    v = np.einsum("q,eq,eq->e", wq, phi, be)
+                    ok = (dof >= 0) & (v != 0.0)
+                    rows_all.append(dof[ok])
+                    cols_all.append(np.full(int(ok.sum()), a * per_atom + l, dtype=np.int64))
+                    vals_all.append(v[ok])
+    k = natoms * per_atom
+    F = sp.coo_matrix((np.concatenate(vals_all) if vals_all else np.zeros(0),
+                       (np.concatenate(rows_all) if rows_all else np.zeros(0, dtype=np.int64),
+                        np.concatenate(cols_all) if cols_all else np.zeros(0, dtype=np.int64))),
+                      shape=(n, k)).tocsc()
+    F.sum_duplicates()
+    F.sort_indices()
+    g = [energies[0]] + ([energies[1]] * 3 if per_atom == 4 else [])
+    G = np.diag(np.tile(np.asarray(g, dtype=np.float64), natoms))
+    return F, G
 
 
 def _on_pattern(A: sp.csr_matrix, pat: sp.csr_matrix) -> np.ndarray:
@@ -388,6 +475,9 @@ WORKLOADS = {
     # the 250- and 16k-dof cells with flat enrichments: cond(S) above 1e8
     "c1i": dict(L=6.0, ne=6, natoms=1, nev=4, alpha=1e-3),
     "c2i": dict(L=12.0, ne=24, natoms=8, nev=32, alpha=1e-2),
+    # the 250- and 16k-dof cells with a nonlocal term H_nl = F G F^T of four projectors per atom
+    "c1nl": dict(L=6.0, ne=6, natoms=1, nev=4, projectors=4),
+    "c2nl": dict(L=12.0, ne=24, natoms=8, nev=32, projectors=4),
 }
 
 
@@ -397,10 +487,15 @@ def guard_vectors(nev: int) -> int:
 
 
 def workload(name: str, seed: int = 0, **kw) -> Problem:
+    """The named cell's pencil; for cells with a nonlocal term its projectors are attached as
+    P.F (n x k CSC) and P.G (k x k), and P.h_val stays the local part."""
     w = WORKLOADS[name]
     if "alpha" in w:
         kw.setdefault("alpha", w["alpha"])
-    return generate(w["L"], w["ne"], w["natoms"], seed, **kw)
+    P = generate(w["L"], w["ne"], w["natoms"], seed, **kw)
+    if w.get("projectors"):
+        P.F, P.G = nonlocal_projectors(P, w["projectors"])
+    return P
 
 
 def start_block(n: int, b: int, seed: int) -> np.ndarray:

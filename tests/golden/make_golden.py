@@ -32,6 +32,9 @@ def digest(P):
     h = hashlib.sha256()
     for a in (P.rowptr, P.col, P.h_val, P.s_val):
         h.update(np.ascontiguousarray(a).tobytes())
+    if P.F is not None:
+        for a in (P.F.indptr, P.F.indices, P.F.data, P.G):
+            h.update(np.ascontiguousarray(a).tobytes())
     return h.hexdigest()
 
 
@@ -39,12 +42,17 @@ def path_of(name):
     return os.path.join(HERE, "%s_eigs.json" % name)
 
 
+def hamiltonian(P):
+    """The full H of the cell: the local part, plus F G F^T where the cell has projectors."""
+    return P.H() if P.F is None else eigs.full_hamiltonian(P.H(), P.F, P.G)
+
+
 def add_eigsh(P, out, m):
     """ARPACK shift-invert route at sigma = eps_bar (below lambda_1); a few pairs past m
     are computed so the m-th value is not at the edge of the Krylov window."""
     t = time.perf_counter()
     extra = max(8, m // 16)
-    lam, _ = eigs.shift_invert_eigs(P.H(), P.S(), m + extra, P.eps_bar)
+    lam, _ = eigs.shift_invert_eigs(hamiltonian(P), P.S(), m + extra, P.eps_bar)
     out["lam_eigsh"] = lam[:m].tolist()
     out["lam_eigsh_next"] = lam[m:].tolist()
     out["eigsh_route"] = ("scipy eigsh shift-invert (ARPACK Lanczos on (H - eps_bar S)^-1 S, SuperLU MMD "
@@ -58,17 +66,21 @@ def main(names):
         m = w["nev"]
         m0 = pufe.guard_vectors(m)
         prm = labpsd.Params(nev=m, m0=m0, tol=1e-11, sigma0=P.sigma0, eps_bar=P.eps_bar)
-        res = labpsd.solve(P.H(), P.S(), prm, pufe.start_block(P.n, m + m0, 0))
+        H = hamiltonian(P)
+        res = labpsd.solve(H, P.S(), prm, pufe.start_block(P.n, m + m0, 0))
         out = dict(workload=name, seed=0, n=P.n, nnz=P.nnz, nev=m, m0=m0, sha256=digest(P),
                    sigma0=P.sigma0, eps_bar=P.eps_bar, tol=1e-11, converged=bool(res.converged),
                    lam=res.lam.tolist(), res=res.res.tolist(), outer_iters=res.outer_iters,
                    route="oracle.labpsd.solve (tol 1e-11, cold start seed 0)")
         if P.n <= 3000:
-            lam, _ = eigs.dense_eigs(P.H(), P.S(), m)
+            lam, _ = eigs.dense_eigs(H, P.S(), m)
             out["lam_dense"] = lam.tolist()
         if P.n <= 300:
             # mpmath at 40 digits: exact to far below FP64 rounding, whatever cond(S)
-            out["lam_mp"] = eigs.mp_eigs(P.H(), P.S(), dps=40)[:m].tolist()
+            out["lam_mp"] = eigs.mp_eigs(H, P.S(), dps=40)[:m].tolist()
+        if P.F is not None:
+            out["projectors"] = int(P.F.shape[1])
+            out["f_nnz"] = int(P.F.nnz)
         if "alpha" in w:
             out["alpha"] = w["alpha"]
         add_eigsh(P, out, m)

@@ -87,3 +87,46 @@ def test_enrichment_makes_s_ill_conditioned(seed):
     c = np.linalg.cond(P.S().toarray())
     c0 = np.linalg.cond(P0.S().toarray())
     assert c > 100 * c0          # enrichment raises cond(S) sharply (Table 1 trend)
+
+
+# ------------------------------------------------------------------ nonlocal projectors
+
+def test_projector_partition_of_unity_and_symmetry():
+    """The standard hats sum to one at every point (partition of unity), so summing an
+    s projector's column over the standard dofs gives the quadrature of beta_s itself,
+    which at h = 0.5 matches the closed form of the Gaussian cut at radius Rc,
+    (2 pi rc^2)^(3/2) [erf(x / sqrt 2) - sqrt(2 / pi) x exp(-x^2 / 2)] with x = Rc / rc
+    (the chi distribution's CDF), to 1e-6 (the cut runs through elements); the p
+    projectors are odd about the atom, so their sums vanish.  G is diagonal and positive
+    (s, p x 3 per atom), and F >= 0 in every s column."""
+    import math
+    from pufe.generate import PROJ_RC, PROJ_CUT, PROJ_ENERGY
+    P = pufe.workload("c2nl", 0)
+    F, G = P.F, P.G
+    assert F.shape == (P.n, 4 * len(P.atoms))
+    std = P.dof_atom < 0
+    sums = np.asarray(F[std].sum(axis=0)).ravel()
+    x = math.sqrt(2.0 * math.log(1.0 / PROJ_CUT))
+    closed = (2 * math.pi * PROJ_RC ** 2) ** 1.5 * (math.erf(x / math.sqrt(2.0))
+                                                   - math.sqrt(2.0 / math.pi) * x * math.exp(-x * x / 2))
+    assert np.abs(sums[0::4] - closed).max() < 1e-6 * closed
+    for l in (1, 2, 3):
+        assert np.abs(sums[l::4]).max() < 1e-6 * closed
+    assert np.allclose(np.diag(G)[0::4], PROJ_ENERGY[0]) and np.allclose(np.diag(G)[1::4], PROJ_ENERGY[1])
+    assert np.count_nonzero(G - np.diag(np.diag(G))) == 0
+    Fs = F[:, 0::4]
+    assert Fs.data.min() >= 0.0
+
+
+def test_nonlocal_term_raises_the_spectrum():
+    """G is positive semidefinite, so H_loc + F G F^T >= H_loc and every eigenvalue rises
+    (Weyl); eps_bar stays below lambda_1 of both pencils."""
+    import scipy.linalg as sla
+    from oracle import eigs
+    P = pufe.workload("c1nl", 0)
+    H = eigs.full_hamiltonian(P.H(), P.F, P.G)
+    assert abs(H - H.T).max() == 0.0
+    l0 = sla.eigh(P.H().toarray(), P.S().toarray(), eigvals_only=True)
+    l1 = sla.eigh(H.toarray(), P.S().toarray(), eigvals_only=True)
+    assert np.all(l1 >= l0 - 1e-12 * np.abs(l0).max())
+    assert P.eps_bar < l0[0] <= l1[0]
