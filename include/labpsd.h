@@ -100,6 +100,23 @@ labpsd_status labpsd_problem_update_h(labpsd_problem* p, const double* h_val, la
 void labpsd_problem_destroy(labpsd_problem* p);
 int64_t labpsd_problem_n(const labpsd_problem* p);
 
+/* The nonlocal part of H (Section 2, eq. (ghep); Section 4, eqs. (k1), (fgf)):
+ * H = H_loc + F G F^T with F n x k and G k x k symmetric (k projectors).  F is given by
+ * columns: colptr int64[k+1] (colptr[0] = 0), rowidx int32[nnz] (strictly increasing
+ * within a column, < n), fval float64[nnz]; G float64[k*k] column-major.  Host arrays,
+ * copied.  Every product with H (the solve's H Psi and H P, labpsd_spmm, the shifted
+ * products of the refinement) then includes F (G (F^T x)), and the global apply becomes
+ * (H_loc + F G F^T - eps_bar S)^{-1} by the Sherman-Morrison-Woodbury steps of Section 4
+ * (Fh = (H_loc - eps_bar S)^{-1} F, T = I + G F^T Fh, then P -= Fh T^{-1} G F^T P after
+ * every plain apply); the factorisation itself stays that of H_loc - eps_bar S.  The
+ * SMW factor is built here if a global preconditioner exists, else by
+ * labpsd_set_global_precond (with the FP64 panels when uploaded, else the FP32 ones).
+ * k = 0 removes the term.  labpsd_problem_update_h replaces H_loc only.  EINVAL on
+ * malformed F, an empty F, k > n, a G that is not symmetric or a singular T.       */
+labpsd_status labpsd_problem_set_nonlocal(labpsd_problem* p, int k, const int64_t* colptr,
+                                          const int32_t* rowidx, const double* fval,
+                                          const double* G);
+
 /* Global preconditioner K = (H - eps_bar S)^{-1} (eq. (globalprecond), eq. (k1p)).
  * Factorises H - eps_bar S once on the host (FP64 supernodal Cholesky after a
  * nested-dissection ordering; eq. (ldl) with 1x1 pivots only, since eps_bar

@@ -93,6 +93,7 @@ _SIGS = {
     "labpsd_version": ([], ctypes.c_char_p),
     "labpsd_problem_create": ([_p, _i64, _i64, _p, _p, _p, _p, _i32, ctypes.POINTER(_p)], _i32),
     "labpsd_problem_update_h": ([_p, _p, _i32], _i32),
+    "labpsd_problem_set_nonlocal": ([_p, _i32, _p, _p, _p, _p], _i32),
     "labpsd_problem_destroy": ([_p], None),
     "labpsd_problem_n": ([_p], _i64),
     "labpsd_set_global_precond": ([_p, _d, _p, ctypes.c_uint], _i32),
@@ -231,7 +232,11 @@ class Problem:
 
     @classmethod
     def from_pencil(cls, ctx: Context, P) -> "Problem":
-        return cls(ctx, P.n, P.rowptr, P.col, P.h_val, P.s_val)
+        """The pencil of a pufe cell, with its nonlocal term when it has one (P.F, P.G)."""
+        pr = cls(ctx, P.n, P.rowptr, P.col, P.h_val, P.s_val)
+        if getattr(P, "F", None) is not None:
+            pr.set_nonlocal(P.F, P.G)
+        return pr
 
     def update_h(self, h_val):
         """New H values on the same pattern: numpy array or torch device tensor."""
@@ -244,6 +249,20 @@ class Problem:
             where = MEM_DEVICE
         self.ctx.sync_stream()
         _check(_lib.labpsd_problem_update_h(self.h, _ptr(h_val), where), "labpsd_problem_update_h")
+
+    def set_nonlocal(self, F, G):
+        """The nonlocal term H_nl = F G F^T: F an n x k scipy sparse matrix, G k x k."""
+        import scipy.sparse as sp
+        Fc = sp.csc_matrix(F)
+        Fc.sort_indices()
+        k = int(Fc.shape[1])
+        cp = np.ascontiguousarray(Fc.indptr, dtype=np.int64)
+        ri = np.ascontiguousarray(Fc.indices, dtype=np.int32)
+        fv = np.ascontiguousarray(Fc.data, dtype=np.float64)
+        Gm = np.asfortranarray(np.asarray(G, dtype=np.float64).reshape(k, k))
+        self.ctx.sync_stream()
+        _check(_lib.labpsd_problem_set_nonlocal(self.h, k, _ptr(cp), _ptr(ri), _ptr(fv), _ptr(Gm)),
+               "labpsd_problem_set_nonlocal")
 
     def set_global_precond(self, eps_bar: float, coords=None, panels: int = 0):
         """panels: PANELS_FP64 | PANELS_FP32 mask of the factor copies to upload (0: both)."""

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "liblabpsd.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["spmm.hip", "dense.hip", "rr.hip", "precond.hip", "minres.hip", "api.hip", "serve.hip", "noalloc.hip"]
+HIP_SOURCES = ["spmm.hip", "dense.hip", "rr.hip", "precond.hip", "minres.hip", "api.hip", "serve.hip", "noalloc.hip", "nonlocal.hip"]
 CPP_SOURCES = ["factor.cpp"]
 
 HIPCC_FLAGS = [

@@ -341,6 +341,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     SolveBuffers B;
     PrecWS<T> Wt;
     carve<T>(P, n, b, m, B, Wt);
+    const NonLocal* nlp = P.nl.k ? &P.nl : nullptr;   // H = H_loc + F G F^T
     const int nblk = residual_blocks(n);
     labpsd_stats st{};
     StepTimer tm;
@@ -382,7 +383,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     else
         launch_random_block(n, b, prm.seed, Z(0), ldz, s);
     tm.begin(S_PROD_PSI);
-    launch_spmm_hs(P.sell, Z(0), ldz, b, Z(1), Z(2), ldz, s);
+    launch_spmm_hs(P.sell, Z(0), ldz, b, Z(1), Z(2), ldz, s, nlp);
     tm.end();
     st.n_launch[S_PROD_PSI] += 1;
     st.n_cols[S_PROD_PSI] += b;
@@ -436,7 +437,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     bool orth_pending = false;
     auto refresh = [&]() {
         tm.begin(S_PROD_PSI);
-        launch_spmm_hs(P.sell, Z(0), ldz, b, Z(1), Z(2), ldz, s);
+        launch_spmm_hs(P.sell, Z(0), ldz, b, Z(1), Z(2), ldz, s, nlp);
         tm.end();
         st.n_launch[S_PROD_PSI] += 1;
         st.n_cols[S_PROD_PSI] += b;
@@ -559,7 +560,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         st.n_launch[S_CAST] += q ? 2 : 1;
         st.n_cols[S_CAST] += q ? 2 * p : p;
         tm.begin(S_GLOBAL);
-        launch_precond_solve<T>(*P.factor, Wt.Y, Wt.W1, Wt.W2, n, p, s);
+        launch_precond_solve<T>(*P.factor, Wt.Y, Wt.W1, Wt.W2, n, p, s, nlp);
         tm.end();
         st.n_launch[S_GLOBAL] += 1;
         st.n_cols[S_GLOBAL] += p;
@@ -577,7 +578,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
             int64_t nl = 0;
             run_minres<T>(P.sell, Wt.W1, n, Wt.RT, n, q, B.loc, B.shifts, B.stopn, lp.eta,
                           lp.max_inner, B.its, Wt.mres, B.scal, h_int.p, s, &nl, ev_flag0,
-                          ev_flag1, its_total, lp.method);
+                          ev_flag1, its_total, lp.method, nlp);
             tm.end();
             st.n_launch[S_LOCAL] += nl;
             st.n_cols[S_LOCAL] += q;
@@ -593,7 +594,7 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
         // step 7: P_H, P_S
         tm.begin(S_PROD_P);
         launch_spmm_hs(P.sell, Z(0) + (size_t)b * ldz, ldz, p, Z(1) + (size_t)b * ldz,
-                       Z(2) + (size_t)b * ldz, ldz, s);
+                       Z(2) + (size_t)b * ldz, ldz, s, nlp);
         tm.end();
         st.n_launch[S_PROD_P] += 1;
         st.n_cols[S_PROD_P] += p;
@@ -712,7 +713,7 @@ static void local_refine_impl(Problem* p, DBuf<T>& arena, const double* R, int64
     HBuf<int32_t> flag;
     flag.alloc(2 * (size_t)q);
     run_minres<T>(p->sell, PT, n, RT, n, q, iota, shift, rn, eta, max_inner, its, mws, scal, flag.p, s,
-                  nullptr, nullptr, nullptr, nullptr, p->local.method);
+                  nullptr, nullptr, nullptr, nullptr, p->local.method, p->nl.k ? &p->nl : nullptr);
     launch_scatter_cast<T, double>(n, q, PT, n, cols, 1.0, Pm, ldp, s);
     LABPSD_HIP(hipStreamSynchronize(s));
 }
@@ -863,6 +864,8 @@ labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const
         if (rc != 0) throw Error{LABPSD_EINVAL, msg};
         const double t0 = wall();
         upload_factor(*p, F, eps_bar, panels);
+        // the factor is of H_loc - eps_bar S; the nonlocal term enters through SMW
+        if (p->nl.k) nonlocal_smw_setup(*p);
         p->factor->info.t_upload_s = wall() - t0;
         return LABPSD_OK;
     });
@@ -930,7 +933,7 @@ labpsd_status labpsd_spmm(labpsd_problem* p, const double* X, int64_t ldx, int w
     return guarded([&]() -> labpsd_status {
         LABPSD_REQUIRE(p && X && YH && YS, "NULL argument");
         LABPSD_REQUIRE(w >= 0 && ldx >= p->n && ldy >= p->n, "bad width or leading dimension");
-        launch_spmm_hs(p->sell, X, ldx, w, YH, YS, ldy, p->ctx->stream);
+        launch_spmm_hs(p->sell, X, ldx, w, YH, YS, ldy, p->ctx->stream, p->nl.k ? &p->nl : nullptr);
         return LABPSD_OK;
     });
 }
@@ -941,10 +944,11 @@ labpsd_status labpsd_spmm_shifted(labpsd_problem* p, int precision, const void* 
         LABPSD_REQUIRE(p && X && Y && shift, "NULL argument");
         LABPSD_REQUIRE(w >= 0 && ldx >= p->n && ldy >= p->n, "bad width or leading dimension");
         if (precision == LABPSD_MIXED)
-            launch_spmm_shift<float>(p->sell, (const float*)X, ldx, w, shift, (float*)Y, ldy, p->ctx->stream);
+            launch_spmm_shift<float>(p->sell, (const float*)X, ldx, w, shift, (float*)Y, ldy, p->ctx->stream,
+                                     p->nl.k ? &p->nl : nullptr);
         else if (precision == LABPSD_FP64)
             launch_spmm_shift<double>(p->sell, (const double*)X, ldx, w, shift, (double*)Y, ldy,
-                                      p->ctx->stream);
+                                      p->ctx->stream, p->nl.k ? &p->nl : nullptr);
         else
             throw Error{LABPSD_EINVAL, "invalid precision"};
         return LABPSD_OK;
@@ -979,13 +983,15 @@ labpsd_status labpsd_precond_apply(labpsd_problem* p, int precision, const doubl
             p->ws32.alloc(3 * (size_t)n * ncols);
             float* Y = p->ws32.p;
             launch_cast_to_rm<double, float>(n, ncols, R, ldr, nullptr, -1.0, Y, s);
-            launch_precond_solve<float>(*p->factor, Y, Y + n * ncols, Y + 2 * n * ncols, n, ncols, s);
+            launch_precond_solve<float>(*p->factor, Y, Y + n * ncols, Y + 2 * n * ncols, n, ncols, s,
+                                        p->nl.k ? &p->nl : nullptr);
             launch_cast_from_rm<float, double>(n, ncols, Y + 2 * n * ncols, 1.0, Pout, ldp, s);
         } else if (precision == LABPSD_FP64) {
             p->red.alloc(3 * (size_t)n * ncols);
             double* Y = p->red.p;
             launch_cast_to_rm<double, double>(n, ncols, R, ldr, nullptr, -1.0, Y, s);
-            launch_precond_solve<double>(*p->factor, Y, Y + n * ncols, Y + 2 * n * ncols, n, ncols, s);
+            launch_precond_solve<double>(*p->factor, Y, Y + n * ncols, Y + 2 * n * ncols, n, ncols, s,
+                                         p->nl.k ? &p->nl : nullptr);
             launch_cast_from_rm<double, double>(n, ncols, Y + 2 * n * ncols, 1.0, Pout, ldp, s);
         } else {
             throw Error{LABPSD_EINVAL, "invalid precision"};

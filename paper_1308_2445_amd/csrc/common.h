@@ -242,6 +242,27 @@ __device__ __forceinline__ void slice_reduce(T (&ah)[CW], T (&as)[CW], T* red) {
     }
 }
 
+// The nonlocal term H_nl = F G F^T of a product (Section 4, eq. (fgf)), added to the H
+// part of a sliced-ELL product row by row: the kernel's row i gains
+// sum_e F[i, c_e] W[c_e, j] over the entries of row i of F, with W = G F^T X formed
+// beforehand (k x w, column stride ldw).  rp == nullptr: no nonlocal term.
+template <typename T, typename TW>
+struct NlEpi {
+    const int64_t* rp = nullptr;   // F rows: row pointers (n + 1)
+    const int32_t* ci = nullptr;   // projector index of every entry
+    const T* fv = nullptr;         // F values
+    const TW* W = nullptr;         // G F^T X, k x w
+    int64_t ldw = 0;
+};
+
+template <typename T, typename TW>
+__device__ __forceinline__ T nl_row_term(const NlEpi<T, TW>& nl, int64_t row, int col) {
+    T s = T(0);
+    const int64_t e1 = nl.rp[row + 1];
+    for (int64_t e = nl.rp[row]; e < e1; ++e) s += nl.fv[e] * (T)nl.W[nl.ci[e] + (int64_t)col * nl.ldw];
+    return s;
+}
+
 struct Sell {
     int64_t n = 0;
     int64_t nslices = 0;
@@ -341,6 +362,54 @@ struct labpsd_ctx : labpsd::Ctx {};
 
 namespace labpsd {
 
+// The nonlocal term H_nl = F G F^T (Section 4, eq. (fgf)) on the device: F by columns
+// (for F^T X) and by rows (for the product epilogues) in FP64 and FP32, G in both, and
+// for the global apply the SMW factor Ft = (H_loc - eps_bar S)^{-1} F T^{-1} G with
+// T = I + G F^T (H_loc - eps_bar S)^{-1} F (n x k row-major, built with the factor), so
+// that P = P_loc - Ft (F^T P_loc) (the update that ends the SMW outline of Section 4).
+struct NonLocal {
+    int k = 0;
+    std::vector<int64_t> h_colptr, h_rowptr;
+    std::vector<int32_t> h_rowidx, h_colidx;
+    std::vector<double> h_cval, h_rval, h_G;
+    DBuf<int64_t> colptr, rowptr;
+    DBuf<int32_t> rowidx, colidx;
+    DBuf<double> cval64, rval64, G64;
+    DBuf<float> cval32, rval32, G32;
+    DBuf<double> Ft64;
+    DBuf<float> Ft32;
+    bool smw_ready = false;
+    // W = F^T X and G W for the products (k x w FP64 or FP32)
+    mutable DBuf<double> w64a, w64b;
+    mutable DBuf<float> w32a, w32b;
+    template <typename T, typename TW>
+    NlEpi<T, TW> epi(const TW* W, int64_t ldw) const {
+        NlEpi<T, TW> e;
+        if (k == 0) return e;
+        e.rp = rowptr.p;
+        e.ci = colidx.p;
+        if constexpr (sizeof(T) == 8) e.fv = rval64.p;
+        else e.fv = rval32.p;
+        e.W = W;
+        e.ldw = ldw;
+        return e;
+    }
+};
+
+// G F^T X for the w columns of X (column-major, ld ldx; xcols[j] selects column j, or the
+// identity when null) into nl.w*b (k x w), and the epilogue view of it; a view with
+// rp == nullptr when there is no nonlocal term.
+template <typename T>
+NlEpi<T, T> nl_prepare(const NonLocal& nl, const T* X, int64_t ldx, const int32_t* xcols, int w,
+                       hipStream_t s);
+// Row-major forms for the global apply: W (k x m, row-major) = F^T X for X n x m row-major;
+// D = alpha A B + beta D for A n x k, B k x m, D n x m, all row-major.
+template <typename T>
+void launch_nl_ftx_rm(const NonLocal& nl, const T* X, int m, T* W, hipStream_t s);
+template <typename T>
+void launch_rm_gemm(int64_t n, int k, int m, const T* A, const T* B, T* D, double alpha, double beta,
+                    hipStream_t s);
+
 struct Problem {
     labpsd_ctx* ctx = nullptr;
     int64_t n = 0, nnz = 0;
@@ -348,6 +417,7 @@ struct Problem {
     std::vector<double> h_val, s_val;
     Sell sell;
     DevFactor* factor = nullptr;
+    NonLocal nl;
     LocalParams local;
     // solver workspace (kept between solves)
     DBuf<double> ws64;
@@ -394,13 +464,13 @@ void refresh_sell_h(Sell& S, const double* hv, hipStream_t s);
 // the guarded-call wrapper of the C ABI (maps exceptions to status codes)
 labpsd_status abi_guard(const std::function<labpsd_status()>& f);
 
-// YH = H X, YS = S X (FP64)
+// YH = H X, YS = S X (FP64); nl: the nonlocal term of H (null: none)
 void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
-                    int64_t ldy, hipStream_t s);
+                    int64_t ldy, hipStream_t s, const NonLocal* nl = nullptr);
 // Y = (H - shift_j S) X (T = double or float; shift in double)
 template <typename T>
 void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
-                       int64_t ldy, hipStream_t s);
+                       int64_t ldy, hipStream_t s, const NonLocal* nl = nullptr);
 
 // X (n x b, ld ldx) := i.i.d. standard normals, entry (i, j) from counter i + n j of `seed`
 void launch_random_block(int64_t n, int b, uint64_t seed, double* X, int64_t ldx, hipStream_t s);
@@ -463,9 +533,13 @@ void launch_colnorms(int64_t n, int q, const T* src, int64_t ld, const int32_t* 
 
 // Global preconditioner: W2 := K^{-1} Y for n x ncols row-major blocks (element (i, j)
 // at i * ncols + j) of precision T; Y is consumed, W1 is scratch
+// With nl (its SMW factor built), the result is corrected to (H - eps_bar S)^{-1} Y for
+// H = H_loc + F G F^T: W2 -= Ft (F^T W2), with W1 holding F^T W2 (k x ncols).
 template <typename T>
 void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int ncols,
-                          hipStream_t s);
+                          hipStream_t s, const NonLocal* nl = nullptr);
+// Build the SMW factor of P's nonlocal term with its global factor (synchronises).
+void nonlocal_smw_setup(Problem& P);
 
 // MINRES batched refinement (T = double or float). P (n x *, ld ldp) in precision T is
 // refined in place on the columns cols[0..q), with the residual columns R[:, cols[j]] in
@@ -481,7 +555,7 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
                 int32_t* flag_host_pinned, hipStream_t s, int64_t* launches, hipEvent_t ev0 = nullptr,
                 hipEvent_t ev1 = nullptr, unsigned long long* its_total = nullptr,
-                int method = LABPSD_REFINE_MINRES);
+                int method = LABPSD_REFINE_MINRES, const NonLocal* nl = nullptr);
 
 // Wait until everything enqueued on s so far has finished.  With an event the host polls
 // it (spins) instead of blocking, which shortens the wake-up after the small read-backs

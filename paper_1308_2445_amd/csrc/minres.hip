@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
     const int32_t* __restrict__ xcols, const T* __restrict__ aux, int64_t ldaux,
     const int32_t* __restrict__ auxcols, const double* __restrict__ shift,
     const MinresScal* __restrict__ sc, T* __restrict__ out, double* __restrict__ partial,
-    int64_t npart, int q) {
+    int64_t npart, int q, NlEpi<T, T> nl) {
     constexpr int SPB = 4 / WPS;   // slices per work-group
     constexpr int NS = MODE == 0 ? 1 : 3;   // partial sums per column
     __shared__ T sred[WPS > 1 ? 256 * 2 * CW : 1];
@@ -94,7 +94,9 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
 #pragma unroll
         for (int w = 0; w < NS; ++w) c[w] = 0.0;
         if (act[j] && lead && row < n) {
-            const T y = ah[j] - (T)shift[jj] * as[j];
+            // the nonlocal term belongs to H: (H_loc + F G F^T - shift S) x
+            const T hx = nl.rp ? ah[j] + nl_row_term(nl, row, jj) : ah[j];
+            const T y = hx - (T)shift[jj] * as[j];
             T v;
             if constexpr (MODE == 0) {
                 v = -(y + aux[row + (int64_t)auxcols[jj] * ldaux]);
@@ -376,13 +378,13 @@ template <typename T, int MODE, int CW, int WPS>
 int64_t launch_spmv_s(const Sell& A, const T* hv, const T* sv, const T* X, int64_t ldx,
                       const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
                       const double* shift, const MinresScal* sc, T* out, double* partial, int q,
-                      hipStream_t s) {
+                      hipStream_t s, NlEpi<T, T> nl) {
     constexpr int SPB = 4 / WPS;
     const int64_t nblk = (A.nslices + SPB - 1) / SPB;
     const dim3 g((unsigned)nblk, (unsigned)((q + CW - 1) / CW));
     hipLaunchKernelGGL((k_minres_spmv<T, MODE, CW, WPS>), g, dim3(256), 0, s, A.slice_off.p, A.col.p, hv,
                        sv, A.n, A.nslices, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, nblk,
-                       q);
+                       q, nl);
     return nblk;
 }
 
@@ -392,10 +394,12 @@ template <typename T, int MODE>
 int64_t launch_spmv(const Sell& A, SellShape sh, const T* hv, const T* sv, const T* X, int64_t ldx,
                     const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
                     const double* shift, const MinresScal* sc, T* out, double* partial, int q,
-                    hipStream_t s) {
+                    hipStream_t s, const NonLocal* nlp) {
+    // the nonlocal term: G F^T x of the product's columns first, then the epilogue
+    const NlEpi<T, T> nl = nlp ? nl_prepare<T>(*nlp, X, ldx, xcols, q, s) : NlEpi<T, T>{};
 #define LABPSD_SPMV(CW, WPS) \
     launch_spmv_s<T, MODE, CW, WPS>(A, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q, \
-                                    s)
+                                    s, nl)
     if (sh.wps == 4) {
         if (sh.cw >= 4) return LABPSD_SPMV(4, 4);
         if (sh.cw == 2) return LABPSD_SPMV(2, 4);
@@ -429,8 +433,9 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
                 const int32_t* cols_dev, const double* shift_dev, const double* rnorm_dev,
                 double eta, int max_inner, int32_t* its_dev, T* ws, double* scal_ws,
                 int32_t* flag_host_pinned, hipStream_t s, int64_t* launches, hipEvent_t ev0,
-                hipEvent_t ev1, unsigned long long* its_total, int method) {
+                hipEvent_t ev1, unsigned long long* its_total, int method, const NonLocal* nlt) {
     if (q <= 0 || A.n == 0) return;
+    if (nlt && nlt->k == 0) nlt = nullptr;
     const bool onestep = method == LABPSD_REFINE_ONESTEP;
     const int64_t n = A.n;
     T* V = ws;
@@ -471,7 +476,7 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     // b = -((H - eps S) p + r); beta1 = ||b||
     // spmv partials: one per work-group and column (at most nslices)
     const int64_t npa = launch_spmv<T, 0>(A, sh, hv, sv, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev, sa, V,
-                                          pa, q, s);
+                                          pa, q, s, nlt);
     if (onestep) {
         hipLaunchKernelGGL(k_onestep_init_finish, gcol, dim3(256), 0, s, (const double*)pa, npa, q, rnorm_dev,
                            eta, max_inner, sa);
@@ -500,7 +505,7 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
         const bool check = it + 1 < max_inner && (it + 1) % kCheckEvery == 0;
         if (onestep) {
             // u = A g (beta is 0 in the one-step state), then the step
-            launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, V, n, nullptr, shift_dev, cur, Wb, pa, q, s);
+            launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, V, n, nullptr, shift_dev, cur, Wb, pa, q, s, nlt);
             hipLaunchKernelGGL((k_onestep_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
                                (const MinresScal*)cur, nxt, (const double*)pa, npa, V, (const T*)Wb, Xs,
                                check ? flag_dev + (size_t)slot * q : nullptr);
@@ -508,7 +513,7 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
             nl += 2;
             MinresScal* t2 = cur; cur = nxt; nxt = t2;
         } else {
-        launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s);
+        launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s, nlt);
         hipLaunchKernelGGL((k_minres_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
                            (const MinresScal*)cur, nxt, (const double*)pa, npa, (const T*)V, Wb,
                            (const T*)D1, D2, Xs, check ? flag_dev + (size_t)slot * q : nullptr);
@@ -545,10 +550,10 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
 template void run_minres<double>(const Sell&, double*, int64_t, const double*, int64_t, int,
                                  const int32_t*, const double*, const double*, double, int, int32_t*,
                                  double*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t,
-                                 unsigned long long*, int);
+                                 unsigned long long*, int, const NonLocal*);
 template void run_minres<float>(const Sell&, float*, int64_t, const float*, int64_t, int,
                                 const int32_t*, const double*, const double*, double, int, int32_t*,
                                 float*, double*, int32_t*, hipStream_t, int64_t*, hipEvent_t, hipEvent_t,
-                                unsigned long long*, int);
+                                unsigned long long*, int, const NonLocal*);
 
 }  // namespace labpsd

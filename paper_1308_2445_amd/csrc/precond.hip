@@ -306,10 +306,21 @@ void launch_level(const DevFactor& F, const SnTask* tasks, int64_t ntasks, const
 
 // Y: right-hand sides on entry (consumed); W2: result K^{-1} Y; W1 is not used.
 // All are n x ncols row-major.
+// The SMW step of the nonlocal term: W2 -= Ft (F^T W2), with W1 as the k x ncols scratch
+template <typename T>
+static void smw_correct(const NonLocal* nl, T* W1, T* W2, int64_t n, int ncols, hipStream_t s) {
+    if (!nl || nl->k == 0 || ncols <= 0) return;
+    LABPSD_REQUIRE(nl->smw_ready, "nonlocal term set but its SMW factor is not built");
+    const T* Ft;
+    if constexpr (sizeof(T) == 8) Ft = nl->Ft64.p;
+    else Ft = nl->Ft32.p;
+    launch_nl_ftx_rm<T>(*nl, W2, ncols, W1, s);
+    launch_rm_gemm<T>(n, nl->k, ncols, Ft, W1, W2, -1.0, 1.0, s);
+}
+
 template <typename T>
 void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int ncols,
-                          hipStream_t s) {
-    (void)W1;
+                          hipStream_t s, const NonLocal* nl) {
     const T* panels;
     if constexpr (sizeof(T) == 8) panels = F.panels64.p;
     else panels = F.panels32.p;
@@ -339,6 +350,7 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
             hipLaunchKernelGGL((k_sn_sweep<T, TC, KS>), dim3((unsigned)(ntasks * groups)), dim3(256), 0, s,
                                F.sweep.p, ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn, groups);
         LABPSD_HIP(hipGetLastError());
+        smw_correct<T>(nl, W1, W2, n, ncols, s);
         return;
     }
     const int L = F.nlevels;
@@ -350,6 +362,7 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
     for (int l = L - 1; l >= 0; --l)
         launch_level<T, OP_OFFD_T>(F, F.tasks.p + F.lev_off[4 * l + 2], F.lev_count[4 * l + 2], panels, W2,
                                    W2, ncols, s);
+    smw_correct<T>(nl, W1, W2, n, ncols, s);
 }
 
 void check_precond_sweep(const DevFactor& F, hipStream_t s) {
@@ -365,8 +378,8 @@ void check_precond_sweep(const DevFactor& F, hipStream_t s) {
 }
 
 template void launch_precond_solve<double>(const DevFactor&, double*, double*, double*, int64_t, int,
-                                           hipStream_t);
+                                           hipStream_t, const NonLocal*);
 template void launch_precond_solve<float>(const DevFactor&, float*, float*, float*, int64_t, int,
-                                          hipStream_t);
+                                          hipStream_t, const NonLocal*);
 
 }  // namespace labpsd

@@ -24,7 +24,8 @@ __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off
                                                  const double* __restrict__ sv, int64_t n,
                                                  int64_t nslices, const double* __restrict__ X,
                                                  int64_t ldx, int w, double* __restrict__ YH,
-                                                 double* __restrict__ YS, int64_t ldy) {
+                                                 double* __restrict__ YS, int64_t ldy,
+                                                 NlEpi<double, double> nl) {
     constexpr int SPB = 4 / WPS;
     __shared__ double red[WPS > 1 ? 256 * 2 * CW : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -50,7 +51,8 @@ __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off
 #pragma unroll
         for (int j = 0; j < CW; ++j) {
             if (j < nc) {
-                YH[row + (int64_t)(j0 + j) * ldy] = ah[j];
+                const double yh = nl.rp ? ah[j] + nl_row_term(nl, row, j0 + j) : ah[j];
+                YH[row + (int64_t)(j0 + j) * ldy] = yh;
                 YS[row + (int64_t)(j0 + j) * ldy] = as[j];
             }
         }
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ 
                                                     int64_t nslices, const T* __restrict__ X,
                                                     int64_t ldx, int w,
                                                     const double* __restrict__ shift,
-                                                    T* __restrict__ Y, int64_t ldy) {
+                                                    T* __restrict__ Y, int64_t ldy, NlEpi<T, T> nl) {
     constexpr int SPB = 4 / WPS;
     __shared__ T red[WPS > 1 ? 256 * 2 * CW : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -93,7 +95,8 @@ __global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ 
         for (int j = 0; j < CW; ++j) {
             if (j < nc) {
                 const T sh = (T)shift[j0 + j];
-                Y[row + (int64_t)(j0 + j) * ldy] = ah[j] - sh * as[j];
+                const T h = nl.rp ? ah[j] + nl_row_term(nl, row, j0 + j) : ah[j];
+                Y[row + (int64_t)(j0 + j) * ldy] = h - sh * as[j];
             }
         }
     }
@@ -184,36 +187,38 @@ SellShape sell_shape(int64_t nslices, int w, int max_cw, int64_t want_waves) {
 
 template <int CW, int WPS>
 static void spmm_hs_cw(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
-                       int64_t ldy, hipStream_t s) {
+                       int64_t ldy, hipStream_t s, NlEpi<double, double> nl) {
     constexpr int SPB = 4 / WPS;
     dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)((w + CW - 1) / CW));
     hipLaunchKernelGGL((k_spmm_hs<CW, WPS>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, A.hv.p,
-                       A.sv.p, A.n, A.nslices, X, ldx, w, YH, YS, ldy);
+                       A.sv.p, A.n, A.nslices, X, ldx, w, YH, YS, ldy, nl);
     LABPSD_HIP(hipGetLastError());
 }
 
 template <int CW>
 static void spmm_hs_w(const Sell& A, int wps, const double* X, int64_t ldx, int w, double* YH,
-                      double* YS, int64_t ldy, hipStream_t s) {
-    if (wps == 4) spmm_hs_cw<CW, 4>(A, X, ldx, w, YH, YS, ldy, s);
-    else spmm_hs_cw<CW, 1>(A, X, ldx, w, YH, YS, ldy, s);
+                      double* YS, int64_t ldy, hipStream_t s, NlEpi<double, double> nl) {
+    if (wps == 4) spmm_hs_cw<CW, 4>(A, X, ldx, w, YH, YS, ldy, s, nl);
+    else spmm_hs_cw<CW, 1>(A, X, ldx, w, YH, YS, ldy, s, nl);
 }
 
 void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
-                    int64_t ldy, hipStream_t s) {
+                    int64_t ldy, hipStream_t s, const NonLocal* nlp) {
     if (w <= 0 || A.n == 0) return;
+    const NlEpi<double, double> nl =
+        nlp ? nl_prepare<double>(*nlp, X, ldx, nullptr, w, s) : NlEpi<double, double>{};
     const SellShape sh = sell_shape(A.nslices, w, 8, 2048);
     switch (sh.cw) {
-        case 8: spmm_hs_w<8>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
-        case 4: spmm_hs_w<4>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
-        case 2: spmm_hs_w<2>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
-        default: spmm_hs_w<1>(A, sh.wps, X, ldx, w, YH, YS, ldy, s); break;
+        case 8: spmm_hs_w<8>(A, sh.wps, X, ldx, w, YH, YS, ldy, s, nl); break;
+        case 4: spmm_hs_w<4>(A, sh.wps, X, ldx, w, YH, YS, ldy, s, nl); break;
+        case 2: spmm_hs_w<2>(A, sh.wps, X, ldx, w, YH, YS, ldy, s, nl); break;
+        default: spmm_hs_w<1>(A, sh.wps, X, ldx, w, YH, YS, ldy, s, nl); break;
     }
 }
 
 template <typename T, int CW, int WPS>
 static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
-                          int64_t ldy, hipStream_t s) {
+                          int64_t ldy, hipStream_t s, NlEpi<T, T> nl) {
     constexpr int SPB = 4 / WPS;
     dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)((w + CW - 1) / CW));
     const T* hv;
@@ -226,33 +231,34 @@ static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const d
         sv = A.sv32.p;
     }
     hipLaunchKernelGGL((k_spmm_shift<T, CW, WPS>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, hv, sv,
-                       A.n, A.nslices, X, ldx, w, shift, Y, ldy);
+                       A.n, A.nslices, X, ldx, w, shift, Y, ldy, nl);
     LABPSD_HIP(hipGetLastError());
 }
 
 template <typename T, int CW>
 static void spmm_shift_w(const Sell& A, int wps, const T* X, int64_t ldx, int w, const double* shift,
-                         T* Y, int64_t ldy, hipStream_t s) {
-    if (wps == 4) spmm_shift_cw<T, CW, 4>(A, X, ldx, w, shift, Y, ldy, s);
-    else spmm_shift_cw<T, CW, 1>(A, X, ldx, w, shift, Y, ldy, s);
+                         T* Y, int64_t ldy, hipStream_t s, NlEpi<T, T> nl) {
+    if (wps == 4) spmm_shift_cw<T, CW, 4>(A, X, ldx, w, shift, Y, ldy, s, nl);
+    else spmm_shift_cw<T, CW, 1>(A, X, ldx, w, shift, Y, ldy, s, nl);
 }
 
 template <typename T>
 void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
-                       int64_t ldy, hipStream_t s) {
+                       int64_t ldy, hipStream_t s, const NonLocal* nlp) {
     if (w <= 0 || A.n == 0) return;
+    const NlEpi<T, T> nl = nlp ? nl_prepare<T>(*nlp, X, ldx, nullptr, w, s) : NlEpi<T, T>{};
     const SellShape sh = sell_shape(A.nslices, w, 8, 2048);
     switch (sh.cw) {
-        case 8: spmm_shift_w<T, 8>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
-        case 4: spmm_shift_w<T, 4>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
-        case 2: spmm_shift_w<T, 2>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
-        default: spmm_shift_w<T, 1>(A, sh.wps, X, ldx, w, shift, Y, ldy, s); break;
+        case 8: spmm_shift_w<T, 8>(A, sh.wps, X, ldx, w, shift, Y, ldy, s, nl); break;
+        case 4: spmm_shift_w<T, 4>(A, sh.wps, X, ldx, w, shift, Y, ldy, s, nl); break;
+        case 2: spmm_shift_w<T, 2>(A, sh.wps, X, ldx, w, shift, Y, ldy, s, nl); break;
+        default: spmm_shift_w<T, 1>(A, sh.wps, X, ldx, w, shift, Y, ldy, s, nl); break;
     }
 }
 
 template void launch_spmm_shift<double>(const Sell&, const double*, int64_t, int, const double*,
-                                        double*, int64_t, hipStream_t);
+                                        double*, int64_t, hipStream_t, const NonLocal*);
 template void launch_spmm_shift<float>(const Sell&, const float*, int64_t, int, const double*,
-                                       float*, int64_t, hipStream_t);
+                                       float*, int64_t, hipStream_t, const NonLocal*);
 
 }  // namespace labpsd
