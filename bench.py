@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--rate", type=float, default=4.0, help="system arrivals per second (Poisson)")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--ablation", action="store_true",
+                    help="global-only / local-only / hybrid preconditioning over SCF-like sequences")
+    ap.add_argument("--abl-workload", default="c2nl")
+    ap.add_argument("--abl-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 8 plain device copies of 512 MiB (the scale for the HBM byte counters)")
     return ap.parse_args()
@@ -249,6 +253,80 @@ def serving_line(args):
     print(json.dumps(line), flush=True)
 
 
+def ablation(args):
+    """Section 5.4's comparison on synthetic SCF-like sequences: the same chain of GHEPs
+    (potential amplitudes drifting by up to 1% per step, every step warm-started from the
+    previous one's resident block and Ritz values) solved with the global preconditioner
+    only (step 6(a); outer cap 200), the local one only (localised pairs refined by MINRES
+    from zero; outer cap 100, MINRES cap 500; the first, cold step global only, as the
+    paper's footnote does until pairs localise) and the hybrid scheme (caps 200 / 20); and
+    the hybrid scheme again with a global factor computed in single precision (the
+    conclusions' suggestion).  Reports Hp, La, stalled steps and the chain's time."""
+    import torch
+
+    import paper_1308_2445_amd as lp
+    import pufe
+    P = pufe.workload(args.abl_workload, 0)
+    nev = pufe.WORKLOADS[args.abl_workload]["nev"]
+    m0 = pufe.guard_vectors(nev)
+    rng = np.random.default_rng(77)
+    scales = np.cumprod(1.0 + rng.uniform(-0.01, 0.01, args.abl_steps))
+    ctx = lp.Context(0)
+    # eps_bar: the default reading (V_min - 0.1, far below the wanted pairs); "global_near"
+    # repeats global-only with eps_bar just below lambda_1 (from the hybrid run's first step)
+    configs = [("hybrid", lp.HYBRID, 200, 20, 0, None), ("global", lp.GLOBAL_ONLY, 200, 20, 0, None),
+               ("global_near", lp.GLOBAL_ONLY, 200, 20, 0, "near"), ("local", lp.LOCAL_ONLY, 100, 500, 0, None),
+               ("hybrid_fp32_factor", lp.HYBRID, 200, 20, lp.FACTOR_FP32, None)]
+    out = {"workload": "%s: n=%d, nev=%d, m0=%d, %s, %d SCF-like steps (amplitude drift <= 1%%/step), tol %g, "
+                       "mixed precision" % (args.abl_workload, P.n, nev, m0,
+                                            "k=%d projectors" % P.F.shape[1] if P.F is not None else "local V only",
+                                            args.abl_steps, args.tol), "modes": {}}
+    ref_lam = None
+    lam1 = None
+    for name, mode, cap_outer, cap_inner, fmask, shift in configs:
+        pr = lp.Problem.from_pencil(ctx, P)
+        t0 = time.perf_counter()
+        eps_bar = P.eps_bar if shift is None else lam1 - 0.1
+        pr.set_global_precond(eps_bar, pufe.dof_coordinates(P), panels=lp.PANELS_FP32 | fmask)
+        t_fac = time.perf_counter() - t0
+        srv = lp.Server(ctx, 1 << 40, 1)
+        steps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(args.abl_steps):
+            # the cold step of the local-only run uses the global preconditioner (paper's footnote)
+            pr.set_local_precond(mode=lp.GLOBAL_ONLY if (mode == lp.LOCAL_ONLY and j == 0) else mode,
+                                 max_inner=cap_inner)
+            rid = srv.submit(pr, nev, m0, X0=pufe.start_block(P.n, nev + m0, 0) if j == 0 else None,
+                             h_val=P.h_scaled(scales[j]), tol=args.tol, max_outer=cap_outer, sigma0=P.sigma0,
+                             precision=lp.MIXED)
+            r = srv.wait(rid)
+            steps.append(dict(outer=r.stats["outer_iters"], minres=r.stats["minres_iters"],
+                              converged=bool(r.converged), seconds=r.finished - r.started, lam=r.lam))
+        t_chain = time.perf_counter() - t0
+        srv.close()
+        pr.close()
+        outer = sum(st["outer"] for st in steps)
+        minres = sum(st["minres"] for st in steps)
+        lam_last = steps[-1]["lam"]
+        if name == "hybrid":
+            ref_lam = lam_last
+            lam1 = float(steps[0]["lam"][0])
+        rec = {"Hp": outer / len(steps), "La": minres / max(1, outer * nev), "outer_per_step": [st["outer"] for st in steps],
+               "minres_per_step": [st["minres"] for st in steps],
+               "stalled_steps": sum(1 for st in steps if not st["converged"]), "chain_s": t_chain,
+               "factor_s": t_fac, "warm_Hp": float(np.mean([st["outer"] for st in steps[1:]])) if len(steps) > 1 else None,
+               "eps_bar": eps_bar}
+        if name != "hybrid" and steps[-1]["converged"]:
+            rec["last_step_max_rel_diff_vs_hybrid"] = float(np.max(np.abs(lam_last - ref_lam) / np.abs(ref_lam - P.sigma0)))
+        out["modes"][name] = rec
+        print("[ablation] %s: Hp %.2f (warm %.2f) La %.2f stalled %d chain %.2fs factor %.1fs" % (
+            name, rec["Hp"], rec["warm_Hp"] or 0, rec["La"], rec["stalled_steps"], t_chain, t_fac), flush=True)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"ablation": out}), flush=True)
+
+
 def golden_lam(name):
     """Stored eigenvalues of an independent CPU route for this workload (ARPACK shift-invert
     Lanczos, written by tests/golden/make_golden.py), or None."""
@@ -315,6 +393,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.ablation:
+        ablation(args)
         return
     import torch
 

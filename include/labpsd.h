@@ -123,13 +123,15 @@ labpsd_status labpsd_problem_set_nonlocal(labpsd_problem* p, int k, const int64_
  * below lambda_1 makes the matrix positive definite) and uploads the factor
  * panels in the precisions that `precisions` selects: LABPSD_PANELS_FP64 (the
  * apply of LABPSD_FP64 solves), LABPSD_PANELS_FP32 (the apply of LABPSD_MIXED
- * solves), or their OR; 0 means both.  A solve or apply in a precision whose
- * panels were not uploaded returns ESTATE.  `coords` (host float64[n*3],
+ * solves), or their OR; neither means both.  A solve or apply in a precision whose
+ * panels were not uploaded returns ESTATE.  LABPSD_FACTOR_FP32 (ORed in) runs the
+ * numeric factorisation itself in single precision (the conclusions' suggestion):
+ * fronts, pivots and inverses in FP32; FP64 panels, if uploaded, hold those values.  `coords` (host float64[n*3],
  * row-major x,y,z per dof, or NULL) guides the ordering by coordinate
  * bisection; with NULL a breadth-first level-structure bisection of the graph
  * is used.  ENOTSPD if a pivot is not positive (eps_bar too high); EINVAL for a
  * mask with other bits set.                                                  */
-enum { LABPSD_PANELS_FP64 = 1, LABPSD_PANELS_FP32 = 2 };
+enum { LABPSD_PANELS_FP64 = 1, LABPSD_PANELS_FP32 = 2, LABPSD_FACTOR_FP32 = 4 };
 labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const double* coords,
                                         unsigned precisions);
 

@@ -851,15 +851,17 @@ labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const
     return guarded([&]() -> labpsd_status {
         LABPSD_REQUIRE(p != nullptr, "problem is NULL");
         LABPSD_REQUIRE(std::isfinite(eps_bar), "eps_bar must be finite");
-        LABPSD_REQUIRE((precisions & ~(unsigned)(LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32)) == 0,
+        LABPSD_REQUIRE((precisions & ~(unsigned)(LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32 | LABPSD_FACTOR_FP32)) == 0,
                        "precision mask has unknown bits");
-        const unsigned panels = precisions ? precisions : (LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32);
+        const bool single = (precisions & LABPSD_FACTOR_FP32) != 0;
+        const unsigned sel = precisions & (unsigned)(LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32);
+        const unsigned panels = sel ? sel : (LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32);
         LABPSD_HIP(hipSetDevice(p->ctx->device));
         std::vector<double> kval(p->nnz);
         for (int64_t e = 0; e < p->nnz; ++e) kval[e] = p->h_val[e] - eps_bar * p->s_val[e];
         HostFactor F;
         std::string msg;
-        const int rc = factorize(p->csr, kval.data(), coords, F, msg);
+        const int rc = factorize(p->csr, kval.data(), coords, F, msg, single);
         if (rc == -4) throw Error{LABPSD_ENOTSPD, msg};
         if (rc != 0) throw Error{LABPSD_EINVAL, msg};
         const double t0 = wall();

@@ -212,33 +212,34 @@ class Dissector {
 // C[i, j] -= sum_p A[i, p] * A[j, p] for rows i in [r0, nf), i >= j, columns j in
 // [j0, j1).  A is the packed panel: rows [a0, nf) in blocks of 8, each block
 // kw x 8 contiguous (block-major), so A[i, p] = Ap[((i - a0) / 8) * kw * 8 + p * 8 + (i - a0) % 8].
-void syrk_cols(double* F, int64_t ld, int64_t nf, const double* Ap, int64_t a0, int kw, int64_t j0,
+template <typename T>
+void syrk_cols(T* F, int64_t ld, int64_t nf, const T* Ap, int64_t a0, int kw, int64_t j0,
                int64_t j1) {
     constexpr int MR = 8, NR = 4;
-    double bj[64 * NR];
+    T bj[64 * NR];
     for (int64_t j = j0; j < j1; j += NR) {
         const int nr = (int)std::min<int64_t>(NR, j1 - j);
         for (int jj = 0; jj < NR; ++jj) {
             int64_t col = j + (jj < nr ? jj : 0);
             int64_t blk = (col - a0) / MR, off = (col - a0) % MR;
-            for (int p = 0; p < kw; ++p) bj[p * NR + jj] = jj < nr ? Ap[blk * kw * MR + p * MR + off] : 0.0;
+            for (int p = 0; p < kw; ++p) bj[p * NR + jj] = jj < nr ? Ap[blk * kw * MR + p * MR + off] : T(0);
         }
         // first 8-row block containing row j
         int64_t ib0 = ((j - a0) / MR) * MR + a0;
         for (int64_t i = ib0; i < nf; i += MR) {
-            const double* a = Ap + ((i - a0) / MR) * kw * MR;
-            double acc[NR][MR];
+            const T* a = Ap + ((i - a0) / MR) * kw * MR;
+            T acc[NR][MR];
             for (int jj = 0; jj < NR; ++jj)
-                for (int r = 0; r < MR; ++r) acc[jj][r] = 0.0;
+                for (int r = 0; r < MR; ++r) acc[jj][r] = T(0);
             for (int p = 0; p < kw; ++p) {
-                const double* ap = a + p * MR;
+                const T* ap = a + p * MR;
                 for (int jj = 0; jj < NR; ++jj) {
-                    const double b = bj[p * NR + jj];
+                    const T b = bj[p * NR + jj];
                     for (int r = 0; r < MR; ++r) acc[jj][r] += ap[r] * b;
                 }
             }
             for (int jj = 0; jj < nr; ++jj) {
-                double* c = F + (j + jj) * ld;
+                T* c = F + (j + jj) * ld;
                 for (int r = 0; r < MR; ++r) {
                     int64_t row = i + r;
                     if (row >= j + jj && row < nf) c[row] -= acc[jj][r];
@@ -250,23 +251,24 @@ void syrk_cols(double* F, int64_t ld, int64_t nf, const double* Ap, int64_t a0, 
 
 // Partial Cholesky of the front F (nf x nf, ld nf, lower triangle): eliminate the
 // first ncol columns.  Returns -1 on success or the failing column.
-int64_t partial_cholesky(double* F, int64_t nf, int64_t ncol, int nthreads) {
+template <typename T>
+int64_t partial_cholesky(T* F, int64_t nf, int64_t ncol, int nthreads) {
     const int64_t ld = nf;
     constexpr int NB = 64;
-    std::vector<double> Ap;
+    std::vector<T> Ap;
     for (int64_t k0 = 0; k0 < ncol; k0 += NB) {
         const int kw = (int)std::min<int64_t>(NB, ncol - k0);
         const int64_t k1 = k0 + kw;
         // 1. diagonal block, unblocked right-looking
         for (int64_t j = k0; j < k1; ++j) {
-            double d = F[j + j * ld];
-            if (!(d > 0.0) || !std::isfinite(d)) return j;
+            T d = F[j + j * ld];
+            if (!(d > T(0)) || !std::isfinite(d)) return j;
             d = std::sqrt(d);
             F[j + j * ld] = d;
-            const double inv = 1.0 / d;
+            const T inv = T(1) / d;
             for (int64_t i = j + 1; i < k1; ++i) F[i + j * ld] *= inv;
             for (int64_t jj = j + 1; jj < k1; ++jj) {
-                const double f = F[jj + j * ld];
+                const T f = F[jj + j * ld];
                 for (int64_t i = jj; i < k1; ++i) F[i + jj * ld] -= F[i + j * ld] * f;
             }
         }
@@ -277,49 +279,50 @@ int64_t partial_cholesky(double* F, int64_t nf, int64_t ncol, int nthreads) {
         parallel_for((nbelow + rchunk - 1) / rchunk, nthreads, [&](int64_t c) {
             const int64_t r0 = k1 + c * rchunk, r1 = std::min(nf, r0 + rchunk);
             for (int64_t j = k0; j < k1; ++j) {
-                double* cj = F + j * ld;
+                T* cj = F + j * ld;
                 for (int64_t p = k0; p < j; ++p) {
-                    const double l = F[j + p * ld];
-                    const double* cp = F + p * ld;
+                    const T l = F[j + p * ld];
+                    const T* cp = F + p * ld;
                     for (int64_t i = r0; i < r1; ++i) cj[i] -= cp[i] * l;
                 }
-                const double inv = 1.0 / F[j + j * ld];
+                const T inv = T(1) / F[j + j * ld];
                 for (int64_t i = r0; i < r1; ++i) cj[i] *= inv;
             }
         });
         // 3. trailing update of the lower triangle F[k1:nf, k1:nf] by the panel
         const int64_t a0 = k1;
         const int64_t nblk = (nbelow + 7) / 8;
-        Ap.assign((size_t)nblk * kw * 8, 0.0);
+        Ap.assign((size_t)nblk * kw * 8, T(0));
         parallel_for(nblk, nthreads, [&](int64_t b) {
             for (int p = 0; p < kw; ++p)
                 for (int r = 0; r < 8; ++r) {
                     int64_t row = a0 + b * 8 + r;
-                    Ap[b * kw * 8 + p * 8 + r] = row < nf ? F[row + (k0 + p) * ld] : 0.0;
+                    Ap[b * kw * 8 + p * 8 + r] = row < nf ? F[row + (k0 + p) * ld] : T(0);
                 }
         });
         const int64_t cblk = 32;
         const int64_t ncb = (nbelow + cblk - 1) / cblk;
         parallel_for(ncb, nthreads, [&](int64_t c) {
             const int64_t j0 = k1 + c * cblk, j1 = std::min(nf, j0 + cblk);
-            syrk_cols(F, ld, nf, Ap.data(), a0, kw, j0, j1);
+            syrk_cols<T>(F, ld, nf, Ap.data(), a0, kw, j0, j1);
         });
     }
     return -1;
 }
 
 // X = L^{-1} for the lower-triangular L (n x n, ld ldl); X column-major ld n.
-void invert_lower(const double* L, int64_t ldl, int64_t n, double* X, int nthreads) {
+template <typename T>
+void invert_lower(const T* L, int64_t ldl, int64_t n, T* X, int nthreads) {
     parallel_for(n, nthreads, [&](int64_t j) {
-        double* x = X + j * n;
-        for (int64_t i = 0; i < j; ++i) x[i] = 0.0;
-        for (int64_t i = j; i < n; ++i) x[i] = 0.0;
-        x[j] = 1.0;
+        T* x = X + j * n;
+        for (int64_t i = 0; i < j; ++i) x[i] = T(0);
+        for (int64_t i = j; i < n; ++i) x[i] = T(0);
+        x[j] = T(1);
         for (int64_t k = j; k < n; ++k) {
-            const double xk = x[k] / L[k + k * ldl];
+            const T xk = x[k] / L[k + k * ldl];
             x[k] = xk;
-            if (xk == 0.0) continue;
-            const double* lk = L + k * ldl;
+            if (xk == T(0)) continue;
+            const T* lk = L + k * ldl;
             for (int64_t i = k + 1; i < n; ++i) x[i] -= lk[i] * xk;
         }
     });
@@ -330,7 +333,7 @@ void invert_lower(const double* L, int64_t ldl, int64_t n, double* X, int nthrea
 // ------------------------------------------------------------------ factorize
 
 int factorize(const HostCSR& A, const double* kval, const double* coords, HostFactor& F,
-              std::string& msg) {
+              std::string& msg, bool single) {
     const int64_t n = A.n;
     const int nthreads = host_threads();
     double t0 = wall();
@@ -443,12 +446,16 @@ int factorize(const HostCSR& A, const double* kval, const double* coords, HostFa
 
     // numeric: subtrees below the top levels run in parallel, one thread each;
     // the top supernodes then run one at a time with threaded dense kernels
-    std::vector<std::unique_ptr<std::vector<double>>> upd(nsn);
     std::atomic<int> fail(-1);
+    // the arithmetic of the fronts in FP64, or in FP32 (single: the conclusions'
+    // single-precision factorisation); the panels are kept in FP64 either way
+    auto numeric = [&](auto zero) {
+    using T = decltype(zero);
+    std::vector<std::unique_ptr<std::vector<T>>> upd(nsn);
     auto do_node = [&](int i, std::vector<int32_t>& loc, int nt) {
         const Supernode& s = F.sn[i];
         const int64_t nc = s.ncol, nf = s.nrow, nb = nf - nc;
-        std::vector<double> Fr((size_t)nf * nf, 0.0);
+        std::vector<T> Fr((size_t)nf * nf, T(0));
         for (int64_t k = 0; k < nc; ++k) loc[s.pos0 + k] = (int32_t)k;
         for (int64_t k = 0; k < nb; ++k) loc[B[i][k]] = (int32_t)(nc + k);
         for (int64_t jj = 0; jj < nc; ++jj) {
@@ -456,25 +463,25 @@ int factorize(const HostCSR& A, const double* kval, const double* coords, HostFa
             const int32_t v = F.perm[pj];
             for (int64_t e = A.rowptr[v]; e < A.rowptr[v + 1]; ++e) {
                 const int32_t q = invperm[A.col[e]];
-                if (q >= pj) Fr[loc[q] + jj * nf] += kval[e];
+                if (q >= pj) Fr[loc[q] + jj * nf] += (T)kval[e];
             }
         }
         for (int c : kids[i]) {
             const std::vector<int32_t>& bc = B[c];
             const int64_t m = (int64_t)bc.size();
-            const double* U = upd[c]->data();
+            const T* U = upd[c]->data();
             std::vector<int32_t> li(m);
             for (int64_t a = 0; a < m; ++a) li[a] = loc[bc[a]];
             for (int64_t bcol = 0; bcol < m; ++bcol) {
-                double* fc = Fr.data() + (int64_t)li[bcol] * nf;
-                const double* uc = U + bcol * m;
+                T* fc = Fr.data() + (int64_t)li[bcol] * nf;
+                const T* uc = U + bcol * m;
                 for (int64_t a = bcol; a < m; ++a) fc[li[a]] += uc[a];
             }
             upd[c].reset();
         }
         for (int64_t k = 0; k < nc; ++k) loc[s.pos0 + k] = -1;
         for (int64_t k = 0; k < nb; ++k) loc[B[i][k]] = -1;
-        int64_t bad = partial_cholesky(Fr.data(), nf, nc, nt);
+        int64_t bad = partial_cholesky<T>(Fr.data(), nf, nc, nt);
         if (bad >= 0) {
             int expected = -1;
             fail.compare_exchange_strong(expected, i);
@@ -483,32 +490,33 @@ int factorize(const HostCSR& A, const double* kval, const double* coords, HostFa
         double* panel = F.panels.data() + s.val_off;
         // X = inv(L11) (lower, ld nc); the panel receives G = X^T X = (L11 L11^T)^{-1} on
         // top (full, symmetric) and F = L21 X below
-        std::vector<double> X((size_t)nc * nc);
-        invert_lower(Fr.data(), nf, nc, X.data(), nt);
+        std::vector<T> X((size_t)nc * nc);
+        invert_lower<T>(Fr.data(), nf, nc, X.data(), nt);
         parallel_for(nc, nt, [&](int64_t b) {
             // column b of G: G[a, b] = sum_{k >= max(a, b)} X[k, a] X[k, b]
-            const double* xb = X.data() + b * nc;
+            const T* xb = X.data() + b * nc;
             for (int64_t a = 0; a < nc; ++a) {
-                const double* xa = X.data() + a * nc;
-                double acc = 0.0;
+                const T* xa = X.data() + a * nc;
+                T acc = T(0);
                 for (int64_t k = std::max(a, b); k < nc; ++k) acc += xa[k] * xb[k];
-                panel[a + b * nf] = acc;
+                panel[a + b * nf] = (double)acc;
             }
             // column b of F: F[i, b] = sum_{k >= b} L21[i, k] X[k, b]
-            double* fb = panel + b * nf + nc;
-            for (int64_t i = 0; i < nb; ++i) fb[i] = 0.0;
+            std::vector<T> fb(nb, T(0));
             for (int64_t k = b; k < nc; ++k) {
-                const double xkb = xb[k];
-                if (xkb == 0.0) continue;
-                const double* l21k = Fr.data() + k * nf + nc;
+                const T xkb = xb[k];
+                if (xkb == T(0)) continue;
+                const T* l21k = Fr.data() + k * nf + nc;
                 for (int64_t i = 0; i < nb; ++i) fb[i] += l21k[i] * xkb;
             }
+            double* fp = panel + b * nf + nc;
+            for (int64_t i = 0; i < nb; ++i) fp[i] = (double)fb[i];
         });
         if (nb > 0) {
-            auto U = std::make_unique<std::vector<double>>((size_t)nb * nb);
+            auto U = std::make_unique<std::vector<T>>((size_t)nb * nb);
             for (int64_t j = 0; j < nb; ++j)
                 std::memcpy(U->data() + j * nb + j, Fr.data() + (nc + j) * nf + nc + j,
-                            sizeof(double) * (nb - j));
+                            sizeof(T) * (nb - j));
             upd[i] = std::move(U);
         }
     };
@@ -540,6 +548,9 @@ int factorize(const HostCSR& A, const double* kval, const double* coords, HostFa
             do_node(i, loc, nthreads);
         }
     }
+    };
+    if (single) numeric(0.0f);
+    else numeric(0.0);
     F.t_factor = wall() - t1;
     if (fail.load() >= 0) {
         msg = "H - eps_bar S is not positive definite (non-positive pivot in supernode " +

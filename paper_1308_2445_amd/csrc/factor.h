@@ -62,10 +62,12 @@ struct HostFactor {
     double t_subtrees = 0.0;   // part of t_factor spent in the parallel subtrees
 };
 
-// Factor K (values `kval` on the pattern of A).  Returns 0, or -4 when a pivot is
-// not positive (msg names the supernode), or -1 on an internal inconsistency.
+// Factor K (values `kval` on the pattern of A).  single: the numeric factorisation
+// (fronts, Cholesky, inverses, panels) in FP32 arithmetic, the panels then stored
+// widened to FP64.  Returns 0, or -4 when a pivot is not positive (msg names the
+// supernode), or -1 on an internal inconsistency.
 int factorize(const HostCSR& A, const double* kval, const double* coords, HostFactor& F,
-              std::string& msg);
+              std::string& msg, bool single = false);
 
 // Solve K x = b on the host with the factor (for self-checks): x overwrites b.
 void host_solve(const HostFactor& F, double* b);
