@@ -132,17 +132,17 @@ def one_step_refine(H, S, p, r, eps: float, eta: float, max_inner: int):
     def A(v):
         return H @ v - eps * (S @ v)
     target = eta * float(np.linalg.norm(r))
-    p = np.array(p, dtype=np.float64, copy=True)
+    p = np.array(p, dtype=np.result_type(p, r), copy=True)
     steps = 0
     for _ in range(max_inner):
         rho = A(p) + r
         if float(np.linalg.norm(rho)) <= target:
             break
         Arho = A(rho)
-        den = float(Arho @ Arho)
+        den = float(np.vdot(Arho, Arho).real)
         if den == 0.0:
             break
-        alpha = float(rho @ Arho) / den
+        alpha = np.vdot(Arho, rho) / den     # the minimiser of ||rho - alpha A rho|| (real here)
         p = p - alpha * rho
         steps += 1
     return p, steps
@@ -169,7 +169,7 @@ def solve(H, S, params: Params, X0: np.ndarray, E0: np.ndarray | None = None,
     t1 = time.perf_counter()
 
     # steps 1-3: start block, products
-    E, Psi, PsiH, PsiS = initial_rr(H, S, np.asarray(X0, dtype=np.float64), b)
+    E, Psi, PsiH, PsiS = initial_rr(H, S, np.asarray(X0, dtype=np.result_type(X0, H.dtype)), b)
     E_prev = None if E0 is None else np.asarray(E0, dtype=np.float64)[:m].copy()
     fresh = True
     since_refresh = 0

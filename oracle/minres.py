@@ -27,19 +27,19 @@ def minres(matvec, b: np.ndarray, stop_norm: float, max_iter: int):
     recurred ||b - A x_k|| (residual_norms[0] = ||b||).
     """
     n = b.shape[0]
-    x = np.zeros(n)
+    x = np.zeros(n, dtype=b.dtype)
     beta1 = float(np.linalg.norm(b))
     hist = [beta1]
     if beta1 == 0.0 or beta1 <= stop_norm or max_iter <= 0:
         return x, 0, hist
-    v_prev = np.zeros(n)
+    v_prev = np.zeros(n, dtype=b.dtype)
     v = b / beta1
     beta = beta1          # beta_k: coupling of v_k to v_{k-1} (beta_1 for the first step)
     # Givens state: the rotation from the previous two columns
     c_prev, s_prev = 1.0, 0.0      # rotation k-1
     c_pp, s_pp = 1.0, 0.0          # rotation k-2
-    d_prev = np.zeros(n)           # direction d_{k-1}
-    d_pp = np.zeros(n)             # direction d_{k-2}
+    d_prev = np.zeros(n, dtype=b.dtype)           # direction d_{k-1}
+    d_pp = np.zeros(n, dtype=b.dtype)             # direction d_{k-2}
     phibar = beta1
     its = 0
     for k in range(1, max_iter + 1):
@@ -47,7 +47,7 @@ def minres(matvec, b: np.ndarray, stop_norm: float, max_iter: int):
         w = matvec(v)
         if k > 1:
             w = w - beta * v_prev
-        alpha = float(v @ w)
+        alpha = float(np.vdot(v, w).real)   # real for a Hermitian A
         w = w - alpha * v
         beta_next = float(np.linalg.norm(w))
         # column k of T_k: (beta_k at row k-1, alpha_k at row k, beta_{k+1} at row k+1)

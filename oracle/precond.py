@@ -25,13 +25,13 @@ class GlobalPreconditioner:
         self.K = K
         self.lu = spla.splu(K, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
                             options=dict(SymmetricMode=True))
-        d = self.lu.U.diagonal()
+        d = self.lu.U.diagonal().real
         if np.any(d <= 0):
             raise np.linalg.LinAlgError("H - eps_bar S is not positive definite")
 
     def apply(self, R: np.ndarray) -> np.ndarray:
         """P = -(H - eps_bar S)^{-1} R  (eq. (k1p))."""
-        R = np.asarray(R, dtype=np.float64)
+        R = np.asarray(R, dtype=np.result_type(R, self.K.dtype))
         if R.ndim == 1:
             return -self.lu.solve(R)
         if R.shape[1] == 0:

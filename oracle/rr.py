@@ -17,10 +17,10 @@ RANK_TOL = 1e-14
 
 
 def gram(Z: np.ndarray, ZH: np.ndarray, ZS: np.ndarray):
-    """H_R = Z^T (HZ), S_R = Z^T (SZ), each replaced by its symmetric part (step 8)."""
-    HR = Z.T @ ZH
-    SR = Z.T @ ZS
-    return 0.5 * (HR + HR.T), 0.5 * (SR + SR.T)
+    """H_R = Z^H (HZ), S_R = Z^H (SZ), each replaced by its Hermitian part (step 8)."""
+    HR = Z.conj().T @ ZH
+    SR = Z.conj().T @ ZS
+    return 0.5 * (HR + HR.conj().T), 0.5 * (SR + SR.conj().T)
 
 
 def rayleigh_ritz(HR: np.ndarray, SR: np.ndarray, nwant: int):
@@ -38,7 +38,7 @@ def rayleigh_ritz(HR: np.ndarray, SR: np.ndarray, nwant: int):
         return gam, W, 0
     except np.linalg.LinAlgError:
         pass
-    d = np.diag(SR).copy()
+    d = np.diag(SR).real.copy()
     keep_cols = d > 0
     D = np.zeros(k)
     D[keep_cols] = 1.0 / np.sqrt(d[keep_cols])
@@ -50,8 +50,8 @@ def rayleigh_ritz(HR: np.ndarray, SR: np.ndarray, nwant: int):
     if r < nwant:
         raise np.linalg.LinAlgError("search space rank %d below the block width %d" % (r, nwant))
     T = Q[:, keep] / np.sqrt(lam[keep])[None, :]
-    C = T.T @ Hs @ T
-    C = 0.5 * (C + C.T)
+    C = T.conj().T @ Hs @ T
+    C = 0.5 * (C + C.conj().T)
     gam, V = np.linalg.eigh(C)
     W = D[:, None] * (T @ V[:, :nwant])
     return gam[:nwant], W, k - r

@@ -60,6 +60,7 @@ class Problem:
     alpha: float = ENRICH_ALPHA       # enrichment exponent the pencil was built with
     F: object = None                  # nonlocal projectors (n x k CSC) or None
     G: np.ndarray | None = None       # their k x k coupling
+    kpoint: np.ndarray | None = None  # reduced k-point of a Bloch-periodic (complex) pencil
 
     def h_scaled(self, scale: float) -> np.ndarray:
         """H values with every potential amplitude multiplied by ``scale``."""
@@ -169,14 +170,22 @@ def _potential_at(elem_ijk: np.ndarray, xi: np.ndarray, h: float,
 
 
 def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
-             atoms: np.ndarray | None = None, alpha: float = ENRICH_ALPHA) -> Problem:
+             atoms: np.ndarray | None = None, alpha: float = ENRICH_ALPHA, kpoint=None) -> Problem:
     """Assemble the PUFE-shaped pencil for a periodic cube (see module docstring).
 
     alpha is the exponent of the enrichment g(r) = exp(-alpha |r - R|^2).  The named
     workloads use 1.0; a smaller alpha makes g flatter over a node's support, so each
     enriched function approaches a multiple of its hat function and S approaches
     singularity (cond(S) grows roughly like 1/alpha^2), the regime of Section 2's
-    Table 1 where enrichment drives cond(S) to 1e8 and beyond."""
+    Table 1 where enrichment drives cond(S) to 1e8 and beyond.
+
+    kpoint (three reduced coordinates k_f, the wave vector 2 pi k_f / L) assembles the
+    Bloch-periodic pencil of that k-point (Section 2's k-point sampling): a basis function
+    that an element reaches through the periodic boundary with lattice translation T L
+    carries the phase exp(2 pi i k_f . T), so element entry (a, b) is multiplied by
+    exp(2 pi i k_f . (T_b - T_a)) and H, S become complex Hermitian.  None (or the Gamma
+    point, where every phase is one) gives the real pencil of the same construction."""
+    kf = None if kpoint is None else np.asarray(kpoint, dtype=np.float64).reshape(3)
     h = L / ne
     nnode = ne ** 3
     if atoms is None:
@@ -232,6 +241,10 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
         o = _LOCAL_OFF[a]
         enodes[:, a] = ((E[:, 0] + o[0]) % ne) + ne * (((E[:, 1] + o[1]) % ne) + ne * ((E[:, 2] + o[2]) % ne))
     enr_elem = nenr_node[enodes].sum(axis=1) > 0
+    # Bloch phases of the element-local nodes (k-point cells): T = wraps of E + offset
+    if kf is not None:
+        wraps = (E[:, None, :] + _LOCAL_OFF[None, :, :]) // ne                 # (nel, 8, 3)
+        node_phase = np.exp(2j * np.pi * np.einsum("ead,d->ea", wraps, kf))   # (nel, 8)
 
     rows_all, cols_all, hv_all, sv_all, kv_all = [], [], [], [], []
     vmin = np.inf
@@ -254,8 +267,13 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
         dofs = first_dof[enodes[els]]                                   # (e,8)
         rows_all.append(np.repeat(dofs, 8, axis=1).ravel())
         cols_all.append(np.tile(dofs, (1, 8)).ravel())
+        Kl = np.broadcast_to(Kref, Hloc.shape)
+        if kf is not None:
+            ph = node_phase[els]
+            pab = np.conj(ph)[:, :, None] * ph[:, None, :]
+            Hloc, Sloc, Kl = Hloc * pab, Sloc * pab, Kl * pab
         hv_all.append(Hloc.reshape(-1))
-        kv_all.append(np.broadcast_to(Kref, Hloc.shape).reshape(-1))
+        kv_all.append(np.ascontiguousarray(Kl).reshape(-1))
         sv_all.append(np.ascontiguousarray(Sloc).reshape(-1))
 
     # ---- enriched elements: 4^3 Gauss, 8 hats plus the enriched functions of their nodes
@@ -283,6 +301,7 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
         org = E[els] * h                                                # unwrapped element origin
         rq = org[:, None, :] + h * xi4[None, :, :]                      # (e,nq,3)
         slot = 8
+        slot_node = list(range(8))
         for a in range(8):
             nd = nodes[:, a]
             xnode = org + _LOCAL_OFF[a] * h                             # (e,3) local node position
@@ -304,11 +323,18 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
                 grad[:, :, slot, :] = np.where(m[..., None], gr, 0.0)
                 dof[:, slot] = np.where(has, pdof, 0)
                 valid[:, slot] = has
+                slot_node.append(a)
                 slot += 1
         wq = w4 * h ** 3
         Kloc = 0.5 * np.einsum("q,eqfd,eqgd->efg", wq, grad, grad, optimize=True)
         Hloc = Kloc + np.einsum("q,eq,eqf,eqg->efg", wq, Vq, phi, phi, optimize=True)
         Sloc = np.einsum("q,eqf,eqg->efg", wq, phi, phi, optimize=True)
+        if kf is not None:
+            ph = node_phase[els][:, slot_node]                          # (e, used slots)
+            ns = ph.shape[1]
+            pab = np.ones((ne_c, F, F), dtype=np.complex128)
+            pab[:, :ns, :ns] = np.conj(ph)[:, :, None] * ph[:, None, :]
+            Hloc, Sloc, Kloc = Hloc * pab, Sloc * pab, Kloc * pab
         vv = valid[:, :, None] & valid[:, None, :]
         R_ = np.repeat(dof[:, :, None], F, axis=2)
         C_ = np.repeat(dof[:, None, :], F, axis=1)
@@ -323,10 +349,15 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
     Hc = sp.coo_matrix((np.concatenate(hv_all), (rows, cols)), shape=(n, n)).tocsr()
     Sc = sp.coo_matrix((np.concatenate(sv_all), (rows, cols)), shape=(n, n)).tocsr()
     Kc = sp.coo_matrix((np.concatenate(kv_all), (rows, cols)), shape=(n, n)).tocsr()
-    Kc = ((Kc + Kc.T) * 0.5).tocsr()
-    # exact symmetry (duplicate summation order may differ between (i,j) and (j,i))
-    Hc = ((Hc + Hc.T) * 0.5).tocsr()
-    Sc = ((Sc + Sc.T) * 0.5).tocsr()
+    # exact (Hermitian) symmetry: duplicate summation order may differ between (i,j) and (j,i)
+    if kf is None:
+        Kc = ((Kc + Kc.T) * 0.5).tocsr()
+        Hc = ((Hc + Hc.T) * 0.5).tocsr()
+        Sc = ((Sc + Sc.T) * 0.5).tocsr()
+    else:
+        Kc = ((Kc + Kc.conj().T) * 0.5).tocsr()
+        Hc = ((Hc + Hc.conj().T) * 0.5).tocsr()
+        Sc = ((Sc + Sc.conj().T) * 0.5).tocsr()
     # one shared pattern: union of both patterns, explicit zeros kept
     pat = (abs(Hc) + abs(Sc)).tocsr()
     pat.sort_indices()
@@ -338,7 +369,7 @@ def generate(L: float, ne: int, natoms: int, seed: int, *, amplitudes=None,
     return Problem(n=n, rowptr=pat.indptr.astype(np.int64), col=pat.indices.astype(np.int32),
                    h_val=Hc, s_val=Sc, v_min=vmin, sigma0=vmin - 1.0, eps_bar=vmin - 0.1,
                    L=float(L), ne=int(ne), atoms=atoms, amplitudes=amps, dof_node=dof_node,
-                   dof_atom=dof_atom, seed=int(seed), k_val=Kc, alpha=float(alpha))
+                   dof_atom=dof_atom, seed=int(seed), k_val=Kc, alpha=float(alpha), kpoint=kf)
 
 
 # ------------------------------------------------------------------ nonlocal projectors
@@ -429,7 +460,7 @@ def _on_pattern(A: sp.csr_matrix, pat: sp.csr_matrix) -> np.ndarray:
     """Values of A laid out on the CSR pattern ``pat`` (zeros where A has none)."""
     A = A.tocsr()
     A.sort_indices()
-    out = np.zeros(pat.indices.shape[0])
+    out = np.zeros(pat.indices.shape[0], dtype=A.dtype)
     # both sorted per row: merge by row-wise search
     n = pat.shape[0]
     prow = np.repeat(np.arange(n), np.diff(pat.indptr))
@@ -478,6 +509,9 @@ WORKLOADS = {
     # the 250- and 16k-dof cells with a nonlocal term H_nl = F G F^T of four projectors per atom
     "c1nl": dict(L=6.0, ne=6, natoms=1, nev=4, projectors=4),
     "c2nl": dict(L=12.0, ne=24, natoms=8, nev=32, projectors=4),
+    # the paper's second k-point, k_f = (0.12, -0.24, 0.37): complex Hermitian pencils
+    "c1k": dict(L=6.0, ne=6, natoms=1, nev=4, kpoint=(0.12, -0.24, 0.37)),
+    "c2k": dict(L=12.0, ne=24, natoms=8, nev=32, kpoint=(0.12, -0.24, 0.37)),
 }
 
 
@@ -492,6 +526,8 @@ def workload(name: str, seed: int = 0, **kw) -> Problem:
     w = WORKLOADS[name]
     if "alpha" in w:
         kw.setdefault("alpha", w["alpha"])
+    if "kpoint" in w:
+        kw.setdefault("kpoint", w["kpoint"])
     P = generate(w["L"], w["ne"], w["natoms"], seed, **kw)
     if w.get("projectors"):
         P.F, P.G = nonlocal_projectors(P, w["projectors"])
@@ -504,18 +540,22 @@ def start_block(n: int, b: int, seed: int) -> np.ndarray:
     return np.asfortranarray(rng.standard_normal((n, b)))
 
 
-def free_particle_eigs(ne: int, L: float, count: int) -> np.ndarray:
+def free_particle_eigs(ne: int, L: float, count: int, kpoint=None) -> np.ndarray:
     """Exact spectrum of the assembled trilinear pencil with V = 0 and no enrichment.
 
     Separable: per dimension the 1-D linear-element pencil on a periodic ring has
-    K_1 = (2 - 2cos t)/h and M_1 = h (4 + 2cos t)/6 at wavenumber t = 2 pi j / ne;
+    K_1 = (2 - 2cos t)/h and M_1 = h (4 + 2cos t)/6 at wavenumber t = 2 pi j / ne
+    (t = 2 pi (j + k_d) / ne for the Bloch-periodic pencil of reduced k-point k);
     the 3-D stiffness is sum_d K_d prod_{e!=d} M_e and the mass prod_d M_d,
     so lambda = 1/2 sum_d K_d / M_d.
     """
     h = L / ne
-    t = 2.0 * np.pi * np.arange(ne) / ne
-    k1 = (2.0 - 2.0 * np.cos(t)) / h
-    m1 = h * (4.0 + 2.0 * np.cos(t)) / 6.0
-    r = k1 / m1
-    lam = 0.5 * (r[:, None, None] + r[None, :, None] + r[None, None, :])
+    kf = np.zeros(3) if kpoint is None else np.asarray(kpoint, dtype=np.float64)
+    rs = []
+    for d in range(3):
+        t = 2.0 * np.pi * (np.arange(ne) + kf[d]) / ne
+        k1 = (2.0 - 2.0 * np.cos(t)) / h
+        m1 = h * (4.0 + 2.0 * np.cos(t)) / 6.0
+        rs.append(k1 / m1)
+    lam = 0.5 * (rs[0][:, None, None] + rs[1][None, :, None] + rs[2][None, None, :])
     return np.sort(lam.ravel())[:count]

@@ -130,3 +130,43 @@ def test_nonlocal_term_raises_the_spectrum():
     l1 = sla.eigh(H.toarray(), P.S().toarray(), eigvals_only=True)
     assert np.all(l1 >= l0 - 1e-12 * np.abs(l0).max())
     assert P.eps_bar < l0[0] <= l1[0]
+
+
+# ------------------------------------------------------------------ k-points (Bloch-periodic pencils)
+
+KF = (0.12, -0.24, 0.37)
+
+
+def test_kpoint_pencil_is_hermitian_and_reduces_to_gamma():
+    """At a k-point H and S are complex Hermitian with S positive definite; at k = 0 (and at
+    any integer k, a reciprocal lattice vector) the phases are one and the pencil is the
+    real one; k and -k give complex-conjugate pencils (time reversal)."""
+    G = pufe.generate(6.0, 6, 1, 0)
+    P = pufe.generate(6.0, 6, 1, 0, kpoint=KF)
+    assert np.iscomplexobj(P.h_val) and np.abs(P.h_val.imag).max() > 1e-3
+    H, S = P.H().toarray(), P.S().toarray()
+    assert np.abs(H - H.conj().T).max() == 0.0 and np.abs(S - S.conj().T).max() == 0.0
+    assert np.linalg.eigvalsh(S).min() > 0
+    for k in ((0.0, 0.0, 0.0), (1.0, -1.0, 2.0)):
+        Q = pufe.generate(6.0, 6, 1, 0, kpoint=k)
+        assert np.array_equal(Q.col, G.col)
+        assert np.abs(Q.h_val - G.h_val).max() < 1e-14 and np.abs(Q.s_val - G.s_val).max() < 1e-14
+    M = pufe.generate(6.0, 6, 1, 0, kpoint=tuple(-x for x in KF))
+    assert np.abs(M.h_val - np.conj(P.h_val)).max() < 1e-15
+
+
+def test_kpoint_free_particle_closed_form():
+    """V = 0, no enrichment, Bloch-periodic at k: the spectrum is separable with wave
+    numbers 2 pi (j + k_d) / ne per dimension; dense LAPACK and the oracle's LABPSD (complex
+    Hermitian arithmetic) reproduce it, which pins the phase convention of the assembly."""
+    from oracle import eigs, labpsd
+    P = pufe.generate(4.0, 8, 0, 0, kpoint=KF)
+    ref = pufe.free_particle_eigs(8, 4.0, 7, kpoint=KF)
+    lam, _ = eigs.dense_eigs(P.H(), P.S(), 7)
+    assert np.abs(lam - ref).max() < 1e-12
+    prm = labpsd.Params(nev=7, m0=4, tol=1e-11, sigma0=-1.0, eps_bar=-0.1)
+    res = labpsd.solve(P.H(), P.S(), prm, pufe.start_block(P.n, 11, 0) + 1j * pufe.start_block(P.n, 11, 1))
+    assert res.converged
+    assert np.max(np.abs(res.lam - ref) / np.abs(ref + 1.0)) < 1e-11
+    S = P.S()
+    assert np.abs(res.X.conj().T @ (S @ res.X) - np.eye(7)).max() < 1e-10
