@@ -219,6 +219,41 @@ labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* params,
                            double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where,
                            labpsd_stats* stats);
 
+/* ------------------------------------------------------------------ k-points
+ * Away from the Gamma point (Section 2's k-point sampling) H and S are complex Hermitian
+ * (the paper solves the reduced problem with ZHEGVX).  The library stores such a pencil
+ * as its real symmetric embedding: a complex vector x = a + i b is the interleaved real
+ * vector (a_0, b_0, a_1, b_1, ...) (the same memory as a column-major complex128 array),
+ * entry h of H becomes the 2 x 2 block [Re h, -Im h; Im h, Re h], and every eigenvalue of
+ * (H, S) is an eigenvalue of the embedded pencil twice.  Every step of the solve is the
+ * real one on the embedded pencil (2n dofs, 2 nev pairs, 2 m0 guards).                */
+
+/* Upload a complex Hermitian pencil: host rowptr int64[n+1], col int32[nnz] as for
+ * labpsd_problem_create, and the real and imaginary parts of H and S on that pattern
+ * (float64[nnz] each).  EINVAL as labpsd_problem_create, or if H or S is not Hermitian
+ * to rounding.  labpsd_set_global_precond then takes coordinates of the n complex dofs
+ * and factorises the embedding of H - eps_bar S (Hermitian positive definite below
+ * lambda_1).  labpsd_solve refuses such a problem; the nonlocal term is not supported. */
+labpsd_status labpsd_problem_create_hermitian(labpsd_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
+                                              const int32_t* col, const double* h_re, const double* h_im,
+                                              const double* s_re, const double* s_im, labpsd_problem** out);
+/* New H values (real and imaginary parts, host float64[nnz]) on the same pattern.    */
+labpsd_status labpsd_problem_update_h_hermitian(labpsd_problem* p, const double* h_re, const double* h_im);
+/* LABPSD for the nev lowest pairs of a Hermitian problem.  X0: complex n x (nev+m0)
+ * (interleaved, as a column-major complex128 array; host or device per in_where) or
+ * NULL (seeded real start block of the embedding); E0 as labpsd_solve.  Outputs:
+ * lambda[nev] ascending; X complex n x nev (interleaved), S-orthonormal (X^H S X = I);
+ * res_hist, ritz_hist, n_hist and stats are those of the embedded real solve (2 nev
+ * residuals and 2 (nev+m0) Ritz values per iteration).  After the solve, the 2 nev real
+ * eigenvectors read as complex vectors span the wanted complex subspace twice over; a
+ * Rayleigh-Ritz step on their span (rank-revealing: the nev dominant directions of
+ * Z^H S Z) returns it once, its small Hermitian eigenproblems on the host.  ERANK if the
+ * span has fewer than nev complex directions.                                         */
+labpsd_status labpsd_solve_hermitian(labpsd_problem* p, const labpsd_solve_params* params, const double* X0,
+                                     const double* E0, labpsd_mem in_where, double* lambda, double* X,
+                                     double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where,
+                                     labpsd_stats* stats);
+
 /* ------------------------------------------------------------------ hot-path steps
  * The steps of one LABPSD iteration, each callable on its own for testing and
  * measurement.  All pointers are device pointers; work is enqueued on the

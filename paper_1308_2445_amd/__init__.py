@@ -94,6 +94,10 @@ _SIGS = {
     "labpsd_problem_create": ([_p, _i64, _i64, _p, _p, _p, _p, _i32, ctypes.POINTER(_p)], _i32),
     "labpsd_problem_update_h": ([_p, _p, _i32], _i32),
     "labpsd_problem_set_nonlocal": ([_p, _i32, _p, _p, _p, _p], _i32),
+    "labpsd_problem_create_hermitian": ([_p, _i64, _i64, _p, _p, _p, _p, _p, _p, ctypes.POINTER(_p)], _i32),
+    "labpsd_problem_update_h_hermitian": ([_p, _p, _p], _i32),
+    "labpsd_solve_hermitian": ([_p, ctypes.POINTER(SolveParams), _p, _p, _i32, _p, _p, _p, _p,
+                                ctypes.POINTER(ctypes.c_int), _i32, ctypes.POINTER(Stats)], _i32),
     "labpsd_problem_destroy": ([_p], None),
     "labpsd_problem_n": ([_p], _i64),
     "labpsd_set_global_precond": ([_p, _d, _p, ctypes.c_uint], _i32),
@@ -232,7 +236,10 @@ class Problem:
 
     @classmethod
     def from_pencil(cls, ctx: Context, P) -> "Problem":
-        """The pencil of a pufe cell, with its nonlocal term when it has one (P.F, P.G)."""
+        """The pencil of a pufe cell, with its nonlocal term when it has one (P.F, P.G); a
+        complex (k-point) cell gives a HermitianProblem."""
+        if np.iscomplexobj(P.h_val) or np.iscomplexobj(P.s_val):
+            return HermitianProblem(ctx, P.n, P.rowptr, P.col, P.h_val, P.s_val)
         pr = cls(ctx, P.n, P.rowptr, P.col, P.h_val, P.s_val)
         if getattr(P, "F", None) is not None:
             pr.set_nonlocal(P.F, P.G)
@@ -341,6 +348,60 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+class HermitianProblem(Problem):
+    """A complex Hermitian pencil (a k-point), solved through its real embedding."""
+
+    def __init__(self, ctx: Context, n, rowptr, col, h_val, s_val):
+        self.ctx = ctx
+        self.n = int(n)
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        h_val = np.asarray(h_val, dtype=np.complex128)
+        s_val = np.asarray(s_val, dtype=np.complex128)
+        hr, hi = np.ascontiguousarray(h_val.real), np.ascontiguousarray(h_val.imag)
+        sr, si = np.ascontiguousarray(s_val.real), np.ascontiguousarray(s_val.imag)
+        self.nnz = int(col.shape[0])
+        h = _p()
+        ctx.sync_stream()
+        _check(_lib.labpsd_problem_create_hermitian(ctx.h, self.n, self.nnz, _ptr(rowptr), _ptr(col), _ptr(hr),
+                                                    _ptr(hi), _ptr(sr), _ptr(si), ctypes.byref(h)),
+               "labpsd_problem_create_hermitian")
+        self.h = h
+
+    def update_h(self, h_val):
+        h_val = np.asarray(h_val, dtype=np.complex128)
+        hr, hi = np.ascontiguousarray(h_val.real), np.ascontiguousarray(h_val.imag)
+        self.ctx.sync_stream()
+        _check(_lib.labpsd_problem_update_h_hermitian(self.h, _ptr(hr), _ptr(hi)), "labpsd_problem_update_h_hermitian")
+
+    def solve(self, nev: int, m0: int, X0, *, tol=1e-8, max_outer=200, sigma0=0.0, precision=FP64,
+              refresh_every=10, timing=False, E0=None, reorth_tol=0.0, seed=0, device_out=False):
+        """X0: complex n x (nev + m0) numpy array or None.  Returns complex X (n x nev); the
+        histories are those of the embedded real solve (2 nev residuals per iteration)."""
+        b = nev + m0
+        n = self.n
+        self.ctx.sync_stream()
+        x0 = None
+        if X0 is not None:
+            x0 = np.asfortranarray(np.asarray(X0, dtype=np.complex128))
+            assert x0.shape == (n, b)
+        E0a = None if E0 is None else np.ascontiguousarray(E0, dtype=np.float64)
+        prm = SolveParams(nev, m0, tol, max_outer, sigma0, precision, refresh_every, 1 if timing else 0,
+                          reorth_tol, seed)
+        hist = np.zeros(2 * (max_outer + 1) * nev)
+        rhist = np.zeros(2 * (max_outer + 1) * b)
+        nh = ctypes.c_int(0)
+        st = Stats()
+        lam = np.zeros(nev)
+        X = np.zeros((n, nev), dtype=np.complex128, order="F")
+        rc = _lib.labpsd_solve_hermitian(self.h, ctypes.byref(prm), _ptr(x0), _ptr(E0a), MEM_HOST, _ptr(lam),
+                                         _ptr(X), _ptr(hist), _ptr(rhist), ctypes.byref(nh), MEM_HOST,
+                                         ctypes.byref(st))
+        _check(rc, "labpsd_solve_hermitian", allow=(OK, NOT_CONVERGED))
+        return SolveResult(status=rc, lam=lam, X=X, res_hist=hist[: nh.value * 2 * nev].reshape(nh.value, 2 * nev),
+                           stats=st.as_dict(), ritz_hist=rhist[: nh.value * 2 * b].reshape(nh.value, 2 * b))
 
 
 # ------------------------------------------------------------------ hot-path steps

@@ -18,7 +18,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["spmm.hip", "dense.hip", "rr.hip", "precond.hip", "minres.hip", "api.hip", "serve.hip", "noalloc.hip", "nonlocal.hip"]
-CPP_SOURCES = ["factor.cpp"]
+CPP_SOURCES = ["factor.cpp", "hermitian.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -12,6 +12,7 @@
 #include <memory>
 
 #include "common.h"
+#include "hermitian.h"
 
 namespace labpsd {
 
@@ -780,6 +781,42 @@ labpsd_status labpsd_ctx_set_stream(labpsd_ctx* ctx, void* stream) {
     });
 }
 
+// Validate a host CSR pencil and build the problem (shared by the real and the Hermitian
+// entry points).
+static std::unique_ptr<labpsd_problem> make_problem(labpsd_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
+                                                    const int32_t* col, const double* h_val, const double* s_val) {
+    LABPSD_REQUIRE(rowptr[0] == 0 && rowptr[n] == nnz, "rowptr does not span [0, nnz]");
+    for (int64_t i = 0; i < n; ++i) {
+        LABPSD_REQUIRE(rowptr[i + 1] > rowptr[i], "empty row " + std::to_string(i));
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            LABPSD_REQUIRE(col[e] >= 0 && col[e] < n, "column index out of range in row " + std::to_string(i));
+            if (e > rowptr[i])
+                LABPSD_REQUIRE(col[e] > col[e - 1], "columns not strictly increasing in row " + std::to_string(i));
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            const int32_t* b0 = col + rowptr[j];
+            const int32_t* b1 = col + rowptr[j + 1];
+            LABPSD_REQUIRE(std::binary_search(b0, b1, (int32_t)i),
+                           "pattern not structurally symmetric at (" + std::to_string(i) + "," +
+                               std::to_string(j) + ")");
+        }
+    auto p = std::make_unique<labpsd_problem>();
+    p->ctx = ctx;
+    p->n = n;
+    p->nnz = nnz;
+    p->csr.n = n;
+    p->csr.nnz = nnz;
+    p->csr.rowptr.assign(rowptr, rowptr + n + 1);
+    p->csr.col.assign(col, col + nnz);
+    p->h_val.assign(h_val, h_val + nnz);
+    p->s_val.assign(s_val, s_val + nnz);
+    build_sell(p->sell, p->csr, h_val, s_val, ctx->stream);
+    return p;
+}
+
 labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr_in,
                                     const int32_t* col_in, const double* h_in, const double* s_in,
                                     labpsd_mem where, labpsd_problem** out) {
@@ -791,40 +828,50 @@ labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz, con
         LABPSD_HIP(hipSetDevice(ctx->device));
         std::vector<int64_t> rp_keep;
         const int64_t* rowptr = host_view(ctx, rowptr_in, (size_t)n + 1, where, rp_keep);
-        LABPSD_REQUIRE(rowptr[0] == 0 && rowptr[n] == nnz, "rowptr does not span [0, nnz]");
+        LABPSD_REQUIRE(rowptr[n] == nnz, "rowptr does not span [0, nnz]");
         std::vector<int32_t> col_keep;
         std::vector<double> h_keep, s_keep;
         const int32_t* col = host_view(ctx, col_in, (size_t)nnz, where, col_keep);
         const double* h_val = host_view(ctx, h_in, (size_t)nnz, where, h_keep);
         const double* s_val = host_view(ctx, s_in, (size_t)nnz, where, s_keep);
-        for (int64_t i = 0; i < n; ++i) {
-            LABPSD_REQUIRE(rowptr[i + 1] > rowptr[i], "empty row " + std::to_string(i));
-            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-                LABPSD_REQUIRE(col[e] >= 0 && col[e] < n, "column index out of range in row " + std::to_string(i));
-                if (e > rowptr[i])
-                    LABPSD_REQUIRE(col[e] > col[e - 1], "columns not strictly increasing in row " + std::to_string(i));
-            }
-        }
+        *out = make_problem(ctx, n, nnz, rowptr, col, h_val, s_val).release();
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_problem_create_hermitian(labpsd_ctx* ctx, int64_t n, int64_t nnz, const int64_t* rowptr,
+                                              const int32_t* col, const double* h_re, const double* h_im,
+                                              const double* s_re, const double* s_im, labpsd_problem** out) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(ctx && out && rowptr && col && h_re && h_im && s_re && s_im, "NULL argument");
+        *out = nullptr;
+        LABPSD_REQUIRE(n >= 1 && 2 * n < (int64_t)INT32_MAX, "n out of range");
+        LABPSD_REQUIRE(nnz >= n && rowptr[0] == 0 && rowptr[n] == nnz, "rowptr does not span [0, nnz]");
+        // Hermitian values: the (j, i) entry is the conjugate of (i, j)
         for (int64_t i = 0; i < n; ++i)
             for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
                 const int32_t j = col[e];
+                LABPSD_REQUIRE(j >= 0 && j < n, "column index out of range in row " + std::to_string(i));
                 const int32_t* b0 = col + rowptr[j];
                 const int32_t* b1 = col + rowptr[j + 1];
-                LABPSD_REQUIRE(std::binary_search(b0, b1, (int32_t)i),
-                               "pattern not structurally symmetric at (" + std::to_string(i) + "," +
-                                   std::to_string(j) + ")");
+                const int32_t* f = std::lower_bound(b0, b1, (int32_t)i);
+                LABPSD_REQUIRE(f != b1 && *f == (int32_t)i, "pattern not structurally symmetric");
+                const int64_t t = rowptr[j] + (f - b0);
+                const double tol = 1e-13 * (std::fabs(h_re[e]) + std::fabs(h_im[e]) + std::fabs(s_re[e]) +
+                                            std::fabs(s_im[e])) + 1e-300;
+                LABPSD_REQUIRE(std::fabs(h_re[t] - h_re[e]) <= tol && std::fabs(h_im[t] + h_im[e]) <= tol &&
+                                   std::fabs(s_re[t] - s_re[e]) <= tol && std::fabs(s_im[t] + s_im[e]) <= tol,
+                               "H or S is not Hermitian at (" + std::to_string(i) + "," + std::to_string(j) + ")");
             }
-        auto p = std::make_unique<labpsd_problem>();
-        p->ctx = ctx;
-        p->n = n;
-        p->nnz = nnz;
-        p->csr.n = n;
-        p->csr.nnz = nnz;
-        p->csr.rowptr.assign(rowptr, rowptr + n + 1);
-        p->csr.col.assign(col, col + nnz);
-        p->h_val.assign(h_val, h_val + nnz);
-        p->s_val.assign(s_val, s_val + nnz);
-        build_sell(p->sell, p->csr, h_val, s_val, ctx->stream);
+        LABPSD_HIP(hipSetDevice(ctx->device));
+        std::vector<int64_t> rp2;
+        std::vector<int32_t> col2;
+        std::vector<double> h2, s2;
+        embed_hermitian(n, nnz, rowptr, col, h_re, h_im, rp2, col2, h2);
+        embed_hermitian(n, nnz, rowptr, col, s_re, s_im, rp2, col2, s2);
+        auto p = make_problem(ctx, 2 * n, 4 * nnz, rp2.data(), col2.data(), h2.data(), s2.data());
+        p->hermitian = true;
+        p->nc = n;
         *out = p.release();
         return LABPSD_OK;
     });
@@ -833,11 +880,36 @@ labpsd_status labpsd_problem_create(labpsd_ctx* ctx, int64_t n, int64_t nnz, con
 labpsd_status labpsd_problem_update_h(labpsd_problem* p, const double* h_in, labpsd_mem where) {
     return guarded([&]() -> labpsd_status {
         LABPSD_REQUIRE(p && h_in, "NULL argument");
+        LABPSD_REQUIRE(!p->hermitian, "Hermitian problem: use labpsd_problem_update_h_hermitian");
         LABPSD_HIP(hipSetDevice(p->ctx->device));
         std::vector<double> keep;
         const double* h_val = host_view(p->ctx, h_in, (size_t)p->nnz, where, keep);
         p->h_val.assign(h_val, h_val + p->nnz);
         refresh_sell_h(p->sell, h_val, p->ctx->stream);
+        return LABPSD_OK;
+    });
+}
+
+labpsd_status labpsd_problem_update_h_hermitian(labpsd_problem* p, const double* h_re, const double* h_im) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && h_re && h_im, "NULL argument");
+        LABPSD_REQUIRE(p->hermitian, "not a Hermitian problem");
+        const int64_t nc = p->nc, nnz = p->nnz / 4;
+        // the complex pattern is every other entry of the even rows of the embedding
+        std::vector<int64_t> rp(nc + 1);
+        std::vector<int32_t> col(nnz);
+        for (int64_t i = 0; i < nc; ++i) {
+            rp[i + 1] = rp[i] + (p->csr.rowptr[2 * i + 1] - p->csr.rowptr[2 * i]) / 2;
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+                col[e] = p->csr.col[p->csr.rowptr[2 * i] + 2 * (e - rp[i])] / 2;
+        }
+        std::vector<int64_t> rp2;
+        std::vector<int32_t> col2;
+        std::vector<double> h2;
+        embed_hermitian(nc, nnz, rp.data(), col.data(), h_re, h_im, rp2, col2, h2);
+        LABPSD_HIP(hipSetDevice(p->ctx->device));
+        p->h_val = h2;
+        refresh_sell_h(p->sell, h2.data(), p->ctx->stream);
         return LABPSD_OK;
     });
 }
@@ -861,6 +933,13 @@ labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const
         for (int64_t e = 0; e < p->nnz; ++e) kval[e] = p->h_val[e] - eps_bar * p->s_val[e];
         HostFactor F;
         std::string msg;
+        std::vector<double> c2;
+        if (p->hermitian && coords) {   // both real dofs of a complex one sit at its point
+            c2.resize(6 * (size_t)p->nc);
+            for (int64_t i = 0; i < p->nc; ++i)
+                for (int d = 0; d < 3; ++d) c2[6 * i + d] = c2[6 * i + 3 + d] = coords[3 * i + d];
+            coords = c2.data();
+        }
         const int rc = factorize(p->csr, kval.data(), coords, F, msg, single);
         if (rc == -4) throw Error{LABPSD_ENOTSPD, msg};
         if (rc != 0) throw Error{LABPSD_EINVAL, msg};
@@ -913,6 +992,7 @@ labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* prm, co
                            double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats) {
     return guarded([&]() -> labpsd_status {
         LABPSD_REQUIRE(p && prm && lambda && X, "NULL argument");
+        LABPSD_REQUIRE(!p->hermitian, "Hermitian problem: use labpsd_solve_hermitian");
         if (!p->factor) throw Error{LABPSD_ESTATE, "labpsd_set_global_precond must come first"};
         require_panels(*p, prm->precision);
         LABPSD_REQUIRE(prm->nev >= 1 && prm->m0 >= 0, "nev must be >= 1 and m0 >= 0");
@@ -925,6 +1005,182 @@ labpsd_status labpsd_solve(labpsd_problem* p, const labpsd_solve_params* prm, co
         LABPSD_HIP(hipSetDevice(p->ctx->device));
         return run_solve(*p, *prm, X0, E0, in_where, lambda, X, res_hist, ritz_hist, n_hist, out_where, stats,
                          p->ctx->stream);
+    });
+}
+
+// The complex Hermitian pencil through its real embedding: LABPSD on (R(H), R(S)) with
+// 2 nev pairs and 2 m0 guards (every complex pair appears twice), then the complex pairs:
+// Z = the 2 nev real eigenvectors read as complex vectors spans the nev-dimensional
+// complex invariant subspace twice over; a Rayleigh-Ritz step on span(Z) with the
+// rank-revealing cut keeps it once.  The O(n) parts run on the device: the products HZ,
+// SZ, the Gram matrices Re(Z^H Y) = U^T R(Y) and Im(Z^H Y) = U^T J^T R(Y) (U = R(Z), J the
+// real form of i; the imaginary parts are antisymmetric, so their upper triangles
+// suffice), and X = Z C = [U, J U] [Re C; Im C] on the block-update kernel.  The
+// 2 nev x 2 nev Hermitian eigenproblems run on the host (cyclic Jacobi), as the paper
+// solves its reduced problem with ZHEGVX.
+labpsd_status labpsd_solve_hermitian(labpsd_problem* p, const labpsd_solve_params* prm, const double* X0,
+                                     const double* E0, labpsd_mem in_where, double* lambda, double* X,
+                                     double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where,
+                                     labpsd_stats* stats) {
+    return guarded([&]() -> labpsd_status {
+        LABPSD_REQUIRE(p && prm && lambda && X, "NULL argument");
+        LABPSD_REQUIRE(p->hermitian, "not a Hermitian problem (labpsd_problem_create_hermitian)");
+        if (!p->factor) throw Error{LABPSD_ESTATE, "labpsd_set_global_precond must come first"};
+        require_panels(*p, prm->precision);
+        const int nev = prm->nev, m0 = prm->m0, b = nev + m0;
+        LABPSD_REQUIRE(nev >= 1 && m0 >= 0, "nev must be >= 1 and m0 >= 0");
+        LABPSD_REQUIRE((int64_t)(2 * nev + m0) <= p->nc, "n < 2 nev + m0");
+        LABPSD_REQUIRE(4 * nev + 2 * m0 <= kRRMax, "block too wide");
+        LABPSD_REQUIRE(prm->tol > 0 && prm->max_outer >= 1 && prm->refresh_every >= 1,
+                       "tol, max_outer and refresh_every must be positive");
+        LABPSD_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t s = p->ctx->stream;
+        const int64_t nc = p->nc, n2 = 2 * nc;
+        const int kk = 2 * nev, br = 2 * b;
+        labpsd_solve_params pr = *prm;
+        pr.nev = kk;
+        pr.m0 = 2 * m0;
+        // start block: R(x_j) and R(i x_j) for the b complex columns of X0
+        DBuf<double> start, lam_r, U, HU, SU, JH, JS, GH, GS, GHi, GSi, Zc, Wd, o1, o2;
+        const double* X0r = nullptr;
+        if (X0) {
+            start.alloc((size_t)n2 * br);
+            LABPSD_HIP(hipMemcpyAsync(start.p, X0, (size_t)n2 * b * sizeof(double),
+                                      in_where == LABPSD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+            launch_apply_j(nc, b, start.p, n2, start.p + (size_t)n2 * b, n2, false, s);
+            X0r = start.p;
+        }
+        std::vector<double> E0r;
+        if (E0) {
+            E0r.resize(br);
+            for (int j = 0; j < b; ++j) E0r[2 * j] = E0r[2 * j + 1] = E0[j];
+        }
+        lam_r.alloc(kk);
+        U.alloc((size_t)n2 * kk);
+        const labpsd_status rc = run_solve(*p, pr, X0r, E0 ? E0r.data() : nullptr, LABPSD_MEM_DEVICE, lam_r.p, U.p,
+                                           res_hist, ritz_hist, n_hist, LABPSD_MEM_HOST, stats, s);
+        // products and the complex Gram matrices of span(Z)
+        HU.alloc((size_t)n2 * kk);
+        SU.alloc((size_t)n2 * kk);
+        JH.alloc((size_t)n2 * kk);
+        JS.alloc((size_t)n2 * kk);
+        launch_spmm_hs(p->sell, U.p, n2, kk, HU.p, SU.p, n2, s);
+        launch_apply_j(nc, kk, HU.p, n2, JH.p, n2, true, s);
+        launch_apply_j(nc, kk, SU.p, n2, JS.p, n2, true, s);
+        GH.alloc((size_t)kk * kk);
+        GS.alloc((size_t)kk * kk);
+        GHi.alloc((size_t)kk * kk);
+        GSi.alloc((size_t)kk * kk);
+        p->ctx->scratch.alloc(gram_ws_doubles(n2, kk, p->ctx->cu_count) + 1);
+        launch_gram(n2, kk, U.p, HU.p, SU.p, n2, GH.p, GS.p, kk, p->ctx->scratch.p, p->ctx->cu_count, s);
+        LABPSD_HIP(hipStreamSynchronize(s));
+        launch_gram(n2, kk, U.p, JH.p, JS.p, n2, GHi.p, GSi.p, kk, p->ctx->scratch.p, p->ctx->cu_count, s);
+        std::vector<double> hr((size_t)kk * kk), sr(hr.size()), hi(hr.size()), si(hr.size());
+        LABPSD_HIP(hipMemcpyAsync(hr.data(), GH.p, hr.size() * 8, hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipMemcpyAsync(sr.data(), GS.p, sr.size() * 8, hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipMemcpyAsync(hi.data(), GHi.p, hi.size() * 8, hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipMemcpyAsync(si.data(), GSi.p, si.size() * 8, hipMemcpyDeviceToHost, s));
+        LABPSD_HIP(hipStreamSynchronize(s));
+        // the Gram kernel mirrors its upper triangle; the imaginary parts are antisymmetric
+        for (int j = 0; j < kk; ++j)
+            for (int i = 0; i <= j; ++i) {
+                const size_t u = (size_t)i + (size_t)j * kk, l = (size_t)j + (size_t)i * kk;
+                hi[l] = -hi[u];
+                si[l] = -si[u];
+                if (i == j) hi[u] = si[u] = 0.0;
+            }
+        // S-orthonormal basis of the complex span: the nev dominant eigenvectors of Z^H S Z
+        std::vector<double> Vr, Vi;
+        hermitian_jacobi(kk, sr, si, Vr, Vi);
+        std::vector<int> ord(kk);
+        for (int i = 0; i < kk; ++i) ord[i] = i;
+        std::sort(ord.begin(), ord.end(), [&](int a, int c) { return sr[(size_t)a * kk + a] > sr[(size_t)c * kk + c]; });
+        const double mu_min = sr[(size_t)ord[nev - 1] * kk + ord[nev - 1]];
+        if (!(mu_min > 1e-8 * sr[(size_t)ord[0] * kk + ord[0]]))
+            throw Error{LABPSD_ERANK, "the real eigenvectors span fewer than nev complex directions"};
+        std::vector<double> Tr((size_t)kk * nev), Ti(Tr.size());
+        for (int c = 0; c < nev; ++c) {
+            const int q = ord[c];
+            const double sc = 1.0 / std::sqrt(sr[(size_t)q * kk + q]);
+            for (int i = 0; i < kk; ++i) {
+                Tr[i + (size_t)c * kk] = Vr[i + (size_t)q * kk] * sc;
+                Ti[i + (size_t)c * kk] = Vi[i + (size_t)q * kk] * sc;
+            }
+        }
+        // reduced Hermitian matrix T^H (Z^H H Z) T and its eigenpairs
+        std::vector<double> Mr((size_t)kk * nev), Mi(Mr.size()), Ar((size_t)nev * nev), Ai(Ar.size());
+        for (int c = 0; c < nev; ++c)
+            for (int i = 0; i < kk; ++i) {
+                double a = 0.0, bb = 0.0;
+                for (int k2 = 0; k2 < kk; ++k2) {
+                    const double gr = hr[i + (size_t)k2 * kk], gi = hi[i + (size_t)k2 * kk];
+                    const double tr = Tr[k2 + (size_t)c * kk], ti = Ti[k2 + (size_t)c * kk];
+                    a += gr * tr - gi * ti;
+                    bb += gr * ti + gi * tr;
+                }
+                Mr[i + (size_t)c * kk] = a;
+                Mi[i + (size_t)c * kk] = bb;
+            }
+        for (int c = 0; c < nev; ++c)
+            for (int r = 0; r < nev; ++r) {
+                double a = 0.0, bb = 0.0;
+                for (int i = 0; i < kk; ++i) {   // conj(T[i, r]) * M[i, c]
+                    const double tr = Tr[i + (size_t)r * kk], ti = Ti[i + (size_t)r * kk];
+                    const double mr = Mr[i + (size_t)c * kk], mi = Mi[i + (size_t)c * kk];
+                    a += tr * mr + ti * mi;
+                    bb += tr * mi - ti * mr;
+                }
+                Ar[r + (size_t)c * nev] = a;
+                Ai[r + (size_t)c * nev] = bb;
+            }
+        for (int c = 0; c < nev; ++c)
+            for (int r = 0; r < c; ++r) {   // exact Hermitian symmetry
+                const size_t u = r + (size_t)c * nev, l = c + (size_t)r * nev;
+                const double ar = 0.5 * (Ar[u] + Ar[l]), ai = 0.5 * (Ai[u] - Ai[l]);
+                Ar[u] = Ar[l] = ar;
+                Ai[u] = ai;
+                Ai[l] = -ai;
+            }
+        std::vector<double> Wr, Wi;
+        hermitian_jacobi(nev, Ar, Ai, Wr, Wi);
+        std::vector<int> o2i(nev);
+        for (int i = 0; i < nev; ++i) o2i[i] = i;
+        std::sort(o2i.begin(), o2i.end(), [&](int a, int c) { return Ar[(size_t)a * nev + a] < Ar[(size_t)c * nev + c]; });
+        std::vector<double> lam_h(nev), W2((size_t)2 * kk * nev);
+        for (int c = 0; c < nev; ++c) {
+            const int q = o2i[c];
+            lam_h[c] = Ar[(size_t)q * nev + q];
+            // C[:, c] = T W[:, q]; W2 = [Re C ; Im C] (2 kk x nev)
+            for (int i = 0; i < kk; ++i) {
+                double a = 0.0, bb = 0.0;
+                for (int r = 0; r < nev; ++r) {
+                    const double tr = Tr[i + (size_t)r * kk], ti = Ti[i + (size_t)r * kk];
+                    const double wr = Wr[r + (size_t)q * nev], wi = Wi[r + (size_t)q * nev];
+                    a += tr * wr - ti * wi;
+                    bb += tr * wi + ti * wr;
+                }
+                W2[i + (size_t)c * 2 * kk] = a;
+                W2[kk + i + (size_t)c * 2 * kk] = bb;
+            }
+        }
+        // X = [U, J U] [Re C ; Im C]
+        Zc.alloc((size_t)n2 * 2 * kk);
+        Wd.alloc(W2.size());
+        o1.alloc((size_t)n2 * nev);
+        o2.alloc((size_t)n2 * nev);
+        LABPSD_HIP(hipMemcpyAsync(Zc.p, U.p, (size_t)n2 * kk * 8, hipMemcpyDeviceToDevice, s));
+        launch_apply_j(nc, kk, U.p, n2, Zc.p + (size_t)n2 * kk, n2, false, s);
+        LABPSD_HIP(hipMemcpyAsync(Wd.p, W2.data(), W2.size() * 8, hipMemcpyHostToDevice, s));
+        double* Xd = out_where == LABPSD_MEM_DEVICE ? X : o1.p;
+        launch_block_update(n2, 2 * kk, nev, Zc.p, Zc.p, Zc.p, n2, Wd.p, 2 * kk, Xd, o2.p, o2.p, n2, s);
+        if (out_where == LABPSD_MEM_DEVICE) {
+            LABPSD_HIP(hipMemcpyAsync(lambda, lam_h.data(), nev * 8, hipMemcpyHostToDevice, s));
+        } else {
+            LABPSD_HIP(hipMemcpyAsync(X, o1.p, (size_t)n2 * nev * 8, hipMemcpyDeviceToHost, s));
+            std::memcpy(lambda, lam_h.data(), nev * 8);
+        }
+        LABPSD_HIP(hipStreamSynchronize(s));
+        return rc;
     });
 }
 

@@ -418,6 +418,9 @@ struct Problem {
     Sell sell;
     DevFactor* factor = nullptr;
     NonLocal nl;
+    // a complex Hermitian pencil stored as its real embedding (interleaved, n = 2 nc)
+    bool hermitian = false;
+    int64_t nc = 0;
     LocalParams local;
     // solver workspace (kept between solves)
     DBuf<double> ws64;
@@ -471,6 +474,11 @@ void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* 
 template <typename T>
 void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
                        int64_t ldy, hipStream_t s, const NonLocal* nl = nullptr);
+
+// Interleaved complex columns (nc complex entries each): dst = J src, or J^T src, with J the
+// real form of multiplication by i
+void launch_apply_j(int64_t nc, int ncols, const double* src, int64_t lds, double* dst, int64_t ldd, bool transpose,
+                    hipStream_t s);
 
 // X (n x b, ld ldx) := i.i.d. standard normals, entry (i, j) from counter i + n j of `seed`
 void launch_random_block(int64_t n, int b, uint64_t seed, double* X, int64_t ldx, hipStream_t s);

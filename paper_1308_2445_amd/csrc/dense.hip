@@ -104,6 +104,23 @@ __global__ __launch_bounds__(256) void k_random_block(int64_t n, int64_t total, 
     }
 }
 
+// ------------------------------------------------------------------ complex embedding
+
+// dst = J src (transpose = false) or J^T src for interleaved complex columns, J the real
+// form of multiplication by i: (J v)_{2k} = -v_{2k+1}, (J v)_{2k+1} = v_{2k}
+__global__ __launch_bounds__(256) void k_apply_j(int64_t nc, const double* __restrict__ src, int64_t lds,
+                                                 double* __restrict__ dst, int64_t ldd, int transpose) {
+    const int j = blockIdx.y;
+    const double* a = src + (int64_t)j * lds;
+    double* d = dst + (int64_t)j * ldd;
+    const double sg = transpose ? -1.0 : 1.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nc; k += (int64_t)gridDim.x * 256) {
+        const double re = a[2 * k], im = a[2 * k + 1];
+        d[2 * k] = -sg * im;
+        d[2 * k + 1] = sg * re;
+    }
+}
+
 // ------------------------------------------------------------------ gather / cast
 
 template <typename TS, typename TD>
@@ -460,6 +477,14 @@ void launch_random_block(int64_t n, int b, uint64_t seed, double* X, int64_t ldx
     if (total <= 0) return;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_random_block, dim3((unsigned)blocks), dim3(256), 0, s, n, total, seed, X, ldx);
+    LABPSD_HIP(hipGetLastError());
+}
+
+void launch_apply_j(int64_t nc, int ncols, const double* src, int64_t lds, double* dst, int64_t ldd, bool transpose,
+                    hipStream_t s) {
+    if (nc <= 0 || ncols <= 0) return;
+    const unsigned bx = (unsigned)std::min<int64_t>((nc + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_apply_j, dim3(bx, ncols), dim3(256), 0, s, nc, src, lds, dst, ldd, transpose ? 1 : 0);
     LABPSD_HIP(hipGetLastError());
 }
 

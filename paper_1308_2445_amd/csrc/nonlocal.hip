@@ -321,6 +321,7 @@ extern "C" labpsd_status labpsd_problem_set_nonlocal(labpsd_problem* p, int k, c
                                                      const double* G) {
     return abi_guard([&]() -> labpsd_status {
         LABPSD_REQUIRE(p != nullptr, "problem is NULL");
+        LABPSD_REQUIRE(!p->hermitian, "the nonlocal term is real here; Hermitian problems take none");
         LABPSD_REQUIRE(k >= 0 && k <= 65536, "k out of range (0 .. 65536)");
         NonLocal& nl = p->nl;
         LABPSD_HIP(hipSetDevice(p->ctx->device));
