@@ -164,13 +164,15 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
     return bid;  // unreachable for bid < nblocks; kept total
 }
 
-// Launch shape of the sliced-ELL kernels: CW right-hand-side columns per wavefront and
-// WPS wavefronts per slice (the slice's slots are dealt round-robin to them, which
-// shortens each wavefront's chain of dependent gathers when there are few slices or
-// few columns).  A 256-thread work-group covers 4 / WPS slices.
+// Launch shape of the sliced-ELL kernels: CW right-hand-side columns per wavefront, WPS
+// wavefronts per slice (the slice's slots are dealt round-robin to them, which shortens
+// each wavefront's chain of dependent gathers when there are few slices or few columns)
+// and `groups` column-chunk groups (grid.y: a work-group walks every groups-th chunk).
+// A 256-thread work-group covers 4 / WPS slices.
 struct SellShape {
     int cw;
     int wps;
+    int groups;
 };
 SellShape sell_shape(int64_t nslices, int w, int max_cw, int64_t want_waves);
 
@@ -501,6 +503,8 @@ void launch_orth_deviation(int b, const double* SR, int64_t ld, double* out, hip
 void launch_gram(int64_t n, int k, const double* Z, const double* ZH, const double* ZS, int64_t ldz,
                  double* HR, double* SR, int64_t ldr, double* ws, int cu_count, hipStream_t s);
 
+// MFMA tiles per wavefront of the wide block update for b output columns (6, 8 or 9)
+int block_update_ct(int b);
 // Block update: out_i = in_i W for i = 0..2
 void launch_block_update(int64_t n, int k, int b, const double* Z, const double* ZH,
                          const double* ZS, int64_t ldz, const double* W, int64_t ldw, double* Psi,

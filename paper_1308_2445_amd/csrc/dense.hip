@@ -222,17 +222,18 @@ __global__ void k_colnorm_finish(int q, const double* __restrict__ partial, int 
 
 // ------------------------------------------------------------------ Gram on MFMA
 
-// Output tile 32 x 32 per work-group: four wavefronts, each one 16 x 16 tile of both
-// H_R and S_R.  Rows of Z are staged in LDS 64 at a time, transposed so that each
-// lane's MFMA operand (row k, column i) is a conflict-free LDS read.
-constexpr int GT = 32;
-constexpr int GR = 64;
-
+// Output tile GT x GT per work-group (GT = 32 or 64): four wavefronts in a 2 x 2 grid,
+// each one (GT/2) x (GT/2) block of both H_R and S_R as (GT/32)^2 MFMA tiles of 16 x 16.
+// Rows of Z are staged in LDS GR at a time, transposed so that each lane's MFMA operand
+// (row k, column i) is a conflict-free LDS read.  The 64 x 64 tile doubles the products
+// per staged byte; it is used from k = 192 up (below, its padding of k costs more).
+template <int GT, int GR>
 __global__ __launch_bounds__(256) void k_gram(int64_t n, int k, const double* __restrict__ Z,
                                               const double* __restrict__ ZH,
                                               const double* __restrict__ ZS, int64_t ld, int nb,
                                               int64_t rows_per_chunk, double* __restrict__ part,
                                               int kp) {
+    constexpr int TW = GT / 32;   // MFMA tiles per wavefront and direction
     int p = blockIdx.x, bi = 0;
     while (p >= nb - bi) { p -= nb - bi; ++bi; }
     const int bj = bi + p;
@@ -243,8 +244,14 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int k, const double* __
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     const int ti = wave >> 1, tj = wave & 1;
-    double4_t accH = {0.0, 0.0, 0.0, 0.0};
-    double4_t accS = {0.0, 0.0, 0.0, 0.0};
+    double4_t aH[TW][TW], aS[TW][TW];
+#pragma unroll
+    for (int u = 0; u < TW; ++u)
+#pragma unroll
+        for (int v = 0; v < TW; ++v) {
+            aH[u][v] = double4_t{0.0, 0.0, 0.0, 0.0};
+            aS[u][v] = double4_t{0.0, 0.0, 0.0, 0.0};
+        }
     const int64_t rb = (int64_t)blockIdx.y * rows_per_chunk;
     const int64_t re = min(n, rb + rows_per_chunk);
     // a stage's loads are all issued before any is used (out-of-range elements read a
@@ -280,13 +287,23 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int k, const double* __
         }
         __syncthreads();
         if (r0 + GR < re) load_stage(r0 + GR);
-#pragma unroll 4
+#pragma unroll 2
         for (int kk = 0; kk < GR; kk += 4) {
-            const double a = sZ[ti * 16 + (lane & 15)][kk + (lane >> 4)];
-            const double bh = sH[tj * 16 + (lane & 15)][kk + (lane >> 4)];
-            const double bs = sS[tj * 16 + (lane & 15)][kk + (lane >> 4)];
-            accH = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bh, accH, 0, 0, 0);
-            accS = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs, accS, 0, 0, 0);
+            const int kr = kk + (lane >> 4);
+            double a[TW], h[TW], sv[TW];
+#pragma unroll
+            for (int u = 0; u < TW; ++u) {
+                a[u] = sZ[ti * (GT / 2) + 16 * u + (lane & 15)][kr];
+                h[u] = sH[tj * (GT / 2) + 16 * u + (lane & 15)][kr];
+                sv[u] = sS[tj * (GT / 2) + 16 * u + (lane & 15)][kr];
+            }
+#pragma unroll
+            for (int u = 0; u < TW; ++u)
+#pragma unroll
+                for (int v = 0; v < TW; ++v) {
+                    aH[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], h[v], aH[u][v], 0, 0, 0);
+                    aS[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], sv[v], aS[u][v], 0, 0, 0);
+                }
         }
         __syncthreads();
     }
@@ -295,12 +312,16 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int k, const double* __
     // accumulator layout of the f64 16x16x4 MFMA on gfx950 (measured): register q of
     // lane l holds row 4q + l / 16 and column l % 16 of the 16 x 16 tile
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int ii = i0 + ti * 16 + 4 * q + (lane >> 4);
-        const int jj = j0 + tj * 16 + (lane & 15);
-        ph[ii + (int64_t)jj * kp] = accH[q];
-        ps[ii + (int64_t)jj * kp] = accS[q];
-    }
+    for (int u = 0; u < TW; ++u)
+#pragma unroll
+        for (int v = 0; v < TW; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ii = i0 + ti * (GT / 2) + 16 * u + 4 * q + (lane >> 4);
+                const int jj = j0 + tj * (GT / 2) + 16 * v + (lane & 15);
+                ph[ii + (int64_t)jj * kp] = aH[u][v][q];
+                ps[ii + (int64_t)jj * kp] = aS[u][v][q];
+            }
 }
 
 // sum the chunk partials of the upper triangle (i <= j) and mirror it: eight lanes per
@@ -377,9 +398,10 @@ __global__ __launch_bounds__(256) void k_block_update(int64_t n, int k, int b,
 
 // The same product for wide blocks (large k or b): each wavefront accumulates 16 rows x
 // 16 CT columns (CT MFMA tiles), so Z is re-read b / (16 CT) times instead of b / 32; W
-// passes through LDS in 16-row chunks (double-buffered, shared by the four wavefronts)
-// and the next chunk's Z operands and W entries are loaded while the current chunk's
-// MFMAs run.
+// passes through LDS in 16-row chunks (double-buffered, shared by the four wavefronts,
+// rows padded by one element against bank conflicts) and the next chunk's Z operands and
+// W entries are loaded while the current chunk's MFMAs run.  CT (6, 8 or 9) is chosen
+// per launch to pad b the least.
 template <int CT>
 __global__ __launch_bounds__(256) void k_block_update_wide(int64_t n, int k, int b,
                                                            const double* __restrict__ Z0,
@@ -391,7 +413,7 @@ __global__ __launch_bounds__(256) void k_block_update_wide(int64_t n, int k, int
                                                            double* __restrict__ O2, int64_t ldo) {
     constexpr int NC = 16 * CT;               // columns per work-group
     constexpr int WL = 16 * NC / 256;         // W entries per thread per chunk
-    __shared__ double Wl[2][16][NC];
+    __shared__ double Wl[2][16][NC + 1];   // + 1: the four k-rows a wavefront reads fall in different banks
     const double* Zm = blockIdx.z == 0 ? Z0 : (blockIdx.z == 1 ? Z1 : Z2);
     double* O = blockIdx.z == 0 ? O0 : (blockIdx.z == 1 ? O1 : O2);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -602,17 +624,23 @@ template void launch_colnorms<double>(int64_t, int, const double*, int64_t, cons
 template void launch_colnorms<float>(int64_t, int, const float*, int64_t, const int32_t*, double*,
                                      double*, hipStream_t);
 
+// tile of the Gram kernel for k columns: 64 x 64 (32-row stages) from k = 192, else
+// 32 x 32 (64-row stages)
+static int gram_tile(int k) { return k >= 192 ? 64 : 32; }
+
 static void gram_shape(int64_t n, int k, int cu_count, int& nb, int& kp, int& nchunk,
                        int64_t& rows) {
-    nb = (k + GT - 1) / GT;
-    kp = nb * GT;
+    const int gt = gram_tile(k), gr = gt == 64 ? 32 : 64;
+    nb = (k + gt - 1) / gt;
+    kp = nb * gt;
     const int pairs = nb * (nb + 1) / 2;
-    // enough work-groups to fill the chip twice, chunks of at least 256 rows
-    int64_t want = std::max<int64_t>(1, (2LL * cu_count + pairs - 1) / pairs);
+    // enough work-groups to cover the chip's resident slots several times over (the
+    // products of a tile pair over a row chunk are short), chunks of at least 256 rows
+    int64_t want = std::max<int64_t>(1, (8LL * cu_count + pairs - 1) / pairs);
     int64_t maxc = std::max<int64_t>(1, (n + 255) / 256);
     nchunk = (int)std::min<int64_t>(want, maxc);
     rows = (n + nchunk - 1) / nchunk;
-    rows = ((rows + GR - 1) / GR) * GR;
+    rows = ((rows + gr - 1) / gr) * gr;
     nchunk = (int)std::max<int64_t>(1, (n + rows - 1) / rows);
 }
 
@@ -630,13 +658,33 @@ void launch_gram(int64_t n, int k, const double* Z, const double* ZH, const doub
     int64_t rows;
     gram_shape(n, k, cu_count, nb, kp, nchunk, rows);
     const int pairs = nb * (nb + 1) / 2;
-    hipLaunchKernelGGL(k_gram, dim3(pairs, nchunk), dim3(256), 0, s, n, k, Z, ZH, ZS, ldz, nb, rows,
-                       ws, kp);
+    if (gram_tile(k) == 64)
+        hipLaunchKernelGGL((k_gram<64, 32>), dim3(pairs, nchunk), dim3(256), 0, s, n, k, Z, ZH, ZS, ldz, nb, rows,
+                           ws, kp);
+    else
+        hipLaunchKernelGGL((k_gram<32, 64>), dim3(pairs, nchunk), dim3(256), 0, s, n, k, Z, ZH, ZS, ldz, nb, rows,
+                           ws, kp);
     LABPSD_HIP(hipGetLastError());
     const int64_t tot = (int64_t)k * k;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((8 * tot + 255) / 256)), dim3(256), 0, s, k, kp,
                        nchunk, ws, HR, SR, ldr);
     LABPSD_HIP(hipGetLastError());
+}
+
+// MFMA tiles per wavefront of the wide block update: the width 16 CT that pads b the
+// least, then the fewest column groups (each group re-reads Z)
+int block_update_ct(int b) {
+    int best_ct = 8;
+    int64_t best_cost = INT64_MAX;
+    for (int ct : {9, 8, 6}) {
+        const int64_t g = (b + 16 * ct - 1) / (16 * ct);
+        const int64_t cost = (g * 16 * ct - b) * 4 + g;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best_ct = ct;
+        }
+    }
+    return best_ct;
 }
 
 void launch_block_update(int64_t n, int k, int b, const double* Z, const double* ZH,
@@ -646,9 +694,17 @@ void launch_block_update(int64_t n, int k, int b, const double* Z, const double*
     dim3 grid((unsigned)((n + 63) / 64), (unsigned)((b + 31) / 32), 3);
     if (k >= 128 || b >= 96) {
         // wide blocks: 128 columns per work-group
-        const dim3 gw((unsigned)((n + 63) / 64), (unsigned)((b + 127) / 128), 3);
-        hipLaunchKernelGGL(k_block_update_wide<8>, gw, dim3(256), 0, s, n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi,
-                           PsiH, PsiS, ldo);
+        const int ct = block_update_ct(b);
+        const dim3 gw((unsigned)((n + 63) / 64), (unsigned)((b + 16 * ct - 1) / (16 * ct)), 3);
+        if (ct == 9)
+            hipLaunchKernelGGL(k_block_update_wide<9>, gw, dim3(256), 0, s, n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi,
+                               PsiH, PsiS, ldo);
+        else if (ct == 6)
+            hipLaunchKernelGGL(k_block_update_wide<6>, gw, dim3(256), 0, s, n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi,
+                               PsiH, PsiS, ldo);
+        else
+            hipLaunchKernelGGL(k_block_update_wide<8>, gw, dim3(256), 0, s, n, k, b, Z, ZH, ZS, ldz, W, ldw, Psi,
+                               PsiH, PsiS, ldo);
         LABPSD_HIP(hipGetLastError());
         return;
     }

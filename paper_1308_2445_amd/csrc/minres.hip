@@ -62,72 +62,76 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
     const int64_t slice = sb * SPB + wave / WPS;
     const int sw = wave % WPS;
     const bool valid = slice < nslices;
-    const int j0 = blockIdx.y * CW;
     const int64_t row = slice * kSlice + lane;
     const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
-    bool act[CW];
-    const T* xc[CW];
-    T ah[CW], as[CW];
-    bool any = false;
-#pragma unroll
-    for (int j = 0; j < CW; ++j) {
-        const int jj = j0 + j;
-        act[j] = jj < q && (MODE == 0 || !sc[jj].done);
-        any = any || act[j];
-        xc[j] = act[j] ? X + (int64_t)(MODE == 0 ? xcols[jj] : jj) * ldx : X;
-        ah[j] = T(0);
-        as[j] = T(0);
-    }
-    // a chunk whose columns have all converged has nothing to do (uniform over the
-    // work-group; the next kernels read no partial of a converged column)
-    if (!any) return;
-    const T* xp[CW];
-#pragma unroll
-    for (int j = 0; j < CW; ++j) xp[j] = xc[j];
-    sell_accumulate<T, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
-    slice_reduce<T, CW, WPS>(ah, as, sred);
     const bool lead = valid && sw == 0;
+    // the work-group walks its column chunks; after the first one the slices' pattern comes
+    // from L1/L2 (chunks whose columns have all converged are skipped, uniformly)
+    const int nch = (q + CW - 1) / CW, cpg = (nch + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int jb = (int)blockIdx.y * cpg * CW, je = min(q, jb + cpg * CW);
+    for (int j0 = jb; j0 < je; j0 += CW) {
+        bool act[CW];
+        const T* xc[CW];
+        T ah[CW], as[CW];
+        bool any = false;
 #pragma unroll
-    for (int j = 0; j < CW; ++j) {
-        const int jj = j0 + j;
-        double c[NS];
+        for (int j = 0; j < CW; ++j) {
+            const int jj = j0 + j;
+            act[j] = jj < q && (MODE == 0 || !sc[jj].done);
+            any = any || act[j];
+            xc[j] = act[j] ? X + (int64_t)(MODE == 0 ? xcols[jj] : jj) * ldx : X;
+            ah[j] = T(0);
+            as[j] = T(0);
+        }
+        if (!any) continue;
+        const T* xp[CW];
 #pragma unroll
-        for (int w = 0; w < NS; ++w) c[w] = 0.0;
-        if (act[j] && lead && row < n) {
-            // the nonlocal term belongs to H: (H_loc + F G F^T - shift S) x
-            const T hx = nl.rp ? ah[j] + nl_row_term(nl, row, jj) : ah[j];
-            const T y = hx - (T)shift[jj] * as[j];
-            T v;
-            if constexpr (MODE == 0) {
-                v = -(y + aux[row + (int64_t)auxcols[jj] * ldaux]);
-                c[0] = (double)v * (double)v;
-            } else {
-                v = y - (T)sc[jj].beta * aux[row + (int64_t)jj * ldaux];
-                const double xv = (double)xc[j][row];
-                c[0] = xv * (double)v;
-                c[1] = (double)v * (double)v;
-                c[2] = xv * xv;
+        for (int j = 0; j < CW; ++j) xp[j] = xc[j];
+        sell_accumulate<T, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
+        slice_reduce<T, CW, WPS>(ah, as, sred);
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const int jj = j0 + j;
+            double c[NS];
+#pragma unroll
+            for (int w = 0; w < NS; ++w) c[w] = 0.0;
+            if (act[j] && lead && row < n) {
+                // the nonlocal term belongs to H: (H_loc + F G F^T - shift S) x
+                const T hx = nl.rp ? ah[j] + nl_row_term(nl, row, jj) : ah[j];
+                const T y = hx - (T)shift[jj] * as[j];
+                T v;
+                if constexpr (MODE == 0) {
+                    v = -(y + aux[row + (int64_t)auxcols[jj] * ldaux]);
+                    c[0] = (double)v * (double)v;
+                } else {
+                    v = y - (T)sc[jj].beta * aux[row + (int64_t)jj * ldaux];
+                    const double xv = (double)xc[j][row];
+                    c[0] = xv * (double)v;
+                    c[1] = (double)v * (double)v;
+                    c[2] = xv * xv;
+                }
+                out[row + (int64_t)jj * n] = v;
             }
-            out[row + (int64_t)jj * n] = v;
-        }
 #pragma unroll
-        for (int w = 0; w < NS; ++w) {
-            const double t = wave_allsum(c[w]);
-            if (lane == 0) red[wave][w][j] = t;
+            for (int w = 0; w < NS; ++w) {
+                const double t = wave_allsum(c[w]);
+                if (lane == 0) red[wave][w][j] = t;
+            }
         }
-    }
-    __syncthreads();
-    // one partial per work-group, column and sum (the slice block sb owns slot sb); the
-    // wavefronts that only helped a slice contributed zeros
-    if (threadIdx.x < NS * CW) {
-        const int w = threadIdx.x / CW, jl = threadIdx.x % CW;
-        const int jj = j0 + jl;
-        if (jj < q) {
-            double t = 0.0;
+        __syncthreads();
+        // one partial per work-group, column and sum (the slice block sb owns slot sb); the
+        // wavefronts that only helped a slice contributed zeros
+        if (threadIdx.x < NS * CW) {
+            const int w = threadIdx.x / CW, jl = threadIdx.x % CW;
+            const int jj = j0 + jl;
+            if (jj < q) {
+                double t = 0.0;
 #pragma unroll
-            for (int v = 0; v < kWaves; ++v) t += red[v][w][jl];
-            partial[((int64_t)w * npart + sb) * q + jj] = (MODE == 0 || !sc[jj].done) ? t : 0.0;
+                for (int v = 0; v < kWaves; ++v) t += red[v][w][jl];
+                partial[((int64_t)w * npart + sb) * q + jj] = (MODE == 0 || !sc[jj].done) ? t : 0.0;
+            }
         }
+        __syncthreads();   // red and sred are rewritten by the next chunk
     }
 }
 
@@ -378,10 +382,10 @@ template <typename T, int MODE, int CW, int WPS>
 int64_t launch_spmv_s(const Sell& A, const T* hv, const T* sv, const T* X, int64_t ldx,
                       const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
                       const double* shift, const MinresScal* sc, T* out, double* partial, int q,
-                      hipStream_t s, NlEpi<T, T> nl) {
+                      hipStream_t s, NlEpi<T, T> nl, int groups) {
     constexpr int SPB = 4 / WPS;
     const int64_t nblk = (A.nslices + SPB - 1) / SPB;
-    const dim3 g((unsigned)nblk, (unsigned)((q + CW - 1) / CW));
+    const dim3 g((unsigned)nblk, (unsigned)groups);
     hipLaunchKernelGGL((k_minres_spmv<T, MODE, CW, WPS>), g, dim3(256), 0, s, A.slice_off.p, A.col.p, hv,
                        sv, A.n, A.nslices, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, nblk,
                        q, nl);
@@ -399,7 +403,7 @@ int64_t launch_spmv(const Sell& A, SellShape sh, const T* hv, const T* sv, const
     const NlEpi<T, T> nl = nlp ? nl_prepare<T>(*nlp, X, ldx, xcols, q, s) : NlEpi<T, T>{};
 #define LABPSD_SPMV(CW, WPS) \
     launch_spmv_s<T, MODE, CW, WPS>(A, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q, \
-                                    s, nl)
+                                    s, nl, sh.groups)
     if (sh.wps == 4) {
         if (sh.cw >= 4) return LABPSD_SPMV(4, 4);
         if (sh.cw == 2) return LABPSD_SPMV(2, 4);

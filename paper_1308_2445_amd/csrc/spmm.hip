@@ -16,7 +16,12 @@ namespace labpsd {
 namespace {
 
 // One work-group of 256 threads covers 4 / WPS slices; wavefront `wave` serves slice
-// sb * (4 / WPS) + wave / WPS and takes every WPS-th slot of it.
+// sb * (4 / WPS) + wave / WPS and takes every WPS-th slot of it.  The work-group walks a
+// contiguous band of column chunks (grid.y bands of about 32 columns): after the band's
+// first chunk the slices' column indices and values come from L1/L2, so the pattern is
+// fetched from HBM once per band rather than once per chunk, while the work-groups in
+// flight share one band of X (~32 columns), which stays in the last-level cache for the
+// neighbouring rows' gathers.
 template <int CW, int WPS>
 __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off,
                                                  const int32_t* __restrict__ col,
@@ -34,28 +39,32 @@ __global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off
     const int64_t slice = sb * SPB + wave / WPS;
     const int sw = wave % WPS;
     const bool valid = slice < nslices;
-    const int j0 = blockIdx.y * CW;
-    const int nc = min(CW, w - j0);
     const int64_t row = slice * kSlice + lane;
     const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
-    double ah[CW], as[CW];
+    const int nch = (w + CW - 1) / CW, cpg = (nch + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int jb = (int)blockIdx.y * cpg * CW, je = min(w, jb + cpg * CW);
+    for (int j0 = jb; j0 < je; j0 += CW) {
+        const int nc = min(CW, w - j0);
+        double ah[CW], as[CW];
 #pragma unroll
-    for (int j = 0; j < CW; ++j) { ah[j] = 0.0; as[j] = 0.0; }
-    const double* Xj = X + (int64_t)j0 * ldx;
-    const double* xp[CW];
+        for (int j = 0; j < CW; ++j) { ah[j] = 0.0; as[j] = 0.0; }
+        const double* Xj = X + (int64_t)j0 * ldx;
+        const double* xp[CW];
 #pragma unroll
-    for (int j = 0; j < CW; ++j) xp[j] = Xj + (j < nc ? (int64_t)j * ldx : 0);
-    sell_accumulate<double, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
-    slice_reduce<double, CW, WPS>(ah, as, red);
-    if (valid && sw == 0 && row < n) {
+        for (int j = 0; j < CW; ++j) xp[j] = Xj + (j < nc ? (int64_t)j * ldx : 0);
+        sell_accumulate<double, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
+        slice_reduce<double, CW, WPS>(ah, as, red);
+        if (valid && sw == 0 && row < n) {
 #pragma unroll
-        for (int j = 0; j < CW; ++j) {
-            if (j < nc) {
-                const double yh = nl.rp ? ah[j] + nl_row_term(nl, row, j0 + j) : ah[j];
-                YH[row + (int64_t)(j0 + j) * ldy] = yh;
-                YS[row + (int64_t)(j0 + j) * ldy] = as[j];
+            for (int j = 0; j < CW; ++j) {
+                if (j < nc) {
+                    const double yh = nl.rp ? ah[j] + nl_row_term(nl, row, j0 + j) : ah[j];
+                    YH[row + (int64_t)(j0 + j) * ldy] = yh;
+                    YS[row + (int64_t)(j0 + j) * ldy] = as[j];
+                }
             }
         }
+        if constexpr (WPS > 1) __syncthreads();   // red is rewritten by the next chunk
     }
 }
 
@@ -77,28 +86,32 @@ __global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ 
     const int64_t slice = sb * SPB + wave / WPS;
     const int sw = wave % WPS;
     const bool valid = slice < nslices;
-    const int j0 = blockIdx.y * CW;
-    const int nc = min(CW, w - j0);
     const int64_t row = slice * kSlice + lane;
     const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
-    T ah[CW], as[CW];
+    const int nch = (w + CW - 1) / CW, cpg = (nch + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int jb = (int)blockIdx.y * cpg * CW, je = min(w, jb + cpg * CW);
+    for (int j0 = jb; j0 < je; j0 += CW) {
+        const int nc = min(CW, w - j0);
+        T ah[CW], as[CW];
 #pragma unroll
-    for (int j = 0; j < CW; ++j) { ah[j] = T(0); as[j] = T(0); }
-    const T* Xj = X + (int64_t)j0 * ldx;
-    const T* xp[CW];
+        for (int j = 0; j < CW; ++j) { ah[j] = T(0); as[j] = T(0); }
+        const T* Xj = X + (int64_t)j0 * ldx;
+        const T* xp[CW];
 #pragma unroll
-    for (int j = 0; j < CW; ++j) xp[j] = Xj + (j < nc ? (int64_t)j * ldx : 0);
-    sell_accumulate<T, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
-    slice_reduce<T, CW, WPS>(ah, as, red);
-    if (valid && sw == 0 && row < n) {
+        for (int j = 0; j < CW; ++j) xp[j] = Xj + (j < nc ? (int64_t)j * ldx : 0);
+        sell_accumulate<T, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
+        slice_reduce<T, CW, WPS>(ah, as, red);
+        if (valid && sw == 0 && row < n) {
 #pragma unroll
-        for (int j = 0; j < CW; ++j) {
-            if (j < nc) {
-                const T sh = (T)shift[j0 + j];
-                const T h = nl.rp ? ah[j] + nl_row_term(nl, row, j0 + j) : ah[j];
-                Y[row + (int64_t)(j0 + j) * ldy] = h - sh * as[j];
+            for (int j = 0; j < CW; ++j) {
+                if (j < nc) {
+                    const T sh = (T)shift[j0 + j];
+                    const T h = nl.rp ? ah[j] + nl_row_term(nl, row, j0 + j) : ah[j];
+                    Y[row + (int64_t)(j0 + j) * ldy] = h - sh * as[j];
+                }
             }
         }
+        if constexpr (WPS > 1) __syncthreads();
     }
 }
 
@@ -164,21 +177,28 @@ void refresh_sell_h(Sell& S, const double* hv, hipStream_t s) {
     LABPSD_HIP(hipStreamSynchronize(s));
 }
 
-// Launch shape: the widest column chunk (fewest passes over the pattern) that, with 1
-// or 4 wavefronts per slice, gives at least want_waves wavefronts to hide the gathers'
-// latency; failing that the shape with the most wavefronts.
+// Launch shape: the widest column chunk (fewest passes over the pattern) that, with one
+// or four wavefronts per slice, gives want_waves wavefronts; bands of about 32 columns
+// (grid.y = their number, more if the wavefront target needs it); when even one chunk
+// per band falls short, the shape with the most wavefronts.
 SellShape sell_shape(int64_t nslices, int w, int max_cw, int64_t want_waves) {
-    const int64_t kWantWaves = want_waves;
-    SellShape best{1, 4};
+    constexpr int kBandCols = 32;
+    SellShape best{1, 4, 1};
     int64_t best_waves = -1;
     for (int cw : {8, 4, 2, 1}) {
         if (cw > max_cw) continue;
+        const int64_t nch = (w + cw - 1) / cw;
         for (int wps : {1, 4}) {
-            const int64_t waves = nslices * ((w + cw - 1) / cw) * wps;
-            if (waves >= kWantWaves) return SellShape{cw, wps};
-            if (waves > best_waves) {
-                best_waves = waves;
-                best = SellShape{cw, wps};
+            const int64_t per_group = nslices * wps;
+            if (per_group * nch >= want_waves) {
+                const int64_t band = std::max(1, kBandCols / cw);
+                const int64_t g = std::max<int64_t>((nch + band - 1) / band,
+                                                    (want_waves + per_group - 1) / per_group);
+                return SellShape{cw, wps, (int)std::max<int64_t>(1, std::min<int64_t>(nch, g))};
+            }
+            if (per_group * nch > best_waves) {
+                best_waves = per_group * nch;
+                best = SellShape{cw, wps, (int)std::max<int64_t>(1, nch)};
             }
         }
     }
@@ -187,19 +207,19 @@ SellShape sell_shape(int64_t nslices, int w, int max_cw, int64_t want_waves) {
 
 template <int CW, int WPS>
 static void spmm_hs_cw(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
-                       int64_t ldy, hipStream_t s, NlEpi<double, double> nl) {
+                       int64_t ldy, hipStream_t s, NlEpi<double, double> nl, int groups) {
     constexpr int SPB = 4 / WPS;
-    dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)((w + CW - 1) / CW));
+    dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)groups);
     hipLaunchKernelGGL((k_spmm_hs<CW, WPS>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, A.hv.p,
                        A.sv.p, A.n, A.nslices, X, ldx, w, YH, YS, ldy, nl);
     LABPSD_HIP(hipGetLastError());
 }
 
 template <int CW>
-static void spmm_hs_w(const Sell& A, int wps, const double* X, int64_t ldx, int w, double* YH,
+static void spmm_hs_w(const Sell& A, SellShape sh, const double* X, int64_t ldx, int w, double* YH,
                       double* YS, int64_t ldy, hipStream_t s, NlEpi<double, double> nl) {
-    if (wps == 4) spmm_hs_cw<CW, 4>(A, X, ldx, w, YH, YS, ldy, s, nl);
-    else spmm_hs_cw<CW, 1>(A, X, ldx, w, YH, YS, ldy, s, nl);
+    if (sh.wps == 4) spmm_hs_cw<CW, 4>(A, X, ldx, w, YH, YS, ldy, s, nl, sh.groups);
+    else spmm_hs_cw<CW, 1>(A, X, ldx, w, YH, YS, ldy, s, nl, sh.groups);
 }
 
 void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
@@ -209,18 +229,18 @@ void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* 
         nlp ? nl_prepare<double>(*nlp, X, ldx, nullptr, w, s) : NlEpi<double, double>{};
     const SellShape sh = sell_shape(A.nslices, w, 8, 2048);
     switch (sh.cw) {
-        case 8: spmm_hs_w<8>(A, sh.wps, X, ldx, w, YH, YS, ldy, s, nl); break;
-        case 4: spmm_hs_w<4>(A, sh.wps, X, ldx, w, YH, YS, ldy, s, nl); break;
-        case 2: spmm_hs_w<2>(A, sh.wps, X, ldx, w, YH, YS, ldy, s, nl); break;
-        default: spmm_hs_w<1>(A, sh.wps, X, ldx, w, YH, YS, ldy, s, nl); break;
+        case 8: spmm_hs_w<8>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
+        case 4: spmm_hs_w<4>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
+        case 2: spmm_hs_w<2>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
+        default: spmm_hs_w<1>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
     }
 }
 
 template <typename T, int CW, int WPS>
 static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
-                          int64_t ldy, hipStream_t s, NlEpi<T, T> nl) {
+                          int64_t ldy, hipStream_t s, NlEpi<T, T> nl, int groups) {
     constexpr int SPB = 4 / WPS;
-    dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)((w + CW - 1) / CW));
+    dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)groups);
     const T* hv;
     const T* sv;
     if constexpr (sizeof(T) == 8) {
@@ -236,10 +256,10 @@ static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const d
 }
 
 template <typename T, int CW>
-static void spmm_shift_w(const Sell& A, int wps, const T* X, int64_t ldx, int w, const double* shift,
+static void spmm_shift_w(const Sell& A, SellShape sh, const T* X, int64_t ldx, int w, const double* shift,
                          T* Y, int64_t ldy, hipStream_t s, NlEpi<T, T> nl) {
-    if (wps == 4) spmm_shift_cw<T, CW, 4>(A, X, ldx, w, shift, Y, ldy, s, nl);
-    else spmm_shift_cw<T, CW, 1>(A, X, ldx, w, shift, Y, ldy, s, nl);
+    if (sh.wps == 4) spmm_shift_cw<T, CW, 4>(A, X, ldx, w, shift, Y, ldy, s, nl, sh.groups);
+    else spmm_shift_cw<T, CW, 1>(A, X, ldx, w, shift, Y, ldy, s, nl, sh.groups);
 }
 
 template <typename T>
@@ -249,10 +269,10 @@ void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const doub
     const NlEpi<T, T> nl = nlp ? nl_prepare<T>(*nlp, X, ldx, nullptr, w, s) : NlEpi<T, T>{};
     const SellShape sh = sell_shape(A.nslices, w, 8, 2048);
     switch (sh.cw) {
-        case 8: spmm_shift_w<T, 8>(A, sh.wps, X, ldx, w, shift, Y, ldy, s, nl); break;
-        case 4: spmm_shift_w<T, 4>(A, sh.wps, X, ldx, w, shift, Y, ldy, s, nl); break;
-        case 2: spmm_shift_w<T, 2>(A, sh.wps, X, ldx, w, shift, Y, ldy, s, nl); break;
-        default: spmm_shift_w<T, 1>(A, sh.wps, X, ldx, w, shift, Y, ldy, s, nl); break;
+        case 8: spmm_shift_w<T, 8>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
+        case 4: spmm_shift_w<T, 4>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
+        case 2: spmm_shift_w<T, 2>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
+        default: spmm_shift_w<T, 1>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
     }
 }
 
