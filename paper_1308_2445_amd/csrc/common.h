@@ -164,43 +164,73 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
     return bid;  // unreachable for bid < nblocks; kept total
 }
 
-// Launch shape of the sliced-ELL kernels: CW right-hand-side columns per wavefront, WPS
-// wavefronts per slice (the slice's slots are dealt round-robin to them, which shortens
-// each wavefront's chain of dependent gathers when there are few slices or few columns)
-// and `groups` column-chunk groups (grid.y: a work-group walks every groups-th chunk).
-// A 256-thread work-group covers 4 / WPS slices.
+struct Sell;
+
+// Launch shape of the sliced-ELL kernels over many right-hand-side columns.  One slice
+// per work-group of kSellWaves wavefronts: the slice's pattern (column indices, H and S
+// values) is staged in LDS, in segments of at most `lseg` slots, and each wavefront takes
+// CW columns of every round of kSellWaves * CW columns from there, so the pattern leaves
+// HBM once per band of columns instead of once per few columns.  grid.y splits the
+// columns into `bands` of about 96: the neighbouring slices' gathers of a band's X
+// columns then meet in the caches.
+constexpr int kSellWaves = 8;
+constexpr size_t kSellLdsBytes = 80 * 1024;   // two work-groups per CU
 struct SellShape {
     int cw;
-    int wps;
-    int groups;
+    int bands;
+    int lseg;
+    size_t lds_bytes;
 };
-SellShape sell_shape(int64_t nslices, int w, int max_cw, int64_t want_waves);
+SellShape sell_shape(const Sell& A, int w, size_t value_bytes);
+// raise a kernel's dynamic-LDS limit to kSellLdsBytes on the current device (once)
+void allow_sell_lds(const void* kernel);
 
-// Accumulate ah[j] += H(row, :) x_j and as[j] += S(row, :) x_j over this lane's slots
-// e = e_first, e_first + stride, ... < e1 of a slice, for the CW columns whose bases
-// xp[j] gives.  U slots at a time (4, or 2 for 8 columns): their indices and values, then
-// every gather, then the products, so one wait covers U slots.  The slot count of a slice is the same for all
-// its rows (padded slot-major), so the bound test is uniform; slots past the end read the
-// first slot and contribute zero.  Callers point unused columns at a valid column and
-// discard their sums, which keeps the loop free of branches.
+template <typename T>
+struct SliceLds {
+    T* h;
+    T* s;
+    int32_t* c;
+};
+
+template <typename T>
+__device__ __forceinline__ SliceLds<T> slice_lds(void* base, int lseg) {
+    T* h = (T*)base;
+    T* s = h + (int64_t)lseg * kSlice;
+    return SliceLds<T>{h, s, (int32_t*)(s + (int64_t)lseg * kSlice)};
+}
+
+// Copy slots s0 .. s0 + ns - 1 of the slice whose entries start at e0 into LDS (every
+// thread of the work-group takes part).
+template <typename T>
+__device__ __forceinline__ void sell_stage(const int32_t* __restrict__ col, const T* __restrict__ hv,
+                                           const T* __restrict__ sv, int64_t e0, int s0, int ns,
+                                           SliceLds<T> L) {
+    const int64_t b = e0 + (int64_t)s0 * kSlice;
+    for (int i = threadIdx.x; i < ns * kSlice; i += blockDim.x) {
+        L.c[i] = col[b + i];
+        L.h[i] = hv[b + i];
+        L.s[i] = sv[b + i];
+    }
+}
+
+// ah[j] += H(row, :) x_j and as[j] += S(row, :) x_j over the ns staged slots, for the CW
+// columns whose bases xp[j] gives (row = the lane's row of the slice).  Two slots at a
+// time: both slots' gathers of every column are issued before the products.  Padding
+// slots hold the lane's own row and zero values.
 template <typename T, int CW>
-__device__ __forceinline__ void sell_accumulate(const int32_t* __restrict__ col, const T* __restrict__ hv,
-                                                const T* __restrict__ sv, int64_t e_first, int64_t e1,
-                                                int64_t stride, const T* const (&xp)[CW], T (&ah)[CW],
-                                                T (&as)[CW]) {
-    constexpr int U = CW >= 8 ? 2 : 4;
-    for (int64_t e = e_first; e < e1; e += stride * U) {
+__device__ __forceinline__ void sell_lds_accumulate(SliceLds<T> L, int ns, const T* const (&xp)[CW],
+                                                    T (&ah)[CW], T (&as)[CW]) {
+    const int lane = threadIdx.x & 63;
+    constexpr int U = 2;
+    int k = 0;
+    for (; k + U <= ns; k += U) {
         int32_t c[U];
         T h[U], s[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t idx = e + (int64_t)u * stride;
-            const bool ok = idx < e1;
-            const int64_t ic = ok ? idx : e;
-            c[u] = col[ic];
-            const T hh = hv[ic], ss = sv[ic];
-            h[u] = ok ? hh : T(0);
-            s[u] = ok ? ss : T(0);
+            c[u] = L.c[(k + u) * kSlice + lane];
+            h[u] = L.h[(k + u) * kSlice + lane];
+            s[u] = L.s[(k + u) * kSlice + lane];
         }
         T x[U][CW];
 #pragma unroll
@@ -215,31 +245,14 @@ __device__ __forceinline__ void sell_accumulate(const int32_t* __restrict__ col,
                 as[j] = fma(s[u], x[u][j], as[j]);
             }
     }
-}
-
-// Sum the per-lane accumulators of the WPS wavefronts that share a slice; the sums are
-// valid in the slice's first wavefront.  red: LDS of 256 * 2 * CW elements.  Every
-// thread of the work-group must call it.
-template <typename T, int CW, int WPS>
-__device__ __forceinline__ void slice_reduce(T (&ah)[CW], T (&as)[CW], T* red) {
-    if constexpr (WPS > 1) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, sw = wave % WPS;
-        if (sw != 0) {
+    if (k < ns) {
+        const int32_t c = L.c[k * kSlice + lane];
+        const T h = L.h[k * kSlice + lane], s = L.s[k * kSlice + lane];
 #pragma unroll
-            for (int j = 0; j < CW; ++j) {
-                red[(wave * 2 * CW + j) * 64 + lane] = ah[j];
-                red[(wave * 2 * CW + CW + j) * 64 + lane] = as[j];
-            }
-        }
-        __syncthreads();
-        if (sw == 0) {
-#pragma unroll
-            for (int w = 1; w < WPS; ++w)
-#pragma unroll
-                for (int j = 0; j < CW; ++j) {
-                    ah[j] += red[((wave + w) * 2 * CW + j) * 64 + lane];
-                    as[j] += red[((wave + w) * 2 * CW + CW + j) * 64 + lane];
-                }
+        for (int j = 0; j < CW; ++j) {
+            const T x = xp[j][c];
+            ah[j] = fma(h, x, ah[j]);
+            as[j] = fma(s, x, as[j]);
         }
     }
 }
@@ -269,6 +282,7 @@ struct Sell {
     int64_t n = 0;
     int64_t nslices = 0;
     int64_t stored = 0;          // padded entries
+    int max_slots = 0;           // slots of the longest slice
     DBuf<int64_t> slice_off;     // nslices + 1 offsets (entries)
     DBuf<int32_t> col;
     DBuf<double> hv, sv;         // FP64 values

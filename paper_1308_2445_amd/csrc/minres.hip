@@ -6,14 +6,15 @@
 // MINRES (Paige and Saunders): Lanczos on A = H - eps_j S builds an orthonormal Krylov
 // basis with A V_k = V_{k+1} T_k; the least-squares problem with T_k is solved by one
 // Givens rotation per step, whose running product gives the residual norm for free.
-// All localised columns advance together, two kernels per iteration:
+// All localised columns advance together, three kernels per iteration:
 //   spmv    u = A v - beta_k v_prev, per-slice FP64 partial sums of v.u, u.u and v.v
 //           (one pattern pass)
+//   colsums the three sums of every live column from its slices' partials
 //   update  alpha_k = v.u; w = u - alpha_k v, whose norm follows from the sums without
 //           another pass: ||w||^2 = u.u - 2 alpha_k v.u + alpha_k^2 v.v; beta_{k+1} = ||w||,
 //           the new rotation, tau_k and |phibar_k|;
 //           d = (v - delta_k d1 - eps_k d2) / gamma_k, x += tau_k d, v_next = w / beta_{k+1}
-// Every block recomputes the column's scalars from the partial sums (identical values);
+// Every block recomputes the column's scalars from the column sums (identical values);
 // block 0 of the column stores the new scalar state into the other half of a double
 // buffer, so no block reads a state that another block of the same kernel writes.
 // The one-step variant (the conclusions' first-order method) shares the SpMV and the
@@ -42,34 +43,36 @@ __device__ __forceinline__ T wave_sum_t(T v) {
     return v;
 }
 
-constexpr int kWaves = 4;
-
-template <typename T, int MODE, int CW, int WPS>
-__global__ __launch_bounds__(256) void k_minres_spmv(
+// One slice per work-group (the sliced-ELL walk of the products: pattern staged in LDS,
+// wavefronts on different columns); a wavefront covers all 64 rows of the slice for its
+// CW columns, so each column's per-slice sums are one wavefront reduction, stored as the
+// slice's partial: partial[(w q + j) npart + slice], npart = nslices, the slices of one
+// sum and column contiguous for k_minres_colsums.  Columns that have all converged skip the products
+// (every barrier stays uniform: only the segment staging has barriers).
+template <typename T, int MODE, int CW>
+__global__ __launch_bounds__(64 * kSellWaves) void k_minres_spmv(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, const T* __restrict__ hv,
     const T* __restrict__ sv, int64_t n, int64_t nslices, const T* __restrict__ X, int64_t ldx,
     const int32_t* __restrict__ xcols, const T* __restrict__ aux, int64_t ldaux,
     const int32_t* __restrict__ auxcols, const double* __restrict__ shift,
     const MinresScal* __restrict__ sc, T* __restrict__ out, double* __restrict__ partial,
-    int64_t npart, int q, NlEpi<T, T> nl) {
-    constexpr int SPB = 4 / WPS;   // slices per work-group
+    int64_t npart, int q, int cpb, int lseg, NlEpi<T, T> nl) {
     constexpr int NS = MODE == 0 ? 1 : 3;   // partial sums per column
-    __shared__ T sred[WPS > 1 ? 256 * 2 * CW : 1];
-    __shared__ double red[kWaves][NS][CW];
+    extern __shared__ double sell_dyn[];
+    const SliceLds<T> L = slice_lds<T>(sell_dyn, lseg);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t nblk = (nslices + SPB - 1) / SPB;
-    const int64_t sb = xcd_block(blockIdx.x, nblk);
-    const int64_t slice = sb * SPB + wave / WPS;
-    const int sw = wave % WPS;
-    const bool valid = slice < nslices;
+    const int64_t slice = xcd_block(blockIdx.x, nslices);
+    const int64_t e0 = off[slice];
+    const int nsl = (int)((off[slice + 1] - e0) / kSlice);
+    const int nseg = (nsl + lseg - 1) / lseg;
     const int64_t row = slice * kSlice + lane;
-    const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
-    const bool lead = valid && sw == 0;
-    // the work-group walks its column chunks; after the first one the slices' pattern comes
-    // from L1/L2 (chunks whose columns have all converged are skipped, uniformly)
-    const int nch = (q + CW - 1) / CW, cpg = (nch + (int)gridDim.y - 1) / (int)gridDim.y;
-    const int jb = (int)blockIdx.y * cpg * CW, je = min(q, jb + cpg * CW);
-    for (int j0 = jb; j0 < je; j0 += CW) {
+    const int jb = (int)blockIdx.y * cpb, je = min(q, jb + cpb);
+    if (nseg == 1) {
+        sell_stage<T>(col, hv, sv, e0, 0, nsl, L);
+        __syncthreads();
+    }
+    for (int r = jb; r < je; r += kSellWaves * CW) {
+        const int j0 = r + wave * CW;
         bool act[CW];
         const T* xc[CW];
         T ah[CW], as[CW];
@@ -77,25 +80,33 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
 #pragma unroll
         for (int j = 0; j < CW; ++j) {
             const int jj = j0 + j;
-            act[j] = jj < q && (MODE == 0 || !sc[jj].done);
+            act[j] = jj < je && (MODE == 0 || !sc[jj].done);
             any = any || act[j];
             xc[j] = act[j] ? X + (int64_t)(MODE == 0 ? xcols[jj] : jj) * ldx : X;
             ah[j] = T(0);
             as[j] = T(0);
         }
-        if (!any) continue;
         const T* xp[CW];
 #pragma unroll
         for (int j = 0; j < CW; ++j) xp[j] = xc[j];
-        sell_accumulate<T, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
-        slice_reduce<T, CW, WPS>(ah, as, sred);
+        for (int sg = 0; sg < nseg; ++sg) {
+            const int s0 = sg * lseg, ns = min(lseg, nsl - s0);
+            if (nseg > 1) {
+                __syncthreads();
+                sell_stage<T>(col, hv, sv, e0, s0, ns, L);
+                __syncthreads();
+            }
+            if (any) sell_lds_accumulate<T, CW>(L, ns, xp, ah, as);
+        }
+        if (!any) continue;   // wavefront-uniform; no barrier follows in this round
 #pragma unroll
         for (int j = 0; j < CW; ++j) {
             const int jj = j0 + j;
+            if (jj >= je) break;
             double c[NS];
 #pragma unroll
             for (int w = 0; w < NS; ++w) c[w] = 0.0;
-            if (act[j] && lead && row < n) {
+            if (act[j] && row < n) {
                 // the nonlocal term belongs to H: (H_loc + F G F^T - shift S) x
                 const T hx = nl.rp ? ah[j] + nl_row_term(nl, row, jj) : ah[j];
                 const T y = hx - (T)shift[jj] * as[j];
@@ -115,49 +126,26 @@ __global__ __launch_bounds__(256) void k_minres_spmv(
 #pragma unroll
             for (int w = 0; w < NS; ++w) {
                 const double t = wave_allsum(c[w]);
-                if (lane == 0) red[wave][w][j] = t;
+                if (lane == 0) partial[((int64_t)w * q + jj) * npart + slice] = act[j] ? t : 0.0;
             }
         }
-        __syncthreads();
-        // one partial per work-group, column and sum (the slice block sb owns slot sb); the
-        // wavefronts that only helped a slice contributed zeros
-        if (threadIdx.x < NS * CW) {
-            const int w = threadIdx.x / CW, jl = threadIdx.x % CW;
-            const int jj = j0 + jl;
-            if (jj < q) {
-                double t = 0.0;
-#pragma unroll
-                for (int v = 0; v < kWaves; ++v) t += red[v][w][jl];
-                partial[((int64_t)w * npart + sb) * q + jj] = (MODE == 0 || !sc[jj].done) ? t : 0.0;
-            }
-        }
-        __syncthreads();   // red and sred are rewritten by the next chunk
     }
 }
 
-// sum of the np partials of column j, computed by one wavefront (fixed order, so every
-// wavefront that computes it gets the same value)
-template <typename T>
-__device__ double column_sum(const T* partial, int64_t np, int q, int j) {
-    double s = 0.0;
-    for (int64_t i = threadIdx.x & 63; i < np; i += 64) s += (double)partial[i * q + j];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    return __shfl(s, 0, 64);
-}
-
-// the three sums (stride np q apart) for a whole work-group: wavefronts 0, 1 and 2 each
-// compute one, LDS broadcasts them; called once per kernel
-__device__ void block_column_sums3(const double* partial, int64_t np, int q, int j, double out[3]) {
-    __shared__ double bc[3];
-    const int w = threadIdx.x >> 6;
-    if (w < 3) {
-        const double v = column_sum(partial + (int64_t)w * np * q, np, q, j);
-        if ((threadIdx.x & 63) == 0) bc[w] = v;
-    }
-    __syncthreads();
-    out[0] = bc[0];
-    out[1] = bc[1];
-    out[2] = bc[2];
+// sums[t] = the sum over the npart slices of partial set t = w q + j (w < nsets), one
+// wavefront per set and column in a fixed order (so the values are reproducible); columns
+// already done (sc != nullptr) are skipped, their sums are not read
+__global__ __launch_bounds__(256) void k_minres_colsums(const double* __restrict__ partial, int64_t npart, int q,
+                                                        int nsets, const MinresScal* __restrict__ sc,
+                                                        double* __restrict__ sums) {
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= nsets * q) return;
+    if (sc && sc[t % q].done) return;
+    const double* p = partial + (int64_t)t * npart;
+    double v = 0.0;
+    for (int64_t i = threadIdx.x & 63; i < npart; i += 64) v += p[i];
+    v = wave_sum_t(v);
+    if ((threadIdx.x & 63) == 0) sums[t] = v;
 }
 
 // sum over the work-group, valid in thread 0
@@ -170,15 +158,13 @@ __device__ T block_sum(T v) {
     return w[0] + w[1] + w[2] + w[3];
 }
 
-__global__ __launch_bounds__(256) void k_minres_init_finish(const double* __restrict__ partial,
-                                                            int64_t nslices, int q,
+__global__ __launch_bounds__(256) void k_minres_init_finish(const double* __restrict__ sums, int q,
                                                             const double* __restrict__ rnorm,
                                                             double eta, int max_inner,
                                                             MinresScal* __restrict__ sc) {
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= q) return;
-    const double b2 = column_sum(partial, nslices, q, j);
-    if ((threadIdx.x & 63) != 0) return;
+    const double b2 = sums[j];
     const double beta1 = sqrt(b2);
     MinresScal s{};
     s.beta = beta1;
@@ -217,7 +203,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max_inner,
                                                        const MinresScal* __restrict__ sc_in,
                                                        MinresScal* __restrict__ sc_out,
-                                                       const double* __restrict__ part, int64_t npa,
+                                                       const double* __restrict__ csum,
                                                        const T* __restrict__ V, T* __restrict__ Wb,
                                                        const T* __restrict__ D1, T* __restrict__ D2,
                                                        T* __restrict__ Xs, int32_t* __restrict__ done_out) {
@@ -231,8 +217,8 @@ __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max
         }
         return;
     }
-    double sums[3];   // v.u, u.u, v.v
-    block_column_sums3(part, npa, q, j, sums);
+    // v.u, u.u, v.v
+    const double sums[3] = {csum[j], csum[q + j], csum[2 * q + j]};
     const double al = sums[0];
     const double bnext = sqrt(fmax(sums[1] - al * (2.0 * sums[0] - al * sums[2]), 0.0));
     const int k = s.its + 1;
@@ -287,15 +273,13 @@ __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max
 // g -= alpha u, ||g||^2 = g.g - (g.u)^2 / u.u.  The scalar state reuses MinresScal:
 // beta = 0 always, phibar = ||g||.
 
-__global__ __launch_bounds__(256) void k_onestep_init_finish(const double* __restrict__ partial,
-                                                             int64_t nslices, int q,
+__global__ __launch_bounds__(256) void k_onestep_init_finish(const double* __restrict__ sums, int q,
                                                              const double* __restrict__ rnorm,
                                                              double eta, int max_inner,
                                                              MinresScal* __restrict__ sc) {
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= q) return;
-    const double g2 = column_sum(partial, nslices, q, j);
-    if ((threadIdx.x & 63) != 0) return;
+    const double g2 = sums[j];
     MinresScal s{};
     s.beta = 0.0;
     s.cprev = 1.0; s.sprev = 0.0; s.cpp = 1.0; s.spp = 0.0;
@@ -317,7 +301,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_onestep_update(int64_t n, int q, int max_inner,
                                                         const MinresScal* __restrict__ sc_in,
                                                         MinresScal* __restrict__ sc_out,
-                                                        const double* __restrict__ part, int64_t npa,
+                                                        const double* __restrict__ csum,
                                                         T* __restrict__ G, const T* __restrict__ U,
                                                         T* __restrict__ Xs, int32_t* __restrict__ done_out) {
     const int j = blockIdx.y;
@@ -330,8 +314,8 @@ __global__ __launch_bounds__(256) void k_onestep_update(int64_t n, int q, int ma
         }
         return;
     }
-    double sums[3];   // g.u, u.u, g.g
-    block_column_sums3(part, npa, q, j, sums);
+    // g.u, u.u, g.g
+    const double sums[3] = {csum[j], csum[q + j], csum[2 * q + j]};
     if (!(sums[1] > 0.0)) {   // A g = 0: no step reduces the residual
         if (lead) {
             MinresScal t = s;
@@ -378,22 +362,22 @@ __global__ __launch_bounds__(256) void k_minres_final(int64_t n, int q, const in
     }
 }
 
-template <typename T, int MODE, int CW, int WPS>
-int64_t launch_spmv_s(const Sell& A, const T* hv, const T* sv, const T* X, int64_t ldx,
+template <typename T, int MODE, int CW>
+int64_t launch_spmv_s(const Sell& A, SellShape sh, const T* hv, const T* sv, const T* X, int64_t ldx,
                       const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
                       const double* shift, const MinresScal* sc, T* out, double* partial, int q,
-                      hipStream_t s, NlEpi<T, T> nl, int groups) {
-    constexpr int SPB = 4 / WPS;
-    const int64_t nblk = (A.nslices + SPB - 1) / SPB;
-    const dim3 g((unsigned)nblk, (unsigned)groups);
-    hipLaunchKernelGGL((k_minres_spmv<T, MODE, CW, WPS>), g, dim3(256), 0, s, A.slice_off.p, A.col.p, hv,
-                       sv, A.n, A.nslices, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, nblk,
-                       q, nl);
-    return nblk;
+                      hipStream_t s, NlEpi<T, T> nl) {
+    allow_sell_lds((const void*)k_minres_spmv<T, MODE, CW>);
+    const int cpb = (q + sh.bands - 1) / sh.bands;
+    const dim3 g((unsigned)A.nslices, (unsigned)sh.bands);
+    hipLaunchKernelGGL((k_minres_spmv<T, MODE, CW>), g, dim3(64 * kSellWaves), sh.lds_bytes, s, A.slice_off.p,
+                       A.col.p, hv, sv, A.n, A.nslices, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out,
+                       partial, A.nslices, q, cpb, sh.lseg, nl);
+    return A.nslices;
 }
 
-// (H - eps_j S) products of the MINRES columns in the launch shape sell_shape picks (at
-// most 4 columns per wavefront); returns the number of partials per column
+// (H - eps_j S) products of the MINRES columns in the launch shape sell_shape picks;
+// returns the number of partials per column (one per slice)
 template <typename T, int MODE>
 int64_t launch_spmv(const Sell& A, SellShape sh, const T* hv, const T* sv, const T* X, int64_t ldx,
                     const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
@@ -401,24 +385,21 @@ int64_t launch_spmv(const Sell& A, SellShape sh, const T* hv, const T* sv, const
                     hipStream_t s, const NonLocal* nlp) {
     // the nonlocal term: G F^T x of the product's columns first, then the epilogue
     const NlEpi<T, T> nl = nlp ? nl_prepare<T>(*nlp, X, ldx, xcols, q, s) : NlEpi<T, T>{};
-#define LABPSD_SPMV(CW, WPS) \
-    launch_spmv_s<T, MODE, CW, WPS>(A, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q, \
-                                    s, nl, sh.groups)
-    if (sh.wps == 4) {
-        if (sh.cw >= 4) return LABPSD_SPMV(4, 4);
-        if (sh.cw == 2) return LABPSD_SPMV(2, 4);
-        return LABPSD_SPMV(1, 4);
-    }
-    if (sh.cw >= 4) return LABPSD_SPMV(4, 1);
-    if (sh.cw == 2) return LABPSD_SPMV(2, 1);
-    return LABPSD_SPMV(1, 1);
-#undef LABPSD_SPMV
+    if (sh.cw >= 4)
+        return launch_spmv_s<T, MODE, 4>(A, sh, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial,
+                                         q, s, nl);
+    if (sh.cw == 2)
+        return launch_spmv_s<T, MODE, 2>(A, sh, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial,
+                                         q, s, nl);
+    return launch_spmv_s<T, MODE, 1>(A, sh, hv, sv, X, ldx, xcols, aux, ldaux, auxcols, shift, sc, out, partial, q,
+                                     s, nl);
 }
 
 }  // namespace
 
 size_t minres_ws_elems(int64_t n, int q) {
-    // six vectors, then 3 FP64 partial sums per slice and column (as T elements)
+    // six vectors, then 3 FP64 partial sums per slice and column and the 3 q column sums
+    // (as T elements: 6 (nslices + 1) q of them hold 3 (nslices + 1) q doubles even for float)
     return (size_t)6 * n * q + 3 * (8 / sizeof(float)) * (size_t)((n + 63) / 64 + 1) * q;
 }
 
@@ -448,8 +429,7 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     T* D1 = Wb + n * q;
     T* D2 = D1 + n * q;
     T* Xs = D2 + n * q;
-    // the MINRES products are latency-bound at these sizes: more, narrower chunks
-    const SellShape sh = sell_shape(A.nslices, q, 4, 4096);
+    const SellShape sh = sell_shape(A, q, sizeof(T));
     const unsigned G = rowwise_groups(n);
     // spmv partials: 3 sets of at most nslices per column, FP64 (6 n q T elements precede,
     // an even count, so the address is 8-byte aligned)
@@ -472,27 +452,31 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     const T* sv;
     if constexpr (sizeof(T) == 8) { hv = A.hv.p; sv = A.sv.p; }
     else { hv = A.hv32.p; sv = A.sv32.p; }
-    const dim3 gcol((unsigned)((q + 3) / 4));
     const unsigned bx = (unsigned)std::min<int64_t>((n + 255) / 256, 512);
     const dim3 gel(bx, q);
     const dim3 grow(G, q);
     int64_t nl = 0;
     // b = -((H - eps S) p + r); beta1 = ||b||
-    // spmv partials: one per work-group and column (at most nslices)
+    // spmv partials: one per slice and column
     const int64_t npa = launch_spmv<T, 0>(A, sh, hv, sv, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev, sa, V,
                                           pa, q, s, nlt);
+    // the column sums of the partials (3 q doubles after the 3 nslices q partials)
+    double* csum = pa + 3 * A.nslices * (int64_t)q;
+    const dim3 gsum1((unsigned)((q + 3) / 4)), gsum3((unsigned)((3 * q + 3) / 4)), gq((unsigned)((q + 255) / 256));
+    hipLaunchKernelGGL(k_minres_colsums, gsum1, dim3(256), 0, s, (const double*)pa, npa, q, 1,
+                       (const MinresScal*)nullptr, csum);
     if (onestep) {
-        hipLaunchKernelGGL(k_onestep_init_finish, gcol, dim3(256), 0, s, (const double*)pa, npa, q, rnorm_dev,
+        hipLaunchKernelGGL(k_onestep_init_finish, gq, dim3(256), 0, s, (const double*)csum, q, rnorm_dev,
                            eta, max_inner, sa);
         hipLaunchKernelGGL((k_zero_cols<T>), gel, dim3(256), 0, s, n, Xs);
     } else {
-        hipLaunchKernelGGL(k_minres_init_finish, gcol, dim3(256), 0, s, (const double*)pa, npa, q, rnorm_dev,
+        hipLaunchKernelGGL(k_minres_init_finish, gq, dim3(256), 0, s, (const double*)csum, q, rnorm_dev,
                            eta, max_inner, sa);
         hipLaunchKernelGGL((k_minres_init_vectors<T>), gel, dim3(256), 0, s, n, q, (const MinresScal*)sa, V,
                            VP, D1, D2, Xs);
     }
     LABPSD_HIP(hipGetLastError());
-    nl += 3;
+    nl += 4;
     MinresScal* cur = sa;
     MinresScal* nxt = sb;
     // The host reads the active count every kCheckEvery iterations; iterations issued
@@ -510,19 +494,23 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
         if (onestep) {
             // u = A g (beta is 0 in the one-step state), then the step
             launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, V, n, nullptr, shift_dev, cur, Wb, pa, q, s, nlt);
+            hipLaunchKernelGGL(k_minres_colsums, gsum3, dim3(256), 0, s, (const double*)pa, npa, q, 3,
+                               (const MinresScal*)cur, csum);
             hipLaunchKernelGGL((k_onestep_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
-                               (const MinresScal*)cur, nxt, (const double*)pa, npa, V, (const T*)Wb, Xs,
+                               (const MinresScal*)cur, nxt, (const double*)csum, V, (const T*)Wb, Xs,
                                check ? flag_dev + (size_t)slot * q : nullptr);
             LABPSD_HIP(hipGetLastError());
-            nl += 2;
+            nl += 3;
             MinresScal* t2 = cur; cur = nxt; nxt = t2;
         } else {
         launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s, nlt);
+        hipLaunchKernelGGL(k_minres_colsums, gsum3, dim3(256), 0, s, (const double*)pa, npa, q, 3,
+                           (const MinresScal*)cur, csum);
         hipLaunchKernelGGL((k_minres_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
-                           (const MinresScal*)cur, nxt, (const double*)pa, npa, (const T*)V, Wb,
+                           (const MinresScal*)cur, nxt, (const double*)csum, (const T*)V, Wb,
                            (const T*)D1, D2, Xs, check ? flag_dev + (size_t)slot * q : nullptr);
         LABPSD_HIP(hipGetLastError());
-        nl += 2;
+        nl += 3;
         // rotate: v_prev <- v, v <- w (now scaled), w <- old v_prev; d1 <- new d, d2 <- old d1
         T* t0 = VP; VP = V; V = Wb; Wb = t0;
         T* t1 = D1; D1 = D2; D2 = t1;

@@ -3,115 +3,132 @@
 // forms (H - sigma S) v for any shift).
 //
 // Layout: sliced ELL with 64-row slices (one row per lane), each slice padded to its
-// longest row and stored slot-major, so a wavefront's loads of column indices and
-// values are contiguous.  A slice's slots go to one wavefront, or round-robin to four
-// whose sums meet in LDS when the launch would otherwise have too few wavefronts.  H and S values sit on the same
-// pattern, so one pass over the pattern and one gather of X serve both products.
-// Work-groups map slices XCD-locally: consecutive slices land on the same XCD so the
-// neighbouring rows' gathers of X hit the same L2.
+// longest row and stored slot-major, so the loads of a slot's column indices and values
+// are contiguous.  H and S values sit on the same pattern, so one pass over the pattern
+// and one gather of X serve both products.
+// A work-group of kSellWaves wavefronts owns one slice: it stages the slice's pattern in
+// LDS (once when the slice fits one segment) and its wavefronts walk the band's columns
+// CW at a time, gathering X straight from global memory.  Work-groups map slices
+// XCD-locally: consecutive slices land on the same XCD, so neighbouring rows' gathers of
+// X hit the same L2.
 #include "common.h"
+
+#include <mutex>
+#include <set>
+#include <utility>
 
 namespace labpsd {
 
 namespace {
 
-// One work-group of 256 threads covers 4 / WPS slices; wavefront `wave` serves slice
-// sb * (4 / WPS) + wave / WPS and takes every WPS-th slot of it.  The work-group walks a
-// contiguous band of column chunks (grid.y bands of about 32 columns): after the band's
-// first chunk the slices' column indices and values come from L1/L2, so the pattern is
-// fetched from HBM once per band rather than once per chunk, while the work-groups in
-// flight share one band of X (~32 columns), which stays in the last-level cache for the
-// neighbouring rows' gathers.
-template <int CW, int WPS>
-__global__ __launch_bounds__(256) void k_spmm_hs(const int64_t* __restrict__ off,
-                                                 const int32_t* __restrict__ col,
-                                                 const double* __restrict__ hv,
-                                                 const double* __restrict__ sv, int64_t n,
-                                                 int64_t nslices, const double* __restrict__ X,
-                                                 int64_t ldx, int w, double* __restrict__ YH,
-                                                 double* __restrict__ YS, int64_t ldy,
-                                                 NlEpi<double, double> nl) {
-    constexpr int SPB = 4 / WPS;
-    __shared__ double red[WPS > 1 ? 256 * 2 * CW : 1];
+template <int CW>
+__global__ __launch_bounds__(64 * kSellWaves) void k_spmm_hs(const int64_t* __restrict__ off,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ hv,
+                                                            const double* __restrict__ sv, int64_t n,
+                                                            int64_t nslices, const double* __restrict__ X,
+                                                            int64_t ldx, int w, int cpb, int lseg,
+                                                            double* __restrict__ YH, double* __restrict__ YS,
+                                                            int64_t ldy, NlEpi<double, double> nl) {
+    extern __shared__ double sell_dyn[];
+    const SliceLds<double> L = slice_lds<double>(sell_dyn, lseg);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t nblk = (nslices + SPB - 1) / SPB;
-    const int64_t sb = xcd_block(blockIdx.x, nblk);
-    const int64_t slice = sb * SPB + wave / WPS;
-    const int sw = wave % WPS;
-    const bool valid = slice < nslices;
+    const int64_t slice = xcd_block(blockIdx.x, nslices);
+    const int64_t e0 = off[slice];
+    const int nsl = (int)((off[slice + 1] - e0) / kSlice);
+    const int nseg = (nsl + lseg - 1) / lseg;
     const int64_t row = slice * kSlice + lane;
-    const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
-    const int nch = (w + CW - 1) / CW, cpg = (nch + (int)gridDim.y - 1) / (int)gridDim.y;
-    const int jb = (int)blockIdx.y * cpg * CW, je = min(w, jb + cpg * CW);
-    for (int j0 = jb; j0 < je; j0 += CW) {
-        const int nc = min(CW, w - j0);
+    const int jb = (int)blockIdx.y * cpb, je = min(w, jb + cpb);
+    if (nseg == 1) {
+        sell_stage<double>(col, hv, sv, e0, 0, nsl, L);
+        __syncthreads();
+    }
+    for (int r = jb; r < je; r += kSellWaves * CW) {
+        const int j0 = r + wave * CW;
+        const bool act = j0 < je;
         double ah[CW], as[CW];
-#pragma unroll
-        for (int j = 0; j < CW; ++j) { ah[j] = 0.0; as[j] = 0.0; }
-        const double* Xj = X + (int64_t)j0 * ldx;
         const double* xp[CW];
 #pragma unroll
-        for (int j = 0; j < CW; ++j) xp[j] = Xj + (j < nc ? (int64_t)j * ldx : 0);
-        sell_accumulate<double, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
-        slice_reduce<double, CW, WPS>(ah, as, red);
-        if (valid && sw == 0 && row < n) {
+        for (int j = 0; j < CW; ++j) {
+            ah[j] = 0.0;
+            as[j] = 0.0;
+            xp[j] = X + (int64_t)(j0 + j < je ? j0 + j : jb) * ldx;   // unused columns read a valid one
+        }
+        for (int sg = 0; sg < nseg; ++sg) {
+            const int s0 = sg * lseg, ns = min(lseg, nsl - s0);
+            if (nseg > 1) {   // uniform over the work-group
+                __syncthreads();
+                sell_stage<double>(col, hv, sv, e0, s0, ns, L);
+                __syncthreads();
+            }
+            if (act) sell_lds_accumulate<double, CW>(L, ns, xp, ah, as);
+        }
+        if (act && row < n) {
 #pragma unroll
             for (int j = 0; j < CW; ++j) {
-                if (j < nc) {
+                if (j0 + j < je) {
                     const double yh = nl.rp ? ah[j] + nl_row_term(nl, row, j0 + j) : ah[j];
                     YH[row + (int64_t)(j0 + j) * ldy] = yh;
                     YS[row + (int64_t)(j0 + j) * ldy] = as[j];
                 }
             }
         }
-        if constexpr (WPS > 1) __syncthreads();   // red is rewritten by the next chunk
     }
 }
 
 // Y[:, j] = H X[:, j] - shift[j] S X[:, j]
-template <typename T, int CW, int WPS>
-__global__ __launch_bounds__(256) void k_spmm_shift(const int64_t* __restrict__ off,
-                                                    const int32_t* __restrict__ col,
-                                                    const T* __restrict__ hv,
-                                                    const T* __restrict__ sv, int64_t n,
-                                                    int64_t nslices, const T* __restrict__ X,
-                                                    int64_t ldx, int w,
-                                                    const double* __restrict__ shift,
-                                                    T* __restrict__ Y, int64_t ldy, NlEpi<T, T> nl) {
-    constexpr int SPB = 4 / WPS;
-    __shared__ T red[WPS > 1 ? 256 * 2 * CW : 1];
+template <typename T, int CW>
+__global__ __launch_bounds__(64 * kSellWaves) void k_spmm_shift(const int64_t* __restrict__ off,
+                                                               const int32_t* __restrict__ col,
+                                                               const T* __restrict__ hv,
+                                                               const T* __restrict__ sv, int64_t n,
+                                                               int64_t nslices, const T* __restrict__ X,
+                                                               int64_t ldx, int w, int cpb, int lseg,
+                                                               const double* __restrict__ shift,
+                                                               T* __restrict__ Y, int64_t ldy, NlEpi<T, T> nl) {
+    extern __shared__ double sell_dyn[];
+    const SliceLds<T> L = slice_lds<T>(sell_dyn, lseg);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t nblk = (nslices + SPB - 1) / SPB;
-    const int64_t sb = xcd_block(blockIdx.x, nblk);
-    const int64_t slice = sb * SPB + wave / WPS;
-    const int sw = wave % WPS;
-    const bool valid = slice < nslices;
+    const int64_t slice = xcd_block(blockIdx.x, nslices);
+    const int64_t e0 = off[slice];
+    const int nsl = (int)((off[slice + 1] - e0) / kSlice);
+    const int nseg = (nsl + lseg - 1) / lseg;
     const int64_t row = slice * kSlice + lane;
-    const int64_t e0 = valid ? off[slice] : 0, e1 = valid ? off[slice + 1] : 0;
-    const int nch = (w + CW - 1) / CW, cpg = (nch + (int)gridDim.y - 1) / (int)gridDim.y;
-    const int jb = (int)blockIdx.y * cpg * CW, je = min(w, jb + cpg * CW);
-    for (int j0 = jb; j0 < je; j0 += CW) {
-        const int nc = min(CW, w - j0);
+    const int jb = (int)blockIdx.y * cpb, je = min(w, jb + cpb);
+    if (nseg == 1) {
+        sell_stage<T>(col, hv, sv, e0, 0, nsl, L);
+        __syncthreads();
+    }
+    for (int r = jb; r < je; r += kSellWaves * CW) {
+        const int j0 = r + wave * CW;
+        const bool act = j0 < je;
         T ah[CW], as[CW];
-#pragma unroll
-        for (int j = 0; j < CW; ++j) { ah[j] = T(0); as[j] = T(0); }
-        const T* Xj = X + (int64_t)j0 * ldx;
         const T* xp[CW];
 #pragma unroll
-        for (int j = 0; j < CW; ++j) xp[j] = Xj + (j < nc ? (int64_t)j * ldx : 0);
-        sell_accumulate<T, CW>(col, hv, sv, e0 + sw * kSlice + lane, e1, (int64_t)kSlice * WPS, xp, ah, as);
-        slice_reduce<T, CW, WPS>(ah, as, red);
-        if (valid && sw == 0 && row < n) {
+        for (int j = 0; j < CW; ++j) {
+            ah[j] = T(0);
+            as[j] = T(0);
+            xp[j] = X + (int64_t)(j0 + j < je ? j0 + j : jb) * ldx;
+        }
+        for (int sg = 0; sg < nseg; ++sg) {
+            const int s0 = sg * lseg, ns = min(lseg, nsl - s0);
+            if (nseg > 1) {
+                __syncthreads();
+                sell_stage<T>(col, hv, sv, e0, s0, ns, L);
+                __syncthreads();
+            }
+            if (act) sell_lds_accumulate<T, CW>(L, ns, xp, ah, as);
+        }
+        if (act && row < n) {
 #pragma unroll
             for (int j = 0; j < CW; ++j) {
-                if (j < nc) {
+                if (j0 + j < je) {
                     const T sh = (T)shift[j0 + j];
                     const T h = nl.rp ? ah[j] + nl_row_term(nl, row, j0 + j) : ah[j];
                     Y[row + (int64_t)(j0 + j) * ldy] = h - sh * as[j];
                 }
             }
         }
-        if constexpr (WPS > 1) __syncthreads();
     }
 }
 
@@ -129,6 +146,9 @@ void build_sell(Sell& S, const HostCSR& A, const double* hv, const double* sv, h
         S.h_slice_off[sl + 1] = S.h_slice_off[sl] + mx * kSlice;
     }
     S.stored = S.h_slice_off[S.nslices];
+    S.max_slots = 0;
+    for (int64_t sl = 0; sl < S.nslices; ++sl)
+        S.max_slots = std::max<int>(S.max_slots, (int)((S.h_slice_off[sl + 1] - S.h_slice_off[sl]) / kSlice));
     std::vector<int32_t> col(S.stored);
     std::vector<double> h(S.stored, 0.0), sv_(S.stored, 0.0);
     std::vector<float> h32(S.stored, 0.0f), s32(S.stored, 0.0f);
@@ -177,49 +197,41 @@ void refresh_sell_h(Sell& S, const double* hv, hipStream_t s) {
     LABPSD_HIP(hipStreamSynchronize(s));
 }
 
-// Launch shape: the widest column chunk (fewest passes over the pattern) that, with one
-// or four wavefronts per slice, gives want_waves wavefronts; bands of about 32 columns
-// (grid.y = their number, more if the wavefront target needs it); when even one chunk
-// per band falls short, the shape with the most wavefronts.
-SellShape sell_shape(int64_t nslices, int w, int max_cw, int64_t want_waves) {
-    constexpr int kBandCols = 32;
-    SellShape best{1, 4, 1};
-    int64_t best_waves = -1;
-    for (int cw : {8, 4, 2, 1}) {
-        if (cw > max_cw) continue;
-        const int64_t nch = (w + cw - 1) / cw;
-        for (int wps : {1, 4}) {
-            const int64_t per_group = nslices * wps;
-            if (per_group * nch >= want_waves) {
-                const int64_t band = std::max(1, kBandCols / cw);
-                const int64_t g = std::max<int64_t>((nch + band - 1) / band,
-                                                    (want_waves + per_group - 1) / per_group);
-                return SellShape{cw, wps, (int)std::max<int64_t>(1, std::min<int64_t>(nch, g))};
-            }
-            if (per_group * nch > best_waves) {
-                best_waves = per_group * nch;
-                best = SellShape{cw, wps, (int)std::max<int64_t>(1, nch)};
-            }
-        }
-    }
-    return best;
+// Launch shape: 4 columns per wavefront from 32 columns up (2 from 16, else 1), bands of
+// about 96 columns (at least one round of kSellWaves * CW each), and LDS segments of as
+// many slots as kSellLdsBytes holds (the longest slice's count when it fits).
+SellShape sell_shape(const Sell& A, int w, size_t value_bytes) {
+    SellShape sh{};
+    sh.cw = w >= 32 ? 4 : (w >= 16 ? 2 : 1);
+    const int per_round = kSellWaves * sh.cw;
+    sh.bands = std::max(1, (w + 63) / 96);
+    sh.bands = std::max(1, std::min(sh.bands, (w + per_round - 1) / per_round));
+    const size_t slot_bytes = (size_t)kSlice * (2 * value_bytes + sizeof(int32_t));
+    sh.lseg = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(1, A.max_slots), kSellLdsBytes / slot_bytes));
+    sh.lds_bytes = (size_t)sh.lseg * slot_bytes;
+    return sh;
 }
 
-template <int CW, int WPS>
-static void spmm_hs_cw(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
-                       int64_t ldy, hipStream_t s, NlEpi<double, double> nl, int groups) {
-    constexpr int SPB = 4 / WPS;
-    dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)groups);
-    hipLaunchKernelGGL((k_spmm_hs<CW, WPS>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, A.hv.p,
-                       A.sv.p, A.n, A.nslices, X, ldx, w, YH, YS, ldy, nl);
-    LABPSD_HIP(hipGetLastError());
+void allow_sell_lds(const void* kernel) {
+    static std::mutex mu;
+    static std::set<std::pair<const void*, int>> done;
+    int dev = 0;
+    LABPSD_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({kernel, dev})) return;
+    LABPSD_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSellLdsBytes));
+    done.insert({kernel, dev});
 }
 
 template <int CW>
-static void spmm_hs_w(const Sell& A, SellShape sh, const double* X, int64_t ldx, int w, double* YH,
-                      double* YS, int64_t ldy, hipStream_t s, NlEpi<double, double> nl) {
-    if (sh.wps == 4) spmm_hs_cw<CW, 4>(A, X, ldx, w, YH, YS, ldy, s, nl, sh.groups);
-    else spmm_hs_cw<CW, 1>(A, X, ldx, w, YH, YS, ldy, s, nl, sh.groups);
+static void spmm_hs_cw(const Sell& A, SellShape sh, const double* X, int64_t ldx, int w, double* YH,
+                       double* YS, int64_t ldy, hipStream_t s, NlEpi<double, double> nl) {
+    allow_sell_lds((const void*)k_spmm_hs<CW>);
+    const int cpb = (w + sh.bands - 1) / sh.bands;
+    const dim3 grid((unsigned)A.nslices, (unsigned)sh.bands);
+    hipLaunchKernelGGL((k_spmm_hs<CW>), grid, dim3(64 * kSellWaves), sh.lds_bytes, s, A.slice_off.p, A.col.p,
+                       A.hv.p, A.sv.p, A.n, A.nslices, X, ldx, w, cpb, sh.lseg, YH, YS, ldy, nl);
+    LABPSD_HIP(hipGetLastError());
 }
 
 void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* YH, double* YS,
@@ -227,20 +239,17 @@ void launch_spmm_hs(const Sell& A, const double* X, int64_t ldx, int w, double* 
     if (w <= 0 || A.n == 0) return;
     const NlEpi<double, double> nl =
         nlp ? nl_prepare<double>(*nlp, X, ldx, nullptr, w, s) : NlEpi<double, double>{};
-    const SellShape sh = sell_shape(A.nslices, w, 8, 2048);
+    const SellShape sh = sell_shape(A, w, sizeof(double));
     switch (sh.cw) {
-        case 8: spmm_hs_w<8>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
-        case 4: spmm_hs_w<4>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
-        case 2: spmm_hs_w<2>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
-        default: spmm_hs_w<1>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
+        case 4: spmm_hs_cw<4>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
+        case 2: spmm_hs_cw<2>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
+        default: spmm_hs_cw<1>(A, sh, X, ldx, w, YH, YS, ldy, s, nl); break;
     }
 }
 
-template <typename T, int CW, int WPS>
-static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const double* shift, T* Y,
-                          int64_t ldy, hipStream_t s, NlEpi<T, T> nl, int groups) {
-    constexpr int SPB = 4 / WPS;
-    dim3 grid((unsigned)((A.nslices + SPB - 1) / SPB), (unsigned)groups);
+template <typename T, int CW>
+static void spmm_shift_cw(const Sell& A, SellShape sh, const T* X, int64_t ldx, int w, const double* shift,
+                          T* Y, int64_t ldy, hipStream_t s, NlEpi<T, T> nl) {
     const T* hv;
     const T* sv;
     if constexpr (sizeof(T) == 8) {
@@ -250,16 +259,12 @@ static void spmm_shift_cw(const Sell& A, const T* X, int64_t ldx, int w, const d
         hv = A.hv32.p;
         sv = A.sv32.p;
     }
-    hipLaunchKernelGGL((k_spmm_shift<T, CW, WPS>), grid, dim3(256), 0, s, A.slice_off.p, A.col.p, hv, sv,
-                       A.n, A.nslices, X, ldx, w, shift, Y, ldy, nl);
+    allow_sell_lds((const void*)k_spmm_shift<T, CW>);
+    const int cpb = (w + sh.bands - 1) / sh.bands;
+    const dim3 grid((unsigned)A.nslices, (unsigned)sh.bands);
+    hipLaunchKernelGGL((k_spmm_shift<T, CW>), grid, dim3(64 * kSellWaves), sh.lds_bytes, s, A.slice_off.p,
+                       A.col.p, hv, sv, A.n, A.nslices, X, ldx, w, cpb, sh.lseg, shift, Y, ldy, nl);
     LABPSD_HIP(hipGetLastError());
-}
-
-template <typename T, int CW>
-static void spmm_shift_w(const Sell& A, SellShape sh, const T* X, int64_t ldx, int w, const double* shift,
-                         T* Y, int64_t ldy, hipStream_t s, NlEpi<T, T> nl) {
-    if (sh.wps == 4) spmm_shift_cw<T, CW, 4>(A, X, ldx, w, shift, Y, ldy, s, nl, sh.groups);
-    else spmm_shift_cw<T, CW, 1>(A, X, ldx, w, shift, Y, ldy, s, nl, sh.groups);
 }
 
 template <typename T>
@@ -267,12 +272,11 @@ void launch_spmm_shift(const Sell& A, const T* X, int64_t ldx, int w, const doub
                        int64_t ldy, hipStream_t s, const NonLocal* nlp) {
     if (w <= 0 || A.n == 0) return;
     const NlEpi<T, T> nl = nlp ? nl_prepare<T>(*nlp, X, ldx, nullptr, w, s) : NlEpi<T, T>{};
-    const SellShape sh = sell_shape(A.nslices, w, 8, 2048);
+    const SellShape sh = sell_shape(A, w, sizeof(T));
     switch (sh.cw) {
-        case 8: spmm_shift_w<T, 8>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
-        case 4: spmm_shift_w<T, 4>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
-        case 2: spmm_shift_w<T, 2>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
-        default: spmm_shift_w<T, 1>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
+        case 4: spmm_shift_cw<T, 4>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
+        case 2: spmm_shift_cw<T, 2>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
+        default: spmm_shift_cw<T, 1>(A, sh, X, ldx, w, shift, Y, ldy, s, nl); break;
     }
 }
 
