@@ -226,6 +226,7 @@ def serving(args, ctx=None):
         time.sleep(0.0005)
     makespan = time.perf_counter() - start
     torch.cuda.synchronize()
+    mem = srv.memory()
     srv.close()
     for pr in systems:
         pr.close()
@@ -235,6 +236,8 @@ def serving(args, ctx=None):
     pairs = sum(pencils[i][1] for i, _, _ in done)
     return {"value": pairs / makespan, "unit": "eigenpairs/s", "requests": len(done),
             "makespan_s": makespan, "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+            "memory_bytes": {"budget": int(args.budget_gb * 2 ** 30), "held_at_end": mem["held"],
+                             "peak": mem["peak"]},
             "workload": "%d systems x %d SCF-like steps, meshes 12-32^3 at h=0.5, 1-16 atoms, nev 8-64, "
                         "Poisson arrivals %.1f/s, mixed precision, %d slots"
                         % (args.systems, args.chain, args.rate, args.slots),

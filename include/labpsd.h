@@ -341,8 +341,15 @@ labpsd_status labpsd_block_update(labpsd_ctx* ctx, int64_t n, int k, int b, cons
  * thread-safe.                                                                     */
 typedef struct labpsd_server labpsd_server;
 
-/* hbm_budget_bytes bounds the sum of the footprints (labpsd_solve_footprint) of the
- * requests in flight; max_slots (1..64) bounds how many run at once.              */
+/* hbm_budget_bytes bounds the device memory the server holds beyond the systems'
+ * own storage (H, S, their sliced-ELL layout and factor): every slot keeps its solve
+ * workspace between requests, grown to the largest request it ran, and every system
+ * it served keeps its last block for the next warm start (charged from its first
+ * request on).  A request starts when a slot is free, its system idle and the held
+ * bytes plus its growth stay within the budget; idle slots give their workspace back
+ * when a request would not fit otherwise.  A request that cannot fit even then, with
+ * every slot idle, finishes with ENOMEM.  max_slots (1..64) bounds how many requests
+ * run at once.                                                                      */
 labpsd_status labpsd_server_create(labpsd_ctx* ctx, size_t hbm_budget_bytes, int max_slots,
                                    labpsd_server** out);
 /* Queue one GHEP.  system: a problem with its global preconditioner set (it must
@@ -362,8 +369,12 @@ labpsd_status labpsd_server_poll(labpsd_server* s, uint64_t req_id, double* lamb
 /* As labpsd_server_poll, but blocks until the request has finished.               */
 labpsd_status labpsd_server_wait(labpsd_server* s, uint64_t req_id, double* lambda, double* X,
                                  labpsd_stats* stats, double* times);
-/* Device bytes one request of this shape reserves while it runs.                  */
+/* Device bytes one request of this shape needs: its solve workspace plus the
+ * resident block it leaves (n x (nev+m0) doubles).                                 */
 size_t labpsd_solve_footprint(int64_t n, int nev, int m0, int precision);
+/* The device bytes the server holds now (slot workspaces and resident blocks, as
+ * charged against the budget) and the most it has held; either may be NULL.         */
+labpsd_status labpsd_server_memory(labpsd_server* s, size_t* held, size_t* peak);
 /* Stops admitting, waits for running requests, frees the slots.                   */
 void labpsd_server_destroy(labpsd_server* s);
 

@@ -122,6 +122,7 @@ _SIGS = {
     "labpsd_server_poll": ([_p, ctypes.c_uint64, _p, _p, ctypes.POINTER(Stats), _p], _i32),
     "labpsd_server_wait": ([_p, ctypes.c_uint64, _p, _p, ctypes.POINTER(Stats), _p], _i32),
     "labpsd_solve_footprint": ([_i64, _i32, _i32, _i32], ctypes.c_size_t),
+    "labpsd_server_memory": ([_p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], _i32),
     "labpsd_server_destroy": ([_p], None),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -529,6 +530,13 @@ class Server:
 
     def wait(self, rid: int) -> Served:
         return self._collect(rid, True)
+
+    def memory(self) -> dict:
+        """Device bytes the server holds now and at most so far (slot workspaces and
+        resident blocks, as charged against the budget)."""
+        held, peak = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.labpsd_server_memory(self.h, ctypes.byref(held), ctypes.byref(peak)), "labpsd_server_memory")
+        return {"held": held.value, "peak": peak.value}
 
     def close(self):
         if getattr(self, "h", None):

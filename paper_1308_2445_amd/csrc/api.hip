@@ -266,20 +266,18 @@ struct SolveBuffers {
 
 }  // namespace
 
-// Reserve the solve workspace inside the problem and carve it up.
+// Reserve the solve workspace inside the problem and carve it up (sizes from
+// solve_arena_elems).
 template <typename T>
 static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T>& W) {
     const int kmax = b + m;
     const int nblk = residual_blocks(n);
-    // the Gram partial layout depends on k; reserve the largest over every k <= kmax
     size_t gws = 0;
     for (int k = 1; k <= kmax; ++k) gws = std::max(gws, gram_ws_doubles(n, k, P.ctx->cu_count));
     const size_t rrb = (rr_ws_bytes(kmax) + 7) / 8;
-    size_t need = 6 * (size_t)n * kmax + (size_t)n * m + 2 * (size_t)kmax * kmax +
-                  (size_t)kmax * b + (size_t)b + 2 * (size_t)m +
-                  std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m) + gws + 2 * (size_t)m +
-                  (2 * (size_t)m + 4) + minres_scal_doubles(m) + 4 + rrb + 64;
-    P.ws64.alloc(need);
+    const ArenaElems need =
+        solve_arena_elems(n, m, b - m, sizeof(T) == 8 ? LABPSD_FP64 : LABPSD_MIXED, P.ctx->cu_count);
+    P.ws64.alloc(need.ws64);
     double* p = P.ws64.p;
     for (int a = 0; a < 2; ++a)
         for (int c = 0; c < 3; ++c) { B.Zb[a][c] = p; p += (size_t)n * kmax; }
@@ -309,15 +307,13 @@ static void carve(Problem& P, int64_t n, int b, int m, SolveBuffers& B, PrecWS<T
     B.scal = p; p += minres_scal_doubles(m) + 4;
     B.rr_ws = (void*)p; p += rrb;
     // T-precision blocks
-    const size_t mw = minres_ws_elems(n, m);
-    const size_t needT = 4 * (size_t)n * m + mw;
     T* t;
     if constexpr (sizeof(T) == 8) {
         // FP64 mode: the preconditioner blocks live in a second FP64 arena
-        P.red.alloc(needT);
+        P.red.alloc(need.red);
         t = P.red.p;
     } else {
-        P.ws32.alloc(needT);
+        P.ws32.alloc(need.ws32);
         t = P.ws32.p;
     }
     W.Y = t; t += (size_t)n * m;
@@ -662,19 +658,31 @@ labpsd_status run_solve(Problem& P, const labpsd_solve_params& prm, const double
                               stats, stream);
 }
 
-size_t solve_footprint_bytes(int64_t n, int nev, int m0, int precision, int cu_count) {
+ArenaElems solve_arena_elems(int64_t n, int nev, int m0, int precision, int cu_count) {
     const int b = nev + m0, m = nev, kmax = b + m;
     const int nblk = residual_blocks(n);
+    // the Gram partial layout depends on k; reserve the largest over every k <= kmax
     size_t gws = 0;
     for (int k = 1; k <= kmax; ++k) gws = std::max(gws, gram_ws_doubles(n, k, cu_count));
     const size_t rrb = (rr_ws_bytes(kmax) + 7) / 8;
-    const size_t f64 = 6 * (size_t)n * kmax + (size_t)n * m + 2 * (size_t)kmax * kmax +
-                       (size_t)kmax * b + (size_t)b + 2 * (size_t)m +
-                       std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m) + gws +
-                       2 * (size_t)m + minres_scal_doubles(m) + 4 + rrb + 64;
-    const size_t tel = 4 * (size_t)n * m + minres_ws_elems(n, m);
-    const size_t tb = precision == LABPSD_MIXED ? 4 : 8;
-    return f64 * 8 + tel * tb + (size_t)n * b * 8 /* resident block */ + (4 * (size_t)m + 8) * 4;
+    ArenaElems a;
+    // carve(): the six search-space blocks, R, H_R and S_R, W, the read-back and upload
+    // blocks, the residual partials, the Gram partials, the MINRES scalars, the
+    // Rayleigh-Ritz workspace
+    a.ws64 = 6 * (size_t)n * kmax + (size_t)n * m + 2 * (size_t)kmax * kmax + (size_t)kmax * b + (size_t)b +
+             2 * (size_t)m + std::max<size_t>((size_t)nblk * m * 2, (size_t)nblk * m) + gws + 2 * (size_t)m +
+             (2 * (size_t)m + 4) + minres_scal_doubles(m) + 4 + rrb + 64;
+    // the preconditioner blocks Y, W1, W2, R^T and the MINRES workspace, in the solve's
+    // refinement precision
+    const size_t t = 4 * (size_t)n * m + minres_ws_elems(n, m);
+    if (precision == LABPSD_MIXED) a.ws32 = t;
+    else a.red = t;
+    return a;
+}
+
+size_t solve_footprint_bytes(int64_t n, int nev, int m0, int precision, int cu_count) {
+    return solve_arena_elems(n, nev, m0, precision, cu_count).bytes() +
+           (size_t)n * (nev + m0) * 8 /* resident block */;
 }
 
 labpsd_status abi_guard(const std::function<labpsd_status()>& f) { return guarded(f); }

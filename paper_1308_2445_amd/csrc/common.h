@@ -7,10 +7,12 @@
 #include <cstdint>
 #include <functional>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/labpsd.h"
 #include "factor.h"
+#include "serve_policy.h"
 
 namespace labpsd {
 
@@ -62,6 +64,10 @@ struct DBuf {
                                            " bytes failed: " + hipGetErrorString(e)};
         }
         n = count;
+    }
+    void swap(DBuf& o) noexcept {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
     }
     void upload(const T* h, size_t count, hipStream_t s) {
         alloc(count);
@@ -472,7 +478,9 @@ labpsd_status run_solve(Problem& P, const labpsd_solve_params& prm, const double
                         const double* E0, labpsd_mem in_where, double* lambda, double* X,
                         double* res_hist, double* ritz_hist, int* n_hist, labpsd_mem out_where, labpsd_stats* stats,
                         hipStream_t stream);
-// Device bytes one solve reserves beyond the resident problem.
+// The solve arenas of one solve (carve() cuts them up) and the device bytes one solve
+// reserves beyond the resident problem (the arenas plus the resident block it leaves).
+ArenaElems solve_arena_elems(int64_t n, int nev, int m0, int precision, int cu_count);
 size_t solve_footprint_bytes(int64_t n, int nev, int m0, int precision, int cu_count);
 
 // ------------------------------------------------------------------ kernel launchers

@@ -9,6 +9,9 @@
 // as soon as a slot is free and its device footprint fits under the budget next to the
 // requests already in flight; requests of one system keep submission order and run one
 // at a time (the next warm start needs the previous result).
+// Device memory: each slot owns its solve arenas (lent to the system for the duration of
+// a request), so the server's memory is bounded by the ledger of serve_policy.h: slot
+// arenas and the resident blocks of the systems it served, within the budget.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -37,7 +40,7 @@ struct Request {
     std::vector<double> h_val;      // empty: keep H
     std::vector<double> X0;         // empty: warm start
     labpsd_solve_params prm{};
-    size_t footprint = 0;
+    AdmitItem item;                 // what the admission policy charges
     double t_submit = 0, t_start = 0, t_done = 0;
     bool done = false;
     labpsd_status status = LABPSD_PENDING;
@@ -57,30 +60,74 @@ struct Server {
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> pending;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> table;
-    std::unordered_set<Problem*> busy;
-    size_t in_use = 0;
+    std::unique_ptr<Admission> adm;   // the memory ledger and the slots' states
     bool stop = false;
     uint64_t next_id = 1;
     std::vector<std::thread> workers;
+    // per slot: its solve arenas
+    struct Slot {
+        DBuf<double> ws64, red;
+        DBuf<float> ws32;
+        ArenaElems have() const {
+            ArenaElems a;
+            a.ws64 = ws64.n;
+            a.red = red.n;
+            a.ws32 = ws32.n;
+            return a;
+        }
+    };
+    std::vector<std::unique_ptr<Slot>> slot;
 
-    // first queued request that can start now: its system idle, its footprint fits
-    std::shared_ptr<Request> take_admissible() {
-        std::unordered_set<Problem*> seen;
-        for (auto it = pending.begin(); it != pending.end(); ++it) {
-            Request& r = **it;
-            if (seen.count(r.sys)) continue;   // keep each system's order
-            seen.insert(r.sys);
-            if (busy.count(r.sys)) continue;
-            if (in_use + r.footprint > budget) continue;
-            auto out = *it;
-            pending.erase(it);
+    // The next queued request slot k starts now (mu held), or one that can never fit
+    // (*reject set; the caller fails it), or nullptr.  Books the admission.
+    std::shared_ptr<Request> take_admissible(int k, bool* reject) {
+        *reject = false;
+        std::vector<AdmitItem> items;
+        items.reserve(pending.size());
+        for (auto& r : pending) {
+            // a resident block left by earlier solves outside the server counts at its size
+            items.push_back(r->item);
+            items.back().block_bytes = std::max(items.back().block_bytes, r->sys->resident_X.n * sizeof(double));
+        }
+        const Pick pk = adm->pick(items, k);
+        if (pk.index < 0) return nullptr;
+        auto it = pending.begin() + pk.index;
+        auto out = *it;
+        pending.erase(it);
+        if (pk.reject) {
+            *reject = true;
             return out;
         }
-        return nullptr;
+        if (pk.trim) {
+            // the idle slots' arenas are not in use (their last request finished and
+            // synchronised its stream); give them back
+            adm->trim_idle();
+            for (int i = 0; i < (int)slot.size(); ++i)
+                if (!adm->running(i)) {
+                    slot[i]->ws64.release();
+                    slot[i]->red.release();
+                    slot[i]->ws32.release();
+                }
+        }
+        out->item = items[pk.index];
+        adm->start(out->item, pk, k);
+        return out;
     }
 
-    void run_one(Request& r, hipStream_t stream) {
+    void run_one(Request& r, Slot& sl, hipStream_t stream) {
         Problem& P = *r.sys;
+        // lend the slot's arenas to the system for this solve (its own come back after)
+        struct Lend {
+            Problem& P;
+            Slot& sl;
+            Lend(Problem& p, Slot& s) : P(p), sl(s) { swap(); }
+            ~Lend() { swap(); }
+            void swap() {
+                P.ws64.swap(sl.ws64);
+                P.red.swap(sl.red);
+                P.ws32.swap(sl.ws32);
+            }
+        } lend(P, sl);
         const int64_t n = P.n;
         const int nev = r.prm.nev, b = r.prm.nev + r.prm.m0;
         if (!r.h_val.empty()) {
@@ -101,19 +148,13 @@ struct Server {
         }
         r.lambda.assign(nev, 0.0);
         r.X.assign((size_t)n * nev, 0.0);
-        // the warm-start block is read before the solve overwrites the resident copy
-        DBuf<double> start;
-        if (where == LABPSD_MEM_DEVICE) {
-            start.alloc((size_t)n * b);
-            LABPSD_HIP(hipMemcpyAsync(start.p, X0, (size_t)n * b * sizeof(double),
-                                      hipMemcpyDeviceToDevice, stream));
-            X0 = start.p;
-        }
+        // a warm start reads the resident block in place: the solve copies it into its
+        // arena first and overwrites the resident block last, both on this stream
         r.status = run_solve(P, r.prm, X0, E0.empty() ? nullptr : E0.data(), where, r.lambda.data(),
                              r.X.data(), nullptr, nullptr, nullptr, LABPSD_MEM_HOST, &r.stats, stream);
     }
 
-    void worker() {
+    void worker(int k) {
         hipStream_t stream = nullptr;
         if (hipSetDevice(ctx->device) != hipSuccess ||
             hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
@@ -122,19 +163,28 @@ struct Server {
             std::shared_ptr<Request> r;
             {
                 std::unique_lock<std::mutex> lk(mu);
+                bool reject = false;
                 cv_work.wait(lk, [&] {
                     if (stop) return true;
-                    r = take_admissible();
+                    r = take_admissible(k, &reject);
                     return r != nullptr;
                 });
                 if (!r) break;   // stopping
-                busy.insert(r->sys);
-                in_use += r->footprint;
+                if (reject) {
+                    r->status = LABPSD_ENOMEM;
+                    r->error = "request cannot fit in the server budget next to the resident blocks of the "
+                               "systems already served";
+                    r->t_start = r->t_done = now_s() - t0;
+                    r->done = true;
+                    lk.unlock();
+                    cv_done.notify_all();
+                    continue;
+                }
                 r->t_start = now_s() - t0;
             }
             labpsd_status st = abi_guard([&]() -> labpsd_status {
                 if (!stream) throw Error{LABPSD_EHIP, "slot stream could not be created"};
-                run_one(*r, stream);
+                run_one(*r, *slot[k], stream);
                 return r->status;
             });
             {
@@ -143,8 +193,7 @@ struct Server {
                 if (st < 0) r->error = get_error();
                 r->t_done = now_s() - t0;
                 r->done = true;
-                busy.erase(r->sys);
-                in_use -= r->footprint;
+                adm->settle(r->item, k, slot[k]->have(), r->sys->resident_X.n * sizeof(double));
             }
             cv_done.notify_all();
             cv_work.notify_all();
@@ -194,9 +243,11 @@ labpsd_status labpsd_server_create(labpsd_ctx* ctx, size_t hbm_budget_bytes, int
         auto s = std::make_unique<labpsd_server>();
         s->ctx = ctx;
         s->budget = hbm_budget_bytes;
+        s->adm = std::make_unique<Admission>(hbm_budget_bytes, max_slots);
         s->slots = max_slots;
         s->t0 = now_s();
-        for (int i = 0; i < max_slots; ++i) s->workers.emplace_back([p = s.get()] { p->worker(); });
+        for (int i = 0; i < max_slots; ++i) s->slot.push_back(std::make_unique<Server::Slot>());
+        for (int i = 0; i < max_slots; ++i) s->workers.emplace_back([p = s.get(), i] { p->worker(i); });
         *out = s.release();
         return LABPSD_OK;
     });
@@ -217,9 +268,11 @@ labpsd_status labpsd_server_submit(labpsd_server* s, labpsd_problem* system, con
         auto r = std::make_shared<Request>();
         r->sys = system;
         r->prm = *prm;
-        r->footprint = solve_footprint_bytes(system->n, prm->nev, prm->m0, prm->precision,
-                                             s->ctx->cu_count);
-        if (r->footprint > s->budget) throw Error{LABPSD_ENOMEM, "request footprint exceeds the server budget"};
+        r->item.sys = system;
+        r->item.need = solve_arena_elems(system->n, prm->nev, prm->m0, prm->precision, s->ctx->cu_count);
+        r->item.block_bytes = (size_t)system->n * (prm->nev + prm->m0) * sizeof(double);
+        if (standalone_cost(r->item) > s->budget)
+            throw Error{LABPSD_ENOMEM, "request footprint exceeds the server budget"};
         if (h_val) r->h_val.assign(h_val, h_val + system->nnz);
         if (X0) r->X0.assign(X0, X0 + (size_t)system->n * (prm->nev + prm->m0));
         {
@@ -254,6 +307,16 @@ labpsd_status labpsd_server_wait(labpsd_server* s, uint64_t req_id, double* lamb
 
 size_t labpsd_solve_footprint(int64_t n, int nev, int m0, int precision) {
     return solve_footprint_bytes(n, nev, m0, precision, 256);
+}
+
+labpsd_status labpsd_server_memory(labpsd_server* s, size_t* held, size_t* peak) {
+    return abi_guard([&]() -> labpsd_status {
+        LABPSD_REQUIRE(s != nullptr, "NULL server");
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (held) *held = s->adm->held();
+        if (peak) *peak = s->adm->peak();
+        return LABPSD_OK;
+    });
 }
 
 void labpsd_server_destroy(labpsd_server* s) {

@@ -95,21 +95,76 @@ def test_alone_equals_mix(pencils, precision):
     assert any(iv[i + 1][0] < iv[i][1] for i in range(len(iv) - 1))
 
 
-def test_admission_respects_budget(pencils):
+def test_server_memory_within_budget(pencils):
+    """Seven systems, three slots, two SCF-like steps each, a budget of 1.5 of the largest
+    request's footprint.  The server's ledger (slot workspaces kept between requests and
+    the systems' resident blocks) never exceeds the budget, and the device memory the
+    stream took (hipMemGetInfo before the server and after the stream) stays within the
+    budget up to allocation rounding."""
+    import torch
     lp = _lp()
     ctx = lp.Context(0)
     fps = [lp.solve_footprint(P.n, nev, pufe.guard_vectors(nev), lp.MIXED) for P, nev in pencils]
-    budget = int(max(fps) * 1.5)        # at most one big request at a time, sometimes two
-    r1, r2 = _run(ctx, pencils, 4, budget, 1)
-    rs = r1 + r2
-    fp = fps + fps
-    events = sorted([(r.started, f) for r, f in zip(rs, fp)] + [(r.finished, -f) for r, f in zip(rs, fp)],
-                    key=lambda e: (e[0], e[1]))
-    cur = 0
-    for _, d in events:
-        cur += d
-        assert cur <= budget
+    budget = int(max(fps) * 1.5)
+    systems = _systems(ctx, pencils)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    srv = lp.Server(ctx, budget, 3)
+    first, second = [], []
+    for (P, nev), pr in zip(pencils, systems):
+        m0 = pufe.guard_vectors(nev)
+        first.append(srv.submit(pr, nev, m0, X0=pufe.start_block(P.n, nev + m0, 7), tol=1e-9,
+                                sigma0=P.sigma0, precision=lp.MIXED))
+    for (P, nev), pr in zip(pencils, systems):
+        m0 = pufe.guard_vectors(nev)
+        second.append(srv.submit(pr, nev, m0, h_val=P.h_scaled(1.01), tol=1e-9, sigma0=P.sigma0,
+                                 precision=lp.MIXED))
+    rs = [srv.wait(r) for r in first + second]
+    mem = srv.memory()
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    # device allocations round up to 2 MiB pages: the slots' three arenas, the resident
+    # blocks and the factors' sweep counters
+    slack = 2 * 1024 * 1024 * (3 * 3 + 2 * len(systems))
+    print("[serve] budget %.1f MB, ledger held %.1f MB peak %.1f MB, device memory taken %.1f MB"
+          % (budget / 1e6, mem["held"] / 1e6, mem["peak"] / 1e6, used / 1e6), flush=True)
     assert all(r.converged for r in rs)
+    assert mem["peak"] <= budget
+    assert used <= budget + slack
+    # the resident blocks are all charged and stay charged
+    assert mem["held"] >= sum(P.n * (nev + pufe.guard_vectors(nev)) * 8 for P, nev in pencils)
+    srv.close()
+    for pr in systems:
+        pr.close()
+    ctx.close()
+
+
+def test_resident_blocks_can_crowd_out_a_request(pencils):
+    """One slot, a budget just above the largest request's own footprint: after the five
+    small systems have left their resident blocks, the large request no longer fits even
+    with the slot's workspace given back, and it finishes with ENOMEM instead of waiting
+    forever; the small ones converge."""
+    lp = _lp()
+    ctx = lp.Context(0)
+    small, big = pencils[:5], pencils[5]
+    fp_big = lp.solve_footprint(big[0].n, big[1], pufe.guard_vectors(big[1]), lp.MIXED)
+    systems = _systems(ctx, small + [big])
+    srv = lp.Server(ctx, fp_big + 4096, 1)
+    rids = []
+    for (P, nev), pr in zip(small + [big], systems):
+        m0 = pufe.guard_vectors(nev)
+        rids.append(srv.submit(pr, nev, m0, X0=pufe.start_block(P.n, nev + m0, 3), tol=1e-9, sigma0=P.sigma0,
+                               precision=lp.MIXED))
+    for rid in rids[:-1]:
+        assert srv.wait(rid).converged
+    with pytest.raises(lp.LabpsdError) as e:
+        srv.wait(rids[-1])
+    assert e.value.code == lp.ENOMEM
+    assert srv.memory()["peak"] <= fp_big + 4096
+    srv.close()
+    for pr in systems:
+        pr.close()
+    ctx.close()
 
 
 def test_budget_too_small_is_rejected(pencils):
