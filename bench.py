@@ -57,6 +57,13 @@ def parse():
     ap.add_argument("--abl-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 8 plain device copies of 512 MiB (the scale for the HBM byte counters)")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="write the kernel table of a rocprofv3 --kernel-trace --stats run (to --out)")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
+                    help="write HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of the "
+                         "workload and of --copy-calibration (to --out)")
+    ap.add_argument("--out", help="summary file to write")
+    ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
     return ap.parse_args()
 
 
@@ -148,6 +155,107 @@ def measured_peaks():
     del a, b, c
     torch.cuda.empty_cache()
     return out
+
+
+# ------------------------------------------------------------------ rocprofv3 summaries
+
+KERNEL_SOURCES = {"k_block_update": "dense.hip", "k_gram": "dense.hip", "k_residual": "dense.hip",
+                  "k_spmm_hs": "spmm.hip", "k_sn_sweep": "precond.hip", "k_minres_spmv": "minres.hip"}
+
+
+def short_kernel_name(full):
+    """'void labpsd::(anonymous namespace)::k_gram<64, 32>(long, ...)' -> 'k_gram<64,32>'."""
+    s = full.strip().strip('"')
+    if s.startswith("void "):
+        s = s[5:]
+    s = s.replace("labpsd::(anonymous namespace)::", "").replace("labpsd::", "")
+    return s.split("(")[0].replace(" ", "")
+
+
+def kernel_source(name):
+    base = name.split("<")[0]
+    for k, f in KERNEL_SOURCES.items():
+        if base.startswith(k):
+            return "paper_1308_2445_amd/csrc/" + f
+    return None
+
+
+def _csvs(d, suffix):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+
+
+def summarize_stats(d, out, command):
+    import csv
+    rows = []
+    for path in _csvs(d, "_kernel_stats.csv"):
+        for r in csv.DictReader(open(path)):
+            rows.append((short_kernel_name(r["Name"]), int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+                         float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    rows.sort(key=lambda r: -r[2])
+    total = sum(r[2] for r in rows)
+    with open(out, "w") as f:
+        f.write("# rocprofv3 kernel statistics; durations in microseconds, pct of the total kernel time\n")
+        f.write("# command: %s\n#\n" % command)
+        f.write("%-44s %8s %14s %12s %7s\n" % ("kernel", "calls", "total_us", "avg_us", "pct"))
+        for r in rows[:40]:
+            name = r[0] if len(r[0]) <= 44 else r[0][:41] + "..."
+            f.write("%-44s %8d %14.1f %12.1f %7.2f\n" % ((name,) + r[1:]))
+        f.write("\ntotal kernel time %.1f ms\n" % (total / 1e3))
+
+
+def _counter_means(d, counter):
+    """Mean counter value per dispatch (KiB) of every kernel in a --pmc run."""
+    import csv
+    acc = {}
+    for path in _csvs(d, "_counter_collection.csv"):
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = short_kernel_name(r["Kernel_Name"])
+            v = acc.setdefault(k, [0.0, 0])
+            v[0] += float(r["Counter_Value"])
+            v[1] += 1
+    return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+
+
+def summarize_traffic(dirs, out, command):
+    fetch, write = _counter_means(dirs[0], "FETCH_SIZE"), _counter_means(dirs[1], "WRITE_SIZE")
+    cf, cw = _counter_means(dirs[2], "FETCH_SIZE"), _counter_means(dirs[3], "WRITE_SIZE")
+    copy_kib = 512 * 1024   # --copy-calibration: 512 MiB read and written per dispatch
+    ff = cf["__amd_rocclr_copyBuffer"][0] / copy_kib
+    wf = cw["__amd_rocclr_copyBuffer"][0] / copy_kib
+    with open(out, "w") as f:
+        f.write("# HBM traffic per launch from rocprofv3 counters, one counter per run\n")
+        f.write("# commands: %s\n" % command)
+        f.write("# copy calibration: FETCH_SIZE %.1f KiB per 512 MiB copy -> factor %.4f; WRITE_SIZE %.1f KiB -> "
+                "factor %.4f\n" % (ff * copy_kib, ff, wf * copy_kib, wf))
+        f.write("# bytes_per_launch = (FETCH_SIZE / fetch factor + WRITE_SIZE / write factor) * 1024, mean over the\n"
+                "# kernel's dispatches; sha256 is that of the kernel's source when the counters were taken (bench.py\n"
+                "# reports the figure only while the source is unchanged).  FETCH_SIZE counts L2 fills from the\n"
+                "# fabric, hits in the MALL included, so it bounds HBM reads from above.\n#\n")
+        for k in sorted(set(fetch) & set(write)):
+            src = kernel_source(k)
+            if src is None:
+                continue
+            sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+            by = (fetch[k][0] / ff + write[k][0] / wf) * 1024
+            f.write("kernel=%s source=%s sha256=%s dispatches=%d fetch_kib_per_dispatch=%.1f "
+                    "write_kib_per_dispatch=%.1f fetch_factor=%.4f write_factor=%.4f bytes_per_launch=%.0f\n"
+                    % (k, src, sha, fetch[k][1], fetch[k][0], write[k][0], ff, wf, by))
+
+
+def block_update_ct(b):
+    """MFMA tiles per wavefront of the wide block update for b output columns: the width
+    16 CT (CT in 9, 8, 6) that pads b the least, then the fewest column groups (the
+    library's own choice, repeated here to name the kernel)."""
+    best, cost = 8, None
+    for ct in (9, 8, 6):
+        g = (b + 16 * ct - 1) // (16 * ct)
+        c = (g * 16 * ct - b) * 4 + g
+        if cost is None or c < cost:
+            best, cost = ct, c
+    return best
 
 
 def copy_calibration():
@@ -360,7 +468,8 @@ def rooflines(P, agg, b, steps, hbm_peak, fp64_peak):
     n = P.n
     if nl["block_update"]:
         fl = 6.0 * n * b * cols["block_update"]
-        out["block_update"] = dict(kernel="k_block_update_wide<8>" if b >= 96 else "k_block_update",
+        out["block_update"] = dict(kernel="k_block_update_wide<%d>" % block_update_ct(b) if b >= 96
+                                   else "k_block_update",
                                    bound="mfma", unit="TFLOP/s", peak=fp64_peak, launches=int(nl["block_update"]),
                                    avg_launch_us=1e6 * t["block_update"] / nl["block_update"],
                                    algorithmic_flops_per_launch=fl / nl["block_update"],
@@ -370,14 +479,15 @@ def rooflines(P, agg, b, steps, hbm_peak, fp64_peak):
         # iterations b + p; the mean width reproduces sum k within rounding of sum k^2
         kk = agg["gram_kk"]
         fl = 2.0 * n * kk
-        out["gram"] = dict(kernel="k_gram (+ k_gram_reduce)", bound="mfma", unit="TFLOP/s", peak=fp64_peak,
+        out["gram"] = dict(kernel=("k_gram<64,32>" if b >= 192 else "k_gram<32,64>") + " (+ k_gram_reduce)",
+                           bound="mfma", unit="TFLOP/s", peak=fp64_peak,
                            launches=int(nl["gram"]), avg_launch_us=1e6 * t["gram"] / nl["gram"],
                            algorithmic_flops_per_launch=fl / nl["gram"], achieved=fl / t["gram"] / 1e12)
     nl_pp = nl["products_p"] + nl["products_psi"]
     if nl_pp:
         tp = t["products_p"] + t["products_psi"]
         by = nl_pp * (20.0 * P.nnz + 8.0 * (n + 1)) + 24.0 * n * (cols["products_p"] + cols["products_psi"])
-        out["spmm"] = dict(kernel="k_spmm_hs", bound="hbm", unit="GB/s", peak=hbm_peak, launches=int(nl_pp),
+        out["spmm"] = dict(kernel="k_spmm_hs<4>", bound="hbm", unit="GB/s", peak=hbm_peak, launches=int(nl_pp),
                            avg_launch_us=1e6 * tp / nl_pp, algorithmic_bytes_per_launch=by / nl_pp,
                            achieved=by / tp / 1e9)
     for r in out.values():
@@ -396,6 +506,12 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats, args.out, args.command)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(args.summarize_traffic, args.out, args.command)
         return
     if args.ablation:
         ablation(args)
@@ -474,7 +590,9 @@ def main():
     # update or Gram (one launch per step, timed per launch by the step events)
     dom = max(("block_update", "gram"), key=lambda k: agg["t"][k] if k in rl else -1.0)
     roofline = dict(rl[dom])
-    roofline["traffic"] = measured_traffic(roofline["kernel"].split(" ")[0], args.workload)
+    for r in rl.values():
+        r["traffic"] = measured_traffic(r["kernel"].split(" ")[0], args.workload)
+    roofline["traffic"] = rl[dom]["traffic"]
     roofline["share_of_fp64_solve"] = agg["t"][dom] / (f["ms"] * 1e-3 * args.steps)
     lam64 = f["outs"][0].lam.cpu().numpy()
     gold = golden_lam(args.workload)
