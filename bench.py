@@ -57,6 +57,13 @@ def parse():
     ap.add_argument("--abl-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 8 plain device copies of 512 MiB (the scale for the HBM byte counters)")
+    ap.add_argument("--apply-levels", action="store_true",
+                    help="time the global apply on --workload with the single-launch sweep and level by level "
+                         "(one launch per elimination-tree level and phase)")
+    ap.add_argument("--apply-cols", type=int, default=512)
+    ap.add_argument("--apply-reps", type=int, default=3)
+    ap.add_argument("--summarize-apply-levels", metavar="DIR",
+                    help="write the per-level table of a rocprofv3 --kernel-trace run of --apply-levels (to --out)")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="write the kernel table of a rocprofv3 --kernel-trace --stats run (to --out)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
@@ -243,6 +250,109 @@ def summarize_traffic(dirs, out, command):
             f.write("kernel=%s source=%s sha256=%s dispatches=%d fetch_kib_per_dispatch=%.1f "
                     "write_kib_per_dispatch=%.1f fetch_factor=%.4f write_factor=%.4f bytes_per_launch=%.0f\n"
                     % (k, src, sha, fetch[k][1], fetch[k][0], write[k][0], ff, wf, by))
+
+
+def apply_levels(args):
+    """The global apply of the workload's factor on apply_cols random right-hand sides, in
+    both precisions, with the single-launch sweep and with one launch per level and phase
+    (HIP events on the current stream, apply_reps applies each after a warm-up)."""
+    import torch
+
+    import paper_1308_2445_amd as lp
+    import pufe
+    P = pufe.workload(args.workload, 0)
+    ctx = lp.Context(0)
+    coords = pufe.dof_coordinates(P)
+    routes = {}
+    for name, extra in (("sweep", 0), ("levels", lp.APPLY_LEVELS)):
+        pr = lp.Problem.from_pencil(ctx, P)
+        pr.set_global_precond(P.eps_bar, coords, panels=lp.PANELS_FP64 | lp.PANELS_FP32 | extra)
+        routes[name] = pr
+    fi = routes["sweep"].factor_info()
+    rng = np.random.default_rng(5)
+    R = torch.from_numpy(rng.standard_normal((args.apply_cols, P.n))).cuda()
+    out = {"workload": args.workload, "n": P.n, "cols": args.apply_cols, "levels": fi["n_levels"],
+           "supernodes": fi["n_supernodes"], "nnz_factor": fi["nnz_factor"], "ms": {}}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for prec, pname in ((lp.FP64, "fp64"), (lp.MIXED, "fp32")):
+        for name, pr in routes.items():
+            Pd = torch.empty_like(R)
+            lp.labpsd_precond_apply(pr, prec, R, Pd)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.apply_reps):
+                lp.labpsd_precond_apply(pr, prec, R, Pd)
+            e1.record()
+            torch.cuda.synchronize()
+            out["ms"]["%s_%s" % (pname, name)] = e0.elapsed_time(e1) / args.apply_reps
+            print("[apply] %s %s: %.2f ms per apply of %d columns" % (pname, name, out["ms"]["%s_%s" % (pname, name)],
+                                                                   args.apply_cols), flush=True)
+    for pr in routes.values():
+        pr.close()
+    ctx.close()
+    print(json.dumps({"apply_levels": out}), flush=True)
+
+
+def summarize_apply_levels(d, out, command):
+    """Per-level table of the level-by-level applies in a kernel trace: the k_sn_product
+    dispatches of one apply run forward (leaves first), diagonal, backward (root first)."""
+    import csv
+    rows = []
+    for path in _csvs(d, "_kernel_trace.csv"):
+        for r in csv.DictReader(open(path)):
+            nm = short_kernel_name(r["Kernel_Name"])
+            if nm.startswith("k_sn_product") or nm.startswith("k_sn_sweep"):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), nm, int(r["Grid_Size_X"]),
+                             int(r["Grid_Size_Y"])))
+    rows.sort()
+    # split into applies: a forward product after a backward one (or a sweep) starts a new apply
+    applies, cur, last = [], [], None
+    for r in rows:
+        kind = r[2]
+        if cur and (kind.startswith("k_sn_sweep") or (kind.endswith(",2>") and last is not None
+                                                      and last.endswith(",3>"))):
+            applies.append(cur)
+            cur = []
+        cur.append(r)
+        last = kind
+        if kind.startswith("k_sn_sweep"):
+            applies.append(cur)
+            cur, last = [], None
+    if cur:
+        applies.append(cur)
+    with open(out, "w") as f:
+        f.write("# global apply per elimination-tree level (one launch per level and phase), rocprofv3 kernel trace\n")
+        f.write("# command: %s\n#\n" % command)
+        seen = set()
+        for ap in applies:
+            kinds = {r[2] for r in ap}
+            key = tuple(sorted(kinds))
+            if key in seen:
+                continue   # the first apply of each route and precision (the warm-up)
+            seen.add(key)
+            tot = sum(r[1] - r[0] for r in ap) / 1e3
+            span = (ap[-1][1] - ap[0][0]) / 1e3
+            typ = ap[0][2].split("<")[1].split(",")[0]
+            if ap[0][2].startswith("k_sn_sweep"):
+                f.write("%s single-launch sweep: %.1f us (%d work-groups)\n\n" % (typ, tot, ap[0][3] // 256))
+                continue
+            f.write("%s level by level: %d launches, %.1f us of kernels, %.1f us first start to last end\n"
+                    % (typ, len(ap), tot, span))
+            f.write("%-10s %6s %10s %12s %8s\n" % ("phase", "step", "tasks", "us", "pct"))
+            fi = bi = 0
+            for r in ap:
+                op = r[2].rstrip(">").split(",")[-1]
+                phase = {"2": "forward", "0": "diagonal", "3": "backward"}[op]
+                if op == "2":
+                    step, fi = fi, fi + 1
+                elif op == "3":
+                    step, bi = bi, bi + 1
+                else:
+                    step = 0
+                us = (r[1] - r[0]) / 1e3
+                f.write("%-10s %6d %10d %12.1f %8.2f\n" % (phase, step, r[3] // 256, us, 100 * us / tot))
+            f.write("(forward steps count up from the leaves, backward steps down from the root; tasks = work-groups "
+                    "per right-hand-side group)\n\n")
 
 
 def block_update_ct(b):
@@ -506,6 +616,12 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.apply_levels:
+        apply_levels(args)
+        return
+    if args.summarize_apply_levels:
+        summarize_apply_levels(args.summarize_apply_levels, args.out, args.command)
         return
     if args.summarize_stats:
         summarize_stats(args.summarize_stats, args.out, args.command)

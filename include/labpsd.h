@@ -129,9 +129,12 @@ labpsd_status labpsd_problem_set_nonlocal(labpsd_problem* p, int k, const int64_
  * fronts, pivots and inverses in FP32; FP64 panels, if uploaded, hold those values.  `coords` (host float64[n*3],
  * row-major x,y,z per dof, or NULL) guides the ordering by coordinate
  * bisection; with NULL a breadth-first level-structure bisection of the graph
- * is used.  ENOTSPD if a pivot is not positive (eps_bar too high); EINVAL for a
- * mask with other bits set.                                                  */
-enum { LABPSD_PANELS_FP64 = 1, LABPSD_PANELS_FP32 = 2, LABPSD_FACTOR_FP32 = 4 };
+ * is used.  LABPSD_APPLY_LEVELS (ORed in) applies the factor with one launch per
+ * elimination-tree level and phase instead of the single dependency-ordered
+ * launch: the same products, each level's time separately measurable.  ENOTSPD if
+ * a pivot is not positive (eps_bar too high); EINVAL for a mask with other bits
+ * set.                                                                       */
+enum { LABPSD_PANELS_FP64 = 1, LABPSD_PANELS_FP32 = 2, LABPSD_FACTOR_FP32 = 4, LABPSD_APPLY_LEVELS = 8 };
 labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const double* coords,
                                         unsigned precisions);
 

@@ -30,7 +30,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, NOT_CONVERGED, PENDING = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ENOTSPD, ERANK, ESTATE = -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
-PANELS_FP64, PANELS_FP32, FACTOR_FP32 = 1, 2, 4
+PANELS_FP64, PANELS_FP32, FACTOR_FP32, APPLY_LEVELS = 1, 2, 4, 8
 HYBRID, GLOBAL_ONLY, LOCAL_ONLY = 0, 1, 2
 REFINE_MINRES, REFINE_ONESTEP = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
@@ -274,7 +274,8 @@ class Problem:
 
     def set_global_precond(self, eps_bar: float, coords=None, panels: int = 0):
         """panels: PANELS_FP64 | PANELS_FP32 mask of the factor copies to upload (neither: both),
-        optionally | FACTOR_FP32 for a numeric factorisation in single precision."""
+        optionally | FACTOR_FP32 for a numeric factorisation in single precision, | APPLY_LEVELS for
+        one launch per elimination-tree level and phase instead of the single-launch sweep."""
         c = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64).reshape(-1, 3)
         self.ctx.sync_stream()
         _check(_lib.labpsd_set_global_precond(self.h, float(eps_bar), _ptr(c), int(panels)),

@@ -356,6 +356,10 @@ static labpsd_status solve_impl(Problem& P, const labpsd_solve_params& prm, cons
     h_ib.alloc((size_t)m + 4);
     h_sel.alloc(3 * (size_t)m);
     h_int.alloc(2 * (size_t)m);   // MINRES done flags: two slots of up to m columns
+    // a report word is only ever read after the kernel that writes it has completed; start
+    // every solve from zeros so no value of an earlier solve can stand in for it
+    std::memset(h_ib.p, 0, ((size_t)m + 4) * sizeof(int32_t));
+    std::memset(h_rb.p, 0, (2 * (size_t)m + b + 1) * sizeof(double));
     P.events.ensure();
     hipEvent_t ev_sync = P.events.e[0], ev_flag0 = P.events.e[1], ev_flag1 = P.events.e[2];
     int32_t* h_cols = (int32_t*)(h_sel.p + 2 * (size_t)m);
@@ -931,7 +935,8 @@ labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const
     return guarded([&]() -> labpsd_status {
         LABPSD_REQUIRE(p != nullptr, "problem is NULL");
         LABPSD_REQUIRE(std::isfinite(eps_bar), "eps_bar must be finite");
-        LABPSD_REQUIRE((precisions & ~(unsigned)(LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32 | LABPSD_FACTOR_FP32)) == 0,
+        LABPSD_REQUIRE((precisions & ~(unsigned)(LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32 | LABPSD_FACTOR_FP32 |
+                                                 LABPSD_APPLY_LEVELS)) == 0,
                        "precision mask has unknown bits");
         const bool single = (precisions & LABPSD_FACTOR_FP32) != 0;
         const unsigned sel = precisions & (unsigned)(LABPSD_PANELS_FP64 | LABPSD_PANELS_FP32);
@@ -953,6 +958,7 @@ labpsd_status labpsd_set_global_precond(labpsd_problem* p, double eps_bar, const
         if (rc != 0) throw Error{LABPSD_EINVAL, msg};
         const double t0 = wall();
         upload_factor(*p, F, eps_bar, panels);
+        if (precisions & LABPSD_APPLY_LEVELS) p->factor->use_sweep = false;
         // the factor is of H_loc - eps_bar S; the nonlocal term enters through SMW
         if (p->nl.k) nonlocal_smw_setup(*p);
         p->factor->info.t_upload_s = wall() - t0;

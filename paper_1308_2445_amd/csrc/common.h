@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include <cstdint>
+#include <cstring>
 #include <functional>
 #include <string>
 #include <utility>
@@ -129,6 +130,7 @@ struct HBuf {
         n = 0;
         LABPSD_HIP(hipHostMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
         n = count;
+        std::memset((void*)p, 0, std::max<size_t>(count, 1) * sizeof(T));
     }
 };
 

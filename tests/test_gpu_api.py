@@ -89,7 +89,7 @@ def test_device_resident_csr_and_h(ctx, c1):
 
 def test_precision_mask(ctx, c1):
     """Only the selected factor copies are uploaded: a solve in the other precision is
-    refused (ESTATE), the selected one runs; unknown mask bits (8) are rejected."""
+    refused (ESTATE), the selected one runs; unknown mask bits (16) are rejected."""
     lp = _lp()
     P, lam, _ = c1
     X0 = pufe.start_block(P.n, 8, 0)
@@ -104,6 +104,6 @@ def test_precision_mask(ctx, c1):
         pr.close()
     pr = lp.Problem.from_pencil(ctx, P)
     with pytest.raises(lp.LabpsdError) as e:
-        pr.set_global_precond(P.eps_bar, None, panels=8)     # no such bit
+        pr.set_global_precond(P.eps_bar, None, panels=16)    # no such bit
     assert e.value.code == lp.EINVAL
     pr.close()

@@ -378,3 +378,28 @@ def test_local_refine_one_step(prob, precision):
         else:
             assert abs(int(itg[c]) - itref) <= 2
             assert np.linalg.norm(a) <= 1.5 * eta * rn or int(itg[c]) == cap
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_level_by_level_apply_matches_sweep(prob, ctx, precision):
+    """LABPSD_APPLY_LEVELS: the same products in one launch per level and phase give the
+    single-launch sweep's result (both accumulate atomically, so to rounding) and the
+    oracle's solve."""
+    P, pr = prob
+    import paper_1308_2445_amd as lp
+    torch = _torch()
+    pl = lp.Problem.from_pencil(ctx, P)
+    pl.set_global_precond(P.eps_bar, pufe.dof_coordinates(P), panels=lp.APPLY_LEVELS)
+    rng = np.random.default_rng(15)
+    R = rng.standard_normal((P.n, 40))
+    a = torch.empty((40, P.n), dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    lp.labpsd_precond_apply(pr, precision, dev(R), a)
+    lp.labpsd_precond_apply(pl, precision, dev(R), b)
+    torch.cuda.synchronize()
+    ga, gb = host(a), host(b)
+    tol = 1e-12 if precision == 0 else 1e-5
+    assert np.linalg.norm(ga - gb) <= tol * np.linalg.norm(ga)
+    ref = oprec.GlobalPreconditioner(P.H(), P.S(), P.eps_bar).apply(R)
+    assert np.linalg.norm(gb - ref) <= (1e-9 if precision == 0 else 5e-3) * np.linalg.norm(ref)
+    pl.close()
