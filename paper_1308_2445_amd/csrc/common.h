@@ -190,8 +190,12 @@ struct SellShape {
     size_t lds_bytes;
 };
 SellShape sell_shape(const Sell& A, int w, size_t value_bytes);
-// raise a kernel's dynamic-LDS limit to kSellLdsBytes on the current device (once)
-void allow_sell_lds(const void* kernel);
+// Raise a kernel's dynamic-LDS limit on the current device to the device's maximum
+// per work-group, once (under a lock; never lowered again).  Every kernel launched with
+// more than 64 KB of dynamic LDS calls this first: setting the limit per launch to that
+// launch's size would let a concurrent launch of the same kernel on another stream lower
+// it between another thread's setting and its launch.
+void allow_dynamic_lds(const void* kernel);
 
 template <typename T>
 struct SliceLds {

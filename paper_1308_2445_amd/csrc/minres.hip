@@ -367,7 +367,7 @@ int64_t launch_spmv_s(const Sell& A, SellShape sh, const T* hv, const T* sv, con
                       const int32_t* xcols, const T* aux, int64_t ldaux, const int32_t* auxcols,
                       const double* shift, const MinresScal* sc, T* out, double* partial, int q,
                       hipStream_t s, NlEpi<T, T> nl) {
-    allow_sell_lds((const void*)k_minres_spmv<T, MODE, CW>);
+    allow_dynamic_lds((const void*)k_minres_spmv<T, MODE, CW>);
     const int cpb = (q + sh.bands - 1) / sh.bands;
     const dim3 g((unsigned)A.nslices, (unsigned)sh.bands);
     hipLaunchKernelGGL((k_minres_spmv<T, MODE, CW>), g, dim3(64 * kSellWaves), sh.lds_bytes, s, A.slice_off.p,

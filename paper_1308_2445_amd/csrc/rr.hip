@@ -1946,9 +1946,7 @@ void launch_rr_large(int k, int nwant, const double* HR, const double* SR, int64
     // about eight columns per work-group
     const int G = std::min(128, std::max(8, (k + 7) / 8));
     const size_t lds = 4 * (size_t)kp * sizeof(double);
-    if (lds + 1024 > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)k_rrl_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipGetLastError();
+    if (lds + 1024 > 64 * 1024) allow_dynamic_lds((const void*)k_rrl_tridiag);
     int kk_arg = k;
     double* base_arg = base;
     void* targs[] = {(void*)&kk_arg, (void*)&base_arg};
@@ -1957,9 +1955,7 @@ void launch_rr_large(int k, int nwant, const double* HR, const double* SR, int64
                                    (unsigned)lds, s) == hipSuccess &&
         hipGetLastError() == hipSuccess) {
         const size_t bl = 2 * (size_t)kp * sizeof(double);
-        if (bl + 1024 > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)k_rrl_bisect, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bl);
-        (void)hipGetLastError();
+        if (bl + 1024 > 64 * 1024) allow_dynamic_lds((const void*)k_rrl_bisect);
         hipLaunchKernelGGL(k_rrl_bisect, dim3((nwant + 3) / 4), dim3(kLThreads), bl, s, k, nwant, base);
         hipLaunchKernelGGL(k_rrl_teig, dim3(1), dim3(kRRThreads), 0, s, k, nwant, base, gamma, info, gamma_host,
                            info_host);
@@ -1989,15 +1985,16 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
         launch_rr_large(k, nwant, HR, SR, ldr, gamma, W, ldw, info, ws, s, gamma_host, info_host);
         return;
     }
-    static int lds_limit = -1;
-    if (lds_limit < 0) {
+    // the device's LDS per work-group (initialised once, thread-safely: slot threads of the
+    // server launch this concurrently)
+    static const int lds_limit = [] {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             v = 64 * 1024;
         (void)hipGetLastError();
-        lds_limit = v;
-    }
+        return v;
+    }();
     const RRLayout L = rr_layout(k, nwant | 1);
     const size_t bytes = (size_t)L.total * sizeof(double);
     // register-row width: 8 lanes per row, NT columns per lane
@@ -2019,9 +2016,7 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
                     (void*)&gamma_host, (void*)&info_host, (void*)&run_if};
     if (all_lds) {
         const void* f = pick(std::true_type{});
-        if (bytes > 64 * 1024)
-            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        (void)hipGetLastError();
+        if (bytes > 64 * 1024) allow_dynamic_lds(f);
         if (hipLaunchKernel(f, dim3(1), dim3(kRRThreads), args, bytes, s) == hipSuccess &&
             hipGetLastError() == hipSuccess)
             return;

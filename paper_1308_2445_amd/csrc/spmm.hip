@@ -212,21 +212,28 @@ SellShape sell_shape(const Sell& A, int w, size_t value_bytes) {
     return sh;
 }
 
-void allow_sell_lds(const void* kernel) {
+void allow_dynamic_lds(const void* kernel) {
     static std::mutex mu;
     static std::set<std::pair<const void*, int>> done;
     int dev = 0;
     LABPSD_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(mu);
     if (done.count({kernel, dev})) return;
-    LABPSD_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSellLdsBytes));
+    int mx = 0;
+    LABPSD_HIP(hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // static and dynamic LDS share the work-group's allotment
+    hipFuncAttributes fa{};
+    LABPSD_HIP(hipFuncGetAttributes(&fa, kernel));
+    const int dyn = mx - (int)fa.sharedSizeBytes;
+    LABPSD_REQUIRE(dyn >= (int)kSellLdsBytes, "device offers less LDS per work-group than the kernels need");
+    LABPSD_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
     done.insert({kernel, dev});
 }
 
 template <int CW>
 static void spmm_hs_cw(const Sell& A, SellShape sh, const double* X, int64_t ldx, int w, double* YH,
                        double* YS, int64_t ldy, hipStream_t s, NlEpi<double, double> nl) {
-    allow_sell_lds((const void*)k_spmm_hs<CW>);
+    allow_dynamic_lds((const void*)k_spmm_hs<CW>);
     const int cpb = (w + sh.bands - 1) / sh.bands;
     const dim3 grid((unsigned)A.nslices, (unsigned)sh.bands);
     hipLaunchKernelGGL((k_spmm_hs<CW>), grid, dim3(64 * kSellWaves), sh.lds_bytes, s, A.slice_off.p, A.col.p,
@@ -259,7 +266,7 @@ static void spmm_shift_cw(const Sell& A, SellShape sh, const T* X, int64_t ldx, 
         hv = A.hv32.p;
         sv = A.sv32.p;
     }
-    allow_sell_lds((const void*)k_spmm_shift<T, CW>);
+    allow_dynamic_lds((const void*)k_spmm_shift<T, CW>);
     const int cpb = (w + sh.bands - 1) / sh.bands;
     const dim3 grid((unsigned)A.nslices, (unsigned)sh.bands);
     hipLaunchKernelGGL((k_spmm_shift<T, CW>), grid, dim3(64 * kSellWaves), sh.lds_bytes, s, A.slice_off.p,
