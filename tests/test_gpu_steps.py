@@ -56,11 +56,13 @@ def prob(request, ctx):
 
 
 def test_spmm_fused(prob):
+    """Every launch shape: one, two and four columns per wavefront (w < 16, 16 <= w < 32,
+    w >= 32), one and several column bands (w = 200: two), ragged rounds."""
     P, pr = prob
     import paper_1308_2445_amd as lp
     torch = _torch()
     rng = np.random.default_rng(11)
-    for w in (1, 8, 37):
+    for w in (1, 8, 20, 37, 200):
         X = rng.standard_normal((P.n, w))
         Xd = dev(X)
         YH = torch.empty_like(Xd)
@@ -81,20 +83,20 @@ def test_spmm_shifted(prob, precision):
     import paper_1308_2445_amd as lp
     torch = _torch()
     rng = np.random.default_rng(12)
-    w = 13
-    X = rng.standard_normal((P.n, w))
-    sh = rng.uniform(-0.5, 0.5, w)
-    dt = torch.float64 if precision == 0 else torch.float32
-    Xd = dev(X, dt)
-    Y = torch.empty_like(Xd)
-    lp.labpsd_spmm_shifted(pr, precision, Xd, torch.from_numpy(sh).cuda(), Y)
-    torch.cuda.synchronize()
-    H, S = P.H(), P.S()
-    Xr = X if precision == 0 else X.astype(np.float32).astype(np.float64)
-    ref = H @ Xr - (S @ Xr) * sh[None, :]
-    scale = abs(H) @ np.abs(Xr) + (abs(S) @ np.abs(Xr)) * np.abs(sh)[None, :]
-    tol = 1e-14 if precision == 0 else 2e-6
-    assert np.all(np.abs(host(Y) - ref) <= tol * scale + 1e-30)
+    for w in (13, 24, 150):
+        X = rng.standard_normal((P.n, w))
+        sh = rng.uniform(-0.5, 0.5, w)
+        dt = torch.float64 if precision == 0 else torch.float32
+        Xd = dev(X, dt)
+        Y = torch.empty_like(Xd)
+        lp.labpsd_spmm_shifted(pr, precision, Xd, torch.from_numpy(sh).cuda(), Y)
+        torch.cuda.synchronize()
+        H, S = P.H(), P.S()
+        Xr = X if precision == 0 else X.astype(np.float32).astype(np.float64)
+        ref = H @ Xr - (S @ Xr) * sh[None, :]
+        scale = abs(H) @ np.abs(Xr) + (abs(S) @ np.abs(Xr)) * np.abs(sh)[None, :]
+        tol = 1e-14 if precision == 0 else 2e-6
+        assert np.all(np.abs(host(Y) - ref) <= tol * scale + 1e-30)
 
 
 def test_residual(prob, ctx):
@@ -221,7 +223,8 @@ def test_gram(prob, ctx):
     import paper_1308_2445_amd as lp
     torch = _torch()
     rng = np.random.default_rng(15)
-    for k in (5, 33, 70, 300, 538):
+    # 32 x 32 tiles up to k = 191, 64 x 64 from 192
+    for k in (1, 5, 33, 70, 191, 192, 300, 538):
         Z = rng.standard_normal((P.n, k))
         ZH, ZS = P.H() @ Z, P.S() @ Z
         HR = torch.empty((k, k), dtype=torch.float64, device="cuda")
@@ -317,8 +320,9 @@ def test_block_update(prob, ctx):
     import paper_1308_2445_amd as lp
     torch = _torch()
     rng = np.random.default_rng(17)
-    # the last four shapes take the wide kernel (128 columns per work-group)
-    for k, b in ((8, 5), (45, 33), (70, 36), (129, 40), (60, 130), (300, 150), (538, 282)):
+    # from (129, 40) on the wide kernel, 16 CT columns per work-group with CT chosen per
+    # launch: 6 at b = 40 and 150, 9 at b = 130 and 282, 8 at b = 128
+    for k, b in ((8, 5), (45, 33), (70, 36), (129, 40), (60, 130), (300, 150), (538, 282), (200, 128)):
         Zs = [rng.standard_normal((P.n, k)) for _ in range(3)]
         W = rng.standard_normal((k, b))
         outs = [torch.empty((b, P.n), dtype=torch.float64, device="cuda") for _ in range(3)]
