@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--abl-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 8 plain device copies of 512 MiB (the scale for the HBM byte counters)")
+    ap.add_argument("--next-rows", action="store_true",
+                    help="eigenpairs/s of the variants on the 15,977-dof cell: plain, one-step refinement, "
+                         "FP32 factorisation, nonlocal term, k-point pencil")
     ap.add_argument("--apply-levels", action="store_true",
                     help="time the global apply on --workload with the single-launch sweep and level by level "
                          "(one launch per elimination-tree level and phase)")
@@ -250,6 +253,44 @@ def summarize_traffic(dirs, out, command):
             f.write("kernel=%s source=%s sha256=%s dispatches=%d fetch_kib_per_dispatch=%.1f "
                     "write_kib_per_dispatch=%.1f fetch_factor=%.4f write_factor=%.4f bytes_per_launch=%.0f\n"
                     % (k, src, sha, fetch[k][1], fetch[k][0], write[k][0], ff, wf, by))
+
+
+def next_rows(args):
+    """Each variant solved on its 15,977-dof cell (nev 32, m0 4, tol 1e-8, the library's seeded
+    start), one warm-up and three timed solves per precision (each solve synchronises;
+    wall clock around the call)."""
+    import paper_1308_2445_amd as lp
+    import pufe
+    ctx = lp.Context(0)
+    cases = [("plain", "c2", {}), ("one-step refinement", "c2", {"refine": lp.REFINE_ONESTEP}),
+             ("FP32 factorisation", "c2", {"panels": lp.FACTOR_FP32}), ("nonlocal term", "c2nl", {}),
+             ("k-point", "c2k", {})]
+    out = []
+    for label, wl, opt in cases:
+        P = pufe.workload(wl, 0)
+        nev = pufe.WORKLOADS[wl]["nev"]
+        m0 = pufe.guard_vectors(nev)
+        pr = lp.Problem.from_pencil(ctx, P)
+        pr.set_global_precond(P.eps_bar, pufe.dof_coordinates(P), panels=opt.get("panels", 0))
+        if "refine" in opt:
+            pr.set_refine_method(opt["refine"])
+        for prec, pname in ((lp.FP64, "fp64"), (lp.MIXED, "mixed")):
+            pr.solve(nev, m0, None, tol=args.tol, sigma0=P.sigma0, precision=prec, seed=1)
+            ts, o = [], None
+            for _ in range(3):
+                t0 = time.perf_counter()
+                o = pr.solve(nev, m0, None, tol=args.tol, sigma0=P.sigma0, precision=prec, seed=1)
+                ts.append(time.perf_counter() - t0)
+            assert o.converged, (label, pname)
+            r = {"case": label, "workload": wl, "n": P.n, "precision": pname, "eigenpairs_per_s": nev / np.mean(ts),
+                 "ms_per_solve": 1e3 * np.mean(ts), "outer_iters": o.stats["outer_iters"], "la": o.stats["la"]}
+            out.append(r)
+            print("[next] %-22s %-5s n=%6d: %7.1f eigenpairs/s, %6.1f ms per solve, %d iterations, La %.2f"
+                  % (label, pname, P.n, r["eigenpairs_per_s"], r["ms_per_solve"], r["outer_iters"], r["la"]),
+                  flush=True)
+        pr.close()
+    ctx.close()
+    print(json.dumps({"next_rows": out}), flush=True)
 
 
 def apply_levels(args):
@@ -619,6 +660,9 @@ def main():
         return
     if args.apply_levels:
         apply_levels(args)
+        return
+    if args.next_rows:
+        next_rows(args)
         return
     if args.summarize_apply_levels:
         summarize_apply_levels(args.summarize_apply_levels, args.out, args.command)

@@ -9,7 +9,8 @@
 // All localised columns advance together, three kernels per iteration:
 //   spmv    u = A v - beta_k v_prev, per-slice FP64 partial sums of v.u, u.u and v.v
 //           (one pattern pass)
-//   colsums the three sums of every live column from its slices' partials
+//   colsums the three sums of every live column from its slices' partials (with at most
+//           kMinresOwnSums slices the update kernels sum them themselves instead)
 //   update  alpha_k = v.u; w = u - alpha_k v, whose norm follows from the sums without
 //           another pass: ||w||^2 = u.u - 2 alpha_k v.u + alpha_k^2 v.v; beta_{k+1} = ||w||,
 //           the new rotation, tau_k and |phibar_k|;
@@ -27,6 +28,9 @@
 namespace labpsd {
 
 namespace {
+
+// slices up to which the update kernels sum the MINRES partials themselves
+constexpr int64_t kMinresOwnSums = 1024;
 
 struct MinresScal {
     double beta;        // beta_k: coupling of v_k to v_{k-1}
@@ -148,6 +152,27 @@ __global__ __launch_bounds__(256) void k_minres_colsums(const double* __restrict
     if ((threadIdx.x & 63) == 0) sums[t] = v;
 }
 
+// The three sums (v.u, u.u, v.v or their one-step analogues) of column j straight from
+// its slices' partials, for a whole work-group: wavefronts 0, 1 and 2 each sum one set
+// (contiguous, fixed order) and LDS hands them to all.  Used instead of k_minres_colsums
+// when there are few slices (the launch would cost more than the sums).
+__device__ void block_column_sums3(const double* __restrict__ part, int64_t npart, int q, int j,
+                                   double out[3]) {
+    __shared__ double bc[3];
+    const int w = threadIdx.x >> 6;
+    if (w < 3) {
+        const double* p = part + ((int64_t)w * q + j) * npart;
+        double v = 0.0;
+        for (int64_t i = threadIdx.x & 63; i < npart; i += 64) v += p[i];
+        v = wave_sum_t(v);
+        if ((threadIdx.x & 63) == 0) bc[w] = v;
+    }
+    __syncthreads();
+    out[0] = bc[0];
+    out[1] = bc[1];
+    out[2] = bc[2];
+}
+
 // sum over the work-group, valid in thread 0
 template <typename T>
 __device__ T block_sum(T v) {
@@ -203,6 +228,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max_inner,
                                                        const MinresScal* __restrict__ sc_in,
                                                        MinresScal* __restrict__ sc_out,
+                                                       const double* __restrict__ part, int64_t npa,
                                                        const double* __restrict__ csum,
                                                        const T* __restrict__ V, T* __restrict__ Wb,
                                                        const T* __restrict__ D1, T* __restrict__ D2,
@@ -217,8 +243,15 @@ __global__ __launch_bounds__(256) void k_minres_update(int64_t n, int q, int max
         }
         return;
     }
-    // v.u, u.u, v.v
-    const double sums[3] = {csum[j], csum[q + j], csum[2 * q + j]};
+    // v.u, u.u, v.v: from the column-sum kernel, or summed here when there are few slices
+    double sums[3];
+    if (csum) {
+        sums[0] = csum[j];
+        sums[1] = csum[q + j];
+        sums[2] = csum[2 * q + j];
+    } else {
+        block_column_sums3(part, npa, q, j, sums);
+    }
     const double al = sums[0];
     const double bnext = sqrt(fmax(sums[1] - al * (2.0 * sums[0] - al * sums[2]), 0.0));
     const int k = s.its + 1;
@@ -301,6 +334,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_onestep_update(int64_t n, int q, int max_inner,
                                                         const MinresScal* __restrict__ sc_in,
                                                         MinresScal* __restrict__ sc_out,
+                                                        const double* __restrict__ part, int64_t npa,
                                                         const double* __restrict__ csum,
                                                         T* __restrict__ G, const T* __restrict__ U,
                                                         T* __restrict__ Xs, int32_t* __restrict__ done_out) {
@@ -314,8 +348,15 @@ __global__ __launch_bounds__(256) void k_onestep_update(int64_t n, int q, int ma
         }
         return;
     }
-    // g.u, u.u, g.g
-    const double sums[3] = {csum[j], csum[q + j], csum[2 * q + j]};
+    // g.u, u.u, g.g (as in k_minres_update)
+    double sums[3];
+    if (csum) {
+        sums[0] = csum[j];
+        sums[1] = csum[q + j];
+        sums[2] = csum[2 * q + j];
+    } else {
+        block_column_sums3(part, npa, q, j, sums);
+    }
     if (!(sums[1] > 0.0)) {   // A g = 0: no step reduces the residual
         if (lead) {
             MinresScal t = s;
@@ -460,8 +501,11 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
     // spmv partials: one per slice and column
     const int64_t npa = launch_spmv<T, 0>(A, sh, hv, sv, P, ldp, cols_dev, R, ldr, cols_dev, shift_dev, sa, V,
                                           pa, q, s, nlt);
-    // the column sums of the partials (3 q doubles after the 3 nslices q partials)
+    // the column sums of the partials (3 q doubles after the 3 nslices q partials); with few
+    // slices the update kernels sum the partials themselves (one launch fewer per iteration)
     double* csum = pa + 3 * A.nslices * (int64_t)q;
+    const bool own_sums = A.nslices <= kMinresOwnSums;
+    double* ucsum = own_sums ? nullptr : csum;
     const dim3 gsum1((unsigned)((q + 3) / 4)), gsum3((unsigned)((3 * q + 3) / 4)), gq((unsigned)((q + 255) / 256));
     hipLaunchKernelGGL(k_minres_colsums, gsum1, dim3(256), 0, s, (const double*)pa, npa, q, 1,
                        (const MinresScal*)nullptr, csum);
@@ -494,23 +538,27 @@ void run_minres(const Sell& A, T* P, int64_t ldp, const T* R, int64_t ldr, int q
         if (onestep) {
             // u = A g (beta is 0 in the one-step state), then the step
             launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, V, n, nullptr, shift_dev, cur, Wb, pa, q, s, nlt);
-            hipLaunchKernelGGL(k_minres_colsums, gsum3, dim3(256), 0, s, (const double*)pa, npa, q, 3,
-                               (const MinresScal*)cur, csum);
+            if (!own_sums)
+                hipLaunchKernelGGL(k_minres_colsums, gsum3, dim3(256), 0, s, (const double*)pa, npa, q, 3,
+                                   (const MinresScal*)cur, csum);
             hipLaunchKernelGGL((k_onestep_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
-                               (const MinresScal*)cur, nxt, (const double*)csum, V, (const T*)Wb, Xs,
+                               (const MinresScal*)cur, nxt, (const double*)pa, npa, (const double*)ucsum, V,
+                               (const T*)Wb, Xs,
                                check ? flag_dev + (size_t)slot * q : nullptr);
             LABPSD_HIP(hipGetLastError());
-            nl += 3;
+            nl += own_sums ? 2 : 3;
             MinresScal* t2 = cur; cur = nxt; nxt = t2;
         } else {
         launch_spmv<T, 1>(A, sh, hv, sv, V, n, nullptr, VP, n, nullptr, shift_dev, cur, Wb, pa, q, s, nlt);
-        hipLaunchKernelGGL(k_minres_colsums, gsum3, dim3(256), 0, s, (const double*)pa, npa, q, 3,
-                           (const MinresScal*)cur, csum);
+        if (!own_sums)
+            hipLaunchKernelGGL(k_minres_colsums, gsum3, dim3(256), 0, s, (const double*)pa, npa, q, 3,
+                               (const MinresScal*)cur, csum);
         hipLaunchKernelGGL((k_minres_update<T>), grow, dim3(256), 0, s, n, q, max_inner,
-                           (const MinresScal*)cur, nxt, (const double*)csum, (const T*)V, Wb,
+                           (const MinresScal*)cur, nxt, (const double*)pa, npa, (const double*)ucsum,
+                           (const T*)V, Wb,
                            (const T*)D1, D2, Xs, check ? flag_dev + (size_t)slot * q : nullptr);
         LABPSD_HIP(hipGetLastError());
-        nl += 3;
+        nl += own_sums ? 2 : 3;
         // rotate: v_prev <- v, v <- w (now scaled), w <- old v_prev; d1 <- new d, d2 <- old d1
         T* t0 = VP; VP = V; V = Wb; Wb = t0;
         T* t1 = D1; D1 = D2; D2 = t1;

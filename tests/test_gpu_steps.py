@@ -388,15 +388,16 @@ def test_local_refine_one_step(prob, precision):
 def test_level_by_level_apply_matches_sweep(prob, ctx, precision):
     """LABPSD_APPLY_LEVELS: the same products in one launch per level and phase give the
     single-launch sweep's result (both accumulate atomically, so to rounding) and the
-    oracle's solve."""
+    oracle's solve.  150 columns: the default problem takes the sweep (small factors with
+    fewer than 128 columns take the level route by default)."""
     P, pr = prob
     import paper_1308_2445_amd as lp
     torch = _torch()
     pl = lp.Problem.from_pencil(ctx, P)
     pl.set_global_precond(P.eps_bar, pufe.dof_coordinates(P), panels=lp.APPLY_LEVELS)
     rng = np.random.default_rng(15)
-    R = rng.standard_normal((P.n, 40))
-    a = torch.empty((40, P.n), dtype=torch.float64, device="cuda")
+    R = rng.standard_normal((P.n, 150))
+    a = torch.empty((150, P.n), dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     lp.labpsd_precond_apply(pr, precision, dev(R), a)
     lp.labpsd_precond_apply(pl, precision, dev(R), b)
