@@ -55,6 +55,8 @@ def parse():
                     help="global-only / local-only / hybrid preconditioning over SCF-like sequences")
     ap.add_argument("--abl-workload", default="c2nl")
     ap.add_argument("--abl-steps", type=int, default=10)
+    ap.add_argument("--no-measured-peaks", action="store_true",
+                    help="skip the device copy and DGEMM that measure this GPU's peaks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 8 plain device copies of 512 MiB (the scale for the HBM byte counters)")
     ap.add_argument("--next-rows", action="store_true",
@@ -794,12 +796,13 @@ def main():
     del X0
     torch.cuda.synchronize()
     pr.close()
-    try:
-        mp = measured_peaks()
-        line["measured_peaks"] = mp
-        line["roofline"]["frac_of_measured"] = roofline["achieved"] / mp["fp64_dgemm_TFLOPs"]
-    except Exception as exc:   # the peaks are context; the line is printed regardless
-        line["measured_peaks"] = {"error": str(exc)}
+    if not args.no_measured_peaks:
+        try:
+            mp = measured_peaks()
+            line["measured_peaks"] = mp
+            line["roofline"]["frac_of_measured"] = roofline["achieved"] / mp["fp64_dgemm_TFLOPs"]
+        except Exception as exc:   # the peaks are context; the line is printed regardless
+            line["measured_peaks"] = {"error": str(exc)}
     if not args.no_serving:
         sv = serving(args, ctx)
         line["serving"] = sv
