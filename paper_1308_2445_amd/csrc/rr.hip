@@ -1503,8 +1503,12 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_sym(int k, double* __restrict
 // same arithmetic, to the published column, from which it builds the next reflector
 // itself.  Vectors shared between work-groups (p, the partial sums, the published
 // column; double-buffered by parity, so a work-group running one step ahead never
-// overwrites what another still reads) go through device-scope atomics.
-// Dynamic LDS: 4 kp doubles.
+// overwrites what another still reads) go through device-scope atomics.  A work-group's
+// own columns stay in LDS from the first reflector to the last (the dot products and the
+// rank-2 updates read and write LDS, not L2) and go back to C at the end (OWN_LDS; orders
+// whose columns do not fit keep them in C).
+// Dynamic LDS: (4 + ceil(k / G)) kp doubles with OWN_LDS, else 4 kp.
+template <bool OWN_LDS>
 __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __restrict__ base) {
     if (rrl_failed(base)) return;
     const RRLLayout Lo = rrl_layout(k, 1);
@@ -1523,9 +1527,15 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
     double* svn = sm + kp;           // v_{j+1}
     double* sp = sm + 2 * kp;        // p_j
     double* sy = sm + 3 * kp;        // the published column, updated
+    double* own = sm + 4 * kp;       // this work-group's columns g, g + G, g + 2 G, ...
     __shared__ double red[2][4];
     __shared__ int sok;
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // column c (owned here)
+    auto ocol = [&](int c) -> double* {
+        if constexpr (OWN_LDS) return own + (int64_t)((c - g) / G) * kp;
+        else return C + (int64_t)c * kp;
+    };
     int nbar = 0;
     // grid-wide barrier: this thread's stores and atomics have completed before the
     // work-group counts itself in; false once any work-group has given up
@@ -1575,7 +1585,7 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
         __syncthreads();
         double scal;
         reflector(alpha, sigma, t, beta, scal);
-        double* col = C + (int64_t)c * kp;
+        double* col = keep ? ocol(c) : nullptr;
         for (int i = c + 1 + tid; i < k; i += kLThreads) {
             const double vi = (i == c + 1) ? 1.0 : y[i] * scal;
             vn[i] = vi;
@@ -1588,7 +1598,13 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
         t += ((wave - t) % 4 + 4) % 4;
         return g + t * G;
     };
-    // reflector 0 from column 0, in every work-group
+    // this work-group's columns into LDS; reflector 0 from column 0, in every work-group
+    if constexpr (OWN_LDS)
+        for (int c = g; c < k; c += G) {
+            double* oc = ocol(c);
+            const double* src = C + (int64_t)c * kp;
+            for (int64_t i = tid; i < kp; i += kLThreads) oc[i] = src[i];
+        }
     for (int i = tid; i < k; i += kLThreads) sy[i] = C[i];
     __syncthreads();
     double tj, beta0;
@@ -1606,14 +1622,14 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
         double* cbj = colb + ((j + 1) & 1) * kp;
         // the owner of column j + 1 publishes it (its updates up to reflector j - 1 are in)
         if (g == (j + 1) % G) {
-            const double* col = C + (int64_t)(j + 1) * kp;
+            const double* col = ocol(j + 1);
             for (int i = j + 1 + tid; i < k; i += kLThreads)
                 __hip_atomic_store(cbj + i, col[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // p_c = tau (C v)_c for the owned columns, and this work-group's part of p . v
         double mp = 0.0;
         for (int c = first_own(j + 1); c < k; c += 4 * G) {
-            const double* col = C + (int64_t)c * kp;
+            const double* col = ocol(c);
             double dot = 0.0;
             for (int i = j + 1 + lane; i < k; i += 64) dot = fma(col[i], sv[i], dot);
             dot = tj * wave_allsum(dot);
@@ -1636,7 +1652,7 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
         const double K = 0.5 * tj * wave_allsum(ps);
         __syncthreads();
         for (int c = first_own(j + 2); c < k; c += 4 * G) {
-            double* col = C + (int64_t)c * kp;
+            double* col = ocol(c);
             const double vc = sv[c], wc = sp[c] - K * vc;
             for (int i = j + 1 + lane; i < k; i += 64) {
                 const double vi = sv[i];
@@ -1670,6 +1686,15 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_tridiag(int k, double* __rest
         } else if (g == 0 && tid == 0) {   // j + 1 = k - 2: the last off-diagonal
             d[k - 2] = sy[k - 2];
             e[k - 2] = sy[k - 1];
+        }
+    }
+    // the columns (reflectors below the subdiagonal) back to C
+    if constexpr (OWN_LDS) {
+        __syncthreads();
+        for (int c = g; c < k; c += G) {
+            const double* oc = ocol(c);
+            double* dst = C + (int64_t)c * kp;
+            for (int64_t i = tid; i < kp; i += kLThreads) dst[i] = oc[i];
         }
     }
 }
@@ -1922,6 +1947,20 @@ size_t rr_ws_bytes(int k) {
 
 namespace {
 
+// the device's LDS per work-group (initialised once, thread-safely: slot threads of the
+// server launch Rayleigh-Ritz steps concurrently)
+static int device_lds_per_block() {
+    static const int v = [] {
+        int dev = 0, x = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            x = 64 * 1024;
+        (void)hipGetLastError();
+        return x;
+    }();
+    return v;
+}
+
 // the many-work-group route for k >= kRRLargeMin; the one-work-group kernel follows it
 // and runs only if the route gave up (or runs in its place if the cooperative launch
 // is refused)
@@ -1943,15 +1982,18 @@ void launch_rr_large(int k, int nwant, const double* HR, const double* SR, int64
                        base + Lo.B, base);
     hipLaunchKernelGGL(k_rrl_sym, dim3(prep_blocks), dim3(kLThreads), 0, s, k, base);
     LABPSD_HIP(hipGetLastError());
-    // about eight columns per work-group
+    // about eight columns per work-group, kept in LDS when they fit
     const int G = std::min(128, std::max(8, (k + 7) / 8));
-    const size_t lds = 4 * (size_t)kp * sizeof(double);
-    if (lds + 1024 > 64 * 1024) allow_dynamic_lds((const void*)k_rrl_tridiag);
+    const size_t lds_own = (4 + (size_t)((k + G - 1) / G)) * (size_t)kp * sizeof(double);
+    const bool own_lds = lds_own + 1024 <= (size_t)device_lds_per_block();
+    const size_t lds = own_lds ? lds_own : 4 * (size_t)kp * sizeof(double);
+    const void* tridiag = own_lds ? (const void*)k_rrl_tridiag<true> : (const void*)k_rrl_tridiag<false>;
+    if (lds + 1024 > 64 * 1024) allow_dynamic_lds(tridiag);
     int kk_arg = k;
     double* base_arg = base;
     void* targs[] = {(void*)&kk_arg, (void*)&base_arg};
     const int32_t* run_if = (const int32_t*)base;
-    if (hipLaunchCooperativeKernel((const void*)k_rrl_tridiag, dim3(G), dim3(kLThreads), targs,
+    if (hipLaunchCooperativeKernel(tridiag, dim3(G), dim3(kLThreads), targs,
                                    (unsigned)lds, s) == hipSuccess &&
         hipGetLastError() == hipSuccess) {
         const size_t bl = 2 * (size_t)kp * sizeof(double);
@@ -1985,16 +2027,7 @@ void launch_rayleigh_ritz(int k, int nwant, const double* HR, const double* SR, 
         launch_rr_large(k, nwant, HR, SR, ldr, gamma, W, ldw, info, ws, s, gamma_host, info_host);
         return;
     }
-    // the device's LDS per work-group (initialised once, thread-safely: slot threads of the
-    // server launch this concurrently)
-    static const int lds_limit = [] {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-            v = 64 * 1024;
-        (void)hipGetLastError();
-        return v;
-    }();
+    const int lds_limit = device_lds_per_block();
     const RRLayout L = rr_layout(k, nwant | 1);
     const size_t bytes = (size_t)L.total * sizeof(double);
     // register-row width: 8 lanes per row, NT columns per lane
