@@ -34,6 +34,11 @@ constexpr int TR = 64;   // output rows per work-group
 constexpr int TC = 16;   // right-hand sides per work-group
 constexpr int TCW = 64;  // the same for wide blocks (at least kWideCols columns)
 constexpr int kWideCols = 128;
+// FP64 blocks of at least kWide64Cols columns: 128 right-hand sides per deep task (each
+// panel chunk read half as often; 512 columns of the 296k-dof factor: 39.1 against
+// 41.4 ms per apply.  In FP32 the 128-wide tiles lose: 28.0 against 23.8 ms)
+constexpr int TCW64 = 128;
+constexpr int kWide64Cols = 256;
 static_assert(kDeepChunk % 64 == 0, "deep tasks stage 64 reduction indices at a time");
 constexpr int KS = 64;   // reduction chunk per work-group (one LDS stage)
 constexpr int64_t kLevelsMaxNnz = 30000000;   // factors up to this nnz(L) apply level by level (narrow blocks)
@@ -335,7 +340,8 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
         // task list), so each panel chunk is read a quarter as often and each output tile
         // takes a quarter of the atomic adds
         const bool wide = ncols >= kWideCols && F.sweep_deep.n > 0;
-        const int nc = wide ? TCW : TC;
+        const bool wide128 = wide && sizeof(T) == 8 && ncols >= kWide64Cols;
+        const int nc = wide128 ? TCW64 : wide ? TCW : TC;
         const int groups = (ncols + nc - 1) / nc;
         const int64_t ninit = 3 * (int64_t)F.nsn;
         const size_t need = 4 + (size_t)ninit * groups;
@@ -348,7 +354,12 @@ void launch_precond_solve(const DevFactor& F, T* Y, T* W1, T* W2, int64_t n, int
         hipLaunchKernelGGL((k_sweep_init<T>), dim3((unsigned)blocks), dim3(256), 0, s, count, W2,
                            wide ? F.sweep_init_deep.p : F.sweep_init.p, ninit, F.sweep_cnt.p, groups);
         const int64_t ntasks = (int64_t)(wide ? F.sweep_deep.n : F.sweep.n);
-        if (wide)
+        if (wide128) {
+            if constexpr (sizeof(T) == 8)
+                hipLaunchKernelGGL((k_sn_sweep<T, TCW64, kDeepChunk>), dim3((unsigned)(ntasks * groups)), dim3(256),
+                                   0, s, F.sweep_deep.p, ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p,
+                                   F.nsn, groups);
+        } else if (wide)
             hipLaunchKernelGGL((k_sn_sweep<T, TCW, kDeepChunk>), dim3((unsigned)(ntasks * groups)), dim3(256), 0,
                                s, F.sweep_deep.p, ntasks, F.rows.p, panels, Y, W2, ncols, F.sweep_cnt.p, F.nsn,
                                groups);

@@ -120,9 +120,10 @@ def test_residual(prob, ctx):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("p", [21, 150])
+@pytest.mark.parametrize("p", [21, 150, 300])
 def test_global_precond_apply(prob, precision, p):
-    """p = 150 takes the wide tasks (64 right-hand sides each, the last group ragged)."""
+    """p = 150 takes the wide tasks (64 right-hand sides each, the last group ragged);
+    p = 300 in FP64 the 128-wide ones (two full groups and a ragged third)."""
     P, pr = prob
     import paper_1308_2445_amd as lp
     torch = _torch()
