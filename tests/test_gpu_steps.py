@@ -285,11 +285,13 @@ def c2_pencil():
 
 
 @pytest.mark.parametrize("k,nwant,dup,hscale", [(300, 150, 0, 1e100), (538, 282, 0, 1.0), (1076, 564, 0, 1.0),
-                                                (300, 150, 20, 1.0), (144, 1, 0, 1.0), (161, 161, 0, 1e-100)])
+                                                (1400, 700, 0, 1.0), (300, 150, 20, 1.0), (144, 1, 0, 1.0),
+                                                (161, 161, 0, 1e-100)])
 def test_rayleigh_ritz_large(c2_pencil, ctx, k, nwant, dup, hscale):
     """Orders of the 128k- and 296k-dof cells (k up to 538 and 1076) on pencils of the
     16k-dof cell; with repeated directions the Cholesky of S_R fails and the
-    rank-revealing route takes over."""
+    rank-revealing route takes over.  Up to k = 1076 the tridiagonalisation keeps each
+    work-group's columns in LDS; at k = 1400 they do not fit and stay in global memory."""
     P = c2_pencil
     import paper_1308_2445_amd as lp
     torch = _torch()
