@@ -127,10 +127,18 @@ def measured_traffic(kernel, workload):
         src = os.path.join(ROOT, f["source"])
         if not os.path.exists(src):
             return None
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != f["sha256"]:
+        if source_digest(src) != f["sha256"]:
             return None
         return float(f["bytes_per_launch"])
     return None
+
+
+def source_digest(src):
+    """sha256 of a kernel's source file followed by the header every kernel source includes
+    (the shared device helpers, e.g. the sliced-ELL slot loop, live there)."""
+    h = hashlib.sha256(open(src, "rb").read())
+    h.update(open(os.path.join(os.path.dirname(src), "common.h"), "rb").read())
+    return h.hexdigest()
 
 
 def measured_peaks():
@@ -244,14 +252,14 @@ def summarize_traffic(dirs, out, command):
         f.write("# copy calibration: FETCH_SIZE %.1f KiB per 512 MiB copy -> factor %.4f; WRITE_SIZE %.1f KiB -> "
                 "factor %.4f\n" % (ff * copy_kib, ff, wf * copy_kib, wf))
         f.write("# bytes_per_launch = (FETCH_SIZE / fetch factor + WRITE_SIZE / write factor) * 1024, mean over the\n"
-                "# kernel's dispatches; sha256 is that of the kernel's source when the counters were taken (bench.py\n"
-                "# reports the figure only while the source is unchanged).  FETCH_SIZE counts L2 fills from the\n"
-                "# fabric, hits in the MALL included, so it bounds HBM reads from above.\n#\n")
+                "# kernel's dispatches; sha256 is that of the kernel's source file followed by csrc/common.h when\n"
+                "# the counters were taken (bench.py reports the figure only while both are unchanged).  FETCH_SIZE\n"
+                "# counts L2 fills from the fabric, hits in the MALL included, so it bounds HBM reads from above.\n#\n")
         for k in sorted(set(fetch) & set(write)):
             src = kernel_source(k)
             if src is None:
                 continue
-            sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+            sha = source_digest(os.path.join(ROOT, src))
             by = (fetch[k][0] / ff + write[k][0] / wf) * 1024
             f.write("kernel=%s source=%s sha256=%s dispatches=%d fetch_kib_per_dispatch=%.1f "
                     "write_kib_per_dispatch=%.1f fetch_factor=%.4f write_factor=%.4f bytes_per_launch=%.0f\n"

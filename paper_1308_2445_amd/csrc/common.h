@@ -226,14 +226,16 @@ __device__ __forceinline__ void sell_stage(const int32_t* __restrict__ col, cons
 }
 
 // ah[j] += H(row, :) x_j and as[j] += S(row, :) x_j over the ns staged slots, for the CW
-// columns whose bases xp[j] gives (row = the lane's row of the slice).  Two slots at a
-// time: both slots' gathers of every column are issued before the products.  Padding
-// slots hold the lane's own row and zero values.
+// columns whose bases xp[j] gives (row = the lane's row of the slice).  Four slots at a
+// time: all four slots' gathers of every column are issued before the products (two at a
+// time left a wavefront waiting on each pair's gathers: 296k-dof cell, 410 columns, 4.32
+// against 4.10 ms per product; eight gain nothing more).  Padding slots hold the lane's
+// own row and zero values.
 template <typename T, int CW>
 __device__ __forceinline__ void sell_lds_accumulate(SliceLds<T> L, int ns, const T* const (&xp)[CW],
                                                     T (&ah)[CW], T (&as)[CW]) {
     const int lane = threadIdx.x & 63;
-    constexpr int U = 2;
+    constexpr int U = 4;
     int k = 0;
     for (; k + U <= ns; k += U) {
         int32_t c[U];
@@ -257,7 +259,7 @@ __device__ __forceinline__ void sell_lds_accumulate(SliceLds<T> L, int ns, const
                 as[j] = fma(s[u], x[u][j], as[j]);
             }
     }
-    if (k < ns) {
+    for (; k < ns; ++k) {
         const int32_t c = L.c[k * kSlice + lane];
         const T h = L.h[k * kSlice + lane], s = L.s[k * kSlice + lane];
 #pragma unroll
