@@ -116,10 +116,14 @@ def c2_oracle(c2):
     return olab.solve(P.H(), P.S(), prm, pufe.start_block(P.n, m + m0, 0))
 
 
-def test_c2_subspaces_match_oracle(c2, c2_oracle):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_subspaces_match_oracle(c2, c2_oracle, precision):
+    """Every eigenvalue and every cluster's S-principal angles against the oracle's run, in
+    FP64 and with the FP32 preconditioners (the residuals, Gram and Rayleigh-Ritz stay
+    FP64, so the mixed run reaches the same tolerance)."""
     P, pr, g = c2
     m, m0 = g["nev"], g["m0"]
-    out = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-11, sigma0=P.sigma0, precision=0)
+    out = pr.solve(m, m0, pufe.start_block(P.n, m + m0, 0), tol=1e-11, sigma0=P.sigma0, precision=precision)
     assert out.converged
     ref = c2_oracle
     assert _rel_err(out.lam, ref.lam, P.sigma0).max() < 1e-10

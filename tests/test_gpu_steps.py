@@ -137,13 +137,15 @@ def test_global_precond_apply(prob, precision, p):
     ref = K.apply(R)
     A = K.K
     back = np.linalg.norm(A @ got + R, axis=0) / np.linalg.norm(R, axis=0)
+    # column by column against the oracle's apply
+    colerr = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
     if precision == 0:
         assert back.max() < 1e-11
-        assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(ref)
+        assert colerr.max() <= 1e-9
     else:
         # FP32 substitutions: a preconditioner, not a solver (stated, not a parity claim)
         assert back.max() < 5e-3
-        assert np.linalg.norm(got - ref) <= 5e-3 * np.linalg.norm(ref)
+        assert colerr.max() <= 5e-3
 
 
 @pytest.mark.parametrize("precision", [0, 1])
