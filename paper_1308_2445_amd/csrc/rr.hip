@@ -1272,8 +1272,11 @@ constexpr int kRRSpinLimit = 1 << 20;
 __host__ __device__ inline int rrl_kp(int k) { return (k + kLT - 1) / kLT * kLT; }
 
 struct RRLLayout {
-    int64_t ctl, D, A, L, B, Y, d, e, tau, theta, sh, vb, p, part, sc, icl, Zt, U3, total;
+    int64_t ctl, D, A, L, B, Y, d, e, tau, theta, sh, vb, p, part, sc, icl, Zt, U3, wyt, total;
 };
+
+// blocks of kLT reflectors in the back-transformation (k - 2 reflectors)
+__host__ __device__ inline int rrl_wy_blocks(int k) { return k > 2 ? (k - 2 + kLT - 1) / kLT : 1; }
 
 // offsets in doubles; everything before Zt is independent of nwp
 __host__ __device__ inline RRLLayout rrl_layout(int k, int nwp) {
@@ -1297,7 +1300,8 @@ __host__ __device__ inline RRLLayout rrl_layout(int k, int nwp) {
     L.icl = L.sc + 8;          // 2 kp + 4 int32
     L.Zt = L.icl + kp + 2;
     L.U3 = L.Zt + (int64_t)k * nwp;
-    L.total = L.U3 + 3 * (int64_t)k * nwp;
+    L.wyt = L.U3 + 3 * (int64_t)k * nwp;   // kLT x kLT per block of reflectors
+    L.total = L.wyt + (int64_t)kLT * kLT * rrl_wy_blocks(k);
     return L;
 }
 
@@ -1812,7 +1816,63 @@ __global__ __launch_bounds__(kRRThreads) void k_rrl_teig(int k, int nwant, doubl
     }
 }
 
-// W(:, slice) = D L^{-T} Q Z(:, slice) for the 16-column slice blockIdx.x
+// The compact-WY factor T of every block of kLT reflectors (one work-group per block):
+// T upper triangular from tau and V^T V, wyt[kLT kLT b + kLT r + c] = T(r, c) for block b
+// (reflectors kLT b .. kLT b + kLT - 1).  Every 16-column slice of the back-transformation
+// applies the same blocks, so T is formed once here rather than in each of them.
+__global__ __launch_bounds__(kLThreads) void k_rrl_wyt(int k, int nwant, double* __restrict__ base) {
+    if (rrl_failed(base)) return;
+    const int nwp = nwant | 1;
+    const RRLLayout Lo = rrl_layout(k, nwp);
+    const int64_t kp = rrl_kp(k);
+    const double* C = base + Lo.Y;
+    const double* tau = base + Lo.tau;
+    double* wyt = base + Lo.wyt;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    __shared__ double red[4][256];
+    __shared__ double lpp[16][17], tm[16][17];
+    const int i = tid >> 4, j = tid & 15;
+    const int nref = k - 2;
+    const int j0 = (int)blockIdx.x * kLT;
+    const int nb = min(kLT, nref - j0);
+    // V(row, c): 0 above row j0 + c + 1, 1 there, the stored entries below
+    auto vv = [&](int row, int c) -> double {
+        const int top = j0 + c + 1;
+        if (c >= nb || row < top || row >= k) return 0.0;
+        return row == top ? 1.0 : C[row + (int64_t)(j0 + c) * kp];
+    };
+    rr_double4 accG = {0.0, 0.0, 0.0, 0.0};
+    accG = mfma_tile([&](int c, int row) { return vv(row, c); },
+                     [&](int row, int b) { return vv(row, b); }, j0, (int)kp, wave, 4, accG);
+    tile_to_lds(accG, red);
+    __syncthreads();
+    lpp[i][j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];   // V^T V
+    __syncthreads();
+    // T: column c from columns < c
+    if (tid < 16) {
+        const int r = tid;
+        for (int c = 0; c < 16; ++c) {
+            double v = 0.0;
+            if (c < nb && r <= c) {
+                const double tc = tau[j0 + c];
+                if (r == c) {
+                    v = tc;
+                } else {
+                    double acc = 0.0;
+                    for (int m = r; m < c; ++m) acc = fma(tm[r][m], lpp[m][c], acc);
+                    v = -tc * acc;
+                }
+            }
+            tm[r][c] = v;
+        }
+    }
+    __syncthreads();
+    wyt[(int64_t)blockIdx.x * (kLT * kLT) + tid] = tm[i][j];
+}
+
+// W(:, slice) = D L^{-T} Q Z(:, slice) for the 16-column slice blockIdx.x.  XLDS: the
+// slice (kp x 16) lives in dynamic LDS for the whole kernel, else in the workspace.
+template <bool XLDS>
 __global__ __launch_bounds__(kLThreads) void k_rrl_back(int k, int nwant, double* __restrict__ base,
                                                         double* __restrict__ W, int64_t ldw) {
     if (rrl_failed(base)) return;
@@ -1821,14 +1881,15 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_back(int k, int nwant, double
     const int64_t kp = rrl_kp(k);
     const int nrb = (int)(kp / kLT);
     const double* C = base + Lo.Y;
-    const double* tau = base + Lo.tau;
     const double* Zt = base + Lo.Zt;
     const double* L = base + Lo.L;
     const double* At = base + Lo.A;
     const double* D = base + Lo.D;
+    const double* wyt = base + Lo.wyt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q0 = blockIdx.x * kLT;
-    double* X = base + Lo.B + (int64_t)blockIdx.x * kp * kLT;
+    extern __shared__ double xdyn[];
+    double* X = XLDS ? xdyn : base + Lo.B + (int64_t)blockIdx.x * kp * kLT;
     __shared__ double red[4][256];
     __shared__ double t[16][17], lpp[16][17], tm[16][17], w2[16][17];
     for (int64_t el = tid; el < kp * kLT; el += kLThreads) {
@@ -1838,8 +1899,8 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_back(int k, int nwant, double
     }
     __syncthreads();
     // X <- H_j0 ... H_j0+15 X for the blocks of 16 reflectors from the last one down, in
-    // compact WY form I - V T V^T (V: the block's reflectors, rows j0.. kp; T upper
-    // triangular from tau and V^T V): X -= V (T (V^T X))
+    // compact WY form I - V T V^T (V: the block's reflectors, rows j0.. kp; T from
+    // k_rrl_wyt): X -= V (T (V^T X))
     const int i = tid >> 4, j = tid & 15;
     const int nref = k - 2;
     for (int j0 = (nref - 1) / kLT * kLT; j0 >= 0; j0 -= kLT) {
@@ -1850,37 +1911,14 @@ __global__ __launch_bounds__(kLThreads) void k_rrl_back(int k, int nwant, double
             if (c >= nb || row < top || row >= k) return 0.0;
             return row == top ? 1.0 : C[row + (int64_t)(j0 + c) * kp];
         };
-        rr_double4 accW = {0.0, 0.0, 0.0, 0.0}, accG = {0.0, 0.0, 0.0, 0.0};
+        const double tij = wyt[(int64_t)(j0 / kLT) * (kLT * kLT) + tid];
+        rr_double4 accW = {0.0, 0.0, 0.0, 0.0};
         accW = mfma_tile([&](int c, int row) { return vv(row, c); },
                          [&](int row, int b) { return X[(int64_t)row * kLT + b]; }, j0, (int)kp, wave, 4, accW);
-        accG = mfma_tile([&](int c, int row) { return vv(row, c); },
-                         [&](int row, int b) { return vv(row, b); }, j0, (int)kp, wave, 4, accG);
         tile_to_lds(accW, red);
+        tm[i][j] = tij;
         __syncthreads();
         t[i][j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];   // V^T X
-        __syncthreads();
-        tile_to_lds(accG, red);
-        __syncthreads();
-        lpp[i][j] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];   // V^T V
-        __syncthreads();
-        // T into part-free LDS: Tm[r][c] for r <= c < nb (column c from columns < c)
-        if (tid < 16) {
-            const int r = tid;
-            for (int c = 0; c < 16; ++c) {
-                double v = 0.0;
-                if (c < nb && r <= c) {
-                    const double tc = tau[j0 + c];
-                    if (r == c) {
-                        v = tc;
-                    } else {
-                        double acc = 0.0;
-                        for (int m = r; m < c; ++m) acc = fma(tm[r][m], lpp[m][c], acc);
-                        v = -tc * acc;
-                    }
-                }
-                tm[r][c] = v;
-            }
-        }
         __syncthreads();
         // W2 = T (V^T X)
         {
@@ -2001,8 +2039,14 @@ void launch_rr_large(int k, int nwant, const double* HR, const double* SR, int64
         hipLaunchKernelGGL(k_rrl_bisect, dim3((nwant + 3) / 4), dim3(kLThreads), bl, s, k, nwant, base);
         hipLaunchKernelGGL(k_rrl_teig, dim3(1), dim3(kRRThreads), 0, s, k, nwant, base, gamma, info, gamma_host,
                            info_host);
-        hipLaunchKernelGGL(k_rrl_back, dim3((nwant + kLT - 1) / kLT), dim3(kLThreads), 0, s, k, nwant, base, W,
-                           ldw);
+        hipLaunchKernelGGL(k_rrl_wyt, dim3((unsigned)rrl_wy_blocks(k)), dim3(kLThreads), 0, s, k, nwant, base);
+        // the 16-column slice in LDS when it fits beside the kernel's static LDS (about 18 KB)
+        const size_t xl = (size_t)kp * kLT * sizeof(double);
+        const bool xlds = xl + 20 * 1024 <= (size_t)device_lds_per_block();
+        const void* back = xlds ? (const void*)k_rrl_back<true> : (const void*)k_rrl_back<false>;
+        if (xlds && xl > 32 * 1024) allow_dynamic_lds(back);
+        void* bargs[] = {(void*)&k, (void*)&nwant, (void*)&base, (void*)&W, (void*)&ldw};
+        LABPSD_HIP(hipLaunchKernel(back, dim3((nwant + kLT - 1) / kLT), dim3(kLThreads), bargs, xlds ? xl : 0, s));
         LABPSD_HIP(hipGetLastError());
     } else {
         (void)hipGetLastError();
